@@ -1,0 +1,168 @@
+"""ctypes front end of the FP64 CPU oracle (oracle/oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``.  The product path (the HIP
+library and its Python binding) never imports this module.
+
+Every array goes in as float64 (callers hand over their float32 inputs
+promoted to float64, so both sides see identical values).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into liboracle.so with g++ (plain -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, dbl, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+        lib.orc_param_count.argtypes = [P]
+        lib.orc_param_count.restype = i64
+        lib.orc_param_offsets.argtypes = [P, P, i32]
+        lib.orc_param_offsets.restype = i32
+        lib.orc_slogdet.argtypes = [i32, P, P, P]
+        lib.orc_eval.argtypes = [P, i32, P, P, P, P, i32, i32, P, P, P, P, P, P]
+        lib.orc_potential.argtypes = [P, i32, P, P, P, P]
+        lib.orc_param_grad.argtypes = [P, i32, P, P, P, i32, P, i32, P]
+        lib.orc_philox4x32_10.argtypes = [P, P, P]
+        lib.orc_philox4x32_10.restype = None
+        lib.orc_mcmc_noise.argtypes = [i32, i32, i32, u64, u64, P, P]
+        lib.orc_mcmc.argtypes = [P, i32, P, P, P, i32, dbl, P, P, u64, u64, i32, P, P, P]
+        for f in ("orc_slogdet", "orc_eval", "orc_potential", "orc_param_grad", "orc_mcmc_noise", "orc_mcmc"):
+            getattr(lib, f).restype = i32
+        _lib = lib
+    return _lib
+
+
+def _cfg(cfg) -> np.ndarray:
+    return np.array([cfg["n_elec"], cfg["n_up"], cfg["n_down"], cfg["n_nuc"], cfg["n_layers"],
+                     cfg["width1"], cfg["width2"], cfg["n_det"]], dtype=np.int32)
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _threads(n):
+    return int(n) if n else 0
+
+
+def param_count(cfg) -> int:
+    return int(_load().orc_param_count(_p(_cfg(cfg))))
+
+
+def param_offsets(cfg) -> np.ndarray:
+    out = np.zeros(4096, dtype=np.int64)
+    c = _cfg(cfg)
+    k = _load().orc_param_offsets(_p(c), _p(out), out.size)
+    assert k > 0
+    return out[:k].copy()
+
+
+def slogdet(a):
+    a = _d(a)
+    n = a.shape[0]
+    s = np.zeros(1)
+    la = np.zeros(1)
+    _load().orc_slogdet(n, _p(a), _p(s), _p(la))
+    return float(s[0]), float(la[0])
+
+
+def evaluate(cfg, pos, nuc_pos, nuc_charge, params, energy=True, threads=None, grad_pos=False):
+    """sign, log|psi| and (energy=True) E_L, E_kin, E_pot per walker."""
+    pos = _d(pos)
+    W = pos.shape[0]
+    nuc, Z, prm = _d(nuc_pos), _d(nuc_charge), _d(params)
+    c = _cfg(cfg)
+    out = {k: np.zeros(W) for k in ("sign", "logpsi", "e_loc", "e_kin", "e_pot")}
+    gp = np.zeros((W, 3 * cfg["n_elec"])) if grad_pos else None
+    rc = _load().orc_eval(_p(c), W, _p(pos), _p(nuc), _p(Z), _p(prm), 1 if energy else 0, _threads(threads),
+                          _p(out["sign"]), _p(out["logpsi"]), _p(out["e_loc"]), _p(out["e_kin"]),
+                          _p(out["e_pot"]), _p(gp) if gp is not None else None)
+    assert rc == 0, rc
+    if not energy:
+        for k in ("e_loc", "e_kin", "e_pot"):
+            del out[k]
+    if gp is not None:
+        out["grad_pos"] = gp
+    return out
+
+
+def potential(cfg, pos, nuc_pos, nuc_charge):
+    """(V_ee, V_en, V_nn) per walker, [W][3]."""
+    pos = _d(pos)
+    W = pos.shape[0]
+    out = np.zeros((W, 3))
+    rc = _load().orc_potential(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(nuc_charge)), _p(out))
+    assert rc == 0
+    return out
+
+
+def param_grad(cfg, pos, nuc_pos, params, sel, threads=None):
+    """d log|psi_w| / d theta_p for p in sel: [W][len(sel)]."""
+    pos = _d(pos)
+    W = pos.shape[0]
+    sel = np.ascontiguousarray(np.asarray(sel, dtype=np.int64))
+    out = np.zeros((W, sel.size))
+    rc = _load().orc_param_grad(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(params)), sel.size, _p(sel),
+                                _threads(threads), _p(out))
+    assert rc == 0
+    return out
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    o = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def mcmc_noise(W, n_elec, n_steps, seed, counter=0):
+    noise = np.zeros((n_steps, W, 3 * n_elec))
+    uni = np.zeros((n_steps, W))
+    _load().orc_mcmc_noise(W, n_elec, n_steps, seed, counter, _p(noise), _p(uni))
+    return noise, uni
+
+
+def mcmc(cfg, pos, nuc_pos, params, logpsi, sign, n_steps, width, noise=None, uniforms=None, seed=0, counter=0,
+         threads=None):
+    """Replay n_steps Metropolis steps; returns (pos, logpsi, sign, n_accepted)."""
+    pos = _d(pos).copy()
+    W = pos.shape[0]
+    lp = _d(logpsi).copy()
+    sg = _d(sign).copy()
+    acc = np.zeros(W, dtype=np.int32)
+    nz = _d(noise) if noise is not None else None
+    un = _d(uniforms) if uniforms is not None else None
+    rc = _load().orc_mcmc(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(params)), n_steps, float(width),
+                          _p(nz) if nz is not None else None, _p(un) if un is not None else None, seed, counter,
+                          _threads(threads), _p(lp), _p(sg), _p(acc))
+    assert rc == 0
+    return pos, lp, sg, acc

@@ -1,0 +1,561 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics
+fix (no GPU).  Each test names the passage it follows.
+
+The paper prints no worked example of psi or E_L, so the oracle is pinned
+by: brute-force determinants, closed forms of hydrogen-like special cases
+of Eqs. (2), (4), (5), symbolic differentiation of tiny networks,
+invariants (antisymmetry, translation), finite differences and published
+Philox known-answer vectors.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2011_07125_amd import inputs as I
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+
+
+def blank(cfg):
+    return np.zeros(I.param_offsets(cfg)["_total"], dtype=np.float64)
+
+
+def put(params, cfg, name, value):
+    off, shape = I.param_offsets(cfg)[name]
+    size = int(np.prod(shape))
+    params[off:off + size] = np.broadcast_to(np.asarray(value, dtype=np.float64), shape).reshape(-1)
+
+
+def leibniz_det(a):
+    n = a.shape[0]
+    tot = 0.0
+    for perm in itertools.permutations(range(n)):
+        inv = sum(1 for i in range(n) for j in range(i + 1, n) if perm[i] > perm[j])
+        prod = 1.0
+        for i in range(n):
+            prod *= a[i, perm[i]]
+        tot += (-1) ** inv * prod
+    return tot
+
+
+# --------------------------------------------------------------- layout
+def test_layout_matches_interface_and_counts():
+    """The oracle's own layout offsets equal the documented layout, and the
+    parameter counts of the workloads are the ones the shapes imply."""
+    expect = {"be4": 4888, "ne10": 688832, "ar18": 2768800, "c4h6": 808000}
+    for name, count in expect.items():
+        cfg = I.make_workload(name, walkers=1)["cfg"]
+        assert O.param_count(cfg) == count
+        offs = I.param_offsets(cfg)
+        names = [b[0] for b in I.param_blocks(cfg)]
+        assert list(O.param_offsets(cfg)) == [offs[n][0] for n in names] + [offs["_total"]]
+
+
+# ------------------------------------------------------------------- T1
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_slogdet_vs_leibniz(n):
+    """Eq. (4) determinants: LU slogdet equals the permutation sum."""
+    rng = np.random.default_rng(10 + n)
+    for _ in range(20):
+        a = rng.normal(size=(n, n))
+        if n > 1 and rng.random() < 0.5:
+            a[0, 0] = 0.0  # forces a row exchange
+        s, la = O.slogdet(a)
+        d = leibniz_det(a)
+        assert s == np.sign(d)
+        assert abs(la - math.log(abs(d))) < 1e-12 * max(1.0, abs(la))
+
+
+def test_slogdet_singular_and_empty():
+    s, la = O.slogdet(np.array([[1.0, 2.0], [2.0, 4.0]]))
+    assert s == 0.0 and la == -np.inf
+    s, la = O.slogdet(np.zeros((0, 0)))
+    assert s == 1.0 and la == 0.0
+
+
+# --------------------------------------------------------- hydrogenic
+def hydrogenic_cfg(n_up, n_down, L=1, d1=3, d2=2, K=1, N=1):
+    return I.make_cfg(n_up, n_down, N, L, d1, d2, K)
+
+
+def test_T2_zero_variance_hydrogenic():
+    """One electron, network output zeroed, sigma = Z: psi = exp(-Z r) is the
+    exact ground state of Eq. (2) with one nucleus, so E_L = -Z^2/2 for every
+    position (zero variance).  Also covers n_down = 0."""
+    for Z in (1.0, 4.0, 10.0):
+        cfg = hydrogenic_cfg(1, 0)
+        p = blank(cfg)
+        rng = np.random.default_rng(1)
+        p[:] = rng.normal(size=p.size)  # random network ...
+        put(p, cfg, "w_orb0", 0.0)       # ... whose output is zeroed
+        put(p, cfg, "g_orb0", 1.0)
+        put(p, cfg, "pi0", 1.0)
+        put(p, cfg, "sigma0", Z)
+        pos = rng.normal(size=(64, 1, 3)) * 1.3
+        r = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p)
+        np.testing.assert_allclose(r["e_loc"], -Z * Z / 2, rtol=0, atol=1e-11 * Z * Z)
+        np.testing.assert_allclose(r["logpsi"], -Z * np.linalg.norm(pos[:, 0], axis=1), atol=1e-12)
+
+
+def test_T3_hydrogenic_off_exponent_and_two_electrons():
+    """sigma != Z: E_L = -sigma^2/2 + (sigma - Z)/r.  Two electrons (1 up,
+    1 down), product of two determinants: E_L = -sigma^2 +
+    (sigma - Z)(1/r1 + 1/r2) + 1/r12 (Eq. (2) with its e-e term)."""
+    Z, sig = 3.0, 2.2
+    rng = np.random.default_rng(2)
+    cfg = hydrogenic_cfg(1, 0)
+    p = blank(cfg)
+    put(p, cfg, "g_orb0", 1.0)
+    put(p, cfg, "pi0", 1.0)
+    put(p, cfg, "sigma0", -sig)  # the envelope uses |sigma|
+    pos = rng.normal(size=(32, 1, 3))
+    r = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p)
+    rr = np.linalg.norm(pos[:, 0], axis=1)
+    np.testing.assert_allclose(r["e_loc"], -sig ** 2 / 2 + (sig - Z) / rr, rtol=1e-11)
+
+    cfg = hydrogenic_cfg(1, 1, L=2)
+    p = blank(cfg)
+    p[:] = rng.normal(size=p.size)
+    for a in (0, 1):
+        put(p, cfg, f"w_orb{a}", 0.0)
+        put(p, cfg, f"g_orb{a}", 1.0 + a)
+        put(p, cfg, f"pi{a}", 1.0)
+        put(p, cfg, f"sigma{a}", sig)
+    pos = rng.normal(size=(32, 2, 3))
+    r = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p)
+    r1 = np.linalg.norm(pos[:, 0], axis=1)
+    r2 = np.linalg.norm(pos[:, 1], axis=1)
+    r12 = np.linalg.norm(pos[:, 0] - pos[:, 1], axis=1)
+    np.testing.assert_allclose(r["e_loc"], -sig ** 2 + (sig - Z) * (1 / r1 + 1 / r2) + 1 / r12, rtol=1e-11)
+    np.testing.assert_allclose(r["e_pot"], 1 / r12 - Z / r1 - Z / r2, rtol=1e-12)
+
+
+def test_T4_lcao_slater_determinant():
+    """Network zeroed: the orbitals are g_i sum_m pi_im exp(-sigma_im |r-R_m|)
+    (Eq. (5) with isotropic envelope).  The kinetic term then follows in
+    closed form: lap_j D / D = sum_i (A^-1)_{ji} lap phi_i(r_j) with
+    lap exp(-s d) = (s^2 - 2 s / d) exp(-s d), summed over determinants with
+    weights D_k / psi (Eq. (4) without omega)."""
+    rng = np.random.default_rng(4)
+    n_up, n_dn, K = 3, 2, 3
+    nuc = np.array([[0.0, 0.0, 0.0], [1.4, -0.3, 0.5]])
+    Z = np.array([3.0, 2.0])
+    cfg = hydrogenic_cfg(n_up, n_dn, L=2, d1=4, d2=3, K=K, N=2)
+    p = blank(cfg)
+    p[:] = rng.normal(size=p.size)
+    orb = {}
+    for a, na in ((0, n_up), (1, n_dn)):
+        put(p, cfg, f"w_orb{a}", 0.0)
+        g = rng.uniform(0.5, 1.5, size=K * na)
+        pi = rng.uniform(0.3, 1.2, size=(K * na, 2))
+        sg = rng.uniform(0.5, 2.0, size=(K * na, 2))
+        put(p, cfg, f"g_orb{a}", g)
+        put(p, cfg, f"pi{a}", pi)
+        put(p, cfg, f"sigma{a}", sg)
+        orb[a] = (g, pi, sg)
+    W = 24
+    pos = rng.normal(size=(W, n_up + n_dn, 3)) * 1.2
+    res = O.evaluate(cfg, pos, nuc, Z, p)
+
+    def phi_all(a, r):  # values and Laplacians of all K*n_a orbitals at r
+        g, pi, sg = orb[a]
+        d = np.linalg.norm(r[None, :] - nuc, axis=1)  # [2]
+        e = np.exp(-sg * d[None, :])
+        val = g * (pi * e).sum(1)
+        lap = g * (pi * (sg ** 2 - 2 * sg / d[None, :]) * e).sum(1)
+        return val, lap
+
+    for w in range(W):
+        dets, laps = [], []
+        for k in range(K):
+            dk, lk = 1.0, 0.0
+            for a, (j0, na) in enumerate(((0, n_up), (n_up, n_dn))):
+                A = np.zeros((na, na))
+                LA = np.zeros((na, na))
+                for j in range(na):
+                    v, l = phi_all(a, pos[w, j0 + j])
+                    A[:, j] = v[k * na:(k + 1) * na]
+                    LA[:, j] = l[k * na:(k + 1) * na]
+                Ainv = np.linalg.inv(A)
+                dk *= np.linalg.det(A)
+                lk += sum(Ainv[j] @ LA[:, j] for j in range(na))
+            dets.append(dk)
+            laps.append(lk)
+        psi = sum(dets)
+        lap_over_psi = sum(d * l for d, l in zip(dets, laps)) / psi
+        assert res["sign"][w] == np.sign(psi)
+        assert abs(res["logpsi"][w] - math.log(abs(psi))) < 1e-11
+        assert abs(res["e_kin"][w] - (-0.5 * lap_over_psi)) < 1e-8 * max(1, abs(lap_over_psi))
+
+
+def test_T10_coulomb_hand_placed():
+    """Eq. (2) potential terms on hand-placed configurations."""
+    cfg = hydrogenic_cfg(1, 1, N=2)
+    nuc = np.array([[0.0, 0.0, 2.0], [0.0, 2.0, 2.0]])
+    Z = np.array([2.0, 3.0])
+    pos = np.array([[[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]]])
+    v = O.potential(cfg, pos, nuc, Z)[0]
+    assert abs(v[0] - 1.0) < 1e-15
+    en = -(2 / 2.0 + 2 / math.sqrt(5) + 3 / math.sqrt(8) + 3 / math.sqrt(9))
+    assert abs(v[1] - en) < 1e-14
+    assert abs(v[2] - 6 / 2.0) < 1e-15
+
+
+# ------------------------------------------------- symbolic closed forms
+def _sym_energy(expr_logpsi, coords, pot, subs):
+    import sympy as sp
+    grad = [sp.diff(expr_logpsi, c) for c in coords]
+    lap = sum(sp.diff(g, c) for g, c in zip(grad, coords))
+    kin = -sp.Rational(1, 2) * (lap + sum(g * g for g in grad))
+    f = sp.lambdify(coords, [expr_logpsi, kin, pot], "math")
+    return f
+
+
+def test_single_layer_network_closed_form():
+    """One electron, one layer: the orbital is (w tanh(p) + g) exp(-s r) with
+    p = (a + c) x + beta r + b, where a picks x from h_i, c picks x from the
+    spin-up mean field (which includes the electron itself) and beta picks
+    |r - R|.  Its E_L from symbolic differentiation must equal the oracle."""
+    import sympy as sp
+    cfg = I.make_cfg(1, 0, 1, 1, 1, 2, 1)
+    a, c, beta, b, w, g, s, Z = 0.7, -0.4, 0.35, 0.2, 1.3, 0.6, 1.7, 2.0
+    p = blank(cfg)
+    V = np.zeros((20, 1))
+    V[0, 0] = a      # h_i x-component
+    V[4 + 0, 0] = c  # hbar^up x-component
+    V[3, 0] = beta   # h_i |r - R|
+    put(p, cfg, "V0", V)
+    put(p, cfg, "b0", b)
+    put(p, cfg, "w_orb0", w)
+    put(p, cfg, "g_orb0", g)
+    put(p, cfg, "pi0", 1.0)
+    put(p, cfg, "sigma0", s)
+    x, y, z = sp.symbols("x y z", real=True)
+    r = sp.sqrt(x * x + y * y + z * z)
+    pre = (a + c) * x + beta * r + b
+    logpsi = sp.log((w * sp.tanh(pre) + g) ** 2) / 2 - s * r
+    f = _sym_energy(logpsi, [x, y, z], -Z / r, None)
+    rng = np.random.default_rng(5)
+    pos = rng.normal(size=(16, 1, 3))
+    res = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p)
+    for k in range(16):
+        lp, kin, pot = f(*pos[k, 0])
+        assert abs(res["logpsi"][k] - lp) < 1e-12
+        assert abs(res["e_kin"][k] - kin) < 1e-9 * max(1, abs(kin))
+        assert abs(res["e_pot"][k] - pot) < 1e-12
+
+
+def test_two_electron_features_closed_form():
+    """1 up + 1 down electron, one layer: the up electron reads the x- and
+    distance components of its down-spin pair feature h_01 = (r_0 - r_1,
+    |r_0 - r_1|); the down electron those of its up-spin pair feature
+    h_10 = (r_1 - r_0, |r_1 - r_0|).  f_i is ordered [h_i, hbar^up,
+    hbar^down, g^up_i, g^down_i] with 4-wide blocks."""
+    import sympy as sp
+    cfg = I.make_cfg(1, 1, 1, 1, 1, 2, 1)
+    a0, e0, a1, e1 = 0.8, -0.3, -0.5, 0.45
+    wu, gu, wd, gd, s, Z = 1.1, 0.4, -0.9, 0.7, 1.3, 2.0
+    p = blank(cfg)
+    V = np.zeros((20, 1))
+    V[16, 0] = a0  # g^down_i x
+    V[19, 0] = e0  # g^down_i |r_ij|
+    V[12, 0] = a1  # g^up_i x
+    V[15, 0] = e1  # g^up_i |r_ij|
+    put(p, cfg, "V0", V)
+    put(p, cfg, "w_orb0", wu)
+    put(p, cfg, "g_orb0", gu)
+    put(p, cfg, "w_orb1", wd)
+    put(p, cfg, "g_orb1", gd)
+    for k in (0, 1):
+        put(p, cfg, f"pi{k}", 1.0)
+        put(p, cfg, f"sigma{k}", s)
+    X = sp.symbols("x0 y0 z0 x1 y1 z1", real=True)
+    r0 = sp.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)
+    r1 = sp.sqrt(X[3] ** 2 + X[4] ** 2 + X[5] ** 2)
+    r01 = sp.sqrt((X[0] - X[3]) ** 2 + (X[1] - X[4]) ** 2 + (X[2] - X[5]) ** 2)
+    # electron 0 (up): g^up_0 = h_00 = 0 ; g^down_0 = h_01
+    p0 = a0 * (X[0] - X[3]) + e0 * r01
+    # electron 1 (down): g^up_1 = h_10 ; g^down_1 = h_11 = 0
+    p1 = a1 * (X[3] - X[0]) + e1 * r01
+    logpsi = (sp.log((wu * sp.tanh(p0) + gu) ** 2) / 2 - s * r0 + sp.log((wd * sp.tanh(p1) + gd) ** 2) / 2 - s * r1)
+    f = _sym_energy(logpsi, list(X), 1 / r01 - Z / r0 - Z / r1, None)
+    rng = np.random.default_rng(6)
+    pos = rng.normal(size=(12, 2, 3))
+    res = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p)
+    for k in range(12):
+        lp, kin, pot = f(*pos[k].reshape(-1))
+        assert abs(res["logpsi"][k] - lp) < 1e-12
+        assert abs(res["e_kin"][k] - kin) < 1e-9 * max(1, abs(kin))
+        assert abs(res["e_pot"][k] - pot) < 1e-12
+
+
+def test_residual_and_zero_layer():
+    """A layer with zero weights adds tanh(b) to every feature through the
+    residual: an L=2 network with V1 = 0, b1 = beta equals the L=1 network
+    whose orbital bias absorbed w . tanh(beta)."""
+    rng = np.random.default_rng(7)
+    c1 = I.make_cfg(2, 1, 1, 1, 3, 2, 2)
+    c2 = I.make_cfg(2, 1, 1, 2, 3, 2, 2)
+    p1 = rng.normal(size=I.param_offsets(c1)["_total"])
+    p2 = blank(c2)
+    for name in ("V0", "b0", "w_orb0", "w_orb1", "pi0", "pi1", "sigma0", "sigma1"):
+        o1, sh = I.param_offsets(c1)[name]
+        put(p2, c2, name, p1[o1:o1 + int(np.prod(sh))].reshape(sh))
+    beta = 0.3
+    put(p2, c2, "b1", beta)
+    put(p2, c2, "W0", rng.normal(size=(4, 2)))
+    for a in (0, 1):
+        o1, sh = I.param_offsets(c1)[f"w_orb{a}"]
+        wo = p1[o1:o1 + int(np.prod(sh))].reshape(sh)
+        og, shg = I.param_offsets(c1)[f"g_orb{a}"]
+        g1 = p1[og:og + int(np.prod(shg))]
+        put(p2, c2, f"g_orb{a}", g1 - np.tanh(beta) * wo.sum(0))
+    pos = rng.normal(size=(8, 3, 3))
+    r1 = O.evaluate(c1, pos, np.zeros((1, 3)), [3.0], p1)
+    r2 = O.evaluate(c2, pos, np.zeros((1, 3)), [3.0], p2)
+    np.testing.assert_allclose(r2["logpsi"], r1["logpsi"], atol=1e-12)
+    np.testing.assert_allclose(r2["e_loc"], r1["e_loc"], rtol=1e-10)
+    assert (r2["sign"] == r1["sign"]).all()
+
+
+# ---------------------------------------------------------- invariants
+def small_workload(seed=11, W=6, biases=True):
+    w = I.custom_workload(3, 2, [[0, 0, 0], [0.9, 0.4, -0.6]], [3.0, 2.0], W, 3, 6, 4, 3, seed)
+    p = w["params"].astype(np.float64)
+    if biases:  # non-zero biases so that no accidental symmetry hides a bug
+        rng = np.random.default_rng(seed)
+        for name, shape, kind in I.param_blocks(w["cfg"]):
+            if kind == "bias":
+                put(p, w["cfg"], name, rng.normal(size=shape) * 0.3)
+            elif kind in ("pi", "sigma"):
+                put(p, w["cfg"], name, rng.uniform(0.5, 1.5, size=shape))
+    w["params"] = p
+    return w
+
+
+def ev(w, pos=None, **kw):
+    return O.evaluate(w["cfg"], w["pos"] if pos is None else pos, w["nuc_pos"], w["nuc_charge"], w["params"], **kw)
+
+
+def test_T5_T6_antisymmetry_and_swap_invariance():
+    """psi is antisymmetric under exchange of two same-spin electrons (the
+    orbitals are permutation-equivariant, Eq. (5)); E_L is invariant."""
+    w = small_workload()
+    r = ev(w)
+    for (i, j) in ((0, 1), (0, 2), (3, 4)):
+        pos = w["pos"].astype(np.float64).copy()
+        pos[:, [i, j]] = pos[:, [j, i]]
+        q = ev(w, pos)
+        np.testing.assert_allclose(q["logpsi"], r["logpsi"], atol=1e-12)
+        assert (q["sign"] == -r["sign"]).all()
+        np.testing.assert_allclose(q["e_loc"], r["e_loc"], rtol=1e-9, atol=1e-9)
+
+
+def test_T6_translation_invariance():
+    """Moving all electrons and nuclei by one vector leaves psi and E_L
+    unchanged (the features are differences of positions)."""
+    w = small_workload()
+    r = ev(w)
+    t = np.array([0.37, -1.1, 0.52])
+    q = O.evaluate(w["cfg"], w["pos"].astype(np.float64) + t, w["nuc_pos"].astype(np.float64) + t,
+                   w["nuc_charge"], w["params"])
+    np.testing.assert_allclose(q["logpsi"], r["logpsi"], atol=1e-11)
+    np.testing.assert_allclose(q["e_loc"], r["e_loc"], rtol=1e-8)
+
+
+def _det_slice(cfg, p, ks):
+    """parameters of the same network restricted to determinants ks"""
+    c1 = dict(cfg, n_det=len(ks))
+    q = blank(c1)
+    offs, offs1 = I.param_offsets(cfg), I.param_offsets(c1)
+    for name, shape, kind in I.param_blocks(cfg):
+        o, sh = offs[name]
+        blk = p[o:o + int(np.prod(sh))].reshape(sh)
+        if name.startswith(("w_orb", "g_orb", "pi", "sigma")):
+            a = int(name[-1])
+            na = cfg["n_up"] if a == 0 else cfg["n_down"]
+            cols = np.concatenate([np.arange(k * na, (k + 1) * na) for k in ks])
+            blk = blk[..., cols] if name.startswith(("w_orb", "g_orb")) else blk[cols]
+        put(q, c1, name, blk)
+    return c1, q
+
+
+def test_T7_signed_sum_over_determinants_and_omega():
+    """psi = sum_k det_k^up det_k^down (Eq. (4)); the determinant weights are
+    redundant (Section 3): scaling the up-orbital row i of determinant k by
+    omega scales that determinant's term by omega.  K identical determinants
+    give log|psi| = log K + log|det^up det^down|."""
+    w = small_workload(W=8)
+    cfg, p = w["cfg"], w["params"]
+    K = cfg["n_det"]
+    parts = []
+    for k in range(K):
+        c1, q = _det_slice(cfg, p, [k])
+        parts.append(O.evaluate(c1, w["pos"], w["nuc_pos"], w["nuc_charge"], q, energy=False))
+    psi = sum(pt["sign"] * np.exp(pt["logpsi"]) for pt in parts)
+    r = ev(w, energy=False)
+    np.testing.assert_allclose(r["logpsi"], np.log(np.abs(psi)), atol=1e-12)
+    assert (r["sign"] == np.sign(psi)).all()
+    # omega: scale row 0 (orbital i=0) of determinant 1, spin up
+    omega = -2.5
+    p2 = p.copy()
+    na = cfg["n_up"]
+    for name in ("w_orb0", "g_orb0"):
+        o, sh = I.param_offsets(cfg)[name]
+        blk = p2[o:o + int(np.prod(sh))].reshape(sh)
+        blk[..., 1 * na + 0] *= omega
+    r2 = O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], p2, energy=False)
+    psi2 = sum((omega if k == 1 else 1.0) * pt["sign"] * np.exp(pt["logpsi"]) for k, pt in enumerate(parts))
+    np.testing.assert_allclose(r2["logpsi"], np.log(np.abs(psi2)), atol=1e-11)
+    # K identical determinants
+    c1, q = _det_slice(cfg, p, [2])
+    c3, q3 = _det_slice(cfg, p, [2, 2, 2])
+    a = O.evaluate(c1, w["pos"], w["nuc_pos"], w["nuc_charge"], q)
+    b = O.evaluate(c3, w["pos"], w["nuc_pos"], w["nuc_charge"], q3)
+    np.testing.assert_allclose(b["logpsi"], a["logpsi"] + math.log(3), atol=1e-12)
+    np.testing.assert_allclose(b["e_loc"], a["e_loc"], rtol=1e-10)
+
+
+# ------------------------------------------------ finite differences
+def test_T8_laplacian_and_gradient_vs_finite_differences():
+    """d_c log|psi| and sum_c d^2_c log|psi| from the second-order jets equal
+    central finite differences of the oracle's own value pass (h = 1e-4)."""
+    w = small_workload(W=3)
+    r = ev(w, grad_pos=True)
+    pos = w["pos"].astype(np.float64).reshape(3, -1)
+    n3 = pos.shape[1]
+    h = 1e-4
+    lap = np.zeros(3)
+    grad = np.zeros((3, n3))
+    for q in range(n3):
+        pp, pm = pos.copy(), pos.copy()
+        pp[:, q] += h
+        pm[:, q] -= h
+        lp = ev(w, pp.reshape(3, -1, 3), energy=False)["logpsi"]
+        lm = ev(w, pm.reshape(3, -1, 3), energy=False)["logpsi"]
+        lap += (lp - 2 * r["logpsi"] + lm) / h ** 2
+        grad[:, q] = (lp - lm) / (2 * h)
+    np.testing.assert_allclose(r["grad_pos"], grad, atol=1e-6)
+    kin_fd = -0.5 * (lap + (grad ** 2).sum(1))
+    np.testing.assert_allclose(r["e_kin"], kin_fd, rtol=1e-4, atol=1e-4)
+
+
+def test_T9_param_gradient_vs_finite_differences():
+    """d log|psi| / d theta from dual numbers equals central differences on
+    64 seeded parameters (all block kinds represented)."""
+    w = small_workload(W=3)
+    cfg, p = w["cfg"], w["params"]
+    sel = list(I.fd_param_choice(cfg, 48, seed=3))
+    offs = I.param_offsets(cfg)
+    for name in ("b0", "c0", "g_orb1", "pi0", "sigma1", "W1", "V2"):
+        sel.append(offs[name][0])  # first entry of every kind of block
+    sel = np.array(sorted(set(sel)), dtype=np.int64)
+    g = O.param_grad(cfg, w["pos"], w["nuc_pos"], p, sel)
+    h = 1e-6
+    for s_i, q in enumerate(sel):
+        pp, pm = p.copy(), p.copy()
+        pp[q] += h
+        pm[q] -= h
+        fd = (O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], pp, energy=False)["logpsi"] -
+              O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], pm, energy=False)["logpsi"]) / (2 * h)
+        np.testing.assert_allclose(g[:, s_i], fd, rtol=1e-6, atol=1e-7)
+
+
+# ------------------------------------------------- VMC estimator (T11)
+def test_T11_hydrogenic_energy_and_gradient_estimator():
+    """psi = exp(-s r) sampled exactly from psi^2 (r ~ Gamma(3, 1/(2s))):
+    <E_L> = s^2/2 - Z s (Eq. (3)), and 2 mean((E_L - <E_L>) d_s log psi)
+    estimates dE/ds = s - Z.  Pins E_L, d log psi / d sigma and the factor
+    2 of the energy gradient (the gradient output by the library is the
+    mean without the factor 2)."""
+    Z, s = 2.0, 1.6
+    rng = np.random.default_rng(11)
+    M = 20000
+    rad = rng.gamma(3.0, 1.0 / (2 * s), size=M)
+    v = rng.normal(size=(M, 3))
+    pos = (v / np.linalg.norm(v, axis=1, keepdims=True) * rad[:, None])[:, None, :]
+    cfg = hydrogenic_cfg(1, 0)
+    p = blank(cfg)
+    put(p, cfg, "g_orb0", 1.0)
+    put(p, cfg, "pi0", 1.0)
+    put(p, cfg, "sigma0", s)
+    r = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p, threads=8)
+    e = r["e_loc"]
+    se = e.std() / math.sqrt(M)
+    assert abs(e.mean() - (s * s / 2 - Z * s)) < 5 * se
+    sig_idx = I.param_offsets(cfg)["sigma0"][0]
+    d = O.param_grad(cfg, pos[:2000], np.zeros((1, 3)), p, [sig_idx], threads=8)[:, 0]
+    np.testing.assert_allclose(d, -rad[:2000], rtol=1e-12)
+    est = 2 * np.mean((e - e.mean()) * (-rad))
+    sd = 2 * np.std((e - e.mean()) * rad) / math.sqrt(M)
+    assert abs(est - (s - Z)) < 5 * sd
+
+
+# ------------------------------------------------ Philox and Metropolis
+def test_philox_known_answers():
+    """Philox4x32-10 known-answer vectors published with the Random123
+    library (Salmon et al., SC'11)."""
+    kat = [
+        ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+        ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+        ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+         (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+    ]
+    for ctr, key, out in kat:
+        assert tuple(int(x) for x in O.philox4x32_10(ctr, key)) == out
+
+
+def test_noise_distribution():
+    """The Box-Muller normals are standard normal and the acceptance
+    uniforms lie in (0, 1) with mean 1/2."""
+    z, u = O.mcmc_noise(4000, 5, 2, seed=123, counter=7)
+    z = z.reshape(-1)
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1) < 0.02
+    assert abs(np.mean(z ** 4) - 3) < 0.1
+    assert (u > 0).all() and (u < 1).all() and abs(u.mean() - 0.5) < 0.02
+    z2, u2 = O.mcmc_noise(4000, 5, 1, seed=123, counter=8)
+    np.testing.assert_array_equal(z2[0], O.mcmc_noise(4000, 5, 2, seed=123, counter=7)[0][1])
+
+
+def test_metropolis_samples_psi_squared():
+    """Metropolis on psi^2 (Eq. (3)) for the hydrogen-like orbital exp(-s r):
+    after equilibration <r> = 3/(2 s)."""
+    Z, s = 1.0, 1.0
+    cfg = hydrogenic_cfg(1, 0)
+    p = blank(cfg)
+    put(p, cfg, "g_orb0", 1.0)
+    put(p, cfg, "pi0", 1.0)
+    put(p, cfg, "sigma0", s)
+    W = 2000
+    rng = np.random.default_rng(12)
+    pos = rng.normal(size=(W, 1, 3))
+    r0 = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p, energy=False)
+    x, lp, sg, acc = O.mcmc(cfg, pos, np.zeros((1, 3)), p, r0["logpsi"], r0["sign"], 300, 0.6, seed=5, threads=8)
+    rr = []
+    for blk in range(4):
+        x, lp, sg, acc = O.mcmc(cfg, x, np.zeros((1, 3)), p, lp, sg, 25, 0.6, seed=5, counter=300 + 25 * blk,
+                                threads=8)
+        rr.append(np.linalg.norm(x[:, 0], axis=1).mean())
+    assert abs(np.mean(rr) - 1.5) < 0.05
+    # log psi kept in step with the positions
+    np.testing.assert_allclose(O.evaluate(cfg, x, np.zeros((1, 3)), [Z], p, energy=False)["logpsi"], lp,
+                               atol=1e-12)
+
+
+def test_metropolis_replay_supplied_noise_equals_internal():
+    """Supplied draws equal to the generator's give the same chain."""
+    w = small_workload(W=5)
+    r0 = ev(w, energy=False)
+    noise, uni = O.mcmc_noise(5, 5, 3, seed=9, counter=2)
+    a = O.mcmc(w["cfg"], w["pos"], w["nuc_pos"], w["params"], r0["logpsi"], r0["sign"], 3, 0.3, seed=9, counter=2)
+    b = O.mcmc(w["cfg"], w["pos"], w["nuc_pos"], w["params"], r0["logpsi"], r0["sign"], 3, 0.3,
+               noise=noise, uniforms=uni)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    assert a[3].sum() > 0
