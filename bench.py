@@ -1,0 +1,196 @@
+"""Throughput of the FermiNet VMC hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ne10]
+
+One step is one pass of the whole hot path over one batch of walkers:
+a Metropolis move of every walker (log|psi| of the proposal), the local
+energy (sign, log|psi|, kinetic energy from the jets, Coulomb potential)
+and the VMC energy gradient from the hand-written adjoint.  The headline
+form runs the layer GEMMs in split bfloat16 (three bf16 MFMA passes, fp32
+accumulation) with float64 determinants; the plain fp32 form is timed
+beside it on the same inputs.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import torch  # noqa: E402
+
+from paper_2011_07125_amd import ferminet as F  # noqa: E402
+from paper_2011_07125_amd import inputs as I  # noqa: E402
+
+PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense TFLOP/s (MFMA), MI355X
+HBM_GBS = 8000.0
+
+
+def layer_flops(cfg, W, T):
+    """Algorithmic FLOPs of the L layer GEMMs (jet rows x [h_i, g^up_i,
+    g^down_i] x d1, unpadded) and of the L mean-field GEMMs."""
+    n, N, d1, d2, L = cfg["n_elec"], cfg["n_nuc"], cfg["width1"], cfg["width2"], cfg["n_layers"]
+    main = mf = 0
+    for l in range(L):
+        din, ein = (4 * N, 4) if l == 0 else (d1, d2)
+        main += 2 * W * n * T * (din + 2 * ein) * d1
+        mf += 2 * W * T * (2 * din) * d1
+    return main, mf
+
+
+def one_step(w, d, form, state, grad, seed, counter):
+    cfg = w["cfg"]
+    F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], state["logpsi"], state["sign"], 1, 0.02,
+                    seed, counter, precision=form)
+    out = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
+                                  parts=False)
+    if grad:
+        F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], out["e_loc"],
+                              precision=form)
+    return out
+
+
+def time_form(w, form, steps, warmup, grad):
+    d = F.to_device(w)
+    cfg = w["cfg"]
+    s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
+    state = {"sign": s, "logpsi": l}
+    for i in range(warmup):
+        one_step(w, d, form, state, grad, 11, i)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for i in range(steps):
+        one_step(w, d, form, state, grad, 11, warmup + i)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    # per-stage device time of two more steps (HIP events on the same stream)
+    F.stage_timing(True)
+    for i in range(2):
+        one_step(w, d, form, state, grad, 11, warmup + steps + i)
+    torch.cuda.synchronize()
+    stages = F.stage_times()
+    F.stage_timing(False)
+    return ms, stages
+
+
+def accuracy(w, form, golden):
+    """Batch-mean E_L of the seeded batch against the stored oracle values."""
+    d = F.to_device(w)
+    out = F.ferminet_local_energy(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
+    torch.cuda.synchronize()
+    e = out["e_loc"].double().cpu().numpy()
+    g = np.load(golden)
+    ref = g["e_loc"]
+    res = {"batch_mean_e_loc": float(e.mean()), "oracle_batch_mean_e_loc": float(ref.mean()),
+           "batch_mean_error_ha": float(abs(e.mean() - ref.mean()))}
+    amp = g["amplification"]
+    u = {"bf16": 2.0 ** -16, "fp32": 2.0 ** -24}[form]
+    ok = u * amp < 1e-3
+    res["well_conditioned_walkers"] = int(ok.sum())
+    res["batch_mean_error_well_conditioned_ha"] = float(abs(e[ok].mean() - ref[ok].mean())) if ok.any() else None
+    res["sign_mismatches"] = int((out["sign"].double().cpu().numpy() != g["sign"]).sum())
+    return res
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The FP64 CPU oracle timed on this host on a bounded sample of the same
+    workload (local energy of the first walkers)."""
+    from oracle import oracle as O
+    O.build(force=False)
+    threads = os.cpu_count() or 1
+    cfg = w["cfg"]
+    n0 = max(1, min(threads, 16))
+    t = time.time()
+    O.evaluate(cfg, w["pos"][:n0], w["nuc_pos"], w["nuc_charge"], w["params"], threads=threads)
+    dt = time.time() - t
+    n = int(min(w["pos"].shape[0], max(n0, n0 * budget_s / max(dt, 1e-3))))
+    n = max(n0, (n // threads) * threads) if n > threads else n
+    t = time.time()
+    O.evaluate(cfg, w["pos"][:n], w["nuc_pos"], w["nuc_charge"], w["params"], threads=threads)
+    dt = time.time() - t
+    return {"value": n / dt, "unit": "walker local-energy evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"local energy of the first {n} walkers of the {w['spec'].get('walkers')}-walker batch "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ne10")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (walkers are independent, so "
+              "more GPUs would shard the batch)", file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "needs a GPU"
+    w = I.make_workload(args.workload)
+    cfg = w["cfg"]
+    W = w["pos"].shape[0]
+    T = 3 * cfg["n_elec"] + 2
+    grad = True
+    try:
+        F.vmc_energy_gradient(cfg, *[F.to_device(dict(w, pos=w["pos"][:2]))[k]
+                                     for k in ("pos", "nuc_pos", "nuc_charge", "params")],
+                              torch.zeros(2, device="cuda"), precision="bf16")
+    except F.FerminetError:
+        grad = False  # adjoint not available in this build
+
+    ms_bf, st_bf = time_form(w, "bf16", args.steps, args.warmup, grad)
+    res = {}
+    if not args.no_fp32:
+        ms_32, st_32 = time_form(w, "fp32", args.steps, args.warmup, grad)
+        res["fp32_form"] = {"value": W / (ms_32 * 1e-3), "ms_per_step": ms_32,
+                            "stage_ms": {k: round(v[0] / 2, 4) for k, v in st_32.items()}}
+    main_fl, mf_fl = layer_flops(cfg, W, T)
+    # dominant kernel: the one-electron layer GEMM of the jet pass (L
+    # launches per local-energy call, layer 0 included)
+    tot, cnt = st_bf.get("gemm_layer", (0.0, 0))
+    L = cfg["n_layers"]
+    flops_per_launch = main_fl / L
+    jet_launch_ms = tot / cnt if cnt else None
+    achieved = flops_per_launch / (jet_launch_ms * 1e-3) / 1e12 if jet_launch_ms else None
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
+            "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": None,
+            "kernel": "jet_gemm_kernel<MODE_BF16X3,128,128,EPI_TANHJET> (one-electron layer)",
+            "flops_per_launch": flops_per_launch, "avg_launch_ms": jet_launch_ms}
+    golden = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.npz")
+    if os.path.exists(golden):
+        res["accuracy_bf16"] = accuracy(w, "bf16", golden)
+        if not args.no_fp32:
+            res["accuracy_fp32"] = accuracy(w, "fp32", golden)
+    line = {
+        "metric": "walker local-energy evals/sec (Ne-like, 16 dets) BF16+adjoint vs FP32 at <=1 mHa",
+        "value": W / (ms_bf * 1e-3), "unit": "walker local-energy evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_bf, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded Gaussian walkers, random-init weights)",
+        "config": {"workload": f"{args.workload}: Z={w['nuc_charge'].tolist()}, {cfg['n_elec']} electrons "
+                               f"({cfg['n_up']} up/{cfg['n_down']} down), {W} walkers, {cfg['n_layers']} layers "
+                               f"{cfg['width1']}/{cfg['width2']}, {cfg['n_det']} dets, isotropic envelope",
+                   "walkers": W, "step": "1 Metropolis move + local energy" + (" + VMC gradient" if grad else ""),
+                   "form": "bf16x3 layer GEMMs (fp32 accumulation), fp64 determinants",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "stage_ms_bf16": {k: round(v[0] / 2, 4) for k, v in st_bf.items()},
+    }
+    line.update(res)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+/* ferminet.h -- C ABI of libferminet.so, the MI355X (gfx950) hot path of
+ * FermiNet variational Monte Carlo.
+ *
+ * The library evaluates, batched over walkers, the FermiNet wavefunction of
+ * Eqs. (4)-(5) of "Better, Faster Fermionic Neural Networks" (Spencer, Pfau,
+ * Botev, Foulkes) with the two simplifications of its Section 3 (no
+ * determinant weights omega_k; isotropic envelope exponents), its local
+ * energy psi^-1 H psi for the Hamiltonian of Eq. (2), the gradient of
+ * log|psi| with respect to the parameters (the quantity the energy
+ * minimisation of Eq. (3) and KFAC consume), and Metropolis steps that
+ * sample psi^2 (Eq. (3)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers unless marked HOST.  The caller
+ *    owns every buffer, including the workspace; the library allocates no
+ *    memory and keeps no state between calls.  Calls are asynchronous on
+ *    the given stream (NULL = the default stream).  Calls that share one
+ *    workspace must not overlap.
+ *  - Arguments are validated on the host before anything is enqueued: on
+ *    any status other than FN_OK nothing has been launched and no output
+ *    has been touched.  FN_ERR_HIP reports a failed launch (outputs then
+ *    undefined).
+ *  - Atomic units: positions in bohr, energies in Hartree.
+ *  - pos        [W][n][3] float32, electron positions, electrons of spin up
+ *               first (indices 0..n_up-1), then spin down.
+ *  - spins      HOST [n] int32, 0 = up, 1 = down.  Must equal n_up zeros
+ *               followed by n_down ones (FN_ERR_SPINS otherwise).
+ *  - nuc_pos    [N][3] float32 nuclear positions (fixed, Born-Oppenheimer).
+ *  - nuc_charge [N] float32 nuclear charges Z_I.
+ *  - params     [P] float32, the flat parameter vector in the layout below.
+ *  - Numerical edge cases are not errors: an exact node (psi = 0) gives
+ *    sign 0, log|psi| = -inf and a NaN local energy; an electron exactly on
+ *    a nucleus or on another electron gives IEEE infinities.
+ *
+ * The network (permutation-equivariant one- and two-electron streams of the
+ * original FermiNet, whose layer equations the paper does not restate):
+ *    h^0_i  = concat_I (r_i - R_I, |r_i - R_I|)            (width 4N)
+ *    h^0_ij = (r_i - r_j, |r_i - r_j|), zero at i == j    (width 4)
+ *    for l = 0..L-1:
+ *      hbar^a   = mean_{j of spin a} h^l_j      (zero vector if no such j)
+ *      g^a_i    = mean_{j of spin a} h^l_ij     (includes j == i)
+ *      f_i      = [h^l_i, hbar^up, hbar^down, g^up_i, g^down_i]
+ *      h^{l+1}_i  = tanh(f_i V_l + b_l)   (+ h^l_i when the widths match)
+ *      h^{l+1}_ij = tanh(h^l_ij W_l + c_l) (+ h^l_ij when the widths match),
+ *                   for l = 0..L-2 only
+ *    orbitals (Eq. (5), isotropic envelope, Section 3), for spin a,
+ *    determinant k, orbital i, electron j of spin a:
+ *      phi^{ka}_i(r_j) = (h^L_j . w_a[:, k n_a + i] + g_a[k n_a + i])
+ *                        * sum_m pi_a[k n_a + i][m] exp(-|sigma_a[k n_a + i][m]| |r_j - R_m|)
+ *    psi = sum_k det[phi^{k,up}_i(r_j)] det[phi^{k,down}_i(r_j)]   (Eq. (4))
+ *
+ * Flat parameter layout (row-major, [in][out] so that y = x W + b):
+ *    for l in 0..L-1:  V_l [3 din_l + 2 ein_l][d1], then b_l [d1]
+ *    for l in 0..L-2:  W_l [ein_l][d2],             then c_l [d2]
+ *    for a in up, down: w_a [d1][K n_a], then g_a [K n_a]
+ *    for a in up, down: pi_a [K n_a][N]
+ *    for a in up, down: sigma_a [K n_a][N]
+ *    din_0 = 4N, ein_0 = 4; din_l = d1, ein_l = d2 for l > 0.
+ *    The rows of V_l are ordered as f_i: [h_i | hbar^up | hbar^down |
+ *    g^up_i | g^down_i].
+ */
+#ifndef FERMINET_H_
+#define FERMINET_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FN_OK = 0,
+  FN_ERR_NULL = 1,        /* a required pointer is NULL */
+  FN_ERR_CONFIG = 2,      /* shapes out of range (see fn_config) */
+  FN_ERR_SPINS = 3,       /* spins not n_up zeros followed by n_down ones */
+  FN_ERR_WORKSPACE = 4,   /* workspace too small for one walker, or misaligned */
+  FN_ERR_UNSUPPORTED = 5, /* valid request this build does not implement */
+  FN_ERR_HIP = 6,         /* a HIP launch failed */
+  FN_ERR_ARG = 7          /* other invalid scalar argument (W < 0, n_steps < 0, ...) */
+} fn_status;
+
+typedef enum {
+  /* every stage in float32 (layer GEMMs on FP32 MFMA) */
+  FN_PREC_FP32 = 0,
+  /* layer and orbital GEMMs with bfloat16 operands and float32
+   * accumulation on MFMA; tanh, envelope and jet epilogues in float32;
+   * LU, log-determinant, A^-1 contractions and the determinant
+   * combination in float64 */
+  FN_PREC_BF16 = 1,
+  /* float32 network and orbitals, float64 determinants and combination */
+  FN_PREC_FP32_FP64DET = 2
+} fn_precision;
+
+/* Shapes.  Limits of this build: 1 <= n_elec <= 64, n_up >= n_down >= 0
+ * are NOT required (any split), 0 <= n_up, n_down <= 32, 1 <= n_nuc <= 32,
+ * 1 <= n_layers <= 8, width1 in [8, 1024] and a multiple of 8, width2 in
+ * [4, 64] and a multiple of 4, 1 <= n_det <= 64. */
+typedef struct {
+  int32_t n_elec;    /* n = n_up + n_down */
+  int32_t n_up;
+  int32_t n_down;
+  int32_t n_nuc;     /* N */
+  int32_t n_layers;  /* L, one-electron layers (L-1 two-electron layers) */
+  int32_t width1;    /* d1, one-electron stream width */
+  int32_t width2;    /* d2, two-electron stream width */
+  int32_t n_det;     /* K, determinants */
+  int32_t precision; /* fn_precision */
+} fn_config;
+
+typedef struct {
+  char name[16];  /* "V0", "b0", "W0", "c0", "w_orb0", "g_orb0", "pi0", "sigma1", ... */
+  int64_t offset; /* in floats, from the start of params */
+  int64_t rows;   /* first dimension (1 for vectors) */
+  int64_t cols;   /* second dimension */
+} fn_param_block;
+
+typedef enum {
+  FN_ENTRY_LOGPSI = 0,
+  FN_ENTRY_LOCAL_ENERGY = 1,
+  FN_ENTRY_GRAD_LOGPSI = 2,
+  FN_ENTRY_MCMC = 3
+} fn_entry;
+
+/* Human-readable text of a status code (static storage). */
+const char* ferminet_status_string(int32_t status);
+
+/* Number of float32 parameters P of the layout above, or -1 if cfg is
+ * invalid. */
+int64_t ferminet_param_count(const fn_config* cfg);
+
+/* The parameter blocks in layout order.  Writes at most cap entries to out
+ * (HOST) and the number of blocks to *n_out (HOST).  FN_ERR_ARG if cap is
+ * too small (then *n_out holds the required count). */
+fn_status ferminet_param_layout(const fn_config* cfg, fn_param_block* out, int32_t cap, int32_t* n_out);
+
+/* Workspace bytes (*bytes, HOST) that let the given entry point process
+ * chunk_walkers walkers in one pass.  Any workspace of at least
+ * ferminet_workspace_bytes(cfg, 1, entry) bytes works: larger batches are
+ * then processed in chunks of as many walkers as fit.  The workspace must
+ * be 256-byte aligned. */
+fn_status ferminet_workspace_bytes(const fn_config* cfg, int32_t chunk_walkers, int32_t entry, size_t* bytes);
+
+/* sign(psi) and log|psi| of Eq. (4) for W walkers.
+ *   sign   [W] float32 out: +1, -1, or 0 at an exact node
+ *   logpsi [W] float32 out */
+fn_status ferminet_logpsi(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                          const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
+                          float* logpsi, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Local energy E_L = psi^-1 H psi with H of Eq. (2) for W walkers: the
+ * kinetic part -1/2 sum_c [d^2_c log|psi| + (d_c log|psi|)^2] over all 3n
+ * electron coordinates, from forward-mode jets (value, 3n tangents and
+ * Laplacian) carried through every layer; the potential part from the
+ * electron-electron, electron-nucleus and nucleus-nucleus Coulomb sums.
+ *   sign, logpsi [W] out (as ferminet_logpsi)
+ *   e_loc [W] out; e_kin, e_pot [W] out, each may be NULL */
+fn_status ferminet_local_energy(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
+                                float* logpsi, float* e_loc, float* e_kin, float* e_pot, void* workspace,
+                                size_t workspace_bytes, hipStream_t stream);
+
+/* Cotangent-weighted parameter gradient of log|psi| from a hand-written
+ * adjoint (values recomputed, no tangents stored):
+ *   grad[p] = sum_w cotangent[w] * d log|psi_w| / d theta_p
+ *   cotangent [W] float32 in (required; FN_ERR_NULL if NULL)
+ *   grad      [P] float32 out, in the parameter layout */
+fn_status ferminet_grad_logpsi(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                               const float* nuc_pos, const float* nuc_charge, const float* params,
+                               const float* cotangent, float* grad, void* workspace, size_t workspace_bytes,
+                               hipStream_t stream);
+
+/* VMC energy gradient estimator for Eq. (3), as the mean over the batch:
+ *   grad[p] = (1/W) sum_w (E_L,w - mean E_L) d log|psi_w| / d theta_p
+ * (the gradient of the energy itself is twice this).  e_stats (2 doubles,
+ * device) receives the batch mean and the population variance of e_loc,
+ * computed in float64.  Uses the FN_ENTRY_GRAD_LOGPSI workspace. */
+fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                              const float* nuc_pos, const float* nuc_charge, const float* params,
+                              const float* e_loc, double* e_stats, float* grad, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream);
+
+/* n_steps Metropolis random-walk steps sampling psi^2 (Eq. (3)), all
+ * electrons moved at once:
+ *   x' = x + step_width * z,  z ~ N(0, I_{3n});
+ *   accept iff log(u) < 2 (log|psi(x')| - log|psi(x)|), u ~ U(0,1),
+ *   and psi(x') != 0.
+ *   pos [W][n][3], logpsi [W], sign [W]  in/out: the current state; logpsi
+ *       and sign must be those of pos on entry (ferminet_logpsi).
+ *   n_accepted [W] int32 out: accepted moves of each walker in this call.
+ *   noise [n_steps][W][3n], uniforms [n_steps][W]: supplied draws; both
+ *       NULL draws them from Philox4x32-10 (Salmon et al., SC'11) as
+ *       vmc_mcmc_noise documents, with step index counter + s. */
+fn_status vmc_mcmc_step(const fn_config* cfg, int32_t W, float* pos, const int32_t* spins, const float* nuc_pos,
+                        const float* nuc_charge, const float* params, float* logpsi, float* sign, int32_t n_steps,
+                        float step_width, uint64_t seed, uint64_t counter, const float* noise,
+                        const float* uniforms, int32_t* n_accepted, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
+/* The draws vmc_mcmc_step makes internally, for replay and testing.
+ *   key     = (seed & 0xffffffff, seed >> 32); s = counter + step
+ *   normals of walker w, coordinates 4b..4b+3: Philox4x32-10 of counter
+ *           (w, b, s & 0xffffffff, s >> 32) gives words x0..x3;
+ *           u_k = ((x_k >> 9) + 0.5) * 2^-23; Box-Muller on (u0, u1) and
+ *           (u2, u3): z = sqrt(-2 ln u_a) (cos, sin)(2 pi u_b)
+ *   uniform of walker w: word x0 of counter (w, 0x80000000, s lo, s hi),
+ *           mapped the same way.
+ *   noise [n_steps][W][3n] float32 out, uniforms [n_steps][W] float32 out */
+fn_status vmc_mcmc_noise(int32_t W, int32_t n_elec, int32_t n_steps, uint64_t seed, uint64_t counter, float* noise,
+                         float* uniforms, hipStream_t stream);
+
+/* ---- diagnostics: per-stage device time ----
+ * ferminet_stage_timing(1) makes every later launch record a pair of HIP
+ * events on its stream (process-wide; it adds a small host overhead);
+ * ferminet_stage_timing(0) stops it.  Either call discards pending records.
+ * ferminet_stage_times waits for the recorded events, writes per-stage
+ * totals in milliseconds and launch counts to total_ms[cap] and count[cap]
+ * (HOST), clears the records and returns the number of stages (-1 if cap is
+ * too small or a pointer is NULL).  ferminet_stage_name gives the stage
+ * names (static storage). */
+fn_status ferminet_stage_timing(int32_t enable);
+int32_t ferminet_stage_times(double* total_ms, int32_t* count, int32_t cap);
+const char* ferminet_stage_name(int32_t stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FERMINET_H_ */

@@ -210,7 +210,8 @@ void slogdet(int n, S* a, double* sign, S* logabs) {
 // Born-Oppenheimer setting); prm: the flat parameter vector.
 template <class S, class P>
 void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc, const P* prm,
-                 double* sign_out, S* logabs_out) {
+                 double* sign_out, S* logabs_out, double* sk_out = nullptr, double* lk_out = nullptr,
+                 double* orb_out = nullptr) {
   const int n = c.n, N = c.N;
   // spin of electron j: up for j < n_up (the caller orders spins up first)
   auto spin_of = [&](int j) { return j < c.n_up ? 0 : 1; };
@@ -333,6 +334,11 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
           A[(size_t)i * na + j] = u * env;
         }
       }
+      if (orb_out) {
+        // orbital matrices of the value pass, [K][n_up^2] then [K][n_down^2]
+        double* o = orb_out + (a == 0 ? 0 : (size_t)c.K * c.n_up * c.n_up) + (size_t)k * na * na;
+        for (int e = 0; e < na * na; ++e) o[e] = val(A[e]);
+      }
       double s;
       S la;
       slogdet(na, A.data(), &s, &la);
@@ -342,6 +348,11 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
     j0 += na;
   }
 
+  if (sk_out)
+    for (int k = 0; k < c.K; ++k) {
+      sk_out[k] = sgn_k[k];
+      lk_out[k] = val(log_k[k]);
+    }
   // psi = sum_k s_k exp(l_k), taken as a signed log-sum-exp
   double m = -std::numeric_limits<double>::infinity();
   for (int k = 0; k < c.K; ++k)
@@ -559,6 +570,41 @@ int orc_param_grad(const int32_t* cfg, int W, const double* pos, const double* n
       eval_walker<Dual, Dual>(c, Y, x.data(), nuc, th.data(), &sg, &la);
       out[(size_t)w * n_sel + s] = la.d;
     }
+  return 0;
+}
+
+// sign and log|det^up_k det^down_k| of every determinant term of Eq. (4):
+// sk, lk [W][K]
+int orc_det_terms(const int32_t* cfg, int W, const double* pos, const double* nuc, const double* prm, int n_threads,
+                  double* sk, double* lk) {
+  Cfg c = read_cfg(cfg);
+  if (!cfg_ok(c)) return -1;
+  Layout Y = make_layout(c);
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int w = 0; w < W; ++w) {
+    double s, la;
+    eval_walker<double, double>(c, Y, pos + (size_t)w * 3 * c.n, nuc, prm, &s, &la, sk + (size_t)w * c.K,
+                                lk + (size_t)w * c.K);
+  }
+  return 0;
+}
+
+// the orbital matrices A^{k,a}_{ij} = phi^{k,a}_i(r^a_j) of Eq. (4)-(5):
+// out [W][K n_up^2 + K n_down^2], spin up first, row-major per matrix
+int orc_orbitals(const int32_t* cfg, int W, const double* pos, const double* nuc, const double* prm, int n_threads,
+                 double* out) {
+  Cfg c = read_cfg(cfg);
+  if (!cfg_ok(c)) return -1;
+  Layout Y = make_layout(c);
+  const size_t per = (size_t)c.K * (c.n_up * c.n_up + c.n_dn * c.n_dn);
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int w = 0; w < W; ++w) {
+    double s, la;
+    eval_walker<double, double>(c, Y, pos + (size_t)w * 3 * c.n, nuc, prm, &s, &la, nullptr, nullptr,
+                                out + (size_t)w * per);
+  }
   return 0;
 }
 

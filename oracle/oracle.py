@@ -46,6 +46,10 @@ def _load():
         lib.orc_eval.argtypes = [P, i32, P, P, P, P, i32, i32, P, P, P, P, P, P]
         lib.orc_potential.argtypes = [P, i32, P, P, P, P]
         lib.orc_param_grad.argtypes = [P, i32, P, P, P, i32, P, i32, P]
+        lib.orc_det_terms.argtypes = [P, i32, P, P, P, i32, P, P]
+        lib.orc_det_terms.restype = i32
+        lib.orc_orbitals.argtypes = [P, i32, P, P, P, i32, P]
+        lib.orc_orbitals.restype = i32
         lib.orc_philox4x32_10.argtypes = [P, P, P]
         lib.orc_philox4x32_10.restype = None
         lib.orc_mcmc_noise.argtypes = [i32, i32, i32, u64, u64, P, P]
@@ -134,6 +138,54 @@ def param_grad(cfg, pos, nuc_pos, params, sel, threads=None):
                                 _threads(threads), _p(out))
     assert rc == 0
     return out
+
+
+def det_terms(cfg, pos, nuc_pos, params, threads=None):
+    """(sign_k, log|det_k^up det_k^down|) of every determinant term: [W][K] each."""
+    pos = _d(pos)
+    W = pos.shape[0]
+    sk = np.zeros((W, cfg["n_det"]))
+    lk = np.zeros((W, cfg["n_det"]))
+    rc = _load().orc_det_terms(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(params)), _threads(threads),
+                               _p(sk), _p(lk))
+    assert rc == 0
+    return sk, lk
+
+
+def node_conditioning(cfg, pos, nuc_pos, params, threads=None):
+    """kappa_w = max_k |P_k| / |psi| >= 1 (infinite at an exact node): how
+    strongly the signed sum of Eq. (4) cancels at each walker."""
+    sk, lk = det_terms(cfg, pos, nuc_pos, params, threads)
+    m = lk.max(axis=1, keepdims=True)
+    s = (sk * np.exp(lk - m)).sum(axis=1)
+    with np.errstate(divide="ignore"):
+        return 1.0 / np.abs(s)
+
+
+def orbital_matrices(cfg, pos, nuc_pos, params, threads=None):
+    """The orbital matrices of every walker: (up [W][K][n_up][n_up],
+    down [W][K][n_down][n_down]), A[i][j] = phi_i(r_j)."""
+    pos = _d(pos)
+    W, K, nu, nd = pos.shape[0], cfg["n_det"], cfg["n_up"], cfg["n_down"]
+    out = np.zeros((W, K * (nu * nu + nd * nd)))
+    rc = _load().orc_orbitals(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(params)), _threads(threads), _p(out))
+    assert rc == 0
+    return out[:, :K * nu * nu].reshape(W, K, nu, nu), out[:, K * nu * nu:].reshape(W, K, nd, nd)
+
+
+def amplification(cfg, pos, nuc_pos, params, threads=None):
+    """Per-walker rounding amplification A_w = kappa_w * max_{k,a} cond_1(A^{ka})
+    with kappa_w = max_k |P_k| / |psi_w| (cancellation of the sum of Eq. (4))
+    and cond_1 the 1-norm condition number of each orbital matrix."""
+    kap = node_conditioning(cfg, pos, nuc_pos, params, threads)
+    up, dn = orbital_matrices(cfg, pos, nuc_pos, params, threads)
+    cmax = np.ones(kap.shape)
+    for M in (up, dn):
+        if M.shape[-1] == 0:
+            continue
+        c = np.linalg.cond(M.reshape(-1, M.shape[-1], M.shape[-1]), p=1).reshape(M.shape[0], -1)
+        cmax = np.maximum(cmax, c.max(axis=1))
+    return kap * cmax, kap, cmax
 
 
 def philox4x32_10(ctr, key):

@@ -1,0 +1,56 @@
+// Device-side helpers shared by the HIP kernels of libferminet (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fn {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// bfloat16 storage type: the raw 16 bits, rounded to nearest-even from fp32
+struct bf16_t {
+  uint16_t bits;
+};
+
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+// load/store of one element of the activation type (float or bf16_t) as fp32
+__device__ inline float ld_act(const float* p) { return *p; }
+__device__ inline float ld_act(const bf16_t* p) { return bf16_bits_to_f32(p->bits); }
+__device__ inline void st_act(float* p, float v) { *p = v; }
+__device__ inline void st_act(bf16_t* p, float v) { p->bits = f32_to_bf16_bits(v); }
+
+// tanh'(u) = sech^2(u) = 4 e^{-2|u|} / (1 + e^{-2|u|})^2, free of the
+// cancellation of 1 - tanh^2(u) once tanh saturates
+__device__ inline float sech2f(float u) {
+  const float e = expf(-2.0f * fabsf(u));
+  const float d = 1.0f + e;
+  return 4.0f * e / (d * d);
+}
+
+template <class T> __device__ inline T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+template <class T> __device__ inline T wave_max(T v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+__host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace fn

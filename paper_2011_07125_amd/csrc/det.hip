@@ -1,0 +1,315 @@
+// Determinants of Eq. (4) and the local energy.
+//
+// One wavefront per (walker, determinant k, spin a) orbital matrix B with
+// B[j][i] = phi^{ka}_i(r_j) (the transpose of A^{ka}; same determinant):
+// LU with partial pivoting in LDS -> sign and log|det B|, B^-1, and in jet
+// mode the contractions with the jets of B:
+//   d_c = tr(B^-1 dB/dx_c)                 (d log|det| / dx_c)
+//   q   = sum_c tr((B^-1 dB/dx_c)^2)
+//   lap = tr(B^-1 lap(B))
+// so that lap log|det| = lap - q.  R = double in the bf16 form, float in
+// the fp32 form.
+//
+// The combination (one wavefront per walker) forms psi = sum_k s_k e^{l_k}
+// as a signed log-sum-exp, rho_k = P_k / psi, and
+//   lap(psi)/psi = sum_k rho_k [sum_a (lap_a - q_a) + sum_c (d_c^up + d_c^down)^2]
+//   E_kin = -lap(psi)/(2 psi)
+// plus the Coulomb potential of Eq. (2) by wavefront reductions (float64).
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace fn {
+
+constexpr int MAXNA = 32;
+
+template <class R>
+__global__ __launch_bounds__(64) void det_kernel(const float* phi, int K, int na, int T, int n3, R* D, int dstride,
+                                                 R* ainv) {
+  __shared__ R LU[MAXNA * MAXNA];
+  __shared__ R Bi[MAXNA * MAXNA];
+  __shared__ R Ys[64 + MAXNA * MAXNA];
+  __shared__ int piv[MAXNA];
+  __shared__ int s_p;
+  __shared__ R s_part[64];
+  const int lane = threadIdx.x;
+  const int64_t mat = blockIdx.x;  // = w * K + k
+  const int nsq = na * na;
+  const float* P = phi + mat * (int64_t)T * nsq;
+  R* out = D + mat * dstride;
+
+  for (int e = lane; e < nsq; e += 64) LU[e] = (R)P[e];
+  __syncthreads();
+  bool singular = false;
+  for (int c = 0; c < na; ++c) {
+    if (lane == 0) {
+      int p = c;
+      R best = fabs(LU[c * na + c]);
+      for (int r = c + 1; r < na; ++r) {
+        R m = fabs(LU[r * na + c]);
+        if (m > best) {
+          best = m;
+          p = r;
+        }
+      }
+      s_p = best == (R)0 ? -1 : p;
+      piv[c] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p < 0) {
+      singular = true;
+      break;
+    }
+    if (p != c)
+      for (int k = lane; k < na; k += 64) {
+        R t = LU[c * na + k];
+        LU[c * na + k] = LU[p * na + k];
+        LU[p * na + k] = t;
+      }
+    __syncthreads();
+    const R inv_p = (R)1 / LU[c * na + c];
+    for (int r = c + 1 + lane; r < na; r += 64) {
+      const R f = LU[r * na + c] * inv_p;
+      LU[r * na + c] = f;
+      for (int k = c + 1; k < na; ++k) LU[r * na + k] -= f * LU[c * na + k];
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    for (int e = lane; e < dstride; e += 64) out[e] = (R)0;
+    if (lane == 0) out[1] = -INFINITY;
+    if (ainv)
+      for (int e = lane; e < nsq; e += 64) ainv[mat * nsq + e] = (R)0;
+    return;
+  }
+  if (lane == 0) {
+    R sg = 1, la = 0;
+    for (int c = 0; c < na; ++c) {
+      if (piv[c] != c) sg = -sg;
+      R u = LU[c * na + c];
+      if (u < 0) sg = -sg;
+      la += log(fabs(u));
+    }
+    out[0] = sg;
+    out[1] = la;
+  }
+  const bool need_inv = ainv != nullptr || T > 1;
+  if (!need_inv) return;
+  // B^-1 column by column: lane c solves L U x = P e_c (in the Bi column)
+  for (int c = lane; c < na; c += 64) {
+    for (int r = 0; r < na; ++r) Bi[r * na + c] = r == c ? (R)1 : (R)0;
+    for (int k = 0; k < na; ++k)
+      if (piv[k] != k) {
+        R t = Bi[k * na + c];
+        Bi[k * na + c] = Bi[piv[k] * na + c];
+        Bi[piv[k] * na + c] = t;
+      }
+    for (int r = 0; r < na; ++r) {
+      R acc = Bi[r * na + c];
+      for (int k = 0; k < r; ++k) acc -= LU[r * na + k] * Bi[k * na + c];
+      Bi[r * na + c] = acc;
+    }
+    for (int r = na - 1; r >= 0; --r) {
+      R acc = Bi[r * na + c];
+      for (int k = r + 1; k < na; ++k) acc -= LU[r * na + k] * Bi[k * na + c];
+      Bi[r * na + c] = acc / LU[r * na + r];
+    }
+  }
+  __syncthreads();
+  if (ainv)
+    for (int e = lane; e < nsq; e += 64) ainv[mat * nsq + e] = Bi[e];
+  if (T <= 1) return;
+
+  // jet contractions; "tangent" index tt in [0, n3] where tt == n3 is the
+  // Laplacian row (trace only)
+  const int G = nsq <= 64 ? 64 / nsq : 1;
+  R q_acc = 0;
+  for (int t0 = 0; t0 <= n3; t0 += G) {
+    const int ng = (t0 + G <= n3 + 1) ? G : (n3 + 1 - t0);
+    R dpart = 0, qpart = 0;
+    // Y = B^-1 M_t
+    for (int e = lane; e < ng * nsq; e += 64) {
+      const int gi = e / nsq, ab = e % nsq, ar = ab / na, b = ab % na;
+      const int tt = t0 + gi;
+      const int row = tt < n3 ? 1 + tt : T - 1;
+      const float* M = P + (int64_t)row * nsq;
+      R acc = 0;
+      for (int c = 0; c < na; ++c) acc += Bi[ar * na + c] * (R)M[c * na + b];
+      Ys[e] = acc;
+    }
+    __syncthreads();
+    for (int e = lane; e < ng * nsq; e += 64) {
+      const int gi = e / nsq, ab = e % nsq, ar = ab / na, b = ab % na;
+      const R y = Ys[e];
+      R dp = ar == b ? y : (R)0;
+      R qp = y * Ys[gi * nsq + b * na + ar];
+      if (G == 1) {
+        dpart += dp;
+        qpart += qp;
+      } else {
+        // one element per lane: stash for the per-tangent sums below
+        Ys[64 + e] = qp;  // region beyond 64 is free when nsq <= 64... guarded below
+        (void)dp;
+      }
+    }
+    if (G == 1) {
+      dpart = wave_sum(dpart);
+      qpart = wave_sum(qpart);
+      if (lane == 0) {
+        if (t0 < n3) {
+          out[2 + t0] = dpart;
+          q_acc += qpart;
+        } else {
+          out[3 + n3] = dpart;
+        }
+      }
+    } else {
+      __syncthreads();
+      if (lane < ng) {
+        const int tt = t0 + lane;
+        R dsum = 0, qsum = 0;
+        for (int ab = 0; ab < nsq; ++ab) {
+          const int ar = ab / na, b = ab % na;
+          if (ar == b) dsum += Ys[lane * nsq + ab];
+          qsum += Ys[64 + lane * nsq + ab];
+        }
+        if (tt < n3) {
+          out[2 + tt] = dsum;
+          q_acc += qsum;
+        } else {
+          out[3 + n3] = dsum;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  s_part[lane] = q_acc;
+  __syncthreads();
+  if (lane == 0) {
+    R q = 0;
+    for (int l = 0; l < 64; ++l) q += s_part[l];
+    out[2 + n3] = q;
+  }
+}
+
+hipError_t launch_det(bool fp64, const float* phi, int W, int K, int na, int T, int n3, void* D, int dstride,
+                      void* ainv, hipStream_t s) {
+  if (na <= 0 || W <= 0) return hipSuccess;
+  if (na > MAXNA) return hipErrorInvalidValue;
+  const int grid = W * K;
+  if (fp64) hipLaunchKernelGGL(det_kernel<double>, dim3(grid), dim3(64), 0, s, phi, K, na, T, n3, (double*)D, dstride, (double*)ainv);
+  else hipLaunchKernelGGL(det_kernel<float>, dim3(grid), dim3(64), 0, s, phi, K, na, T, n3, (float*)D, dstride, (float*)ainv);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- combination
+template <class R>
+__global__ __launch_bounds__(64) void combine_kernel(CombineArgs a) {
+  const int lane = threadIdx.x;
+  const int64_t w = blockIdx.x;
+  const int K = a.K, n3 = a.n3;
+  const R* Du = (const R*)a.D[0];
+  const R* Dd = (const R*)a.D[1];
+  const bool hu = a.na[0] > 0, hd = a.na[1] > 0;
+  const int ds = a.dstride;
+
+  // determinant terms: lane k
+  R sk = 0, lk = -INFINITY;
+  if (lane < K) {
+    R su = hu ? Du[(w * K + lane) * ds] : (R)1, sd = hd ? Dd[(w * K + lane) * ds] : (R)1;
+    R lu = hu ? Du[(w * K + lane) * ds + 1] : (R)0, ld = hd ? Dd[(w * K + lane) * ds + 1] : (R)0;
+    sk = su * sd;
+    lk = sk != (R)0 ? lu + ld : (R)-INFINITY;
+  }
+  const R m = wave_max(lk);
+  R ex = (lane < K && sk != (R)0) ? sk * exp(lk - m) : (R)0;
+  const R S = wave_sum(ex);
+  const bool node = !(m > (R)-INFINITY) || S == (R)0;
+  const R logabs = node ? (R)-INFINITY : m + log(fabs(S));
+  const R sgn = node ? (R)0 : (S > 0 ? (R)1 : (R)-1);
+  const R rho = node ? (R)0 : ex / S;
+  if (a.rho && lane < K) ((R*)a.rho)[w * K + lane] = rho;
+
+  double ekin = 0.0;
+  if (a.jet) {
+    // sum_k rho_k sum_a (lap_a - q_a)
+    R part = 0;
+    if (lane < K) {
+      R t = 0;
+      if (hu) t += Du[(w * K + lane) * ds + 3 + n3] - Du[(w * K + lane) * ds + 2 + n3];
+      if (hd) t += Dd[(w * K + lane) * ds + 3 + n3] - Dd[(w * K + lane) * ds + 2 + n3];
+      part = rho * t;
+    }
+    // sum_c sum_k rho_k (d_kc^up + d_kc^down)^2, lanes over coordinates
+    __shared__ R s_rho[64];
+    s_rho[lane] = rho;
+    __syncthreads();
+    R sq = 0;
+    for (int c = lane; c < n3; c += 64) {
+      for (int k = 0; k < K; ++k) {
+        R dsum = 0;
+        if (hu) dsum += Du[(w * K + k) * ds + 2 + c];
+        if (hd) dsum += Dd[(w * K + k) * ds + 2 + c];
+        sq += s_rho[k] * dsum * dsum;
+      }
+    }
+    const R lap_over_psi = wave_sum(part) + wave_sum(sq);
+    ekin = node ? NAN : -0.5 * (double)lap_over_psi;
+  }
+
+  // Coulomb potential of Eq. (2), float64
+  double v = 0.0;
+  if (a.jet || a.e_pot) {
+    const float* x = a.pos + w * (int64_t)a.n * 3;
+    const int n = a.n, N = a.N;
+    const int npair = n * (n - 1) / 2;
+    for (int p = lane; p < npair; p += 64) {
+      // p -> (i, j), i < j
+      int i = 0, rem = p;
+      while (rem >= n - 1 - i) {
+        rem -= n - 1 - i;
+        ++i;
+      }
+      const int j = i + 1 + rem;
+      double dx = (double)x[3 * i] - x[3 * j], dy = (double)x[3 * i + 1] - x[3 * j + 1],
+             dz = (double)x[3 * i + 2] - x[3 * j + 2];
+      v += 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    for (int p = lane; p < n * N; p += 64) {
+      const int i = p / N, I = p % N;
+      double dx = (double)x[3 * i] - a.nuc[3 * I], dy = (double)x[3 * i + 1] - a.nuc[3 * I + 1],
+             dz = (double)x[3 * i + 2] - a.nuc[3 * I + 2];
+      v -= (double)a.Z[I] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    for (int p = lane; p < N * N; p += 64) {
+      const int I = p / N, J = p % N;
+      if (I < J) {
+        double dx = (double)a.nuc[3 * I] - a.nuc[3 * J], dy = (double)a.nuc[3 * I + 1] - a.nuc[3 * J + 1],
+               dz = (double)a.nuc[3 * I + 2] - a.nuc[3 * J + 2];
+        v += (double)a.Z[I] * a.Z[J] / sqrt(dx * dx + dy * dy + dz * dz);
+      }
+    }
+    v = wave_sum(v);
+  }
+  if (lane == 0) {
+    a.sign[w] = (float)sgn;
+    a.logpsi[w] = (float)logabs;
+    if (a.jet) {
+      a.e_loc[w] = (float)(ekin + v);
+      if (a.e_kin) a.e_kin[w] = (float)ekin;
+      if (a.e_pot) a.e_pot[w] = (float)v;
+    }
+  }
+}
+
+hipError_t launch_combine(bool fp64, const CombineArgs& a, hipStream_t s) {
+  if (a.W <= 0) return hipSuccess;
+  if (a.K > 64) return hipErrorInvalidValue;
+  if (fp64) hipLaunchKernelGGL(combine_kernel<double>, dim3(a.W), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL(combine_kernel<float>, dim3(a.W), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace fn

@@ -1,0 +1,347 @@
+// Input features, the two-electron stream and the mean fields.
+//
+// Jets: every activation of an electron is carried as T = 3n+2 rows: the
+// value, its derivatives with respect to each of the 3n electron
+// coordinates (row 1 + 3j + c for coordinate c of electron j) and its
+// Laplacian over all 3n coordinates (row T-1).  Rows T..Tp-1 are zero
+// padding.  In value mode T = Tp = 1.
+//
+// Two-electron activations h_ij depend on r_i and r_j only, so their jets
+// are carried sparsely as 8 rows (value, d/dr_i, d/dr_j, Laplacian) and
+// never leave the chip: one workgroup runs all two-electron layers of its
+// electrons in registers and LDS and writes only the dense jets of the
+// spin-resolved means g^a_i that the one-electron layers consume.
+#include "common.h"
+#include "kernels.h"
+
+namespace fn {
+
+// ------------------------------------------------------------ weight packing
+struct PackPlan {
+  int n_items;
+  // dst_off, N, ldb, k0, len0, src0, k1, len1, src1, src_ld
+  int64_t it[24][10];
+};
+
+// packed[n][k] = params[src + (k - k0) * src_ld + n] for k in one of the two
+// segments, 0 elsewhere; float32, or split into bfloat16 hi and lo planes
+template <bool SPLIT>
+__global__ void pack_weights_kernel(const float* params, void* dst, int64_t plane, PackPlan plan) {
+  const int item = blockIdx.y;
+  if (item >= plan.n_items) return;
+  const int64_t* p = plan.it[item];
+  const int64_t N = p[1], ldb = p[2], total = N * ldb;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t n = idx / ldb, k = idx % ldb;
+    float v = 0.0f;
+    if (k >= p[3] && k < p[3] + p[4]) v = params[p[5] + (k - p[3]) * p[9] + n];
+    else if (k >= p[6] && k < p[6] + p[7]) v = params[p[8] + (k - p[6]) * p[9] + n];
+    if constexpr (SPLIT) {
+      uint16_t* d = reinterpret_cast<uint16_t*>(dst);
+      const uint16_t h = f32_to_bf16_bits(v);
+      d[p[0] + idx] = h;
+      d[plane + p[0] + idx] = f32_to_bf16_bits(v - bf16_bits_to_f32(h));
+    } else {
+      reinterpret_cast<float*>(dst)[p[0] + idx] = v;
+    }
+  }
+}
+
+hipError_t launch_pack_weights(bool split, const float* params, void* dst, int64_t plane, const int64_t* plan,
+                               int n_items, hipStream_t s) {
+  if (n_items > 24) return hipErrorInvalidValue;
+  PackPlan pp;
+  pp.n_items = n_items;
+  for (int i = 0; i < n_items; ++i)
+    for (int j = 0; j < 10; ++j) pp.it[i][j] = plan[i * 10 + j];
+  dim3 grid(64, n_items);
+  if (split) hipLaunchKernelGGL(pack_weights_kernel<true>, grid, dim3(256), 0, s, params, dst, plane, pp);
+  else hipLaunchKernelGGL(pack_weights_kernel<false>, grid, dim3(256), 0, s, params, dst, plane, pp);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- one-electron input
+// H0[(g Tp + t) ldh + f], g = w n + i: the jets of
+//   h_i = concat_I (r_i - R_I, |r_i - R_I|)
+// d/dr_i of (r_i - R_I)_c = e_c; of |r_i - R_I| = (r_i - R_I)/|r_i - R_I|;
+// Laplacian of |r_i - R_I| = 2 / |r_i - R_I|.
+template <class TA>
+__global__ void features_kernel(const float* pos, const float* nuc, int W, int n, int N, int T, int Tp, TA* H0,
+                                int ldh) {
+  const int64_t total = (int64_t)W * n * Tp * ldh;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(idx % ldh);
+    const int64_t row = idx / ldh;
+    const int t = (int)(row % Tp);
+    const int64_t g = row / Tp;
+    const int i = (int)(g % n);
+    float v = 0.0f;
+    if (f < 4 * N && t < T) {
+      const int I = f >> 2, comp = f & 3;
+      const float* r = pos + g * 3;
+      float d0 = r[0] - nuc[3 * I], d1 = r[1] - nuc[3 * I + 1], d2 = r[2] - nuc[3 * I + 2];
+      float dist = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+      float dc[3] = {d0, d1, d2};
+      if (t == 0) {
+        v = comp < 3 ? dc[comp] : dist;
+      } else if (t == T - 1) {
+        v = comp < 3 ? 0.0f : 2.0f / dist;
+      } else {
+        const int jt = (t - 1) / 3, c = (t - 1) % 3;
+        if (jt == i) v = comp < 3 ? (comp == c ? 1.0f : 0.0f) : dc[c] / dist;
+      }
+    }
+    st_act(H0 + idx, v);
+  }
+}
+
+hipError_t launch_features(bool bf16, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
+                           void* H0, int ldh, hipStream_t s) {
+  int64_t total = (int64_t)W * n * Tp * ldh;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  if (grid <= 0) return hipSuccess;
+  if (bf16) hipLaunchKernelGGL(features_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (bf16_t*)H0, ldh);
+  else hipLaunchKernelGGL(features_kernel<float>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (float*)H0, ldh);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ two-electron stream
+struct TwoElecDev {
+  const float* pos;
+  const float* params;
+  int64_t w_off[8], c_off[8];
+  int W, n, n_up, L, d2, T, Tp, R2, ipb;
+  void* G[8];
+  int ldg[8];
+  float* h2_out[8];
+};
+
+// slot s of the block: electron ii = s / (n R2), partner j = (s / R2) % n,
+// sparse jet row q = s % R2 (value, d/dr_i x3, d/dr_j x3, Laplacian).
+// D2 is the two-electron width rounded up to a compiled size; the extra
+// features carry zero weights and stay zero.
+template <class TA, int D2>
+__global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
+  extern __shared__ float sh[];
+  const int n = a.n, R2 = a.R2, d2 = a.d2;
+  float* Ps = sh;                                // [slots][D2]
+  float* Ws = sh + (size_t)a.ipb * n * R2 * D2;  // [D2][D2] then c[D2]
+  const int tid = threadIdx.x;
+  const int slots = a.ipb * n * R2;
+  const int64_t gbase = (int64_t)blockIdx.x * a.ipb;
+  const int64_t n_groups = (int64_t)a.W * n;
+
+  const int s = tid;
+  const bool live = s < slots && (gbase + s / (n * R2)) < n_groups;
+  const int ii = s / (n * R2), j = (s / R2) % n, q = s % R2;
+  const int64_t g = gbase + ii;
+  const int i = (int)(g % n);
+  const int64_t w = g / n;
+
+  // input pair features (r_i - r_j, |r_i - r_j|) and their sparse jets
+  if (live) {
+    float in[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i != j) {
+      const float* ri = a.pos + (w * n + i) * 3;
+      const float* rj = a.pos + (w * n + j) * 3;
+      float dd[3] = {ri[0] - rj[0], ri[1] - rj[1], ri[2] - rj[2]};
+      float dist = sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+      if (q == 0) {
+        in[0] = dd[0]; in[1] = dd[1]; in[2] = dd[2]; in[3] = dist;
+      } else if (q <= 6) {
+        const int c = (q - 1) % 3;
+        const float sgn = q <= 3 ? 1.0f : -1.0f;  // d/dr_i or d/dr_j
+        in[0] = c == 0 ? sgn : 0.0f;
+        in[1] = c == 1 ? sgn : 0.0f;
+        in[2] = c == 2 ? sgn : 0.0f;
+        in[3] = sgn * dd[c] / dist;
+      } else {
+        in[3] = 4.0f / dist;  // Laplacian over r_i and r_j of |r_i - r_j|
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D2; ++k) Ps[(size_t)s * D2 + k] = k < 4 ? in[k] : 0.0f;
+  }
+
+  int ein = 4;
+  const int n_up = a.n_up, n_dn = n - a.n_up;
+  for (int l = 0; l < a.L; ++l) {
+    __syncthreads();
+    // dense jets of g^a_i = mean_{j in a} h_ij from the pair activations in LDS
+    {
+      TA* G = reinterpret_cast<TA*>(a.G[l]);
+      const int ldg = a.ldg[l];
+      const int T = a.T, Tp = a.Tp;
+      const int per = Tp * ldg;
+      for (int idx = tid; idx < a.ipb * per; idx += blockDim.x) {
+        const int e = idx / per, rem = idx % per;
+        const int t = rem / ldg, c = rem % ldg;
+        const int64_t ge = gbase + e;
+        if (ge >= n_groups) continue;
+        const int ie = (int)(ge % n);
+        float v = 0.0f;
+        if (c < 2 * ein && t < T) {
+          const int al = c / ein, o = c % ein;
+          const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n_dn;
+          if (na > 0) {
+            const float* base = Ps + (size_t)e * n * R2 * D2 + o;
+            float acc = 0.0f;
+            if (t == 0) {
+              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2) * D2];
+            } else if (t == T - 1) {
+              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 7) * D2];
+            } else {
+              const int jt = (t - 1) / 3, cc = (t - 1) % 3;
+              if (jt == ie) {
+                for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 1 + cc) * D2];
+              } else if (jt >= j0 && jt < j0 + na) {
+                acc = base[(size_t)(jt * R2 + 4 + cc) * D2];
+              }
+            }
+            v = acc / (float)na;
+          }
+        }
+        st_act(G + (ge * Tp + t) * (int64_t)ldg + c, v);
+      }
+      if (a.h2_out[l] && R2 == 1) {
+        for (int idx = tid; idx < a.ipb * n * ein; idx += blockDim.x) {
+          const int e = idx / (n * ein), jj = (idx / ein) % n, o = idx % ein;
+          const int64_t ge = gbase + e;
+          if (ge < n_groups) a.h2_out[l][(ge * n + jj) * ein + o] = Ps[(size_t)(e * n + jj) * D2 + o];
+        }
+      }
+    }
+    if (l + 1 == a.L) break;
+    // two-electron layer l: h' = tanh(h W_l + c_l) (+ h when widths match)
+    for (int k = tid; k < D2 * D2 + D2; k += blockDim.x) {
+      float v = 0.0f;
+      if (k < D2 * D2) {
+        const int kr = k / D2, o = k % D2;
+        if (kr < ein && o < d2) v = a.params[a.w_off[l] + kr * d2 + o];
+      } else if (k - D2 * D2 < d2) {
+        v = a.params[a.c_off[l] + (k - D2 * D2)];
+      }
+      Ws[k] = v;
+    }
+    __syncthreads();
+    float u[D2];
+#pragma unroll
+    for (int o = 0; o < D2; ++o) u[o] = q == 0 ? Ws[D2 * D2 + o] : 0.0f;
+    if (live) {
+      for (int k = 0; k < ein; ++k) {
+        const float x = Ps[(size_t)s * D2 + k];
+        const float4* wr = reinterpret_cast<const float4*>(Ws + k * D2);
+#pragma unroll
+        for (int o4 = 0; o4 < D2 / 4; ++o4) {
+          const float4 wv = wr[o4];
+          u[4 * o4] += x * wv.x;
+          u[4 * o4 + 1] += x * wv.y;
+          u[4 * o4 + 2] += x * wv.z;
+          u[4 * o4 + 3] += x * wv.w;
+        }
+      }
+    }
+    const bool res = ein == d2;
+#pragma unroll
+    for (int o = 0; o < D2; ++o) {
+      const float uo = u[o];
+      float y, s2 = 0.0f;
+      if (R2 == 8) {
+        const int base = tid & ~7;
+        const float u0 = __shfl(uo, base, 64);
+        float sq = (q >= 1 && q <= 6) ? uo * uo : 0.0f;
+        sq += __shfl_xor(sq, 1, 64);
+        sq += __shfl_xor(sq, 2, 64);
+        sq += __shfl_xor(sq, 4, 64);
+        s2 = sq;
+        y = tanhf(u0);
+      } else {
+        y = tanhf(uo);
+      }
+      const float dy = sech2f(R2 == 8 ? __shfl(uo, tid & ~7, 64) : uo);
+      float outv;
+      if (q == 0) outv = y;
+      else if (q <= 6) outv = dy * uo;
+      else outv = dy * uo - 2.0f * y * dy * s2;
+      if (res && live) outv += Ps[(size_t)s * D2 + o];
+      u[o] = o < d2 ? outv : 0.0f;
+    }
+    ein = d2;
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int o = 0; o < D2; ++o) Ps[(size_t)s * D2 + o] = u[o];
+    }
+  }
+}
+
+template <class TA, int D2>
+static hipError_t run_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
+  size_t shmem = ((size_t)d.ipb * d.n * d.R2 * D2 + (size_t)D2 * D2 + D2) * sizeof(float);
+  hipLaunchKernelGGL((two_electron_kernel<TA, D2>), dim3(grid), dim3(256), shmem, s, d);
+  return hipGetLastError();
+}
+
+template <class TA>
+static hipError_t pick_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
+  if (d.d2 <= 4) return run_two_e<TA, 4>(d, grid, s);
+  if (d.d2 <= 8) return run_two_e<TA, 8>(d, grid, s);
+  if (d.d2 <= 16) return run_two_e<TA, 16>(d, grid, s);
+  if (d.d2 <= 32) return run_two_e<TA, 32>(d, grid, s);
+  return run_two_e<TA, 64>(d, grid, s);
+}
+
+hipError_t launch_two_electron(bool bf16, const TwoElecArgs& a, hipStream_t s) {
+  TwoElecDev d;
+  d.pos = a.pos;
+  d.params = a.params;
+  for (int l = 0; l < 8; ++l) {
+    d.w_off[l] = l + 1 < a.L ? a.w_off[l] : 0;
+    d.c_off[l] = l + 1 < a.L ? a.c_off[l] : 0;
+    d.G[l] = l < a.L ? a.G[l] : nullptr;
+    d.ldg[l] = l < a.L ? a.ldg[l] : 0;
+    d.h2_out[l] = l < a.L ? a.h2_out[l] : nullptr;
+  }
+  d.W = a.W; d.n = a.n; d.n_up = a.n_up; d.L = a.L; d.d2 = a.d2; d.T = a.T; d.Tp = a.Tp;
+  d.R2 = a.T > 1 ? 8 : 1;
+  if (a.d2 > 64 || a.n * d.R2 > 256 || a.L > 8) return hipErrorInvalidValue;
+  // electrons per block: at most 256 slots and at most 64 KiB of LDS
+  const int D2p = a.d2 <= 4 ? 4 : a.d2 <= 8 ? 8 : a.d2 <= 16 ? 16 : a.d2 <= 32 ? 32 : 64;
+  const int lds_cap = (65536 / 4 - D2p * D2p - D2p) / (a.n * d.R2 * D2p);
+  d.ipb = std::min(256 / (a.n * d.R2), lds_cap);
+  if (d.ipb < 1) return hipErrorInvalidValue;
+  const int64_t groups = (int64_t)a.W * a.n;
+  const int grid = (int)((groups + d.ipb - 1) / d.ipb);
+  if (grid <= 0) return hipSuccess;
+  return bf16 ? pick_two_e<bf16_t>(d, grid, s) : pick_two_e<float>(d, grid, s);
+}
+
+// ------------------------------------------------------------ mean fields
+// Hbar[(w Tp + t)][a din_p + f] = mean_{j of spin a} H[((w n + j) Tp + t)][f]
+template <class TA>
+__global__ void meanfield_kernel(const TA* H, int ldh, int W, int n, int n_up, int Tp, int din_p, TA* Hbar) {
+  const int64_t total = (int64_t)W * Tp * 2 * din_p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx % (2 * din_p));
+    const int64_t row = idx / (2 * din_p);
+    const int t = (int)(row % Tp);
+    const int64_t w = row / Tp;
+    const int al = c / din_p, f = c % din_p;
+    const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n - n_up;
+    float acc = 0.0f;
+    for (int j = j0; j < j0 + na; ++j) acc += ld_act(H + ((w * n + j) * Tp + t) * (int64_t)ldh + f);
+    st_act(Hbar + idx, na > 0 ? acc / (float)na : 0.0f);
+  }
+}
+
+hipError_t launch_meanfield(bool bf16, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
+                            hipStream_t s) {
+  int64_t total = (int64_t)W * Tp * 2 * din_p;
+  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  if (grid <= 0) return hipSuccess;
+  if (bf16) hipLaunchKernelGGL(meanfield_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, (const bf16_t*)H, ldh, W, n, n_up, Tp, din_p, (bf16_t*)Hbar);
+  else hipLaunchKernelGGL(meanfield_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p, (float*)Hbar);
+  return hipGetLastError();
+}
+
+}  // namespace fn

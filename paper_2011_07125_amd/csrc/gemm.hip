@@ -1,0 +1,389 @@
+// Jet GEMM on CDNA4 matrix cores with fused epilogues.
+//
+// The one-electron layers of the permutation-equivariant network, the
+// projection of the mean field and the orbital projection of Eq. (5) are
+// all products  rows x K  by  K x N  where every row is one jet row (value,
+// one of the 3n tangents, or the Laplacian) of one electron of one walker.
+// The 3n+2 jet rows of an electron are what make these products dense;
+// a workgroup tile always holds whole electrons so that the epilogue can
+// apply the chain rule of tanh (which needs the sum over tangent rows of
+// the squared pre-activation) or the product rule with the envelope
+// without leaving the tile.
+//
+// Tile: BM rows (whole electrons) x BN columns, K step 32, 256 threads as
+// 2 x 2 wavefronts of 64, each wavefront a grid of 16x16 MFMA tiles.
+// Activations are float32 in HBM.  Two arithmetic modes:
+//   MODE_F32:   v_mfma_f32_16x16x4_f32 on the float32 operands
+//   MODE_BF16X3: each operand split x = hi + lo into two bfloat16 (16
+//               significand bits in all) and x y ~ hi_x hi_y + hi_x lo_y +
+//               lo_x hi_y by three v_mfma_f32_16x16x32_bf16 into one
+//               float32 accumulator; the activations are split while being
+//               staged into LDS, the weights are pre-split by the packer.
+// Global -> register -> LDS double buffering: the next K tile is fetched
+// while the current one is multiplied.
+#include "common.h"
+#include "kernels.h"
+
+namespace fn {
+
+template <int MODE, int BM, int BN>
+struct Smem {
+  static constexpr int BK = 32;
+  // fp32: one plane of floats, row stride BK+4; split bf16: hi and lo planes
+  // of bf16, row stride BK+8
+  static constexpr int LDS_K = MODE == MODE_F32 ? BK + 4 : BK + 8;
+  static constexpr int ESZ = MODE == MODE_F32 ? 4 : 2;
+  static constexpr int PLANES = MODE == MODE_F32 ? 1 : 2;
+  static constexpr int A_PLANE = BM * LDS_K * ESZ;
+  static constexpr int B_PLANE = BN * LDS_K * ESZ;
+  static constexpr int AB_BYTES = PLANES * (A_PLANE + B_PLANE);
+  static constexpr int LDC = BN + 4;
+  static constexpr int C_BYTES = BM * LDC * 4;
+  static constexpr int BYTES = AB_BYTES > C_BYTES ? AB_BYTES : C_BYTES;
+};
+
+__device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+template <int MODE, int BM, int BN, int EPI>
+__global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
+  using SM = Smem<MODE, BM, BN>;
+  constexpr int BK = SM::BK;
+  constexpr int LDS_K = SM::LDS_K;
+  constexpr int TM = BM / 32, TN = BN / 32;
+  constexpr int VPR_A = BK / 4;                             // float4 vectors per A tile row
+  constexpr int VPR_B = MODE == MODE_F32 ? BK / 4 : BK / 8;  // 16-byte vectors per B tile row
+  constexpr int NVA = (BM * VPR_A + 255) / 256;
+  constexpr int NVB = (BN * VPR_B + 255) / 256;
+  __shared__ __attribute__((aligned(16))) char smem[SM::BYTES];
+  float* Cs = reinterpret_cast<float*>(smem);
+
+  // XCD-aware tile order: the n_ntiles column tiles of one row tile are
+  // given block ids that differ by multiples of 8, so they land on the same
+  // XCD and share its L2 for the A tile.
+  const int bid = blockIdx.x;
+  const int n_t = (bid / 8) % n_ntiles;
+  const int m_t = (bid / (8 * n_ntiles)) * 8 + (bid % 8);
+  if (m_t >= n_mtiles) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int rows_per = a.rows_per;
+  const int E = BM / rows_per;
+  const int g0 = m_t * E;
+  const int n0 = n_t * BN;
+  const int K = a.ka0 + a.ka1;
+  const int nkt = K / BK;
+
+  // memory rows of this thread's A vectors (fixed over the K loop)
+  long rowoff[NVA];
+#pragma unroll
+  for (int i = 0; i < NVA; ++i) {
+    int v = tid + i * 256;
+    rowoff[i] = -1;
+    if (v < BM * VPR_A) {
+      int r = v / VPR_A;
+      int e = r / rows_per, t = r % rows_per;
+      int g = g0 + e;
+      if (g < a.n_groups) {
+        long mg = (long)(g / a.n_sub) * a.n_all + a.e_off + (g % a.n_sub);
+        rowoff[i] = mg * rows_per + t;
+      }
+    }
+  }
+
+  uint4 ra[NVA], rb[NVB], rbl[MODE == MODE_F32 ? 1 : NVB];
+  auto load = [&](int kt) {
+    const int kb = kt * BK;
+    const float* src;
+    int lda, kk;
+    if (kb < a.ka0) {
+      src = (const float*)a.a0;
+      lda = a.lda0;
+      kk = kb;
+    } else {
+      src = (const float*)a.a1;
+      lda = a.lda1;
+      kk = kb - a.ka0;
+    }
+#pragma unroll
+    for (int i = 0; i < NVA; ++i) {
+      int v = tid + i * 256;
+      uint4 z = {0, 0, 0, 0};
+      if (v < BM * VPR_A && rowoff[i] >= 0) {
+        int kv = (v % VPR_A) * 4;
+        z = *reinterpret_cast<const uint4*>(src + (size_t)rowoff[i] * lda + kk + kv);
+      }
+      ra[i] = z;
+    }
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) {
+      int v = tid + i * 256;
+      uint4 z = {0, 0, 0, 0}, zl = {0, 0, 0, 0};
+      if (v < BN * VPR_B) {
+        int nn = v / VPR_B, col = n0 + nn;
+        if (col < a.N) {
+          if constexpr (MODE == MODE_F32) {
+            int kv = (v % VPR_B) * 4;
+            z = *reinterpret_cast<const uint4*>((const float*)a.bt + (size_t)col * a.ldb + kb + kv);
+          } else {
+            int kv = (v % VPR_B) * 8;
+            z = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt + (size_t)col * a.ldb + kb + kv);
+            zl = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt_lo + (size_t)col * a.ldb + kb + kv);
+          }
+        }
+      }
+      rb[i] = z;
+      if constexpr (MODE != MODE_F32) rbl[i] = zl;
+    }
+  };
+  auto store = [&]() {
+    if constexpr (MODE == MODE_F32) {
+      float* As = reinterpret_cast<float*>(smem);
+      float* Bs = reinterpret_cast<float*>(smem + SM::A_PLANE);
+#pragma unroll
+      for (int i = 0; i < NVA; ++i) {
+        int v = tid + i * 256;
+        if (v < BM * VPR_A) *reinterpret_cast<uint4*>(As + (v / VPR_A) * LDS_K + (v % VPR_A) * 4) = ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NVB; ++i) {
+        int v = tid + i * 256;
+        if (v < BN * VPR_B) *reinterpret_cast<uint4*>(Bs + (v / VPR_B) * LDS_K + (v % VPR_B) * 4) = rb[i];
+      }
+    } else {
+      uint16_t* Ah = reinterpret_cast<uint16_t*>(smem);
+      uint16_t* Al = reinterpret_cast<uint16_t*>(smem + SM::A_PLANE);
+      uint16_t* Bh = reinterpret_cast<uint16_t*>(smem + 2 * SM::A_PLANE);
+      uint16_t* Bl = reinterpret_cast<uint16_t*>(smem + 2 * SM::A_PLANE + SM::B_PLANE);
+#pragma unroll
+      for (int i = 0; i < NVA; ++i) {
+        int v = tid + i * 256;
+        if (v < BM * VPR_A) {
+          const float x[4] = {__builtin_bit_cast(float, ra[i].x), __builtin_bit_cast(float, ra[i].y),
+                              __builtin_bit_cast(float, ra[i].z), __builtin_bit_cast(float, ra[i].w)};
+          uint16_t h[4], l[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            h[q] = f32_to_bf16_bits(x[q]);
+            l[q] = f32_to_bf16_bits(x[q] - bf16_bits_to_f32(h[q]));
+          }
+          const int off = (v / VPR_A) * LDS_K + (v % VPR_A) * 4;
+          *reinterpret_cast<uint2*>(Ah + off) = uint2{pack2(h[0], h[1]), pack2(h[2], h[3])};
+          *reinterpret_cast<uint2*>(Al + off) = uint2{pack2(l[0], l[1]), pack2(l[2], l[3])};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NVB; ++i) {
+        int v = tid + i * 256;
+        if (v < BN * VPR_B) {
+          const int off = (v / VPR_B) * LDS_K + (v % VPR_B) * 8;
+          *reinterpret_cast<uint4*>(Bh + off) = rb[i];
+          *reinterpret_cast<uint4*>(Bl + off) = rbl[i];
+        }
+      }
+    }
+  };
+
+  floatx4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int arow = wm * (BM / 2) + (lane & 15);
+  const int brow = wn * (BN / 2) + (lane & 15);
+  const int kq = lane >> 4;
+
+  if (nkt > 0) load(0);
+  for (int kt = 0; kt < nkt; ++kt) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kt + 1 < nkt) load(kt + 1);
+    if constexpr (MODE == MODE_F32) {
+      const float* As = reinterpret_cast<const float*>(smem);
+      const float* Bs = reinterpret_cast<const float*>(smem + SM::A_PLANE);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        float af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = As[(arow + i * 16) * LDS_K + ks * 4 + kq];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bfr[j] = Bs[(brow + j * 16) * LDS_K + ks * 4 + kq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      const uint16_t* Ah = reinterpret_cast<const uint16_t*>(smem);
+      const uint16_t* Al = reinterpret_cast<const uint16_t*>(smem + SM::A_PLANE);
+      const uint16_t* Bh = reinterpret_cast<const uint16_t*>(smem + 2 * SM::A_PLANE);
+      const uint16_t* Bl = reinterpret_cast<const uint16_t*>(smem + 2 * SM::A_PLANE + SM::B_PLANE);
+      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        ah[i] = *reinterpret_cast<const bf16x8*>(Ah + (arow + i * 16) * LDS_K + kq * 8);
+        al[i] = *reinterpret_cast<const bf16x8*>(Al + (arow + i * 16) * LDS_K + kq * 8);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        bh[j] = *reinterpret_cast<const bf16x8*>(Bh + (brow + j * 16) * LDS_K + kq * 8);
+        bl[j] = *reinterpret_cast<const bf16x8*>(Bl + (brow + j * 16) * LDS_K + kq * 8);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          // small cross terms first, then the leading term
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+  __syncthreads();
+  // accumulators -> LDS tile [BM][BN]
+  constexpr int LDC = SM::LDC;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Cs[(wm * (BM / 2) + i * 16 + kq * 4 + r) * LDC + wn * (BN / 2) + j * 16 + (lane & 15)] = acc[i][j][r];
+  __syncthreads();
+
+  const int T = a.T;
+  if constexpr (EPI == EPI_PLAIN) {
+    for (int p = tid; p < BM * BN; p += 256) {
+      int r = p / BN, col = p % BN;
+      int e = r / rows_per, t = r % rows_per;
+      int g = g0 + e, gc = n0 + col;
+      if (g < a.n_groups && gc < a.N) a.c[((size_t)g * rows_per + t) * a.ldc + gc] = Cs[r * LDC + col];
+    }
+  } else if constexpr (EPI == EPI_TANHJET) {
+    float* out = reinterpret_cast<float*>(a.out);
+    const float* res = reinterpret_cast<const float*>(a.a0);
+    for (int p = tid; p < E * BN; p += 256) {
+      int e = p / BN, col = p % BN;
+      int g = g0 + e, gc = n0 + col;
+      if (g >= a.n_groups || gc >= a.N) continue;
+      const int w = g / a.n_all;
+      const float* Pr = a.P + (size_t)w * rows_per * a.ldp + gc;
+      const float* Cr = Cs + (e * rows_per) * LDC + col;
+      const size_t orow = (size_t)g * rows_per;
+      float u0 = Cr[0] + Pr[0] + a.bias[gc];
+      float y = tanhf(u0);
+      float dy = sech2f(u0);
+      float r0 = a.res ? res[orow * a.lda0 + gc] : 0.0f;
+      out[orow * a.ldo + gc] = y + r0;
+      if (a.y_out) a.y_out[(size_t)g * a.N + gc] = y;
+      if (T > 1) {
+        float s2 = 0.0f;
+        for (int t = 1; t < T - 1; ++t) {
+          float u = Cr[t * LDC] + Pr[(size_t)t * a.ldp];
+          s2 += u * u;
+        }
+        for (int t = 1; t < T - 1; ++t) {
+          float u = Cr[t * LDC] + Pr[(size_t)t * a.ldp];
+          float rr = a.res ? res[(orow + t) * a.lda0 + gc] : 0.0f;
+          out[(orow + t) * a.ldo + gc] = dy * u + rr;
+        }
+        {
+          int t = T - 1;
+          float u = Cr[t * LDC] + Pr[(size_t)t * a.ldp];
+          float rr = a.res ? res[(orow + t) * a.lda0 + gc] : 0.0f;
+          out[(orow + t) * a.ldo + gc] = dy * u - 2.0f * y * dy * s2 + rr;
+        }
+        for (int t = T; t < rows_per; ++t) out[(orow + t) * a.ldo + gc] = 0.0f;
+      }
+    }
+  } else {  // EPI_ORBITAL
+    const int na = a.n_sub;
+    const int nsq = na * na;
+    const int Kd = a.N / na;
+    for (int p = tid; p < E * BN; p += 256) {
+      int e = p / BN, col = p % BN;
+      int g = g0 + e, gc = n0 + col;
+      if (g >= a.n_groups || gc >= a.N) continue;
+      const int w = g / na, jj = g % na;
+      const int j = a.e_off + jj;  // electron index
+      const int k = gc / na, i = gc % na;
+      const float* rj = a.pos + ((size_t)w * a.n_elec + j) * 3;
+      const float x0 = rj[0], x1 = rj[1], x2 = rj[2];
+      // isotropic envelope sum_m pi exp(-|sigma| d) and its gradient and
+      // Laplacian with respect to r_j
+      float e0 = 0.f, ex = 0.f, ey = 0.f, ez = 0.f, le = 0.f;
+      for (int m = 0; m < a.n_nuc; ++m) {
+        float dx = x0 - a.nuc[3 * m], dyv = x1 - a.nuc[3 * m + 1], dz = x2 - a.nuc[3 * m + 2];
+        float d = sqrtf(dx * dx + dyv * dyv + dz * dz);
+        float s = fabsf(a.sigma[(size_t)gc * a.n_nuc + m]);
+        float v = a.pi[(size_t)gc * a.n_nuc + m] * expf(-s * d);
+        float inv_d = 1.0f / d;
+        e0 += v;
+        ex -= s * v * dx * inv_d;
+        ey -= s * v * dyv * inv_d;
+        ez -= s * v * dz * inv_d;
+        le += v * (s * s - 2.0f * s * inv_d);
+      }
+      const float* Cr = Cs + (e * rows_per) * LDC + col;
+      const float u0 = Cr[0] + a.g_orb[gc];
+      float* ph = a.phi + ((size_t)(w * Kd + k) * T) * nsq + jj * na + i;
+      ph[0] = u0 * e0;
+      if (a.u_out) {
+        size_t o = ((size_t)(w * Kd + k) * na + jj) * na + i;
+        a.u_out[o] = u0;
+        a.env_out[o] = e0;
+      }
+      if (T > 1) {
+        const int tj = 1 + 3 * j;
+        for (int t = 1; t < T - 1; ++t) ph[(size_t)t * nsq] = Cr[t * LDC] * e0;
+        const float ux = Cr[tj * LDC], uy = Cr[(tj + 1) * LDC], uz = Cr[(tj + 2) * LDC];
+        ph[(size_t)tj * nsq] += u0 * ex;
+        ph[(size_t)(tj + 1) * nsq] += u0 * ey;
+        ph[(size_t)(tj + 2) * nsq] += u0 * ez;
+        const float lu = Cr[(T - 1) * LDC];
+        ph[(size_t)(T - 1) * nsq] = lu * e0 + u0 * le + 2.0f * (ux * ex + uy * ey + uz * ez);
+      }
+    }
+  }
+}
+
+template <int MODE, int BM, int BN, int EPI>
+static hipError_t run(const JetGemmArgs& a, hipStream_t s) {
+  const int E = BM / a.rows_per;
+  const int n_mtiles = (a.n_groups + E - 1) / E;
+  const int n_ntiles = (a.N + BN - 1) / BN;
+  const int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
+  hipLaunchKernelGGL((jet_gemm_kernel<MODE, BM, BN, EPI>), dim3(grid), dim3(256), 0, s, a, n_mtiles, n_ntiles);
+  return hipGetLastError();
+}
+
+template <int MODE, int EPI>
+static hipError_t pick(const JetGemmArgs& a, hipStream_t s) {
+  const bool bm96 = a.rows_per == 96;
+  if (!bm96 && (128 % a.rows_per) != 0) return hipErrorInvalidValue;
+  // column tile: 128 unless 64 wastes fewer columns
+  int w128 = (a.N + 127) / 128 * 128 - a.N;
+  int w64 = (a.N + 63) / 64 * 64 - a.N;
+  const bool bn64 = a.N <= 64 || w64 < w128;
+  if (bm96) return bn64 ? run<MODE, 96, 64, EPI>(a, s) : run<MODE, 96, 128, EPI>(a, s);
+  return bn64 ? run<MODE, 128, 64, EPI>(a, s) : run<MODE, 128, 128, EPI>(a, s);
+}
+
+hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t s) {
+  if (a.n_groups <= 0) return hipSuccess;
+  if ((a.ka0 % 32) || (a.ka1 % 32)) return hipErrorInvalidValue;
+  if (mode == MODE_BF16X3) {
+    if (epi == EPI_PLAIN) return pick<MODE_BF16X3, EPI_PLAIN>(a, s);
+    if (epi == EPI_TANHJET) return pick<MODE_BF16X3, EPI_TANHJET>(a, s);
+    return pick<MODE_BF16X3, EPI_ORBITAL>(a, s);
+  }
+  if (epi == EPI_PLAIN) return pick<MODE_F32, EPI_PLAIN>(a, s);
+  if (epi == EPI_TANHJET) return pick<MODE_F32, EPI_TANHJET>(a, s);
+  return pick<MODE_F32, EPI_ORBITAL>(a, s);
+}
+
+}  // namespace fn

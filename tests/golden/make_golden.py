@@ -1,0 +1,33 @@
+"""Writes the oracle's outputs on full seeded workloads (float64) for the
+bench's and the tests' full-batch error reports.  Calls only oracle/ and
+the seeded input generator.
+
+    python tests/golden/make_golden.py ne10 [threads]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2011_07125_amd import inputs as I  # noqa: E402
+
+
+def main(name, threads):
+    w = I.make_workload(name)
+    t = time.time()
+    r = O.evaluate(w["cfg"], w["pos"], w["nuc_pos"], w["nuc_charge"], w["params"], threads=threads)
+    amp, kappa, cond = O.amplification(w["cfg"], w["pos"], w["nuc_pos"], w["params"], threads=threads)
+    out = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(out, sign=r["sign"], logpsi=r["logpsi"], e_loc=r["e_loc"], e_kin=r["e_kin"],
+                        e_pot=r["e_pot"], amplification=amp, kappa=kappa, cond=cond, seed=w["seed"],
+                        walkers=w["pos"].shape[0])
+    print(f"{out}: {w['pos'].shape[0]} walkers in {time.time() - t:.1f}s, mean E_L {r['e_loc'].mean():.6f}")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else os.cpu_count())

@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports
+every function ferminet.h declares, the parameter layout agrees with the
+documented one, and invalid arguments are rejected with the documented
+status codes before anything is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2011_07125_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ferminet.h")
+
+F = pytest.importorskip("paper_2011_07125_amd.ferminet")
+
+
+def _lib_or_skip():
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("libferminet.so not built")
+    return F._lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names) - {"if", "defined"})
+
+
+def test_header_symbols_exported():
+    lib = _lib_or_skip()
+    names = declared_functions()
+    assert len(names) >= 10, names
+    raw = ctypes.CDLL(F.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(F.EXPORTS) == set(names)
+
+
+@pytest.mark.parametrize("name", ["be4", "ne10", "ar18", "c4h6"])
+def test_param_layout_matches_documented(name):
+    _lib_or_skip()
+    cfg = I.make_workload(name, walkers=1)["cfg"]
+    offs = I.param_offsets(cfg)
+    assert F.param_count(cfg) == offs["_total"]
+    lay = F.param_layout(cfg)
+    blocks = I.param_blocks(cfg)
+    assert [b[0] for b in lay] == [b[0] for b in blocks]
+    for (nm, off, rows, cols), (nm2, shape, _) in zip(lay, blocks):
+        assert off == offs[nm][0]
+        assert rows * cols == int(np.prod(shape))
+
+
+def _cfg(**kw):
+    base = dict(n_elec=4, n_up=2, n_down=2, n_nuc=1, n_layers=2, width1=32, width2=8, n_det=4, precision=0)
+    base.update(kw)
+    return F.fn_config(*[base[k] for k in ("n_elec", "n_up", "n_down", "n_nuc", "n_layers", "width1", "width2",
+                                           "n_det", "precision")])
+
+
+def test_config_validation():
+    lib = _lib_or_skip()
+    assert lib.ferminet_param_count(ctypes.byref(_cfg())) == 4888
+    for bad in (dict(n_up=3), dict(width1=40), dict(width1=16), dict(n_det=0), dict(n_layers=9), dict(precision=5),
+                dict(n_elec=33, n_up=17, n_down=16), dict(width2=65), dict(n_nuc=0)):
+        assert lib.ferminet_param_count(ctypes.byref(_cfg(**bad))) == -1, bad
+
+
+def test_workspace_monotone_and_errors():
+    lib = _lib_or_skip()
+    c = _cfg()
+    sz = []
+    for w in (1, 2, 64, 256):
+        out = ctypes.c_size_t(0)
+        assert lib.ferminet_workspace_bytes(ctypes.byref(c), w, 1, ctypes.byref(out)) == 0
+        sz.append(out.value)
+    assert sz == sorted(sz) and sz[0] > 0
+    out = ctypes.c_size_t(0)
+    assert lib.ferminet_workspace_bytes(ctypes.byref(c), 0, 1, ctypes.byref(out)) == 7
+    assert lib.ferminet_workspace_bytes(ctypes.byref(c), 4, 9, ctypes.byref(out)) == 7
+    assert lib.ferminet_workspace_bytes(ctypes.byref(c), 4, 1, None) == 1
+
+
+def test_entry_points_reject_bad_arguments_before_launch():
+    """T13: documented status codes; no pointer is dereferenced and nothing
+    is launched (fake but aligned device addresses are never touched)."""
+    lib = _lib_or_skip()
+    c = _cfg()
+    fake = ctypes.c_void_p(1 << 40)  # aligned, never dereferenced
+    good = (ctypes.c_int32 * 4)(0, 0, 1, 1)
+    bad = (ctypes.c_int32 * 4)(0, 1, 0, 1)
+    f = lib.ferminet_local_energy
+    args = lambda W, spins, ws, nbytes, cfg=c: (ctypes.byref(cfg), W, fake, spins, fake, fake, fake, fake, fake, fake,
+                                                None, None, ws, nbytes, None)
+    assert f(*args(8, bad, fake, 1 << 30)) == 3                     # spins order
+    assert f(*args(8, None, fake, 1 << 30)) == 1                    # NULL spins
+    assert f(*args(8, good, None, 1 << 30)) == 1                    # NULL workspace
+    assert f(*args(8, good, ctypes.c_void_p((1 << 40) + 8), 1 << 30)) == 4  # misaligned
+    assert f(*args(8, good, fake, 16)) == 4                         # too small
+    assert f(*args(-1, good, fake, 1 << 30)) == 7                   # W < 0
+    assert f(*args(0, good, fake, 1 << 30)) == 0                    # empty batch: nothing to do
+    assert f(*args(8, good, fake, 1 << 30, _cfg(n_up=3))) == 2      # config
+    g = lib.vmc_mcmc_step
+    assert g(ctypes.byref(c), 8, fake, good, fake, fake, fake, fake, fake, -1, 0.1, 0, 0, None, None, fake, fake,
+             1 << 30, None) == 7
+    assert g(ctypes.byref(c), 8, fake, good, fake, fake, fake, fake, fake, 1, 0.1, 0, 0, fake, None, fake, fake,
+             1 << 30, None) == 7
+    h = lib.ferminet_grad_logpsi
+    assert h(ctypes.byref(c), 8, fake, good, fake, fake, fake, None, fake, fake, 1 << 30, None) == 1
+    assert lib.vmc_mcmc_noise(-1, 4, 1, 0, 0, fake, fake, None) == 7
+    assert lib.ferminet_status_string(4).decode().startswith("workspace")

@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances (stated for the fp32 form):
+  sign        bit-exact
+  log|psi|    |delta| <= 1e-5 * max(1, |log|psi||)
+  E_L         batch mean within 1e-3 Ha; per walker |delta| <= 1e-3 * max(1, |E_L|)
+              for all but walkers next to a node (reported)
+The bf16 form (bf16 GEMM operands, fp32 accumulation, fp64 determinants)
+reports its error against the oracle for every output; its batch-mean E_L
+is gated at 1 mHa where the oracle's batch is large enough to average.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2011_07125_amd import ferminet as F  # noqa: E402
+from paper_2011_07125_amd import inputs as I  # noqa: E402
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(w, precision=None, max_chunk=None):
+    d = F.to_device(w)
+    out = F.ferminet_local_energy(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"],
+                                  precision=precision, max_chunk=max_chunk)
+    torch.cuda.synchronize()
+    return {k: v.double().cpu().numpy() for k, v in out.items()}
+
+
+def run_oracle(w, energy=True):
+    return O.evaluate(w["cfg"], w["pos"].astype(np.float64), w["nuc_pos"].astype(np.float64),
+                      w["nuc_charge"].astype(np.float64), w["params"].astype(np.float64), energy=energy,
+                      threads=THREADS)
+
+
+# unit roundoff of the arithmetic that produces the orbital matrices in
+# each form: fp32; split bf16 (hi + lo: 16 significand bits); fp64
+U_FORM = {"fp32": 2.0 ** -24, "fp32_fp64det": 2.0 ** -24, "bf16": 2.0 ** -16, "fp64": 2.0 ** -53}
+
+
+def compare(name, g, o, amp, form="fp32", elog_tol=1e-5, mean_tol=1e-3, walker_tol=1e-4):
+    """Tolerance model.  The orbital matrices of Eq. (4)-(5) are computed
+    with unit roundoff u; log|det| and its derivatives are then perturbed by
+    up to ~cond(A) u, and the signed sum over determinants amplifies that by
+    kappa_w = max_k |P_k| / |psi_w|.  With the oracle's per-walker
+    amplification A_w = kappa_w max_{k,a} cond_1(A^{ka}) every walker is
+    checked against its own bound
+        sign         equal wherever u A_w < 0.1
+        |d log|psi|| <= elog_tol max(1, |log|psi||) + u A_w
+        |d E_L|      <= (walker_tol + u A_w) max(1, |E_L|)
+    and the batch mean against the propagated bound
+        |d mean E_L| <= mean_tol + mean_w(u A_w max(1, |E_L|)).
+    The errors and the worst walkers are printed."""
+    u = U_FORM[form]
+    ua = u * amp
+    decided = ua < 0.1
+    sgn_ok = g["sign"] == o["sign"]
+    dl = np.abs(g["logpsi"] - o["logpsi"])
+    de = np.abs(g["e_loc"] - o["e_loc"])
+    scale_e = np.maximum(1.0, np.abs(o["e_loc"]))
+    dmean = abs(g["e_loc"].mean() - o["e_loc"].mean())
+    mean_bound = mean_tol + np.mean(ua * scale_e)
+    worst = np.argsort(de / scale_e)[-3:][::-1]
+    say(f"[{name}] W={len(dl)} u*A median={np.median(ua):.1e} max={ua.max():.1e} | rel dlogpsi max="
+        f"{np.max(dl / np.maximum(1, np.abs(o['logpsi']))):.2e} | mean E_L gpu={g['e_loc'].mean():.6f} "
+        f"oracle={o['e_loc'].mean():.6f} |d mean|={dmean:.2e} (bound {mean_bound:.2e}) | rel dE_L median="
+        f"{np.median(de / scale_e):.2e} max={np.max(de / scale_e):.2e} | sign mismatches={int((~sgn_ok).sum())} "
+        f"(undecided {int((~decided).sum())})")
+    for k in worst:
+        say(f"   worst walker {k}: u*A={ua[k]:.2e} E_L oracle={o['e_loc'][k]:.6g} gpu={g['e_loc'][k]:.6g} "
+            f"dlogpsi={dl[k]:.2e}")
+    assert sgn_ok[decided].all(), f"{name}: sign mismatch at {np.nonzero(~sgn_ok & decided)}"
+    bl = elog_tol * np.maximum(1.0, np.abs(o["logpsi"])) + ua
+    assert (dl <= bl)[decided].all(), f"{name}: log|psi| beyond bound at {np.nonzero((dl > bl) & decided)}"
+    be = (walker_tol + ua) * scale_e
+    assert (de <= be)[decided].all(), f"{name}: E_L beyond bound at {np.nonzero((de > be) & decided)}"
+    assert dmean <= mean_bound, f"{name}: batch-mean E_L error {dmean} > {mean_bound}"
+
+
+def kappa_of(w):
+    """per-walker rounding amplification A_w (see compare)"""
+    return O.amplification(w["cfg"], w["pos"], w["nuc_pos"], w["params"], threads=THREADS)[0]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    O.build(force=False)
+    assert torch.cuda.is_available()
+    F._lib()
+
+
+# ------------------------------------------------------------ fp32 parity
+@pytest.mark.parametrize("name,W", [("be4", 256), ("ne10", 48), ("c4h6", 12)])
+def test_local_energy_fp32_vs_oracle(name, W):
+    say(f"case local_energy fp32 {name} W={W}")
+    w = I.make_workload(name, walkers=W)
+    g = run_gpu(w, "fp32")
+    o = run_oracle(w)
+    compare(f"{name}/fp32", g, o, kappa_of(w))
+
+
+def test_local_energy_ar18_both_forms():
+    say("case local_energy ar18 W=8")
+    w = I.make_workload("ar18", walkers=8)
+    o = run_oracle(w)
+    k = kappa_of(w)
+    compare("ar18/fp32", run_gpu(w, "fp32"), o, k)
+    compare("ar18/bf16", run_gpu(w, "bf16"), o, k, form="bf16", elog_tol=1e-3, mean_tol=5e-2, walker_tol=1e-2)
+
+
+def test_local_energy_bf16_form_error_report():
+    """bf16 form on the Ne-like workload: every output's error against the
+    FP64 oracle is stated; the gate is the batch-mean E_L (1 mHa target is
+    for the full batch; on a 48-walker prefix the bound is 1e-2 Ha)."""
+    say("case local_energy bf16 ne10 W=48")
+    w = I.make_workload("ne10", walkers=48)
+    o = run_oracle(w)
+    g = run_gpu(w, "bf16")
+    compare("ne10/bf16", g, o, kappa_of(w), form="bf16", elog_tol=1e-3, mean_tol=1e-2, walker_tol=1e-2)
+
+
+def test_ragged_and_chunked_batches_are_identical():
+    """W not a multiple of any tile, processed in one pass and in chunks of
+    5 walkers: bitwise-identical outputs (walkers are independent)."""
+    say("case ragged/chunked ne10 W=37")
+    w = I.make_workload("ne10", walkers=37)
+    a = run_gpu(w, "fp32")
+    b = run_gpu(w, "fp32", max_chunk=5)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    wp = dict(w, pos=w["pos"][:6])
+    compare("ne10/ragged-prefix", {k: v[:6] for k, v in a.items()}, run_oracle(wp), kappa_of(wp))
+
+
+def test_determinism_two_runs_bitwise():
+    say("case determinism be4")
+    w = I.make_workload("be4", walkers=256)
+    for prec in ("fp32", "bf16"):
+        a = run_gpu(w, prec)
+        b = run_gpu(w, prec)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), (prec, k)
+
+
+def test_logpsi_entry_matches_local_energy_and_oracle():
+    say("case logpsi ne10 W=64")
+    w = I.make_workload("ne10", walkers=64)
+    d = F.to_device(w)
+    s, l = F.ferminet_logpsi(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision="fp32")
+    g = run_gpu(w, "fp32")
+    o = run_oracle(w, energy=False)
+    s, l = s.double().cpu().numpy(), l.double().cpu().numpy()
+    k = kappa_of(w)
+    assert np.array_equal(s, o["sign"])
+    assert (np.abs(l - o["logpsi"]) <= 1e-5 * np.maximum(1, np.abs(o["logpsi"])) + 64 * U_FORM["fp32"] * k).all()
+    assert np.abs(l - g["logpsi"]).max() <= 1e-5 * np.abs(l).max()
+
+
+def test_full_size_ne10_antisymmetry_and_samples():
+    """Full Ne-like batch (4096 walkers, the benchmark's launch shape):
+    exchanging two same-spin electrons flips every sign and keeps log|psi|
+    and E_L; eight sampled walkers agree with the oracle one by one."""
+    say("case full-size ne10 W=4096")
+    w = I.make_workload("ne10")
+    g = run_gpu(w, "fp32")
+    sw = dict(w)
+    pos = w["pos"].copy()
+    pos[:, [1, 3]] = pos[:, [3, 1]]
+    sw["pos"] = pos
+    h = run_gpu(sw, "fp32")
+    # exchanging electrons reorders the floating-point sums, so the two runs
+    # differ by rounding amplified as in compare(): bound by u A_w per walker
+    ua = U_FORM["fp32"] * kappa_of(w)
+    decided = ua < 0.1
+    assert np.array_equal(h["sign"][decided], -g["sign"][decided])
+    dl = np.abs(h["logpsi"] - g["logpsi"])
+    assert (dl <= 1e-5 * np.maximum(1, np.abs(g["logpsi"])) + 2 * ua)[decided].all()
+    rel = np.abs(h["e_loc"] - g["e_loc"]) / np.maximum(1, np.abs(g["e_loc"]))
+    assert (rel <= 1e-4 + 2 * ua)[decided].all()
+    assert np.median(rel) < 1e-5
+    say(f"[ne10/full swap] undecided={int((~decided).sum())} max dlogpsi={dl.max():.2e} median rel dE={np.median(rel):.1e}")
+    idx = np.random.default_rng(0).choice(4096, size=8, replace=False)
+    ws = dict(w, pos=w["pos"][idx])
+    compare("ne10/full-sampled", {k: v[idx] for k, v in g.items()}, run_oracle(ws), kappa_of(ws))
+
+
+def test_hydrogenic_zero_variance_on_gpu():
+    """One electron, no spin-down electrons, network output zeroed and
+    sigma = Z: E_L = -Z^2/2 exactly (Eq. (2) ground state)."""
+    say("case hydrogenic n_down=0")
+    Z = 3.0
+    w = I.custom_workload(1, 0, [[0, 0, 0]], [Z], 100, 2, 32, 4, 2, seed=5)
+    offs = I.param_offsets(w["cfg"])
+    p = w["params"].copy()
+    for name, val in (("w_orb0", 0.0), ("g_orb0", 1.0), ("pi0", 1.0), ("sigma0", Z)):
+        o, sh = offs[name]
+        p[o:o + int(np.prod(sh))] = val
+    w["params"] = p
+    g = run_gpu(w, "fp32")
+    assert np.abs(g["e_loc"] + Z * Z / 2).max() < 2e-4 * Z * Z
+    gb = run_gpu(w, "bf16")
+    assert np.abs(gb["e_loc"] + Z * Z / 2).max() < 2e-4 * Z * Z
+
+
+def test_empty_batch():
+    w = I.make_workload("be4", walkers=1)
+    d = F.to_device(w)
+    z = d["pos"][:0]
+    out = F.ferminet_local_energy(w["cfg"], z, d["nuc_pos"], d["nuc_charge"], d["params"])
+    assert out["e_loc"].numel() == 0
+
+
+# ---------------------------------------------------------- Metropolis
+def test_mcmc_noise_matches_oracle_generator():
+    say("case mcmc noise")
+    W, n, steps, seed, ctr = 300, 10, 3, 1234, 77
+    zg, ug = F.vmc_mcmc_noise(W, n, steps, seed, ctr)
+    zo, uo = O.mcmc_noise(W, n, steps, seed, ctr)
+    ug = ug.double().cpu().numpy()
+    assert np.array_equal(ug, uo.astype(np.float32).astype(np.float64))  # exact: 23-bit uniforms
+    assert np.abs(zg.double().cpu().numpy() - zo).max() < 2e-5
+
+
+def test_mcmc_replay_matches_oracle():
+    """T12: same noise on both sides; the accept decisions agree except where
+    |2 dlogpsi - log u| is below the fp32 resolution (counted)."""
+    say("case mcmc replay be4")
+    w = I.make_workload("be4", walkers=256)
+    d = F.to_device(w)
+    cfg = w["cfg"]
+    s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision="fp32")
+    steps, width, seed = 4, 0.3, 99
+    acc = F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], l, s, steps, width, seed,
+                          counter=5, precision="fp32")
+    torch.cuda.synchronize()
+    o0 = run_oracle(w, energy=False)
+    xo, lo, so, ao = O.mcmc(cfg, w["pos"], w["nuc_pos"], w["params"], o0["logpsi"], o0["sign"], steps, width,
+                            seed=seed, counter=5, threads=THREADS)
+    ag = acc.cpu().numpy()
+    same = ag == ao
+    say(f"[mcmc] accepted gpu={ag.sum()} oracle={ao.sum()} differing walkers={int((~same).sum())}")
+    assert same.mean() >= 0.98
+    xg = d["pos"].double().cpu().numpy()
+    m = same
+    assert np.abs(xg[m] - xo[m]).max() < 1e-4
+    assert np.abs(l.double().cpu().numpy()[m] - lo[m]).max() < 1e-4 * max(1, np.abs(lo).max())
+    assert 0.2 < ag.mean() / steps < 1.0
+
+
+def test_mcmc_supplied_noise_equals_internal():
+    say("case mcmc supplied noise")
+    w = I.make_workload("be4", walkers=64)
+    cfg = w["cfg"]
+    outs = []
+    for supplied in (False, True):
+        d = F.to_device(w)
+        s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"])
+        kw = {}
+        if supplied:
+            z, u = F.vmc_mcmc_noise(64, cfg["n_elec"], 3, 7, 11)
+            kw = dict(noise=z, uniforms=u)
+        acc = F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], l, s, 3, 0.2, 7, 11, **kw)
+        outs.append((d["pos"].cpu().numpy(), l.cpu().numpy(), acc.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
