@@ -106,13 +106,13 @@ static fn_status make_plan(const fn_config* c, Plan& p) {
   return FN_OK;
 }
 
-// the packing plan: [dst_off, N, ldb, k0, len0, src0, k1, len1, src1, src_ld]
+// the packing plan: [dst_off, N, ldb, k0, len0, src0, k1, len1, src1, src_ld, transpose]
 static int pack_plan(const Plan& p, std::vector<int64_t>& it) {
   it.clear();
   auto add = [&](int64_t dst, int64_t N, int64_t ldb, int64_t k0, int64_t l0, int64_t s0, int64_t k1, int64_t l1,
                  int64_t s1, int64_t sld) {
-    int64_t v[10] = {dst, N, ldb, k0, l0, s0, k1, l1, s1, sld};
-    it.insert(it.end(), v, v + 10);
+    int64_t v[11] = {dst, N, ldb, k0, l0, s0, k1, l1, s1, sld, 1};
+    it.insert(it.end(), v, v + 11);
   };
   for (int l = 0; l < p.L; ++l) {
     const int din = p.din[l], ein = p.ein[l];
@@ -125,7 +125,7 @@ static int pack_plan(const Plan& p, std::vector<int64_t>& it) {
   }
   for (int a = 0; a < 2; ++a)
     if (p.na(a) > 0) add(p.pk_orb[a], (int64_t)p.K * p.na(a), p.d1, 0, p.d1, p.offw[a], 0, 0, 0, (int64_t)p.K * p.na(a));
-  return (int)(it.size() / 10);
+  return (int)(it.size() / 11);
 }
 
 // ----------------------------------------------------------- workspace
@@ -190,10 +190,100 @@ static void carve_forward(const Plan& p, Mode m, int64_t Wc, Carver& cv, Bufs& b
   }
 }
 
+// ------------------------------------------------------ adjoint buffers
+struct AdjBufs {
+  float* H[9];      // values of h^l, l = 0..L ([Wc n][dinp_0] then [Wc n][d1])
+  float* PRE[9];    // pre-activations of layer l output, l = 1..L
+  float* G[8];      // g^l values [Wc n][gwp_l]
+  float* Hbar[8];   // [Wc][2 dinp_l]
+  float* h2[8];     // pair values h^l_ij, l < L-1: [Wc n][n][ein_l]
+  float* Pm;        // [Wc][d1]
+  float* phi[2];
+  float* u[2];
+  float* env[2];
+  void* binv[2];
+  void* D[2];
+  void* rho;
+  float* sign;
+  float* logpsi;
+  float* CH[2];
+  float* CP;
+  float* S;
+  float* CMF;
+  float* CG[8];
+  float* cot_u[2];
+  float* cot_env[2];
+  float* part;
+  float* tmp;
+  float* part2;
+  float* wo[2];     // orbital weights w_a, columns padded to ldu (float32)
+  float* cot;       // [Wc]
+  int ldu;
+  int64_t p2;       // two-electron parameters in all
+};
+
+static constexpr int kRowChunk = 64;
+
+static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
+  const int64_t R = Wc * p.n;
+  const size_t rb = p.fp64 ? 8 : 4;
+  int dmax = 0;
+  for (int l = 0; l < p.L; ++l) dmax = std::max(dmax, p.dinp[l]);
+  b.ldu = round_up(p.K * std::max(p.nu, p.nd), 32);
+  for (int l = 0; l <= p.L; ++l) b.H[l] = (float*)cv.take((size_t)R * (l == 0 ? p.dinp[0] : p.d1) * 4);
+  for (int l = 1; l <= p.L; ++l) b.PRE[l] = (float*)cv.take((size_t)R * p.d1 * 4);
+  b.PRE[0] = nullptr;
+  for (int l = 0; l < p.L; ++l) {
+    b.G[l] = (float*)cv.take((size_t)R * p.gwp[l] * 4);
+    b.Hbar[l] = (float*)cv.take((size_t)Wc * 2 * p.dinp[l] * 4);
+    b.CG[l] = (float*)cv.take((size_t)R * p.gwp[l] * 4);
+    b.h2[l] = l + 1 < p.L ? (float*)cv.take((size_t)R * p.n * p.ein[l] * 4) : nullptr;
+  }
+  b.Pm = (float*)cv.take((size_t)Wc * p.d1 * 4);
+  for (int a = 0; a < 2; ++a) {
+    const size_t m = (size_t)Wc * p.K * p.na(a) * p.na(a);
+    b.phi[a] = (float*)cv.take(m * 4);
+    b.u[a] = (float*)cv.take(m * 4);
+    b.env[a] = (float*)cv.take(m * 4);
+    b.binv[a] = cv.take(m * rb);
+    b.D[a] = cv.take((size_t)Wc * p.K * 2 * rb);
+    b.cot_u[a] = (float*)cv.take((size_t)Wc * p.na(a) * b.ldu * 4);
+    b.cot_env[a] = (float*)cv.take(m * 4);
+    b.wo[a] = (float*)cv.take((size_t)p.d1 * b.ldu * 4);
+  }
+  b.rho = cv.take((size_t)Wc * p.K * rb);
+  b.sign = (float*)cv.take((size_t)Wc * 4);
+  b.logpsi = (float*)cv.take((size_t)Wc * 4);
+  b.CH[0] = (float*)cv.take((size_t)R * p.d1 * 4);
+  b.CH[1] = (float*)cv.take((size_t)R * p.d1 * 4);
+  b.CP = (float*)cv.take((size_t)R * p.d1 * 4);
+  b.S = (float*)cv.take((size_t)Wc * p.d1 * 4);
+  b.CMF = (float*)cv.take((size_t)Wc * 2 * dmax * 4);
+  // X^T Y partials: splits(R) * K1 * N with K1 <= max(d1, dinp, 2 ein), N <= max(d1, K n_a)
+  const int64_t k1max = std::max<int64_t>(p.d1, std::max(dmax, 2 * std::max(4, p.d2)));
+  const int64_t nmax = std::max<int64_t>(p.d1, (int64_t)p.K * std::max(p.nu, p.nd));
+  const int64_t part_n = (int64_t)atb_splits(R) * k1max * nmax;
+  b.part = (float*)cv.take((size_t)part_n * 4);
+  b.p2 = 0;
+  for (int l = 0; l + 1 < p.L; ++l) b.p2 += (int64_t)p.ein[l] * p.d2 + p.d2;
+  b.part2 = (float*)cv.take((size_t)R * std::max<int64_t>(b.p2, 1) * 4);
+  // row-sum partials: column sums over R rows (d1, p2 or ldu columns) and
+  // the reduction of the X^T Y partials over their splits
+  const int64_t t1 = (int64_t)rowsum_chunks(R, kRowChunk) * std::max<int64_t>(std::max<int64_t>(p.d1, b.p2), b.ldu);
+  const int64_t t2 = (int64_t)rowsum_chunks(atb_splits(R), kRowChunk) * k1max * nmax;
+  b.tmp = (float*)cv.take((size_t)std::max(t1, t2) * 4);
+  b.cot = (float*)cv.take((size_t)Wc * 4);
+}
+
 static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   Carver cv{nullptr, 0};
   Bufs b;
   cv.take((size_t)p.pk_total * p.act);
+  if (entry == FN_ENTRY_GRAD_LOGPSI) {
+    AdjBufs ab;
+    carve_adjoint(p, Wc, cv, ab);
+    return cv.used;
+  }
   carve_forward(p, entry == FN_ENTRY_LOCAL_ENERGY ? JET : VALUE, Wc, cv, b, entry == FN_ENTRY_MCMC);
   return cv.used;
 }
@@ -411,6 +501,310 @@ static fn_status check_common(const fn_config* cfg, int32_t W, const float* pos,
   return FN_OK;
 }
 
+// value-only forward pass of one chunk that keeps what the adjoint needs
+static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, const float* nuc, const float* Z,
+                               const float* params, const void* pk, const AdjBufs& b, hipStream_t s) {
+  Bufs fb;
+  fb.pk = const_cast<void*>(pk);
+  FN_T(ST_ADJ_FWD, launch_features(false, pos, nuc, (int)Wc, p.n, p.N, 1, 1, b.H[0], p.dinp[0], s));
+  TwoElecArgs te;
+  memset(&te, 0, sizeof(te));
+  te.pos = pos;
+  te.params = params;
+  te.w_off = p.offW2;
+  te.c_off = p.offc2;
+  te.W = (int)Wc;
+  te.n = p.n;
+  te.n_up = p.nu;
+  te.L = p.L;
+  te.d2 = p.d2;
+  te.T = 1;
+  te.Tp = 1;
+  for (int l = 0; l < p.L; ++l) {
+    te.G[l] = b.G[l];
+    te.ldg[l] = p.gwp[l];
+    te.h2_out[l] = b.h2[l];
+  }
+  FN_T(ST_ADJ_FWD, launch_two_electron(false, te, s));
+  const int mode = p.bf16 ? MODE_BF16X3 : MODE_F32;
+  for (int l = 0; l < p.L; ++l) {
+    const int ldh = l == 0 ? p.dinp[0] : p.d1;
+    FN_T(ST_ADJ_FWD, launch_meanfield(false, b.H[l], ldh, (int)Wc, p.n, p.nu, 1, p.dinp[l], b.Hbar[l], s));
+    JetGemmArgs g;
+    memset(&g, 0, sizeof(g));
+    g.a0 = b.Hbar[l];
+    g.lda0 = 2 * p.dinp[l];
+    g.ka0 = 2 * p.dinp[l];
+    g.bt = wt(fb, p, p.pk_mf[l], false);
+    g.bt_lo = wt(fb, p, p.pk_mf[l], true);
+    g.ldb = p.ld_mf[l];
+    g.n_groups = (int)Wc;
+    g.rows_per = 1;
+    g.T = 1;
+    g.n_sub = 1;
+    g.n_all = 1;
+    g.N = p.d1;
+    g.c = b.Pm;
+    g.ldc = p.d1;
+    FN_T(ST_ADJ_FWD, launch_jet_gemm(mode, EPI_PLAIN, g, s));
+    JetGemmArgs h;
+    memset(&h, 0, sizeof(h));
+    h.a0 = b.H[l];
+    h.lda0 = ldh;
+    h.ka0 = p.dinp[l];
+    h.a1 = b.G[l];
+    h.lda1 = p.gwp[l];
+    h.ka1 = p.gwp[l];
+    h.bt = wt(fb, p, p.pk_main[l], false);
+    h.bt_lo = wt(fb, p, p.pk_main[l], true);
+    h.ldb = p.ld_main[l];
+    h.n_groups = (int)(Wc * p.n);
+    h.rows_per = 1;
+    h.T = 1;
+    h.n_sub = p.n;
+    h.n_all = p.n;
+    h.N = p.d1;
+    h.out = b.H[l + 1];
+    h.ldo = p.d1;
+    h.P = b.Pm;
+    h.ldp = p.d1;
+    h.bias = params + p.offb[l];
+    h.res = p.din[l] == p.d1;
+    h.pre_out = b.PRE[l + 1];
+    FN_T(ST_ADJ_FWD, launch_jet_gemm(mode, EPI_TANHJET, h, s));
+  }
+  for (int a = 0; a < 2; ++a) {
+    const int na = p.na(a);
+    if (na == 0) continue;
+    JetGemmArgs o;
+    memset(&o, 0, sizeof(o));
+    o.a0 = b.H[p.L];
+    o.lda0 = p.d1;
+    o.ka0 = p.d1;
+    o.bt = wt(fb, p, p.pk_orb[a], false);
+    o.bt_lo = wt(fb, p, p.pk_orb[a], true);
+    o.ldb = p.d1;
+    o.n_groups = (int)(Wc * na);
+    o.rows_per = 1;
+    o.T = 1;
+    o.n_sub = na;
+    o.n_all = p.n;
+    o.e_off = a == 0 ? 0 : p.nu;
+    o.N = p.K * na;
+    o.phi = b.phi[a];
+    o.pos = pos;
+    o.nuc = nuc;
+    o.n_nuc = p.N;
+    o.n_elec = p.n;
+    o.g_orb = params + p.offg[a];
+    o.pi = params + p.offpi[a];
+    o.sigma = params + p.offsg[a];
+    o.u_out = b.u[a];
+    o.env_out = b.env[a];
+    FN_T(ST_ADJ_FWD, launch_jet_gemm(mode, EPI_ORBITAL, o, s));
+    FN_T(ST_ADJ_DET, launch_det(p.fp64, b.phi[a], (int)Wc, p.K, na, 1, p.n3, b.D[a], 2, b.binv[a], s));
+  }
+  CombineArgs cb;
+  memset(&cb, 0, sizeof(cb));
+  cb.D[0] = b.D[0];
+  cb.D[1] = b.D[1];
+  cb.dstride = 2;
+  cb.na[0] = p.nu;
+  cb.na[1] = p.nd;
+  cb.W = (int)Wc;
+  cb.K = p.K;
+  cb.n = p.n;
+  cb.n3 = p.n3;
+  cb.N = p.N;
+  cb.jet = 0;
+  cb.pos = pos;
+  cb.nuc = nuc;
+  cb.Z = Z;
+  cb.sign = b.sign;
+  cb.logpsi = b.logpsi;
+  cb.rho = b.rho;
+  FN_T(ST_ADJ_DET, launch_combine(p.fp64, cb, s));
+  return FN_OK;
+}
+
+// X^T Y over R rows added into grad[off ...] (K1 x N block, row-major)
+static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol, int xs, int xa, int xe,
+                         const float* Y, int64_t ldy, int64_t R, int K1, int N, float* dst, hipStream_t s) {
+  AtbArgs a;
+  a.X = X;
+  a.ldx = ldx;
+  a.xcol = xcol;
+  a.xs = xs;
+  a.xa = xa;
+  a.xe = xe;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.R = R;
+  a.K1 = K1;
+  a.N = N;
+  a.part = b.part;
+  FN_T(ST_ADJ_REDUCE, launch_atb(a, s));
+  const int64_t cols = (int64_t)K1 * N;
+  FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part, atb_splits(R), (int)cols, cols, b.tmp, dst, kRowChunk, s));
+  return FN_OK;
+}
+
+// C [rows][K] times (rows of params) [N][ld] transposed: out[r][n] (=/+=) sum_k C[r][k] Wt[n][k]
+static fn_status gemm_cwt(const float* C, int ldc_in, int K, int64_t rows, const float* Wt, int ldw, int N,
+                          float* out, int ldo, int accum, int o_nsub, int o_nall, int o_eoff, int stage,
+                          hipStream_t s) {
+  JetGemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.a0 = C;
+  g.lda0 = ldc_in;
+  g.ka0 = K;
+  g.bt = Wt;
+  g.ldb = ldw;
+  g.n_groups = (int)rows;
+  g.rows_per = 1;
+  g.T = 1;
+  g.n_sub = 1;
+  g.n_all = 1;
+  g.N = N;
+  g.c = out;
+  g.ldc = ldo;
+  g.c_nsub = o_nsub;
+  g.c_nall = o_nall;
+  g.c_eoff = o_eoff;
+  g.c_accum = accum;
+  FN_T(stage, launch_jet_gemm(MODE_F32, EPI_PLAIN, g, s));
+  return FN_OK;
+}
+
+// reverse pass of one chunk with walker cotangents cot[Wc]; adds into grad
+static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const float* nuc, const float* params,
+                          const float* cot, const AdjBufs& b, float* grad, hipStream_t s) {
+  const int64_t R = Wc * p.n;
+  fn_status st;
+  float* CHc = b.CH[0];
+  float* CHn = b.CH[1];
+  // determinants -> orbitals -> envelope
+  for (int a = 0; a < 2; ++a) {
+    const int na = p.na(a);
+    if (na == 0) continue;
+    const int j0 = a == 0 ? 0 : p.nu;
+    FN_T(ST_ADJ_ORB, launch_adj_orbital_cot(p.fp64, b.binv[a], b.rho, cot, b.u[a], b.env[a], (int)Wc, p.K, na, b.ldu,
+                                            b.cot_u[a], b.cot_env[a], s));
+    FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a], (int)Wc,
+                                         p.K, na, j0, p.n, p.N, grad + p.offpi[a], grad + p.offsg[a], s));
+    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.cot_u[a], Wc * na, p.K * na, b.ldu, b.tmp, grad + p.offg[a], kRowChunk, s));
+    st = atb_add(b, b.H[p.L], p.d1, 0, na, p.n, j0, b.cot_u[a], b.ldu, Wc * na, p.d1, p.K * na, grad + p.offw[a], s);
+    if (st != FN_OK) return st;
+    // cot h^L of the electrons of spin a
+    st = gemm_cwt(b.cot_u[a], b.ldu, b.ldu, Wc * na, b.wo[a], b.ldu, p.d1, CHc, p.d1, 0, na, p.n, j0, ST_ADJ_ORB, s);
+    if (st != FN_OK) return st;
+  }
+  // one-electron layers, last to first
+  for (int l = p.L - 1; l >= 0; --l) {
+    const int din = p.din[l], ein = p.ein[l];
+    const float* V = params + p.offV[l];
+    FN_T(ST_ADJ_LAYERS, launch_adj_cp(CHc, b.PRE[l + 1], R * p.d1, b.CP, s));
+    FN_T(ST_ADJ_LAYERS, launch_adj_walker_sum(b.CP, (int)Wc, p.n, p.d1, b.S, s));
+    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.CP, R, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
+    const int ldh = l == 0 ? p.dinp[0] : p.d1;
+    // dA = sum h_i^T cp_i
+    st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s);
+    if (st != FN_OK) return st;
+    // dB^a = sum_w hbar^a_w^T S_w
+    for (int a = 0; a < 2; ++a) {
+      st = atb_add(b, b.Hbar[l], 2 * p.dinp[l], a * p.dinp[l], 0, 0, 0, b.S, p.d1, Wc, din, p.d1,
+                   grad + p.offV[l] + (int64_t)(din + a * din) * p.d1, s);
+      if (st != FN_OK) return st;
+    }
+    // dC = sum g_i^T cp_i (columns a ein + o)
+    st = atb_add(b, b.G[l], p.gwp[l], 0, 0, 0, 0, b.CP, p.d1, R, 2 * ein, p.d1, grad + p.offV[l] + (int64_t)3 * din * p.d1,
+                 s);
+    if (st != FN_OK) return st;
+    // cot g^l_i = cp_i [C^up; C^down]^T  (for the two-electron stream)
+    st = gemm_cwt(b.CP, p.d1, p.d1, R, V + (int64_t)3 * din * p.d1, p.d1, 2 * ein, b.CG[l], p.gwp[l], 0, 0, 0, 0,
+                  ST_ADJ_LAYERS, s);
+    if (st != FN_OK) return st;
+    if (l == 0) break;  // the input features carry no parameters
+    // cot h^l_i = cp_i A^T (+ cot h^{l+1}_i) + cot hbar^{a(i)} / n_a
+    const bool res = din == p.d1;
+    if (res) FN_T(ST_ADJ_LAYERS, launch_copy_f32(CHc, CHn, R * p.d1, s));
+    st = gemm_cwt(b.CP, p.d1, p.d1, R, V, p.d1, din, CHn, p.d1, res ? 1 : 0, 0, 0, 0, ST_ADJ_LAYERS, s);
+    if (st != FN_OK) return st;
+    st = gemm_cwt(b.S, p.d1, p.d1, Wc, V + (int64_t)din * p.d1, p.d1, 2 * din, b.CMF, 2 * din, 0, 0, 0, 0,
+                  ST_ADJ_LAYERS, s);
+    if (st != FN_OK) return st;
+    FN_T(ST_ADJ_LAYERS, launch_adj_scatter_mf(b.CMF, (int)Wc, p.n, p.nu, din, din, CHn, p.d1, s));
+    std::swap(CHc, CHn);
+  }
+  // two-electron stream
+  if (p.L >= 2) {
+    Adj2eArgs a2;
+    memset(&a2, 0, sizeof(a2));
+    a2.params = params;
+    int64_t po = 0;
+    for (int l = 0; l < p.L; ++l) {
+      if (l + 1 < p.L) {
+        a2.w_off[l] = p.offW2[l];
+        a2.c_off[l] = p.offc2[l];
+        a2.p_off[l] = po;
+        po += (int64_t)p.ein[l] * p.d2 + p.d2;
+        a2.h2[l] = b.h2[l];
+      }
+      a2.CG[l] = b.CG[l];
+      a2.ldcg[l] = p.gwp[l];
+    }
+    a2.p2 = b.p2;
+    a2.W = (int)Wc;
+    a2.n = p.n;
+    a2.n_up = p.nu;
+    a2.L = p.L;
+    a2.d2 = p.d2;
+    a2.part = b.part2;
+    FN_T(ST_ADJ_TWO_E, launch_adj_two_electron(a2, s));
+    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part2, R, (int)b.p2, b.p2, b.tmp, grad + p.offW2[0], kRowChunk, s));
+  }
+  return FN_OK;
+}
+
+// the whole adjoint over all chunks: grad = sum_w cot[w] d log|psi_w| / d theta.
+// cot_all: per-walker cotangents [W], or nullptr with e_loc/stats for the
+// VMC estimator ((E_L - mean) / W, computed chunk by chunk on the device).
+static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const float* nuc_pos, const float* nuc_charge,
+                             const float* params, const float* cot_all, const float* e_loc, const double* stats,
+                             float* grad, void* ws, size_t ws_bytes, hipStream_t s) {
+  const int64_t chunk = max_chunk(p, FN_ENTRY_GRAD_LOGPSI, ws_bytes, W);
+  if (chunk < 1) return FN_ERR_WORKSPACE;
+  Carver cv{(char*)ws, 0};
+  void* pk = cv.take((size_t)p.pk_total * p.act);
+  AdjBufs b;
+  carve_adjoint(p, chunk, cv, b);
+  fn_status st = pack(p, params, pk, s);
+  if (st != FN_OK) return st;
+  // orbital weights with zero-padded columns, float32, rows as stored
+  {
+    std::vector<int64_t> it;
+    for (int a = 0; a < 2; ++a) {
+      if (p.na(a) == 0) continue;
+      const int64_t off = (int64_t)((char*)b.wo[a] - (char*)b.wo[0]) / 4;
+      int64_t v[11] = {off, p.d1, b.ldu, 0, (int64_t)p.K * p.na(a), p.offw[a], 0, 0, 0, (int64_t)p.K * p.na(a), 0};
+      it.insert(it.end(), v, v + 11);
+    }
+    if (!it.empty()) FN_T(ST_PACK, launch_pack_weights(false, params, b.wo[0], 0, it.data(), (int)(it.size() / 11), s));
+  }
+  FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+  for (int64_t w0 = 0; w0 < W; w0 += chunk) {
+    const int64_t wc = std::min<int64_t>(chunk, W - w0);
+    const float* x = pos + w0 * p.n3;
+    st = forward_store(p, wc, x, nuc_pos, nuc_charge, params, pk, b, s);
+    if (st != FN_OK) return st;
+    const float* cot = cot_all ? cot_all + w0 : b.cot;
+    if (!cot_all) FN_T(ST_ADJ_REDUCE, launch_cot_from_stats(e_loc + w0, (int)wc, stats, W, b.cot, s));
+    st = backward(p, wc, x, nuc_pos, params, cot, b, grad, s);
+    if (st != FN_OK) return st;
+  }
+  return FN_OK;
+}
+
 }  // namespace fn
 
 using namespace fn;
@@ -600,7 +994,13 @@ fn_status ferminet_grad_logpsi(const fn_config* cfg, int32_t W, const float* pos
   fn_status st = check_common(cfg, W, pos, spins, nuc_pos, nuc_charge, params, workspace, p);
   if (st != FN_OK) return st;
   if (!cotangent || !grad) return FN_ERR_NULL;
-  return FN_ERR_UNSUPPORTED;
+  if (W == 0) {
+    const hipStream_t s = stream;
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+    return FN_OK;
+  }
+  return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, cotangent, nullptr, nullptr, grad, workspace,
+                     workspace_bytes, stream);
 }
 
 fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
@@ -611,7 +1011,12 @@ fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos,
   fn_status st = check_common(cfg, W, pos, spins, nuc_pos, nuc_charge, params, workspace, p);
   if (st != FN_OK) return st;
   if (!e_loc || !e_stats || !grad) return FN_ERR_NULL;
-  return FN_ERR_UNSUPPORTED;
+  if (W == 0) return FN_ERR_ARG;  // the batch mean of an empty batch is undefined
+  if (max_chunk(p, FN_ENTRY_GRAD_LOGPSI, workspace_bytes, W) < 1) return FN_ERR_WORKSPACE;
+  const hipStream_t s = stream;
+  FN_T(ST_ADJ_REDUCE, launch_energy_stats(e_loc, W, e_stats, nullptr, s));
+  return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, nullptr, e_loc, e_stats, grad, workspace,
+                     workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,440 @@
+// Hand-written adjoint of log|psi| with respect to the parameters.
+//
+// Reverse mode over a value-only forward pass (no tangents are stored; the
+// layer values are recomputed by that pass).  With cotangent c_w of
+// log|psi_w|:
+//   log|psi| = log|sum_k P_k|       -> d/d log|P_k| = rho_k = P_k / psi
+//   log|det B| (B[j][i] = phi_i(r_j)) -> d/dB[j][i] = (B^-1)[i][j]
+//   phi = u * env                    -> cot u = cot phi * env, cot env = cot phi * u
+//   u = h^L_j . w[:, ki] + g[ki]      -> dw, dg, cot h^L_j
+//   env = sum_m pi exp(-|s| d)        -> dpi, dsigma
+//   h^{l+1} = tanh(pre) (+ h^l)       -> cot pre = cot h^{l+1} sech^2(pre)
+//   pre_i = h_i A + hbar B + g_i C + b -> dA, dB, dC, db and the cotangents
+//                                        of h_i, hbar (spread over the
+//                                        electrons of its spin) and g_i
+//                                        (spread over the pair features)
+// and the same for the two-electron layers.  Every reduction over walkers,
+// electrons or pairs is done in a fixed order (split partial sums reduced
+// in order): the gradient is bitwise reproducible.
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace fn {
+
+// ---------------------------------------------- determinant / orbital cotangents
+// cot_u[(w na + j) * ldu + k na + i] = c_w rho_k Binv[w][k][i][j] env[w][k][j][i]
+// (zero in the padding columns), cot_env[w][k][j][i] = c_w rho_k Binv[..][i][j] u[..]
+template <class R>
+__global__ void adj_orbital_cot_kernel(const R* binv, const R* rho, const float* cot, const float* u,
+                                       const float* env, int W, int K, int na, int ldu, float* cot_u,
+                                       float* cot_env) {
+  const int64_t total = (int64_t)W * na * ldu;
+  const int nsq = na * na;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % ldu);
+    const int64_t row = idx / ldu;
+    const int j = (int)(row % na);
+    const int64_t w = row / na;
+    float cu = 0.0f;
+    if (col < K * na) {
+      const int k = col / na, i = col % na;
+      const int64_t m = w * K + k;
+      const R cb = (R)cot[w] * rho[m] * binv[m * nsq + i * na + j];
+      const int64_t e = m * nsq + j * na + i;
+      cu = (float)(cb * (R)env[e]);
+      cot_env[e] = (float)(cb * (R)u[e]);
+    }
+    cot_u[idx] = cu;
+  }
+}
+
+hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, const float* cot, const float* u,
+                                  const float* env, int W, int K, int na, int ldu, float* cot_u, float* cot_env,
+                                  hipStream_t s) {
+  const int64_t total = (int64_t)W * na * ldu;
+  if (total <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  if (fp64)
+    hipLaunchKernelGGL(adj_orbital_cot_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)binv,
+                       (const double*)rho, cot, u, env, W, K, na, ldu, cot_u, cot_env);
+  else
+    hipLaunchKernelGGL(adj_orbital_cot_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)binv,
+                       (const float*)rho, cot, u, env, W, K, na, ldu, cot_u, cot_env);
+  return hipGetLastError();
+}
+
+// block reduction of 256 values (fixed order)
+__device__ inline float block_sum256(float v, float* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  float r = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return r;
+}
+
+// envelope parameters: one block per (orbital column (k,i), nucleus m):
+//   dpi    += sum_{w,j} cot_env exp(-|s| d_jm)
+//   dsigma += sum_{w,j} cot_env pi exp(-|s| d_jm) (-sign(s) d_jm)
+__global__ __launch_bounds__(256) void adj_env_grad_kernel(const float* cot_env, const float* pos, const float* nuc,
+                                                           const float* pi, const float* sigma, int W, int K,
+                                                           int na, int j0, int n, int N, float* dpi,
+                                                           float* dsigma) {
+  __shared__ float sh[4];
+  const int col = blockIdx.x / N, m = blockIdx.x % N;
+  const int k = col / na, i = col % na;
+  const float p = pi[col * N + m], sg = sigma[col * N + m], s = fabsf(sg);
+  const float sgn = sg < 0.0f ? -1.0f : 1.0f;
+  float api = 0.0f, asg = 0.0f;
+  const int64_t rows = (int64_t)W * na;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) {
+    const int j = (int)(r % na);
+    const int64_t w = r / na;
+    const float* x = pos + (w * n + j0 + j) * 3;
+    const float dx = x[0] - nuc[3 * m], dy = x[1] - nuc[3 * m + 1], dz = x[2] - nuc[3 * m + 2];
+    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float e = expf(-s * d);
+    const float c = cot_env[((w * K + k) * na + j) * na + i];
+    api += c * e;
+    asg += c * p * e * (-sgn * d);
+  }
+  api = block_sum256(api, sh);
+  asg = block_sum256(asg, sh);
+  if (threadIdx.x == 0) {
+    dpi[col * N + m] += api;
+    dsigma[col * N + m] += asg;
+  }
+}
+
+hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
+                               const float* sigma, int W, int K, int na, int j0, int n, int N, float* dpi,
+                               float* dsigma, hipStream_t s) {
+  if (na <= 0 || W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adj_env_grad_kernel, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W, K, na,
+                     j0, n, N, dpi, dsigma);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- X^T Y
+// part[split][k][nn] = sum_{r in split} X[map(r)][xcol + k] * Y[r][nn],
+// 64 x 64 tiles on v_mfma_f32_16x16x4_f32, 256 rows per split and step 16.
+constexpr int ATB_ROWS = 256;
+
+__global__ __launch_bounds__(256) void atb_kernel(AtbArgs a) {
+  __shared__ float Xs[16][64 + 4];
+  __shared__ float Ys[16][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int tk = blockIdx.x, tn = blockIdx.y, split = blockIdx.z;
+  const int k0 = tk * 64, n0 = tn * 64;
+  const int64_t r_begin = (int64_t)split * ATB_ROWS;
+  const int64_t r_end = std::min<int64_t>(r_begin + ATB_ROWS, a.R);
+  floatx4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid / 16, lc = (tid % 16) * 4;  // loader: row 0..15, 4 columns
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += 16) {
+    const int64_t r = r0 + lr;
+    float xv[4] = {0.f, 0.f, 0.f, 0.f}, yv[4] = {0.f, 0.f, 0.f, 0.f};
+    if (r < r_end) {
+      const int64_t mr = a.xs ? (r / a.xs) * a.xa + a.xe + r % a.xs : r;
+      for (int q = 0; q < 4; ++q) {
+        if (k0 + lc + q < a.K1) xv[q] = a.X[mr * a.ldx + a.xcol + k0 + lc + q];
+        if (n0 + lc + q < a.N) yv[q] = a.Y[r * a.ldy + n0 + lc + q];
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      Xs[lr][lc + q] = xv[q];
+      Ys[lr][lc + q] = yv[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int rr = ks * 4 + (lane >> 4);
+      float af[2], bf[2];
+      for (int i = 0; i < 2; ++i) af[i] = Xs[rr][wm * 32 + i * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) bf[j] = Ys[rr][wn * 32 + j * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  float* out = a.part + (int64_t)split * a.K1 * a.N;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int q = 0; q < 4; ++q) {
+        const int k = k0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+        const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (k < a.K1 && nn < a.N) out[(int64_t)k * a.N + nn] = acc[i][j][q];
+      }
+}
+
+int atb_splits(int64_t R) { return (int)((R + ATB_ROWS - 1) / ATB_ROWS); }
+
+hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
+  if (a.R <= 0 || a.K1 <= 0 || a.N <= 0) return hipSuccess;
+  dim3 grid((a.K1 + 63) / 64, (a.N + 63) / 64, atb_splits(a.R));
+  hipLaunchKernelGGL(atb_kernel, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ row sums
+// pass 1: part[y][c] = sum_{r in chunk y} src[r * lds + c]
+__global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, int64_t lds, int chunk, float* part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
+  const int64_t r1 = std::min<int64_t>(r0 + chunk, rows);
+  float acc = 0.0f;
+  for (int64_t r = r0; r < r1; ++r) acc += src[r * lds + c];
+  part[(int64_t)blockIdx.y * cols + c] = acc;
+}
+// pass 2: dst[c] += sum_y part[y][c]
+__global__ void rowsum_final_kernel(const float* part, int ny, int cols, float* dst) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float acc = 0.0f;
+  for (int y = 0; y < ny; ++y) acc += part[(int64_t)y * cols + c];
+  dst[c] += acc;
+}
+
+int rowsum_chunks(int64_t rows, int chunk) { return (int)((rows + chunk - 1) / chunk); }
+
+hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
+                             int chunk, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int ny = rowsum_chunks(rows, chunk);
+  hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, chunk,
+                     tmp);
+  hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, tmp, ny, cols, dst);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- elementwise
+// CP[r][c] = CH[r][c] * sech^2(PRE[r][c])
+__global__ void adj_cp_kernel(const float* ch, const float* pre, int64_t total, float* cp) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    cp[i] = ch[i] * sech2f(pre[i]);
+}
+
+hipError_t launch_adj_cp(const float* ch, const float* pre, int64_t total, float* cp, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(adj_cp_kernel, dim3(grid), dim3(256), 0, s, ch, pre, total, cp);
+  return hipGetLastError();
+}
+
+// S[w][c] = sum_{i < n} CP[(w n + i)][c]
+__global__ void adj_walker_sum_kernel(const float* cp, int W, int n, int cols, float* S) {
+  const int64_t total = (int64_t)W * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx % cols);
+    const int64_t w = idx / cols;
+    float acc = 0.0f;
+    for (int i = 0; i < n; ++i) acc += cp[(w * n + i) * cols + c];
+    S[idx] = acc;
+  }
+}
+
+hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float* S, hipStream_t s) {
+  const int64_t total = (int64_t)W * cols;
+  if (total <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(adj_walker_sum_kernel, dim3(grid), dim3(256), 0, s, cp, W, n, cols, S);
+  return hipGetLastError();
+}
+
+// CH[(w n + j)][f] += CMF[w][a(j) ldm_half + f] / n_a  for f < din
+__global__ void adj_scatter_mf_kernel(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh) {
+  const int64_t total = (int64_t)W * n * din;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(idx % din);
+    const int64_t g = idx / din;
+    const int j = (int)(g % n);
+    const int64_t w = g / n;
+    const int al = j < n_up ? 0 : 1;
+    const int na = al == 0 ? n_up : n - n_up;
+    ch[g * ldh + f] += cmf[w * 2 * half + al * half + f] / (float)na;
+  }
+}
+
+hipError_t launch_adj_scatter_mf(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh,
+                                 hipStream_t s) {
+  const int64_t total = (int64_t)W * n * din;
+  if (total <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(adj_scatter_mf_kernel, dim3(grid), dim3(256), 0, s, cmf, W, n, n_up, din, half, ch, ldh);
+  return hipGetLastError();
+}
+
+__global__ void fill_f32_kernel(float* p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_f32_kernel, dim3(grid), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void copy_f32_kernel(const float* src, float* dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(copy_f32_kernel, dim3(grid), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- two-electron backward
+// One block per electron i of walker w.  For l = L-2 .. 0, with Ct the
+// cotangent of h^{l+1}_ij (all j):
+//   pre = h^l_ij W_l + c_l ; cp = Ct sech^2(pre)
+//   part_W[k][o] = sum_j h^l_ij[k] cp_j[o] ; part_c[o] = sum_j cp_j[o]
+//   Ct <- cp W_l^T (+ Ct when widths match) + (1/n_a) cot g^{a(j),l}_i
+// starting from Ct = (1/n_a) cot g^{a(j),L-1}_i.  The parameter partials of
+// the block go to part[(w n + i)][...] in the layout of the W_l, c_l blocks.
+__global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a) {
+  extern __shared__ float sh[];
+  const int n = a.n, d2 = a.d2, L = a.L;
+  const int dm = d2 > 4 ? d2 : 4;
+  float* Hs = sh;             // [n][dm]   h^l_ij
+  float* Ct = Hs + n * dm;    // [n][dm]   cotangent of h^{l+1}_ij
+  float* Cp = Ct + n * dm;    // [n][dm]
+  float* Ws = Cp + n * dm;    // [dm][d2] + c[d2]
+  const int tid = threadIdx.x;
+  const int64_t g = blockIdx.x;  // w n + i
+  const int nu = a.n_up;
+  float* part = a.part + g * a.p2;
+  // Ct = mean-field cotangent of layer L-1
+  {
+    const int ein = L - 1 == 0 ? 4 : d2;
+    const float* cg = a.CG[L - 1] + g * a.ldcg[L - 1];
+    for (int idx = tid; idx < n * dm; idx += blockDim.x) {
+      const int j = idx / dm, o = idx % dm;
+      const int al = j < nu ? 0 : 1, na = al == 0 ? nu : n - nu;
+      Ct[idx] = o < ein ? cg[al * ein + o] / (float)na : 0.0f;
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int ein = l == 0 ? 4 : d2;
+    __syncthreads();
+    for (int idx = tid; idx < n * dm; idx += blockDim.x) {
+      const int j = idx / dm, k = idx % dm;
+      Hs[idx] = k < ein ? a.h2[l][(g * n + j) * ein + k] : 0.0f;
+    }
+    for (int idx = tid; idx < ein * d2 + d2; idx += blockDim.x)
+      Ws[idx] = idx < ein * d2 ? a.params[a.w_off[l] + idx] : a.params[a.c_off[l] + idx - ein * d2];
+    __syncthreads();
+    // cp = Ct * sech^2(h W + c)
+    for (int idx = tid; idx < n * d2; idx += blockDim.x) {
+      const int j = idx / d2, o = idx % d2;
+      float pre = Ws[ein * d2 + o];
+      for (int k = 0; k < ein; ++k) pre += Hs[j * dm + k] * Ws[k * d2 + o];
+      Cp[j * dm + o] = Ct[j * dm + o] * sech2f(pre);
+    }
+    __syncthreads();
+    // parameter partials
+    for (int idx = tid; idx < ein * d2 + d2; idx += blockDim.x) {
+      float acc = 0.0f;
+      if (idx < ein * d2) {
+        const int k = idx / d2, o = idx % d2;
+        for (int j = 0; j < n; ++j) acc += Hs[j * dm + k] * Cp[j * dm + o];
+      } else {
+        const int o = idx - ein * d2;
+        for (int j = 0; j < n; ++j) acc += Cp[j * dm + o];
+      }
+      part[a.p_off[l] + idx] = acc;
+    }
+    // Ct <- cp W^T (+ residual) + mean-field cotangent of layer l
+    const float* cg = a.CG[l] + g * a.ldcg[l];
+    const bool res = ein == d2;
+    float newc[4];
+    int cnt = 0;
+    for (int idx = tid; idx < n * dm; idx += blockDim.x, ++cnt) {
+      const int j = idx / dm, k = idx % dm;
+      float v = 0.0f;
+      if (k < ein) {
+        for (int o = 0; o < d2; ++o) v += Cp[j * dm + o] * Ws[k * d2 + o];
+        if (res) v += Ct[idx];
+        const int al = j < nu ? 0 : 1, na = al == 0 ? nu : n - nu;
+        v += cg[al * ein + k] / (float)na;
+      }
+      newc[cnt] = v;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int idx = tid; idx < n * dm; idx += blockDim.x, ++cnt) Ct[idx] = newc[cnt];
+  }
+}
+
+hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s) {
+  if (a.W <= 0 || a.L < 2) return hipSuccess;
+  const int dm = a.d2 > 4 ? a.d2 : 4;
+  if (a.n * dm > 4 * 256) return hipErrorInvalidValue;  // newc[] holds 4 entries per thread
+  const size_t shmem = ((size_t)3 * a.n * dm + (size_t)dm * a.d2 + a.d2) * sizeof(float);
+  hipLaunchKernelGGL(adj_two_electron_kernel, dim3((unsigned)((int64_t)a.W * a.n)), dim3(256), shmem, s, a);
+  return hipGetLastError();
+}
+
+// ----------------------------------------- energy statistics and cotangent
+// cot[w] = (e[w] - mean) / W_total for the walkers of one chunk
+__global__ void cot_from_stats_kernel(const float* e, int Wc, const double* stats, int W_total, float* cot) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < Wc) cot[w] = (float)(((double)e[w] - stats[0]) / (double)W_total);
+}
+
+hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s) {
+  if (Wc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cot_from_stats_kernel, dim3((Wc + 255) / 256), dim3(256), 0, s, e, Wc, stats, W_total, cot);
+  return hipGetLastError();
+}
+
+// one block: mean and population variance of e_loc in float64 (two passes,
+// fixed order)
+__global__ __launch_bounds__(256) void energy_stats_kernel(const float* e, int W, double* stats, float* cot) {
+  __shared__ double sh[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int w = tid; w < W; w += 256) s += (double)e[w];
+  sh[tid] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] += sh[tid + off];
+    __syncthreads();
+  }
+  const double mean = sh[0] / (double)W;
+  __syncthreads();
+  double v = 0.0;
+  for (int w = tid; w < W; w += 256) {
+    const double d = (double)e[w] - mean;
+    v += d * d;
+  }
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) sh[tid] += sh[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    stats[0] = mean;
+    stats[1] = sh[0] / (double)W;
+  }
+  if (cot)
+    for (int w = tid; w < W; w += 256) cot[w] = (float)(((double)e[w] - mean) / (double)W);
+}
+
+hipError_t launch_energy_stats(const float* e, int W, double* stats, float* cot, hipStream_t s) {
+  if (W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(energy_stats_kernel, dim3(1), dim3(256), 0, s, e, W, stats, cot);
+  return hipGetLastError();
+}
+
+}  // namespace fn

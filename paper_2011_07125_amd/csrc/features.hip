@@ -19,11 +19,12 @@ namespace fn {
 // ------------------------------------------------------------ weight packing
 struct PackPlan {
   int n_items;
-  // dst_off, N, ldb, k0, len0, src0, k1, len1, src1, src_ld
-  int64_t it[24][10];
+  // dst_off, N, ldb, k0, len0, src0, k1, len1, src1, src_ld, transpose
+  int64_t it[32][11];
 };
 
-// packed[n][k] = params[src + (k - k0) * src_ld + n] for k in one of the two
+// packed[n][k] = params[src + (k - k0) * src_ld + n] (transpose) or
+// params[src + n * src_ld + (k - k0)] for k in one of the two
 // segments, 0 elsewhere; float32, or split into bfloat16 hi and lo planes
 template <bool SPLIT>
 __global__ void pack_weights_kernel(const float* params, void* dst, int64_t plane, PackPlan plan) {
@@ -34,8 +35,8 @@ __global__ void pack_weights_kernel(const float* params, void* dst, int64_t plan
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     int64_t n = idx / ldb, k = idx % ldb;
     float v = 0.0f;
-    if (k >= p[3] && k < p[3] + p[4]) v = params[p[5] + (k - p[3]) * p[9] + n];
-    else if (k >= p[6] && k < p[6] + p[7]) v = params[p[8] + (k - p[6]) * p[9] + n];
+    if (k >= p[3] && k < p[3] + p[4]) v = params[p[5] + (p[10] ? (k - p[3]) * p[9] + n : n * p[9] + (k - p[3]))];
+    else if (k >= p[6] && k < p[6] + p[7]) v = params[p[8] + (p[10] ? (k - p[6]) * p[9] + n : n * p[9] + (k - p[6]))];
     if constexpr (SPLIT) {
       uint16_t* d = reinterpret_cast<uint16_t*>(dst);
       const uint16_t h = f32_to_bf16_bits(v);
@@ -49,11 +50,11 @@ __global__ void pack_weights_kernel(const float* params, void* dst, int64_t plan
 
 hipError_t launch_pack_weights(bool split, const float* params, void* dst, int64_t plane, const int64_t* plan,
                                int n_items, hipStream_t s) {
-  if (n_items > 24) return hipErrorInvalidValue;
+  if (n_items > 32) return hipErrorInvalidValue;
   PackPlan pp;
   pp.n_items = n_items;
   for (int i = 0; i < n_items; ++i)
-    for (int j = 0; j < 10; ++j) pp.it[i][j] = plan[i * 10 + j];
+    for (int j = 0; j < 11; ++j) pp.it[i][j] = plan[i * 11 + j];
   dim3 grid(64, n_items);
   if (split) hipLaunchKernelGGL(pack_weights_kernel<true>, grid, dim3(256), 0, s, params, dst, plane, pp);
   else hipLaunchKernelGGL(pack_weights_kernel<false>, grid, dim3(256), 0, s, params, dst, plane, pp);

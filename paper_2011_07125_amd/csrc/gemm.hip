@@ -261,7 +261,12 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       int r = p / BN, col = p % BN;
       int e = r / rows_per, t = r % rows_per;
       int g = g0 + e, gc = n0 + col;
-      if (g < a.n_groups && gc < a.N) a.c[((size_t)g * rows_per + t) * a.ldc + gc] = Cs[r * LDC + col];
+      if (g < a.n_groups && gc < a.N) {
+        const long og = a.c_nsub ? (long)(g / a.c_nsub) * a.c_nall + a.c_eoff + (g % a.c_nsub) : (long)g;
+        float* dst = a.c + ((size_t)og * rows_per + t) * a.ldc + gc;
+        const float v = Cs[r * LDC + col];
+        *dst = a.c_accum ? *dst + v : v;
+      }
     }
   } else if constexpr (EPI == EPI_TANHJET) {
     float* out = reinterpret_cast<float*>(a.out);
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       float dy = sech2f(u0);
       float r0 = a.res ? res[orow * a.lda0 + gc] : 0.0f;
       out[orow * a.ldo + gc] = y + r0;
-      if (a.y_out) a.y_out[(size_t)g * a.N + gc] = y;
+      if (a.pre_out) a.pre_out[(size_t)g * a.N + gc] = u0;
       if (T > 1) {
         float s2 = 0.0f;
         for (int t = 1; t < T - 1; ++t) {

@@ -24,17 +24,19 @@ struct JetGemmArgs {
   int n_groups, rows_per, T;
   int n_sub, n_all, e_off;
   int N;
-  // EPI_PLAIN: c[(g * rows_per + t) * ldc + col]
+  // EPI_PLAIN: c[(og * rows_per + t) * ldc + col] (= or += when c_accum) with
+  //   og = g, or (g / c_nsub) * c_nall + c_eoff + g % c_nsub when c_nsub > 0
   float* c; int ldc;
+  int c_nsub, c_nall, c_eoff, c_accum;
   // EPI_TANHJET: out[(g * rows_per + t) * ldo + col] (activation type), with
   //   P[((g / n_all) * rows_per + t) * ldp + col] added to every row, bias on
-  //   the value row, residual from segment 0 when res != 0; y_out[g * N + col]
-  //   receives tanh of the value row when not NULL
+  //   the value row, residual from segment 0 when res != 0; pre_out[g * N + col]
+  //   receives the pre-activation of the value row when not NULL
   void* out; int ldo;
   const float* P; int ldp;
   const float* bias;
   int res;
-  float* y_out;
+  float* pre_out;
   // EPI_ORBITAL: phi[((w * K + k) * T + t) * n_sub^2 + j * n_sub + i] with
   //   w = g / n_sub, j = g % n_sub, col = k * n_sub + i
   float* phi;
@@ -89,5 +91,48 @@ hipError_t launch_accept_offset(float* pos, const float* prop, float* logpsi, fl
                                 const float* sg_new, int32_t* n_acc, int W, int n3, uint64_t seed, uint64_t step,
                                 const float* uniforms, int first, uint32_t w_base, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t s);
+
+// ---- adjoint (adjoint.hip)
+// part[split][k][nn] = sum over the rows r of the split of
+//   X[mr * ldx + xcol + k] * Y[r * ldy + nn],  k < K1, nn < N,
+// mr = r, or (r / xs) * xa + xe + r % xs when xs > 0
+struct AtbArgs {
+  const float* X; int64_t ldx; int xcol; int xs, xa, xe;
+  const float* Y; int64_t ldy;
+  int64_t R; int K1, N;
+  float* part;
+};
+int atb_splits(int64_t R);
+hipError_t launch_atb(const AtbArgs& a, hipStream_t s);
+int rowsum_chunks(int64_t rows, int chunk);
+// dst[c] += sum_r src[r * lds + c] in a fixed order (tmp: rowsum_chunks(rows, chunk) * cols floats)
+hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
+                             int chunk, hipStream_t s);
+hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, const float* cot, const float* u,
+                                  const float* env, int W, int K, int na, int ldu, float* cot_u, float* cot_env,
+                                  hipStream_t s);
+hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
+                               const float* sigma, int W, int K, int na, int j0, int n, int N, float* dpi,
+                               float* dsigma, hipStream_t s);
+hipError_t launch_adj_cp(const float* ch, const float* pre, int64_t total, float* cp, hipStream_t s);
+hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float* S, hipStream_t s);
+hipError_t launch_adj_scatter_mf(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh,
+                                 hipStream_t s);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+struct Adj2eArgs {
+  const float* params;
+  int64_t w_off[8], c_off[8];  // offsets of W_l, c_l in params
+  int64_t p_off[8];            // offsets of W_l within the partial row
+  int64_t p2;                  // floats per partial row (all two-electron parameters)
+  const float* h2[8];          // h^l_ij values [w n + i][n][ein_l], l < L-1
+  const float* CG[8];          // cot g^l_i [w n + i][ldcg_l] (columns a ein_l + o)
+  int ldcg[8];
+  int W, n, n_up, L, d2;
+  float* part;                 // [W n][p2]
+};
+hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s);
+hipError_t launch_energy_stats(const float* e, int W, double* stats, float* cot, hipStream_t s);
+hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s);
 
 }  // namespace fn

@@ -128,7 +128,8 @@ def workspace(cfg: dict, W: int, entry: int, precision=None, device=None, max_ch
         _WS.pop(key, None)
         buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
         _WS[key] = buf
-    return buf
+    # exactly the requested size, so that a smaller max_chunk takes effect
+    return buf[:nbytes]
 
 
 def release_workspaces():
