@@ -164,7 +164,7 @@ def main():
     achieved = flops_per_launch / (jet_launch_ms * 1e-3) / 1e12 if jet_launch_ms else None
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
             "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": None,
-            "kernel": "jet_gemm_kernel<MODE_BF16X3,128,128,EPI_TANHJET> (one-electron layer)",
+            "kernel": "layer_gemm_kernel<MODE_BF16X3,128,256> (one-electron layer, tanh-jet epilogue)",
             "flops_per_launch": flops_per_launch, "avg_launch_ms": jet_launch_ms}
     golden = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.npz")
     if os.path.exists(golden):

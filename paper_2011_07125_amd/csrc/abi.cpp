@@ -46,7 +46,8 @@ static fn_status make_plan(const fn_config* c, Plan& p) {
   {
     // the two-electron stream keeps one electron's 8-row pair jets in LDS
     const int d2p = p.d2 <= 4 ? 4 : p.d2 <= 8 ? 8 : p.d2 <= 16 ? 16 : p.d2 <= 32 ? 32 : 64;
-    if ((p.n * 8 * d2p + d2p * d2p + d2p) * 4 > 65536) return FN_ERR_CONFIG;
+    // (slot rows of stride d2p + 1, weights aligned to 16 bytes)
+    if ((p.n * 8 * (d2p + 1) + 4 + d2p * d2p + d2p) * 4 > 65536) return FN_ERR_CONFIG;
   }
   p.bf16 = c->precision == FN_PREC_BF16;
   p.fp64 = c->precision != FN_PREC_FP32;
@@ -452,6 +453,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     o.e_off = a == 0 ? 0 : p.nu;
     o.N = p.K * na;
     o.phi = b.phi[a];
+    o.phi_M = det_uses_small(na) ? Wc * p.K : 0;
     o.pos = pos;
     o.nuc = nuc;
     o.n_nuc = p.N;
@@ -592,6 +594,7 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
     o.e_off = a == 0 ? 0 : p.nu;
     o.N = p.K * na;
     o.phi = b.phi[a];
+    o.phi_M = det_uses_small(na) ? Wc * p.K : 0;
     o.pos = pos;
     o.nuc = nuc;
     o.n_nuc = p.N;

@@ -183,22 +183,34 @@ hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
 
 // ------------------------------------------------------------ row sums
 // pass 1: part[y][c] = sum_{r in chunk y} src[r * lds + c]
-__global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, int64_t lds, int chunk, float* part) {
+// (four interleaved accumulators, combined in a fixed order)
+__global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, int64_t lds, int64_t chunk,
+                                      float* part) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   const int64_t r0 = (int64_t)blockIdx.y * chunk;
   const int64_t r1 = std::min<int64_t>(r0 + chunk, rows);
-  float acc = 0.0f;
-  for (int64_t r = r0; r < r1; ++r) acc += src[r * lds + c];
-  part[(int64_t)blockIdx.y * cols + c] = acc;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int64_t r = r0;
+  for (; r + 3 < r1; r += 4) {
+    a0 += src[r * lds + c];
+    a1 += src[(r + 1) * lds + c];
+    a2 += src[(r + 2) * lds + c];
+    a3 += src[(r + 3) * lds + c];
+  }
+  for (; r < r1; ++r) a0 += src[r * lds + c];
+  part[(int64_t)blockIdx.y * cols + c] = (a0 + a1) + (a2 + a3);
 }
-// pass 2: dst[c] += sum_y part[y][c]
-__global__ void rowsum_final_kernel(const float* part, int ny, int cols, float* dst) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// pass 2: dst[c] += sum_y part[y][c]; 64 columns x 4 slices of y per block
+__global__ __launch_bounds__(256) void rowsum_final_kernel(const float* part, int ny, int cols, float* dst) {
+  __shared__ float sh[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
   float acc = 0.0f;
-  for (int y = 0; y < ny; ++y) acc += part[(int64_t)y * cols + c];
-  dst[c] += acc;
+  if (c < cols)
+    for (int y = sl; y < ny; y += 4) acc += part[(int64_t)y * cols + c];
+  sh[sl][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (sl == 0 && c < cols) dst[c] += (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 
 int rowsum_chunks(int64_t rows, int chunk) { return (int)((rows + chunk - 1) / chunk); }
@@ -206,10 +218,14 @@ int rowsum_chunks(int64_t rows, int chunk) { return (int)((rows + chunk - 1) / c
 hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
                              int chunk, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  const int ny = rowsum_chunks(rows, chunk);
-  hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, chunk,
+  // at most 128 partial rows (never more than the tmp sizing of
+  // rowsum_chunks(rows, chunk) assumes)
+  int ny = std::min(rowsum_chunks(rows, chunk), 128);
+  const int64_t ch = (rows + ny - 1) / ny;
+  ny = (int)((rows + ch - 1) / ch);
+  hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, ch,
                      tmp);
-  hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, tmp, ny, cols, dst);
+  hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 63) / 64), dim3(256), 0, s, tmp, ny, cols, dst);
   return hipGetLastError();
 }
 

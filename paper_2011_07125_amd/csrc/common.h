@@ -25,6 +25,15 @@ __host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
   return __builtin_bit_cast(float, (uint32_t)b << 16);
 }
 
+// x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), both rounded to
+// nearest even by the hardware conversion (v_cvt_pk_bf16_f32 on gfx950)
+__device__ inline void split_bf16(float x, uint16_t* h, uint16_t* l) {
+  const __bf16 hb = (__bf16)x;
+  const __bf16 lb = (__bf16)(x - (float)hb);
+  *h = __builtin_bit_cast(uint16_t, hb);
+  *l = __builtin_bit_cast(uint16_t, lb);
+}
+
 // load/store of one element of the activation type (float or bf16_t) as fp32
 __device__ inline float ld_act(const float* p) { return *p; }
 __device__ inline float ld_act(const bf16_t* p) { return bf16_bits_to_f32(p->bits); }
@@ -37,6 +46,17 @@ __device__ inline float sech2f(float u) {
   const float e = expf(-2.0f * fabsf(u));
   const float d = 1.0f + e;
   return 4.0f * e / (d * d);
+}
+
+// tanh(u) and sech^2(u) from one expm1: with m = e^{-2|u|} - 1,
+//   tanh|u| = -m / (2 + m),  sech^2 u = 4 (1 + m) / (2 + m)^2
+// (no cancellation for small |u| or once tanh saturates)
+__device__ inline void tanh_sech2f(float u, float* th, float* s2) {
+  const float m = expm1f(-2.0f * fabsf(u));
+  const float d = 2.0f + m;
+  const float t = -m / d;
+  *th = u < 0.0f ? -t : t;
+  *s2 = 4.0f * (1.0f + m) / (d * d);
 }
 
 template <class T> __device__ inline T wave_sum(T v) {

@@ -194,10 +194,155 @@ __global__ __launch_bounds__(64) void det_kernel(const float* phi, int K, int na
   }
 }
 
+// Small matrices (n_a <= 6): one thread per matrix, everything in registers.
+// The orbital jets are stored matrix-index fastest, phi[(t n_a^2 + e) M + mat]
+// with M = W K, so that consecutive threads read consecutive addresses.
+// Gauss-Jordan elimination with partial pivoting on [B | I] gives B^-1,
+// the pivots give sign and log|det B|.
+template <class R, int NA>
+__global__ __launch_bounds__(256) void det_small_kernel(const float* phi, int64_t M, int T, int n3, R* D, int dstride,
+                                                        R* ainv) {
+  const int64_t mat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mat >= M) return;
+  constexpr int NSQ = NA * NA;
+  R* out = D + mat * dstride;
+  R B[NA][NA], X[NA][NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j)
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      B[j][i] = (R)phi[(int64_t)(j * NA + i) * M + mat];
+      X[j][i] = j == i ? (R)1 : (R)0;
+    }
+  R sg = 1, la = 0;
+  bool singular = false;
+#pragma unroll
+  for (int c = 0; c < NA; ++c) {
+    // pivot row p >= c with the largest |B[p][c]|; exchange rows c and p
+    R best = fabs(B[c][c]);
+    int p = c;
+#pragma unroll
+    for (int r = c + 1; r < NA; ++r)
+      if (fabs(B[r][c]) > best) {
+        best = fabs(B[r][c]);
+        p = r;
+      }
+    if (best == (R)0) singular = true;
+#pragma unroll
+    for (int r = c + 1; r < NA; ++r)
+      if (r == p) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          R t = B[c][k];
+          B[c][k] = B[r][k];
+          B[r][k] = t;
+          t = X[c][k];
+          X[c][k] = X[r][k];
+          X[r][k] = t;
+        }
+      }
+    if (p != c) sg = -sg;
+    const R piv = singular ? (R)1 : B[c][c];
+    if (piv < 0) sg = -sg;
+    la += log(fabs(piv));
+    const R ip = (R)1 / piv;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      B[c][k] *= ip;
+      X[c][k] *= ip;
+    }
+#pragma unroll
+    for (int r = 0; r < NA; ++r)
+      if (r != c) {
+        const R f = B[r][c];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          B[r][k] -= f * B[c][k];
+          X[r][k] -= f * X[c][k];
+        }
+      }
+  }
+  if (singular) {
+    for (int e = 0; e < dstride; ++e) out[e] = (R)0;
+    out[1] = -INFINITY;
+    if (ainv)
+      for (int e = 0; e < NSQ; ++e) ainv[mat * NSQ + e] = (R)0;
+    return;
+  }
+  out[0] = sg;
+  out[1] = la;
+  if (ainv) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NA; ++b) ainv[mat * NSQ + a * NA + b] = X[a][b];
+  }
+  if (T <= 1) return;
+  // d_t = tr(B^-1 M_t), q = sum_t tr((B^-1 M_t)^2), lap = tr(B^-1 lap B)
+  R q = 0;
+  for (int tt = 0; tt <= n3; ++tt) {
+    const int row = tt < n3 ? 1 + tt : T - 1;
+    const float* Pm = phi + (int64_t)row * NSQ * M + mat;
+    R Mt[NA][NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+#pragma unroll
+      for (int b = 0; b < NA; ++b) Mt[c][b] = (R)Pm[(int64_t)(c * NA + b) * M];
+    R Y[NA][NA];
+    R d = 0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NA; ++b) {
+        R acc = 0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c) acc += X[a][c] * Mt[c][b];
+        Y[a][b] = acc;
+      }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) d += Y[a][a];
+    if (tt < n3) {
+      out[2 + tt] = d;
+      R qq = 0;
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int b = 0; b < NA; ++b) qq += Y[a][b] * Y[b][a];
+      q += qq;
+    } else {
+      out[3 + n3] = d;
+    }
+  }
+  out[2 + n3] = q;
+}
+
+template <class R>
+static hipError_t run_det_small(int na, const float* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
+                                hipStream_t s) {
+  const int grid = (int)((M + 255) / 256);
+  switch (na) {
+    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool det_uses_small(int na) { return na <= DET_SMALL_MAX; }
+
 hipError_t launch_det(bool fp64, const float* phi, int W, int K, int na, int T, int n3, void* D, int dstride,
                       void* ainv, hipStream_t s) {
   if (na <= 0 || W <= 0) return hipSuccess;
   if (na > MAXNA) return hipErrorInvalidValue;
+  if (det_uses_small(na)) {
+    const int64_t M = (int64_t)W * K;
+    return fp64 ? run_det_small<double>(na, phi, M, T, n3, (double*)D, dstride, (double*)ainv, s)
+                : run_det_small<float>(na, phi, M, T, n3, (float*)D, dstride, (float*)ainv, s);
+  }
   const int grid = W * K;
   if (fp64) hipLaunchKernelGGL(det_kernel<double>, dim3(grid), dim3(64), 0, s, phi, K, na, T, n3, (double*)D, dstride, (double*)ainv);
   else hipLaunchKernelGGL(det_kernel<float>, dim3(grid), dim3(64), 0, s, phi, K, na, T, n3, (float*)D, dstride, (float*)ainv);

@@ -120,13 +120,19 @@ struct TwoElecDev {
 // slot s of the block: electron ii = s / (n R2), partner j = (s / R2) % n,
 // sparse jet row q = s % R2 (value, d/dr_i x3, d/dr_j x3, Laplacian).
 // D2 is the two-electron width rounded up to a compiled size; the extra
-// features carry zero weights and stay zero.
+// features carry zero weights and stay zero.  The slot rows of Ps have the
+// odd stride D2 + 1, so the 64 slots of a wavefront reading one feature hit
+// distinct LDS banks.
+template <int D2> constexpr int two_e_ps_stride() { return D2 + 1; }
+inline size_t two_e_ws_offset(int slots, int ps) { return ((size_t)slots * ps + 3) / 4 * 4; }
+
 template <class TA, int D2>
 __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
   extern __shared__ float sh[];
+  constexpr int PS = two_e_ps_stride<D2>();
   const int n = a.n, R2 = a.R2, d2 = a.d2;
-  float* Ps = sh;                                // [slots][D2]
-  float* Ws = sh + (size_t)a.ipb * n * R2 * D2;  // [D2][D2] then c[D2]
+  float* Ps = sh;                                                // [slots][PS]
+  float* Ws = sh + ((size_t)a.ipb * n * R2 * PS + 3) / 4 * 4;    // [D2][D2] then c[D2], 16-byte aligned
   const int tid = threadIdx.x;
   const int slots = a.ipb * n * R2;
   const int64_t gbase = (int64_t)blockIdx.x * a.ipb;
@@ -161,7 +167,7 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
       }
     }
 #pragma unroll
-    for (int k = 0; k < D2; ++k) Ps[(size_t)s * D2 + k] = k < 4 ? in[k] : 0.0f;
+    for (int k = 0; k < D2; ++k) Ps[(size_t)s * PS + k] = k < 4 ? in[k] : 0.0f;
   }
 
   int ein = 4;
@@ -173,42 +179,45 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
       TA* G = reinterpret_cast<TA*>(a.G[l]);
       const int ldg = a.ldg[l];
       const int T = a.T, Tp = a.Tp;
-      const int per = Tp * ldg;
-      for (int idx = tid; idx < a.ipb * per; idx += blockDim.x) {
-        const int e = idx / per, rem = idx % per;
-        const int t = rem / ldg, c = rem % ldg;
+      // each thread owns one column c = (spin a, feature o) and a stride of
+      // rows: every division happens once per layer
+      const int c = tid % ldg, rstep = blockDim.x / ldg;
+      const bool colv = c < 2 * ein;
+      const int al = colv ? c / ein : 0, o = colv ? c % ein : 0;
+      const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n_dn;
+      const float inv_na = na > 0 ? 1.0f / (float)na : 0.0f;
+      for (int e = 0; e < a.ipb; ++e) {
         const int64_t ge = gbase + e;
-        if (ge >= n_groups) continue;
+        if (ge >= n_groups) break;
         const int ie = (int)(ge % n);
-        float v = 0.0f;
-        if (c < 2 * ein && t < T) {
-          const int al = c / ein, o = c % ein;
-          const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n_dn;
-          if (na > 0) {
-            const float* base = Ps + (size_t)e * n * R2 * D2 + o;
+        const float* base = Ps + (size_t)e * n * R2 * PS + o;
+        TA* Gr = G + ge * Tp * (int64_t)ldg + c;
+        for (int t = tid / ldg; t < Tp; t += rstep) {
+          float v = 0.0f;
+          if (colv && na > 0 && t < T) {
             float acc = 0.0f;
             if (t == 0) {
-              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2) * D2];
+              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2) * PS];
             } else if (t == T - 1) {
-              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 7) * D2];
+              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 7) * PS];
             } else {
-              const int jt = (t - 1) / 3, cc = (t - 1) % 3;
+              const int jt = (t - 1) / 3, cc = (t - 1) - 3 * jt;
               if (jt == ie) {
-                for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 1 + cc) * D2];
+                for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 1 + cc) * PS];
               } else if (jt >= j0 && jt < j0 + na) {
-                acc = base[(size_t)(jt * R2 + 4 + cc) * D2];
+                acc = base[(size_t)(jt * R2 + 4 + cc) * PS];
               }
             }
-            v = acc / (float)na;
+            v = acc * inv_na;
           }
+          st_act(Gr + (int64_t)t * ldg, v);
         }
-        st_act(G + (ge * Tp + t) * (int64_t)ldg + c, v);
       }
       if (a.h2_out[l] && R2 == 1) {
         for (int idx = tid; idx < a.ipb * n * ein; idx += blockDim.x) {
           const int e = idx / (n * ein), jj = (idx / ein) % n, o = idx % ein;
           const int64_t ge = gbase + e;
-          if (ge < n_groups) a.h2_out[l][(ge * n + jj) * ein + o] = Ps[(size_t)(e * n + jj) * D2 + o];
+          if (ge < n_groups) a.h2_out[l][(ge * n + jj) * ein + o] = Ps[(size_t)(e * n + jj) * PS + o];
         }
       }
     }
@@ -230,7 +239,7 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
     for (int o = 0; o < D2; ++o) u[o] = q == 0 ? Ws[D2 * D2 + o] : 0.0f;
     if (live) {
       for (int k = 0; k < ein; ++k) {
-        const float x = Ps[(size_t)s * D2 + k];
+        const float x = Ps[(size_t)s * PS + k];
         const float4* wr = reinterpret_cast<const float4*>(Ws + k * D2);
 #pragma unroll
         for (int o4 = 0; o4 < D2 / 4; ++o4) {
@@ -246,39 +255,38 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
 #pragma unroll
     for (int o = 0; o < D2; ++o) {
       const float uo = u[o];
-      float y, s2 = 0.0f;
+      float y, dy, s2 = 0.0f;
       if (R2 == 8) {
-        const int base = tid & ~7;
-        const float u0 = __shfl(uo, base, 64);
+        const float u0 = __shfl(uo, tid & ~7, 64);
         float sq = (q >= 1 && q <= 6) ? uo * uo : 0.0f;
         sq += __shfl_xor(sq, 1, 64);
         sq += __shfl_xor(sq, 2, 64);
         sq += __shfl_xor(sq, 4, 64);
         s2 = sq;
-        y = tanhf(u0);
+        tanh_sech2f(u0, &y, &dy);
       } else {
-        y = tanhf(uo);
+        tanh_sech2f(uo, &y, &dy);
       }
-      const float dy = sech2f(R2 == 8 ? __shfl(uo, tid & ~7, 64) : uo);
       float outv;
       if (q == 0) outv = y;
       else if (q <= 6) outv = dy * uo;
       else outv = dy * uo - 2.0f * y * dy * s2;
-      if (res && live) outv += Ps[(size_t)s * D2 + o];
+      if (res && live) outv += Ps[(size_t)s * PS + o];
       u[o] = o < d2 ? outv : 0.0f;
     }
     ein = d2;
     __syncthreads();
     if (live) {
 #pragma unroll
-      for (int o = 0; o < D2; ++o) Ps[(size_t)s * D2 + o] = u[o];
+      for (int o = 0; o < D2; ++o) Ps[(size_t)s * PS + o] = u[o];
     }
   }
 }
 
 template <class TA, int D2>
 static hipError_t run_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
-  size_t shmem = ((size_t)d.ipb * d.n * d.R2 * D2 + (size_t)D2 * D2 + D2) * sizeof(float);
+  const size_t shmem =
+      (two_e_ws_offset(d.ipb * d.n * d.R2, two_e_ps_stride<D2>()) + (size_t)D2 * D2 + D2) * sizeof(float);
   hipLaunchKernelGGL((two_electron_kernel<TA, D2>), dim3(grid), dim3(256), shmem, s, d);
   return hipGetLastError();
 }
@@ -308,7 +316,7 @@ hipError_t launch_two_electron(bool bf16, const TwoElecArgs& a, hipStream_t s) {
   if (a.d2 > 64 || a.n * d.R2 > 256 || a.L > 8) return hipErrorInvalidValue;
   // electrons per block: at most 256 slots and at most 64 KiB of LDS
   const int D2p = a.d2 <= 4 ? 4 : a.d2 <= 8 ? 8 : a.d2 <= 16 ? 16 : a.d2 <= 32 ? 32 : 64;
-  const int lds_cap = (65536 / 4 - D2p * D2p - D2p) / (a.n * d.R2 * D2p);
+  const int lds_cap = (65536 / 4 - 4 - D2p * D2p - D2p) / (a.n * d.R2 * (D2p + 1));
   d.ipb = std::min(256 / (a.n * d.R2), lds_cap);
   if (d.ipb < 1) return hipErrorInvalidValue;
   const int64_t groups = (int64_t)a.W * a.n;
@@ -335,11 +343,44 @@ __global__ void meanfield_kernel(const TA* H, int ldh, int W, int n, int n_up, i
   }
 }
 
+// float32 version: one thread per 4 consecutive features of one (walker,
+// jet row), both spins, 16-byte loads (din_p and ldh multiples of 4)
+__global__ void meanfield4_kernel(const float* H, int ldh, int W, int n, int n_up, int Tp, int din_p, float* Hbar) {
+  const int q4 = din_p / 4;
+  const int64_t total = (int64_t)W * Tp * q4;
+  const float iu = n_up > 0 ? 1.0f / (float)n_up : 0.0f;
+  const float id = n - n_up > 0 ? 1.0f / (float)(n - n_up) : 0.0f;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(idx % q4) * 4;
+    const int64_t row = idx / q4;  // w Tp + t
+    const int t = (int)(row % Tp);
+    const int64_t w = row / Tp;
+    float4 su = {0.f, 0.f, 0.f, 0.f}, sd = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < n; ++j) {
+      const float4 v = *reinterpret_cast<const float4*>(H + ((w * n + j) * Tp + t) * (int64_t)ldh + f);
+      float4& s = j < n_up ? su : sd;
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+    float* o = Hbar + row * 2 * din_p + f;
+    *reinterpret_cast<float4*>(o) = float4{su.x * iu, su.y * iu, su.z * iu, su.w * iu};
+    *reinterpret_cast<float4*>(o + din_p) = float4{sd.x * id, sd.y * id, sd.z * id, sd.w * id};
+  }
+}
+
 hipError_t launch_meanfield(bool bf16, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
                             hipStream_t s) {
   int64_t total = (int64_t)W * Tp * 2 * din_p;
   int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (grid <= 0) return hipSuccess;
+  if (!bf16 && din_p % 4 == 0 && ldh % 4 == 0) {
+    const int64_t t4 = (int64_t)W * Tp * (din_p / 4);
+    hipLaunchKernelGGL(meanfield4_kernel, dim3((unsigned)std::min<int64_t>((t4 + 255) / 256, 1 << 20)), dim3(256), 0, s,
+                       (const float*)H, ldh, W, n, n_up, Tp, din_p, (float*)Hbar);
+    return hipGetLastError();
+  }
   if (bf16) hipLaunchKernelGGL(meanfield_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, (const bf16_t*)H, ldh, W, n, n_up, Tp, din_p, (bf16_t*)Hbar);
   else hipLaunchKernelGGL(meanfield_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p, (float*)Hbar);
   return hipGetLastError();

@@ -163,10 +163,7 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
                               __builtin_bit_cast(float, ra[i].z), __builtin_bit_cast(float, ra[i].w)};
           uint16_t h[4], l[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            h[q] = f32_to_bf16_bits(x[q]);
-            l[q] = f32_to_bf16_bits(x[q] - bf16_bits_to_f32(h[q]));
-          }
+          for (int q = 0; q < 4; ++q) split_bf16(x[q], &h[q], &l[q]);
           const int off = (v / VPR_A) * LDS_K + (v % VPR_A) * 4;
           *reinterpret_cast<uint2*>(Ah + off) = uint2{pack2(h[0], h[1]), pack2(h[2], h[3])};
           *reinterpret_cast<uint2*>(Al + off) = uint2{pack2(l[0], l[1]), pack2(l[2], l[3])};
@@ -244,18 +241,40 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
     }
   }
   __syncthreads();
-  // accumulators -> LDS tile [BM][BN]
+  // accumulators -> LDS tile [BM][BN]; the layer epilogue first adds the
+  // per-walker mean-field term P (every jet row) and the bias (value row),
+  // all loads issued together from the accumulator layout
   constexpr int LDC = SM::LDC;
+  const int T = a.T;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const int row = wm * (BM / 2) + i * 16 + kq * 4 + r;
+      // row bookkeeping once per row (not per element)
+      const float* Prow = nullptr;
+      bool bias_row = false;
+      if constexpr (EPI == EPI_TANHJET) {
+        const int e = row / rows_per, t = row % rows_per;
+        const int g = g0 + e;
+        if (g < a.n_groups && t < T) Prow = a.P + ((size_t)(g / a.n_all) * rows_per + t) * a.ldp;
+        bias_row = t == 0;
+      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        Cs[(wm * (BM / 2) + i * 16 + kq * 4 + r) * LDC + wn * (BN / 2) + j * 16 + (lane & 15)] = acc[i][j][r];
+      for (int j = 0; j < TN; ++j) {
+        const int col = wn * (BN / 2) + j * 16 + (lane & 15);
+        float v = acc[i][j][r];
+        if constexpr (EPI == EPI_TANHJET) {
+          const int gc = n0 + col;
+          if (Prow && gc < a.N) {
+            v += Prow[gc];
+            if (bias_row) v += a.bias[gc];
+          }
+        }
+        Cs[row * LDC + col] = v;
+      }
+    }
   __syncthreads();
-
-  const int T = a.T;
   if constexpr (EPI == EPI_PLAIN) {
     for (int p = tid; p < BM * BN; p += 256) {
       int r = p / BN, col = p % BN;
@@ -269,41 +288,50 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       }
     }
   } else if constexpr (EPI == EPI_TANHJET) {
-    float* out = reinterpret_cast<float*>(a.out);
-    const float* res = reinterpret_cast<const float*>(a.a0);
+    // chain rule of tanh on each (electron, feature) jet, in place in LDS:
+    //   y = tanh(u0), d_c y = sech^2(u0) d_c u,
+    //   lap y = sech^2(u0) lap u - 2 tanh(u0) sech^2(u0) sum_c (d_c u)^2
     for (int p = tid; p < E * BN; p += 256) {
-      int e = p / BN, col = p % BN;
-      int g = g0 + e, gc = n0 + col;
+      const int e = p / BN, col = p % BN;
+      const int g = g0 + e, gc = n0 + col;
       if (g >= a.n_groups || gc >= a.N) continue;
-      const int w = g / a.n_all;
-      const float* Pr = a.P + (size_t)w * rows_per * a.ldp + gc;
-      const float* Cr = Cs + (e * rows_per) * LDC + col;
-      const size_t orow = (size_t)g * rows_per;
-      float u0 = Cr[0] + Pr[0] + a.bias[gc];
-      float y = tanhf(u0);
-      float dy = sech2f(u0);
-      float r0 = a.res ? res[orow * a.lda0 + gc] : 0.0f;
-      out[orow * a.ldo + gc] = y + r0;
+      float* Cr = Cs + (e * rows_per) * LDC + col;
+      const float u0 = Cr[0];
+      float y, dy;
+      tanh_sech2f(u0, &y, &dy);
       if (a.pre_out) a.pre_out[(size_t)g * a.N + gc] = u0;
+      Cr[0] = y;
       if (T > 1) {
         float s2 = 0.0f;
         for (int t = 1; t < T - 1; ++t) {
-          float u = Cr[t * LDC] + Pr[(size_t)t * a.ldp];
+          const float u = Cr[t * LDC];
           s2 += u * u;
         }
-        for (int t = 1; t < T - 1; ++t) {
-          float u = Cr[t * LDC] + Pr[(size_t)t * a.ldp];
-          float rr = a.res ? res[(orow + t) * a.lda0 + gc] : 0.0f;
-          out[(orow + t) * a.ldo + gc] = dy * u + rr;
-        }
-        {
-          int t = T - 1;
-          float u = Cr[t * LDC] + Pr[(size_t)t * a.ldp];
-          float rr = a.res ? res[(orow + t) * a.lda0 + gc] : 0.0f;
-          out[(orow + t) * a.ldo + gc] = dy * u - 2.0f * y * dy * s2 + rr;
-        }
-        for (int t = T; t < rows_per; ++t) out[(orow + t) * a.ldo + gc] = 0.0f;
+        for (int t = 1; t < T - 1; ++t) Cr[t * LDC] *= dy;
+        Cr[(T - 1) * LDC] = dy * Cr[(T - 1) * LDC] - 2.0f * y * dy * s2;
+        for (int t = T; t < rows_per; ++t) Cr[t * LDC] = 0.0f;
       }
+    }
+    __syncthreads();
+    // coalesced write-out of whole rows, residual added on the way
+    float* out = reinterpret_cast<float*>(a.out);
+    const float* res = reinterpret_cast<const float*>(a.a0);
+    constexpr int V4 = BN / 4;
+    for (int p = tid; p < BM * V4; p += 256) {
+      const int r = p / V4, c4 = (p % V4) * 4;
+      const int e = r / rows_per, t = r % rows_per;
+      const int g = g0 + e, gc = n0 + c4;
+      if (g >= a.n_groups || gc >= a.N) continue;
+      const size_t orow = (size_t)g * rows_per + t;
+      float4 v = *reinterpret_cast<const float4*>(Cs + r * LDC + c4);
+      if (a.res) {
+        const float4 rr = *reinterpret_cast<const float4*>(res + orow * a.lda0 + gc);
+        v.x += rr.x;
+        v.y += rr.y;
+        v.z += rr.z;
+        v.w += rr.w;
+      }
+      *reinterpret_cast<float4*>(out + orow * a.ldo + gc) = v;
     }
   } else {  // EPI_ORBITAL
     const int na = a.n_sub;
@@ -335,7 +363,9 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       }
       const float* Cr = Cs + (e * rows_per) * LDC + col;
       const float u0 = Cr[0] + a.g_orb[gc];
-      float* ph = a.phi + ((size_t)(w * Kd + k) * T) * nsq + jj * na + i;
+      const int64_t mat = (int64_t)w * Kd + k;
+      const size_t ts = a.phi_M ? (size_t)nsq * a.phi_M : (size_t)nsq;  // stride between jet rows
+      float* ph = a.phi_M ? a.phi + (size_t)(jj * na + i) * a.phi_M + mat : a.phi + (size_t)mat * T * nsq + jj * na + i;
       ph[0] = u0 * e0;
       if (a.u_out) {
         size_t o = ((size_t)(w * Kd + k) * na + jj) * na + i;
@@ -344,13 +374,13 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       }
       if (T > 1) {
         const int tj = 1 + 3 * j;
-        for (int t = 1; t < T - 1; ++t) ph[(size_t)t * nsq] = Cr[t * LDC] * e0;
+        for (int t = 1; t < T - 1; ++t) ph[(size_t)t * ts] = Cr[t * LDC] * e0;
         const float ux = Cr[tj * LDC], uy = Cr[(tj + 1) * LDC], uz = Cr[(tj + 2) * LDC];
-        ph[(size_t)tj * nsq] += u0 * ex;
-        ph[(size_t)(tj + 1) * nsq] += u0 * ey;
-        ph[(size_t)(tj + 2) * nsq] += u0 * ez;
+        ph[(size_t)tj * ts] += u0 * ex;
+        ph[(size_t)(tj + 1) * ts] += u0 * ey;
+        ph[(size_t)(tj + 2) * ts] += u0 * ez;
         const float lu = Cr[(T - 1) * LDC];
-        ph[(size_t)(T - 1) * nsq] = lu * e0 + u0 * le + 2.0f * (ux * ex + uy * ey + uz * ez);
+        ph[(size_t)(T - 1) * ts] = lu * e0 + u0 * le + 2.0f * (ux * ex + uy * ey + uz * ez);
       }
     }
   }
@@ -381,6 +411,9 @@ static hipError_t pick(const JetGemmArgs& a, hipStream_t s) {
 hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t s) {
   if (a.n_groups <= 0) return hipSuccess;
   if ((a.ka0 % 32) || (a.ka1 % 32)) return hipErrorInvalidValue;
+  // the one-electron layers take the full-width streaming kernel when their
+  // shape allows it
+  if (epi == EPI_TANHJET && layer_gemm_supported(a)) return launch_layer_gemm(mode, a, s);
   if (mode == MODE_BF16X3) {
     if (epi == EPI_PLAIN) return pick<MODE_BF16X3, EPI_PLAIN>(a, s);
     if (epi == EPI_TANHJET) return pick<MODE_BF16X3, EPI_TANHJET>(a, s);

@@ -39,13 +39,19 @@ struct JetGemmArgs {
   float* pre_out;
   // EPI_ORBITAL: phi[((w * K + k) * T + t) * n_sub^2 + j * n_sub + i] with
   //   w = g / n_sub, j = g % n_sub, col = k * n_sub + i
+  //   or, when phi_M > 0 (matrix index fastest, for the small-matrix
+  //   determinant kernel): phi[((t n_sub + j) n_sub + i) * phi_M + w * K + k]
   float* phi;
+  int64_t phi_M;
   const float* pos; const float* nuc; int n_nuc; int n_elec;
   const float* g_orb; const float* pi; const float* sigma;
   float* u_out; float* env_out;  // value mode, optional: [w][K][j][i]
 };
 
 hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t s);
+// full-width streaming kernel for the EPI_TANHJET layers (layer.hip)
+bool layer_gemm_supported(const JetGemmArgs& a);
+hipError_t launch_layer_gemm(int mode, const JetGemmArgs& a, hipStream_t s);
 
 // ---- features and two-electron stream (features.hip)
 // split: write bfloat16 hi planes at dst and lo planes at dst + plane (elements)
@@ -70,6 +76,10 @@ hipError_t launch_meanfield(bool bf16, const void* H, int ldh, int W, int n, int
 // ---- determinants and combination (det.hip)
 // D_a[(w K + k) * dstride + ...]: sign, log|det|, d_c (3n), q, lap  (jet mode)
 //                                  sign, log|det|                      (value mode)
+// matrices up to this size take the one-thread-per-matrix kernel, which
+// expects the matrix-index-fastest layout of the orbital jets (phi_M = W K)
+constexpr int DET_SMALL_MAX = 6;
+bool det_uses_small(int na);
 hipError_t launch_det(bool fp64, const float* phi, int W, int K, int na, int T, int n3, void* D, int dstride,
                       void* ainv, hipStream_t s);
 struct CombineArgs {

@@ -1,0 +1,381 @@
+// One-electron layer GEMM with the tanh-jet epilogue, sized for the tall,
+// skinny products of the jet algebra: rows = walkers x electrons x jet rows
+// (millions), K = d1 + 2 d2, N = d1.
+//
+// Per layer the arithmetic intensity is K N / (2 (K + N)) flop per byte of
+// float32 activations (about 50 for K = 320, N = 256), far below the ridge
+// of the bfloat16 matrix cores, so the kernel is organised around HBM
+// streaming rather than MFMA reuse:
+//  * a 512-thread workgroup owns BM rows (whole electrons, and a whole
+//    number of waves per electron) x BN = 128 columns; the column tiles of
+//    one row tile are issued back to back on the same XCD, so the repeated
+//    read of the activations is served by that XCD's L2;
+//  * in the split-bfloat16 form each activation element is split into hi/lo
+//    parts once, by the thread that stages it into LDS (hardware
+//    round-to-nearest-even conversion); the bfloat16 tiles are stored without
+//    padding under an XOR swizzle of 16-byte chunks (conflict-free fragment
+//    reads), so two stages take 64 KiB and two workgroups share a CU;
+//  * the epilogue does not stage the tile in LDS: per column, the jet rows of
+//    one electron sit in the accumulators of the wave's four lane groups (and
+//    of the electron's other waves when the jet is taller than a wave's
+//    rows).  The sum of squared tangents is reduced with cross-lane shuffles
+//    and a 4 KiB cross-wave exchange in fixed order, the tanh chain rule is
+//    applied in registers, and results go straight to HBM with the residual added.
+#include "common.h"
+#include "kernels.h"
+
+namespace fn {
+
+template <int MODE, int BM, int BN, int WM, int WN>
+struct LayerCfg {
+  static constexpr int NT = 64 * WM * WN, BK = 32;
+  static constexpr int WROWS = BM / WM, WCOLS = BN / WN;
+  static constexpr int TM = WROWS / 16, TN = WCOLS / 16;
+  static constexpr int LDA = MODE == MODE_F32 ? BK + 4 : BK;  // elements per staged row
+  static constexpr int LDB = LDA;
+  static constexpr int A_BYTES = MODE == MODE_F32 ? BM * LDA * 4 : 2 * BM * LDA * 2;
+  static constexpr int B_BYTES = MODE == MODE_F32 ? BN * LDB * 4 : 2 * BN * LDB * 2;
+  static constexpr int STAGE = A_BYTES + B_BYTES;
+  static constexpr int RED_BYTES = 2 * WM * BN * 4;
+  static constexpr int BYTES = 2 * STAGE > RED_BYTES ? 2 * STAGE : RED_BYTES;
+  static constexpr int NA = BM * BK / 4;  // float4 per A tile
+  static constexpr int NVA = (NA + NT - 1) / NT;
+  static constexpr int NB = MODE == MODE_F32 ? BN * BK / 4 : BN * BK / 8;  // 16-byte vectors per B plane
+  static constexpr int NVB = (NB + NT - 1) / NT;
+  static_assert(NT == 512 && WROWS % 16 == 0 && WCOLS % 16 == 0, "tile shape");
+};
+
+__device__ inline uint32_t pk2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+// element offset of 16-byte chunk c (0..3) of row r in an unpadded bfloat16
+// tile of 32-element rows: chunks are permuted by (r >> 1) & 3, so eight
+// consecutive rows read at one chunk index cover all banks once
+__device__ inline int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
+
+template <int MODE, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
+  using C = LayerCfg<MODE, BM, BN, WM, WN>;
+  constexpr int BK = C::BK, LDA = C::LDA, LDB = C::LDB, TM = C::TM, TN = C::TN, WROWS = C::WROWS;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+
+  const int bid = blockIdx.x;
+  const int n_t = (bid / 8) % n_ntiles;
+  const int m_t = (bid / (8 * n_ntiles)) * 8 + (bid % 8);
+  if (m_t >= n_mtiles) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int rows_per = a.rows_per;
+  const int E = BM / rows_per;  // electrons per row tile
+  const int g0 = m_t * E;
+  const int n0 = n_t * BN;
+  const int nkt = (a.ka0 + a.ka1) / BK;
+
+  // A loader: 8 float4 per 32-wide tile row
+  long rowoff[C::NVA];
+#pragma unroll
+  for (int i = 0; i < C::NVA; ++i) {
+    const int v = tid + i * C::NT;
+    const int r = v / (BK / 4);
+    const int e = r / rows_per, t = r - e * rows_per;
+    const int g = g0 + e;
+    rowoff[i] = (v < C::NA && g < a.n_groups)
+                    ? ((long)(g / a.n_sub) * a.n_all + a.e_off + (g % a.n_sub)) * rows_per + t
+                    : -1;
+  }
+  float4 ra[C::NVA];
+  uint4 rb[C::NVB], rbl[MODE == MODE_F32 ? 1 : C::NVB];
+
+  auto gload = [&](int kt) {
+    const int kb = kt * BK;
+    const float* src = kb < a.ka0 ? (const float*)a.a0 : (const float*)a.a1;
+    const int lda = kb < a.ka0 ? a.lda0 : a.lda1;
+    const int kk = kb < a.ka0 ? kb : kb - a.ka0;
+#pragma unroll
+    for (int i = 0; i < C::NVA; ++i) {
+      const int v = tid + i * C::NT;
+      float4 z = {0.f, 0.f, 0.f, 0.f};
+      if (rowoff[i] >= 0) z = *reinterpret_cast<const float4*>(src + (size_t)rowoff[i] * lda + kk + (v % (BK / 4)) * 4);
+      ra[i] = z;
+    }
+#pragma unroll
+    for (int i = 0; i < C::NVB; ++i) {
+      const int v = tid + i * C::NT;
+      uint4 z = {0, 0, 0, 0}, zl = {0, 0, 0, 0};
+      if constexpr (MODE == MODE_F32) {
+        const int nn = v / (BK / 4), col = n0 + nn;
+        if (v < C::NB && col < a.N)
+          z = *reinterpret_cast<const uint4*>((const float*)a.bt + (size_t)col * a.ldb + kb + (v % (BK / 4)) * 4);
+      } else {
+        const int nn = v / (BK / 8), col = n0 + nn;
+        if (v < C::NB && col < a.N) {
+          const size_t off = (size_t)col * a.ldb + kb + (v % (BK / 8)) * 8;
+          z = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt + off);
+          zl = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt_lo + off);
+        }
+      }
+      rb[i] = z;
+      if constexpr (MODE != MODE_F32) rbl[i] = zl;
+    }
+  };
+  auto sstore = [&](int buf) {
+    char* st = smem + buf * C::STAGE;
+    if constexpr (MODE == MODE_F32) {
+      float* As = reinterpret_cast<float*>(st);
+      float* Bs = reinterpret_cast<float*>(st + C::A_BYTES);
+#pragma unroll
+      for (int i = 0; i < C::NVA; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < C::NA) *reinterpret_cast<float4*>(As + (v / (BK / 4)) * LDA + (v % (BK / 4)) * 4) = ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < C::NVB; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < C::NB) *reinterpret_cast<uint4*>(Bs + (v / (BK / 4)) * LDB + (v % (BK / 4)) * 4) = rb[i];
+      }
+    } else {
+      uint16_t* Ah = reinterpret_cast<uint16_t*>(st);
+      uint16_t* Al = Ah + BM * LDA;
+      uint16_t* Bh = reinterpret_cast<uint16_t*>(st + C::A_BYTES);
+      uint16_t* Bl = Bh + BN * LDB;
+#pragma unroll
+      for (int i = 0; i < C::NVA; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < C::NA) {
+          const int q = v % (BK / 4);
+          const int off = swz(v / (BK / 4), q >> 1) + (q & 1) * 4;
+          uint16_t h[4], l[4];
+          split_bf16(ra[i].x, &h[0], &l[0]);
+          split_bf16(ra[i].y, &h[1], &l[1]);
+          split_bf16(ra[i].z, &h[2], &l[2]);
+          split_bf16(ra[i].w, &h[3], &l[3]);
+          *reinterpret_cast<uint2*>(Ah + off) = uint2{pk2(h[0], h[1]), pk2(h[2], h[3])};
+          *reinterpret_cast<uint2*>(Al + off) = uint2{pk2(l[0], l[1]), pk2(l[2], l[3])};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < C::NVB; ++i) {
+        const int v = tid + i * C::NT;
+        if (v < C::NB) {
+          const int off = swz(v / (BK / 8), v % (BK / 8));
+          *reinterpret_cast<uint4*>(Bh + off) = rb[i];
+          *reinterpret_cast<uint4*>(Bl + off) = rbl[i];
+        }
+      }
+    }
+  };
+
+  floatx4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int arow = wm * WROWS + (lane & 15);
+  const int bcol = wn * C::WCOLS + (lane & 15);
+  const int kq = lane >> 4;
+
+  if (nkt > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nkt) gload(kt + 1);
+    const char* st = smem + buf * C::STAGE;
+    if constexpr (MODE == MODE_F32) {
+      const float* As = reinterpret_cast<const float*>(st);
+      const float* Bs = reinterpret_cast<const float*>(st + C::A_BYTES);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        float af[TM], bf[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = As[(arow + i * 16) * LDA + ks * 4 + kq];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bf[j] = Bs[(bcol + j * 16) * LDB + ks * 4 + kq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      const uint16_t* Ah = reinterpret_cast<const uint16_t*>(st);
+      const uint16_t* Al = Ah + BM * LDA;
+      const uint16_t* Bh = reinterpret_cast<const uint16_t*>(st + C::A_BYTES);
+      const uint16_t* Bl = Bh + BN * LDB;
+      bf16x8 ah[TM], al[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        ah[i] = *reinterpret_cast<const bf16x8*>(Ah + swz(arow + i * 16, kq));
+        al[i] = *reinterpret_cast<const bf16x8*>(Al + swz(arow + i * 16, kq));
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(Bh + swz(bcol + j * 16, kq));
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(Bl + swz(bcol + j * 16, kq));
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    if (kt + 1 < nkt) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------------- epilogue
+  // accumulator (i, j, r) of lane (kq, c) is tile row wm WROWS + 16 i + 4 kq + r,
+  // tile column wn WCOLS + 16 j + c
+  const int T = a.T;
+  float* out = reinterpret_cast<float*>(a.out);
+  const float* res = reinterpret_cast<const float*>(a.a0);
+  int gcol[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) gcol[j] = n0 + wn * C::WCOLS + j * 16 + (lane & 15);
+
+  if (rows_per == 1) {
+    // value mode: every row is an electron
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + wm * WROWS + i * 16 + kq * 4 + r;
+        if (g >= a.n_groups) continue;
+        const float* Prow = a.P + (size_t)(g / a.n_all) * a.ldp;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int gc = gcol[j];
+          const float u0 = acc[i][j][r] + Prow[gc] + a.bias[gc];
+          float y, dy;
+          tanh_sech2f(u0, &y, &dy);
+          if (a.pre_out) a.pre_out[(size_t)g * a.N + gc] = u0;
+          if (a.res) y += res[(size_t)g * a.lda0 + gc];
+          out[(size_t)g * a.ldo + gc] = y;
+        }
+      }
+    return;
+  }
+
+  // jet mode: the rows of this wave lie in one electron (rows_per % WROWS == 0)
+  const int wrow0 = wm * WROWS;
+  const int e_loc = wrow0 / rows_per;
+  const int tw0 = wrow0 - e_loc * rows_per;  // jet row of the wave's first row
+  const int g = g0 + e_loc;
+  const bool gval = g < a.n_groups;
+  const float* Pb = a.P + (size_t)(gval ? g / a.n_all : 0) * rows_per * a.ldp;
+  const size_t obase = (size_t)(gval ? g : 0) * rows_per;
+
+  // pre-activation u = acc + P (+ bias on the value row); partial sums of the
+  // squared tangent rows 1..T-2
+  float s2[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) s2[j] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = tw0 + i * 16 + kq * 4 + r;
+      if (gval && t < T) {
+        const float* Prow = Pb + (size_t)t * a.ldp;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          float v = acc[i][j][r] + Prow[gcol[j]];
+          if (t == 0) v += a.bias[gcol[j]];
+          acc[i][j][r] = v;
+          if (t >= 1 && t <= T - 2) s2[j] += v * v;
+        }
+      }
+    }
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    s2[j] += __shfl_xor(s2[j], 16, 64);
+    s2[j] += __shfl_xor(s2[j], 32, 64);
+  }
+  // cross-wave exchange (stage buffers are free after the main loop's last barrier)
+  float* red = reinterpret_cast<float*>(smem);  // [WM][BN] partial sums
+  float* val = red + WM * BN;                   // [WM][BN] value rows
+  const int cl = wn * C::WCOLS + (lane & 15);
+  if (kq == 0) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      red[wm * BN + cl + j * 16] = s2[j];
+      if (tw0 == 0) val[wm * BN + cl + j * 16] = acc[0][j][0];
+    }
+  }
+  __syncthreads();
+  const int wfirst = wm - tw0 / WROWS, wper = rows_per / WROWS;
+  float y[TN], dy[TN], lapc[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    float ss = 0.0f;
+    for (int w = wfirst; w < wfirst + wper; ++w) ss += red[w * BN + cl + j * 16];
+    const float u0 = val[wfirst * BN + cl + j * 16];
+    tanh_sech2f(u0, &y[j], &dy[j]);
+    lapc[j] = -2.0f * y[j] * dy[j] * ss;
+    if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + gcol[j]] = u0;
+  }
+  if (!gval) return;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = tw0 + i * 16 + kq * 4 + r;
+      float* orow = out + (obase + t) * a.ldo;
+      const float* rrow = (a.res && t < T) ? res + (obase + t) * a.lda0 : nullptr;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const float v = acc[i][j][r];
+        float o;
+        if (t == 0) o = y[j];
+        else if (t < T - 1) o = dy[j] * v;
+        else if (t == T - 1) o = dy[j] * v + lapc[j];
+        else o = 0.0f;
+        if (rrow) o += rrow[gcol[j]];
+        orow[gcol[j]] = o;
+      }
+    }
+}
+
+template <int MODE, int BM, int BN, int WM, int WN>
+static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
+  using C = LayerCfg<MODE, BM, BN, WM, WN>;
+  const int E = BM / a.rows_per;
+  const int n_mtiles = (a.n_groups + E - 1) / E;
+  const int n_ntiles = (a.N + BN - 1) / BN;
+  const int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, C::BYTES) != hipSuccess)
+      return hipErrorInvalidValue;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN>), dim3(grid), dim3(C::NT), C::BYTES, s, a, n_mtiles,
+                     n_ntiles);
+  return hipGetLastError();
+}
+
+// tile shapes: a row tile holds whole electrons and each wave's rows lie in
+// one electron (value mode: one row per electron)
+template <int MODE>
+static hipError_t pick_layer(const JetGemmArgs& a, hipStream_t s) {
+  if (a.rows_per == 96) return run_layer<MODE, 96, 128, 2, 4>(a, s);
+  if (a.rows_per == 1 || a.rows_per == 32 || a.rows_per == 64 || a.rows_per == 128)
+    return run_layer<MODE, 128, 128, 4, 2>(a, s);
+  return hipErrorInvalidValue;
+}
+
+bool layer_gemm_supported(const JetGemmArgs& a) {
+  const int rp = a.rows_per;
+  const bool tall = rp == 32 || rp == 64 || rp == 96 || rp == 128;
+  return (rp == 1 ? a.T == 1 : tall && a.T <= rp) && a.N % 128 == 0 && a.ka0 % 32 == 0 && a.ka1 % 32 == 0;
+}
+
+hipError_t launch_layer_gemm(int mode, const JetGemmArgs& a, hipStream_t s) {
+  if (a.n_groups <= 0) return hipSuccess;
+  if (!layer_gemm_supported(a)) return hipErrorInvalidValue;
+  return mode == MODE_BF16X3 ? pick_layer<MODE_BF16X3>(a, s) : pick_layer<MODE_F32>(a, s);
+}
+
+}  // namespace fn
