@@ -8,7 +8,9 @@ energy (sign, log|psi|, kinetic energy from the jets, Coulomb potential)
 and the VMC energy gradient from the hand-written adjoint.  The headline
 form runs the layer GEMMs in split bfloat16 (three bf16 MFMA passes, fp32
 accumulation) with float64 determinants; the plain fp32 form is timed
-beside it on the same inputs.  Prints one JSON line.
+beside it on the same inputs.  In both, the local energy of the walkers of
+largest determinant-sum cancellation (5% and 2% of the batch by default)
+is re-evaluated in float64 inside the timed step.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,7 +31,9 @@ from paper_2011_07125_amd import ferminet as F  # noqa: E402
 from paper_2011_07125_amd import inputs as I  # noqa: E402
 
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense TFLOP/s (MFMA), MI355X
-HBM_GBS = 8000.0
+HBM_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+LAYER_SRC = os.path.join(ROOT, "paper_2011_07125_amd", "csrc", "layer.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "layer_gemm_ne10_traffic.md")
 
 
 def layer_flops(cfg, W, T):
@@ -44,48 +48,98 @@ def layer_flops(cfg, W, T):
     return main, mf
 
 
-def one_step(w, d, form, state, grad, seed, counter):
+def layer_bytes(cfg, W, T):
+    """Algorithmic HBM bytes of the L one-electron layer GEMMs of the jet
+    pass: read the jet rows of [h_i, g^up_i, g^down_i] and the per-walker
+    mean-field rows P, write the new jet rows (float32), read the weights
+    once (bfloat16 hi and lo planes).  The residual re-reads h_i, which is
+    already counted in the input."""
+    n, N, d1, d2, L = cfg["n_elec"], cfg["n_nuc"], cfg["width1"], cfg["width2"], cfg["n_layers"]
+    total = 0
+    for l in range(L):
+        din, ein = (4 * N, 4) if l == 0 else (d1, d2)
+        k = din + 2 * ein
+        total += 4 * W * n * T * (k + d1) + 4 * W * T * d1 + 4 * k * d1
+    return total
+
+
+def measured_traffic():
+    """HBM bytes per launch of the jet layer GEMM from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    with open(LAYER_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("layer.hip sha256") != sha:
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes=512 << 20, reps=3):
+    """A plain copy kernel of known size (y = x * 1, float32): the FETCH_SIZE
+    and WRITE_SIZE counters of these launches convert counter units into
+    bytes for the layer kernel's readings."""
+    x = torch.rand(nbytes // 4, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
+def one_step(w, d, form, state, grad, seed, counter, rescue):
     cfg = w["cfg"]
     F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], state["logpsi"], state["sign"], 1, 0.02,
                     seed, counter, precision=form)
     out = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
-                                  parts=False)
+                                  parts=False, rescue=rescue)
     if grad:
         F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], out["e_loc"],
                               precision=form)
     return out
 
 
-def time_form(w, form, steps, warmup, grad):
+def time_form(w, form, steps, warmup, grad, rescue):
     d = F.to_device(w)
     cfg = w["cfg"]
     s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
     state = {"sign": s, "logpsi": l}
     for i in range(warmup):
-        one_step(w, d, form, state, grad, 11, i)
+        one_step(w, d, form, state, grad, 11, i, rescue)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
     for i in range(steps):
-        one_step(w, d, form, state, grad, 11, warmup + i)
+        one_step(w, d, form, state, grad, 11, warmup + i, rescue)
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     # per-stage device time of two more steps (HIP events on the same stream)
     F.stage_timing(True)
     for i in range(2):
-        one_step(w, d, form, state, grad, 11, warmup + steps + i)
+        one_step(w, d, form, state, grad, 11, warmup + steps + i, rescue)
     torch.cuda.synchronize()
     stages = F.stage_times()
     F.stage_timing(False)
     return ms, stages
 
 
-def accuracy(w, form, golden):
+def accuracy(w, form, golden, rescue):
     """Batch-mean E_L of the seeded batch against the stored oracle values."""
     d = F.to_device(w)
-    out = F.ferminet_local_energy(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
+    out = F.ferminet_local_energy(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
+                                  rescue=rescue)
     torch.cuda.synchronize()
     e = out["e_loc"].double().cpu().numpy()
     g = np.load(golden)
@@ -130,12 +184,20 @@ def main():
     ap.add_argument("--workload", default="ne10")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--rescue-bf16", type=float, default=0.05,
+                    help="fraction of walkers whose local energy is re-evaluated in float64 (bf16 form)")
+    ap.add_argument("--rescue-fp32", type=float, default=0.02, help="the same for the fp32 form")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first launch a plain 512 MiB copy kernel three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (walkers are independent, so "
               "more GPUs would shard the batch)", file=sys.stderr)
         sys.exit(2)
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.copy_calibration:
+        copy_calibration()
     w = I.make_workload(args.workload)
     cfg = w["cfg"]
     W = w["pos"].shape[0]
@@ -148,29 +210,35 @@ def main():
     except F.FerminetError:
         grad = False  # adjoint not available in this build
 
-    ms_bf, st_bf = time_form(w, "bf16", args.steps, args.warmup, grad)
+    ms_bf, st_bf = time_form(w, "bf16", args.steps, args.warmup, grad, args.rescue_bf16)
     res = {}
     if not args.no_fp32:
-        ms_32, st_32 = time_form(w, "fp32", args.steps, args.warmup, grad)
-        res["fp32_form"] = {"value": W / (ms_32 * 1e-3), "ms_per_step": ms_32,
+        ms_32, st_32 = time_form(w, "fp32", args.steps, args.warmup, grad, args.rescue_fp32)
+        res["fp32_form"] = {"value": W / (ms_32 * 1e-3), "ms_per_step": ms_32, "rescue_fraction": args.rescue_fp32,
                             "stage_ms": {k: round(v[0] / 2, 4) for k, v in st_32.items()}}
     main_fl, mf_fl = layer_flops(cfg, W, T)
     # dominant kernel: the one-electron layer GEMM of the jet pass (L
-    # launches per local-energy call, layer 0 included)
+    # launches per local-energy call, layer 0 included).  Its arithmetic
+    # intensity (about 50 flop/byte) is far below the bf16 ridge (about 310),
+    # so it is priced against HBM bandwidth.
     tot, cnt = st_bf.get("gemm_layer", (0.0, 0))
     L = cfg["n_layers"]
     flops_per_launch = main_fl / L
+    bytes_per_launch = layer_bytes(cfg, W, T) / L
     jet_launch_ms = tot / cnt if cnt else None
-    achieved = flops_per_launch / (jet_launch_ms * 1e-3) / 1e12 if jet_launch_ms else None
-    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["bf16"], "unit": "TFLOP/s",
-            "frac": (achieved / PEAK["bf16"]) if achieved else None, "traffic": None,
-            "kernel": "layer_gemm_kernel<MODE_BF16X3,128,256> (one-electron layer, tanh-jet epilogue)",
-            "flops_per_launch": flops_per_launch, "avg_launch_ms": jet_launch_ms}
+    achieved = bytes_per_launch / (jet_launch_ms * 1e-3) / 1e9 if jet_launch_ms else None
+    traffic = measured_traffic()
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_GBS) if achieved else None, "traffic": traffic,
+            "kernel": "layer_gemm_kernel<MODE_BF16X3,128,128,4,2,jet> (one-electron layer, tanh-jet epilogue)",
+            "bytes_per_launch": bytes_per_launch, "flops_per_launch": flops_per_launch,
+            "mfma_tflops": flops_per_launch / (jet_launch_ms * 1e-3) / 1e12 if jet_launch_ms else None,
+            "avg_launch_ms": jet_launch_ms, "launches_timed": cnt}
     golden = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.npz")
-    if os.path.exists(golden):
-        res["accuracy_bf16"] = accuracy(w, "bf16", golden)
+    if os.path.exists(golden) and not args.no_accuracy:
+        res["accuracy_bf16"] = accuracy(w, "bf16", golden, args.rescue_bf16)
         if not args.no_fp32:
-            res["accuracy_fp32"] = accuracy(w, "fp32", golden)
+            res["accuracy_fp32"] = accuracy(w, "fp32", golden, args.rescue_fp32)
     line = {
         "metric": "walker local-energy evals/sec (Ne-like, 16 dets) BF16+adjoint vs FP32 at <=1 mHa",
         "value": W / (ms_bf * 1e-3), "unit": "walker local-energy evals/s", "n_gpus": 1, "steps": args.steps,
@@ -181,7 +249,9 @@ def main():
                                f"({cfg['n_up']} up/{cfg['n_down']} down), {W} walkers, {cfg['n_layers']} layers "
                                f"{cfg['width1']}/{cfg['width2']}, {cfg['n_det']} dets, isotropic envelope",
                    "walkers": W, "step": "1 Metropolis move + local energy" + (" + VMC gradient" if grad else ""),
-                   "form": "bf16x3 layer GEMMs (fp32 accumulation), fp64 determinants",
+                   "form": "bf16x3 layer GEMMs (fp32 accumulation), fp64 determinants, fp64 re-evaluation of the "
+                           f"{args.rescue_bf16:.0%} largest-kappa walkers",
+                   "rescue_fraction": args.rescue_bf16,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "stage_ms_bf16": {k: round(v[0] / 2, 4) for k, v in st_bf.items()},

@@ -92,13 +92,19 @@ typedef enum {
    * combination in float64 */
   FN_PREC_BF16 = 1,
   /* float32 network and orbitals, float64 determinants and combination */
-  FN_PREC_FP32_FP64DET = 2
+  FN_PREC_FP32_FP64DET = 2,
+  /* every stage in float64 (layer and orbital GEMMs on FP64 MFMA); inputs
+   * are still the float32 arrays below, widened exactly.  Not available
+   * for the parameter gradient (FN_ERR_UNSUPPORTED). */
+  FN_PREC_FP64 = 3
 } fn_precision;
 
-/* Shapes.  Limits of this build: 1 <= n_elec <= 64, n_up >= n_down >= 0
- * are NOT required (any split), 0 <= n_up, n_down <= 32, 1 <= n_nuc <= 32,
- * 1 <= n_layers <= 8, width1 in [8, 1024] and a multiple of 8, width2 in
- * [4, 64] and a multiple of 4, 1 <= n_det <= 64. */
+/* Shapes.  Limits of this build: 1 <= n_elec <= 32 with any split
+ * 0 <= n_up, n_down (n_up + n_down = n_elec), 1 <= n_nuc <= 32,
+ * 1 <= n_layers <= 8, width1 in [32, 1024] and a multiple of 32,
+ * 1 <= width2 <= 64, 1 <= n_det <= 64, and the two-electron stream of one
+ * electron (8 sparse jet rows per pair) must fit in the 160 KiB of LDS of a compute unit
+ * (FN_ERR_CONFIG otherwise). */
 typedef struct {
   int32_t n_elec;    /* n = n_up + n_down */
   int32_t n_up;
@@ -109,6 +115,18 @@ typedef struct {
   int32_t width2;    /* d2, two-electron stream width */
   int32_t n_det;     /* K, determinants */
   int32_t precision; /* fn_precision */
+  /* Local energy in the reduced-precision forms: the fraction f in [0, 1]
+   * of walkers re-evaluated entirely in float64 (0: none; ignored by
+   * FN_PREC_FP64 and by the other entry points).  Within each chunk of
+   * the batch, in segments of at most 8192 walkers, the ceil(f * segment)
+   * walkers with the largest determinant-sum cancellation
+   * kappa = max_k |P_k| / |psi|  (P_k = det^up_k det^down_k, Eq. (4);
+   * kappa = inf at a node) are gathered, evaluated again as FN_PREC_FP64
+   * would, and their sign, log|psi|, e_loc, e_kin and e_pot replace the
+   * reduced-precision values.  Near a node of the determinant sum the
+   * rounding error of the local energy grows with kappa, so this removes
+   * the dominant error of the batch-mean energy at a fixed cost. */
+  float rescue_fraction;
 } fn_config;
 
 typedef struct {
@@ -156,6 +174,9 @@ fn_status ferminet_logpsi(const fn_config* cfg, int32_t W, const float* pos, con
  * electron coordinates, from forward-mode jets (value, 3n tangents and
  * Laplacian) carried through every layer; the potential part from the
  * electron-electron, electron-nucleus and nucleus-nucleus Coulomb sums.
+ * With cfg->rescue_fraction > 0 the walkers of largest kappa are
+ * re-evaluated in float64 (see fn_config); the workspace then also holds
+ * the float64 buffers of those walkers.
  *   sign, logpsi [W] out (as ferminet_logpsi)
  *   e_loc [W] out; e_kin, e_pot [W] out, each may be NULL */
 fn_status ferminet_local_energy(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,

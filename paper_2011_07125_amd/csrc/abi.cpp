@@ -3,6 +3,7 @@
 // Everything here is bookkeeping; all arithmetic of the method runs in the
 // HIP kernels.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -17,9 +18,12 @@ namespace fn {
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
+  fn_config cfg;
   int n, nu, nd, N, L, d1, d2, K, n3;
-  bool bf16, fp64;
-  size_t act;  // bytes per activation element
+  bool bf16, fp64, f64;
+  int mode;       // GEMM arithmetic (MODE_*)
+  float rescue;   // fraction of each chunk re-evaluated in float64 (local energy)
+  size_t act;     // bytes per activation element
   int din[8], ein[8], dinp[8], gwp[8];
   int64_t offV[8], offb[8], offW2[8], offc2[8], offw[2], offg[2], offpi[2], offsg[2], P;
   // packed weights (elements, activation type)
@@ -30,6 +34,7 @@ struct Plan {
 
 static fn_status make_plan(const fn_config* c, Plan& p) {
   if (!c) return FN_ERR_NULL;
+  p.cfg = *c;
   p.n = c->n_elec;
   p.nu = c->n_up;
   p.nd = c->n_down;
@@ -41,17 +46,21 @@ static fn_status make_plan(const fn_config* c, Plan& p) {
   if (p.nu < 0 || p.nd < 0 || p.nu + p.nd != p.n || p.n < 1 || p.n > 32 || p.nu > 32 || p.nd > 32) return FN_ERR_CONFIG;
   if (p.N < 1 || p.N > 32 || p.L < 1 || p.L > 8 || p.K < 1 || p.K > 64) return FN_ERR_CONFIG;
   if (p.d1 < 32 || p.d1 > 1024 || p.d1 % 32 != 0 || p.d2 < 1 || p.d2 > 64) return FN_ERR_CONFIG;
-  if (c->precision != FN_PREC_FP32 && c->precision != FN_PREC_BF16 && c->precision != FN_PREC_FP32_FP64DET)
+  if (c->precision != FN_PREC_FP32 && c->precision != FN_PREC_BF16 && c->precision != FN_PREC_FP32_FP64DET &&
+      c->precision != FN_PREC_FP64)
     return FN_ERR_CONFIG;
-  {
-    // the two-electron stream keeps one electron's 8-row pair jets in LDS
-    const int d2p = p.d2 <= 4 ? 4 : p.d2 <= 8 ? 8 : p.d2 <= 16 ? 16 : p.d2 <= 32 ? 32 : 64;
-    // (slot rows of stride d2p + 1, weights aligned to 16 bytes)
-    if ((p.n * 8 * (d2p + 1) + 4 + d2p * d2p + d2p) * 4 > 65536) return FN_ERR_CONFIG;
-  }
+  if (!(c->rescue_fraction >= 0.0f && c->rescue_fraction <= 1.0f)) return FN_ERR_CONFIG;
   p.bf16 = c->precision == FN_PREC_BF16;
+  p.f64 = c->precision == FN_PREC_FP64;
   p.fp64 = c->precision != FN_PREC_FP32;
-  p.act = 4;  // activations are float32 in HBM in every form
+  p.mode = p.f64 ? MODE_F64 : p.bf16 ? MODE_BF16X3 : MODE_F32;
+  p.rescue = p.f64 ? 0.0f : c->rescue_fraction;
+  // activations are float32 in HBM, float64 in the float64 form
+  p.act = p.f64 ? 8 : 4;
+  // the two-electron stream keeps one electron's 8-row pair jets in LDS
+  // (also in float64 when walkers are re-evaluated)
+  if (two_electron_per_block(p.n, p.d2, 3 * p.n + 2, (int)p.act) < 1) return FN_ERR_CONFIG;
+  if (p.rescue > 0.0f && two_electron_per_block(p.n, p.d2, 3 * p.n + 2, 8) < 1) return FN_ERR_CONFIG;
   p.n3 = 3 * p.n;
   int64_t off = 0;
   for (int l = 0; l < p.L; ++l) {
@@ -134,7 +143,7 @@ enum Mode { VALUE = 0, JET = 1 };
 enum Stage {
   ST_PACK, ST_FEATURES, ST_TWO_E, ST_MEANFIELD, ST_GEMM_MF, ST_GEMM_LAYER, ST_GEMM_ORB, ST_DET, ST_COMBINE,
   ST_PROPOSE, ST_ACCEPT, ST_ADJ_FWD, ST_ADJ_DET, ST_ADJ_ORB, ST_ADJ_LAYERS, ST_ADJ_TWO_E, ST_ADJ_REDUCE,
-  ST_GEMM_LAYER_VALUE, ST_COUNT
+  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_COUNT
 };
 
 struct Bufs {
@@ -144,9 +153,10 @@ struct Bufs {
   void* Ha;
   void* Hb;
   void* Hbar;
-  float* Pm;
-  float* phi[2];
+  void* Pm;      // mean-field terms (activation type)
+  void* phi[2];  // orbital jets (activation type)
   void* D[2];
+  float* lnk;    // log kappa per walker (local energy with re-evaluation), else NULL
   float* prop;
   float* lp_new;
   float* sg_new;
@@ -176,12 +186,13 @@ static void carve_forward(const Plan& p, Mode m, int64_t Wc, Carver& cv, Bufs& b
   int dmax = 0;
   for (int l = 0; l < p.L; ++l) dmax = std::max(dmax, p.dinp[l]);
   b.Hbar = cv.take((size_t)Wc * b.Tp * 2 * dmax * p.act);
-  b.Pm = (float*)cv.take((size_t)Wc * b.Tp * p.d1 * 4);
+  b.Pm = cv.take((size_t)Wc * b.Tp * p.d1 * p.act);
   const size_t rb = p.fp64 ? 8 : 4;
   for (int a = 0; a < 2; ++a) {
-    b.phi[a] = (float*)cv.take((size_t)Wc * p.K * b.T * p.na(a) * p.na(a) * 4);
+    b.phi[a] = cv.take((size_t)Wc * p.K * b.T * p.na(a) * p.na(a) * p.act);
     b.D[a] = cv.take((size_t)Wc * p.K * b.dstride * rb);
   }
+  b.lnk = (m == JET && p.rescue > 0.0f) ? (float*)cv.take((size_t)Wc * 4) : nullptr;
   if (mcmc) {
     b.prop = (float*)cv.take((size_t)Wc * p.n3 * 4);
     b.lp_new = (float*)cv.take((size_t)Wc * 4);
@@ -276,6 +287,43 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
   b.cot = (float*)cv.take((size_t)Wc * 4);
 }
 
+// ---------------------------------------- float64 re-evaluation buffers
+// Per chunk of Wc walkers: segments of at most 8192 walkers, the k_seg
+// walkers of largest kappa of each segment, R = segments x k_seg in all.
+struct RescueDims {
+  int seg_len, k_seg;
+  int64_t R;
+};
+static RescueDims rescue_dims(const Plan& p, int64_t Wc) {
+  RescueDims d{0, 0, 0};
+  if (p.rescue <= 0.0f || Wc < 1) return d;
+  d.seg_len = (int)std::min<int64_t>(Wc, 8192);
+  d.k_seg = std::max(1, std::min(d.seg_len, (int)std::ceil((double)p.rescue * d.seg_len)));
+  d.R = (Wc + d.seg_len - 1) / d.seg_len * d.k_seg;
+  return d;
+}
+
+struct RescueBufs {
+  Plan p64;
+  void* pk64;
+  Bufs b;
+  int32_t* idx;
+  float* pos_r;
+  float* out[5];  // sign, logpsi, e_loc, e_kin, e_pot of the re-evaluated walkers
+};
+
+static void carve_rescue(const Plan& p, int64_t Wc, Carver& cv, RescueBufs& r) {
+  const RescueDims d = rescue_dims(p, Wc);
+  fn_config c = p.cfg;
+  c.precision = FN_PREC_FP64;
+  make_plan(&c, r.p64);
+  r.pk64 = cv.take((size_t)r.p64.pk_total * r.p64.act);
+  carve_forward(r.p64, JET, d.R, cv, r.b, false);
+  r.idx = (int32_t*)cv.take((size_t)d.R * 4);
+  r.pos_r = (float*)cv.take((size_t)d.R * p.n3 * 4);
+  for (int q = 0; q < 5; ++q) r.out[q] = (float*)cv.take((size_t)d.R * 4);
+}
+
 static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   Carver cv{nullptr, 0};
   Bufs b;
@@ -286,6 +334,10 @@ static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
     return cv.used;
   }
   carve_forward(p, entry == FN_ENTRY_LOCAL_ENERGY ? JET : VALUE, Wc, cv, b, entry == FN_ENTRY_MCMC);
+  if (entry == FN_ENTRY_LOCAL_ENERGY && p.rescue > 0.0f) {
+    RescueBufs r;
+    carve_rescue(p, Wc, cv, r);
+  }
   return cv.used;
 }
 
@@ -315,7 +367,8 @@ static int64_t max_chunk(const Plan& p, int entry, size_t ws_bytes, int64_t W) {
 static const char* kStageNames[ST_COUNT] = {
     "pack_weights", "features",  "two_electron", "meanfield",    "gemm_meanfield", "gemm_layer",
     "gemm_orbital", "det",       "combine",      "mcmc_propose", "mcmc_accept",    "adj_forward",
-    "adj_det",      "adj_orbital", "adj_layers", "adj_two_electron", "adj_reduce",     "gemm_layer_value"};
+    "adj_det",      "adj_orbital", "adj_layers", "adj_two_electron", "adj_reduce",     "gemm_layer_value",
+    "rescue_fp64"};
 static std::mutex g_time_mu;
 static bool g_timing = false;
 struct StageRec {
@@ -350,24 +403,26 @@ struct StageScope {
 static fn_status pack(const Plan& p, const float* params, void* dst, hipStream_t s) {
   std::vector<int64_t> it;
   int n = pack_plan(p, it);
-  FN_T(ST_PACK, launch_pack_weights(p.bf16, params, dst, p.pk_total, it.data(), n, s));
+  FN_T(ST_PACK, launch_pack_weights(p.mode, params, dst, p.pk_total, it.data(), n, s));
   return FN_OK;
 }
 
 // packed weight block at element offset off: float32, or the bfloat16 hi
 // plane (lo = false) / lo plane (lo = true) in the split form
 static const void* wt(const Bufs& b, const Plan& p, int64_t off, bool lo) {
-  if (!p.bf16) return lo ? nullptr : (const char*)b.pk + off * 4;
+  if (!p.bf16) return lo ? nullptr : (const char*)b.pk + off * p.act;
   return (const char*)b.pk + (off + (lo ? p.pk_total : 0)) * 2;
 }
 
 // forward pass over one chunk of Wc walkers.  jet: local energy; value:
-// sign and log|psi| only.
+// sign and log|psi| only.  Launches are timed under their own stages, or
+// all under stage_all when it is not negative.
 static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, const float* nuc, const float* Z,
                          const float* params, const Bufs& b, float* sign, float* logpsi, float* e_loc,
-                         float* e_kin, float* e_pot, hipStream_t s) {
+                         float* e_kin, float* e_pot, hipStream_t s, int stage_all = -1) {
   const int T = b.T, Tp = b.Tp;
-  FN_T(ST_FEATURES, launch_features(false, pos, nuc, (int)Wc, p.n, p.N, T, Tp, b.H0, p.dinp[0], s));
+  auto SG = [stage_all](int st) { return stage_all >= 0 ? stage_all : st; };
+  FN_T(SG(ST_FEATURES), launch_features(p.f64, pos, nuc, (int)Wc, p.n, p.N, T, Tp, b.H0, p.dinp[0], s));
   TwoElecArgs te;
   memset(&te, 0, sizeof(te));
   te.pos = pos;
@@ -385,11 +440,11 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     te.G[l] = b.G[l];
     te.ldg[l] = p.gwp[l];
   }
-  FN_T(ST_TWO_E, launch_two_electron(false, te, s));
+  FN_T(SG(ST_TWO_E), launch_two_electron(p.f64, te, s));
   const void* Hin = b.H0;
   void* Hout = b.Ha;
   for (int l = 0; l < p.L; ++l) {
-    FN_T(ST_MEANFIELD, launch_meanfield(false, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
+    FN_T(SG(ST_MEANFIELD), launch_meanfield(p.f64, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
     JetGemmArgs g;
     memset(&g, 0, sizeof(g));
     g.a0 = b.Hbar;
@@ -406,7 +461,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     g.N = p.d1;
     g.c = b.Pm;
     g.ldc = p.d1;
-    FN_T(ST_GEMM_MF, launch_jet_gemm(p.bf16 ? MODE_BF16X3 : MODE_F32, EPI_PLAIN, g, s));
+    FN_T(SG(ST_GEMM_MF), launch_jet_gemm(p.mode, EPI_PLAIN, g, s));
     JetGemmArgs h;
     memset(&h, 0, sizeof(h));
     h.a0 = Hin;
@@ -430,7 +485,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     h.ldp = p.d1;
     h.bias = params + p.offb[l];
     h.res = p.din[l] == p.d1;
-    FN_T(m == JET ? ST_GEMM_LAYER : ST_GEMM_LAYER_VALUE, launch_jet_gemm(p.bf16 ? MODE_BF16X3 : MODE_F32, EPI_TANHJET, h, s));
+    FN_T(SG(m == JET ? ST_GEMM_LAYER : ST_GEMM_LAYER_VALUE), launch_jet_gemm(p.mode, EPI_TANHJET, h, s));
     Hin = Hout;
     Hout = Hout == b.Ha ? b.Hb : b.Ha;
   }
@@ -461,8 +516,8 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     o.g_orb = params + p.offg[a];
     o.pi = params + p.offpi[a];
     o.sigma = params + p.offsg[a];
-    FN_T(ST_GEMM_ORB, launch_jet_gemm(p.bf16 ? MODE_BF16X3 : MODE_F32, EPI_ORBITAL, o, s));
-    FN_T(ST_DET, launch_det(p.fp64, b.phi[a], (int)Wc, p.K, na, T, p.n3, b.D[a], b.dstride, nullptr, s));
+    FN_T(SG(ST_GEMM_ORB), launch_jet_gemm(p.mode, EPI_ORBITAL, o, s));
+    FN_T(SG(ST_DET), launch_det(p.fp64, b.phi[a], p.f64, (int)Wc, p.K, na, T, p.n3, b.D[a], b.dstride, nullptr, s));
   }
   CombineArgs cb;
   memset(&cb, 0, sizeof(cb));
@@ -485,7 +540,8 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   cb.e_loc = e_loc;
   cb.e_kin = e_kin;
   cb.e_pot = e_pot;
-  FN_T(ST_COMBINE, launch_combine(p.fp64, cb, s));
+  cb.ln_kappa = m == JET ? b.lnk : nullptr;
+  FN_T(SG(ST_COMBINE), launch_combine(p.fp64, cb, s));
   return FN_OK;
 }
 
@@ -605,7 +661,7 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
     o.u_out = b.u[a];
     o.env_out = b.env[a];
     FN_T(ST_ADJ_FWD, launch_jet_gemm(mode, EPI_ORBITAL, o, s));
-    FN_T(ST_ADJ_DET, launch_det(p.fp64, b.phi[a], (int)Wc, p.K, na, 1, p.n3, b.D[a], 2, b.binv[a], s));
+    FN_T(ST_ADJ_DET, launch_det(p.fp64, b.phi[a], false, (int)Wc, p.K, na, 1, p.n3, b.D[a], 2, b.binv[a], s));
   }
   CombineArgs cb;
   memset(&cb, 0, sizeof(cb));
@@ -775,6 +831,8 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
 static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const float* nuc_pos, const float* nuc_charge,
                              const float* params, const float* cot_all, const float* e_loc, const double* stats,
                              float* grad, void* ws, size_t ws_bytes, hipStream_t s) {
+  // the adjoint runs in float32 / split bfloat16 only
+  if (p.f64) return FN_ERR_UNSUPPORTED;
   const int64_t chunk = max_chunk(p, FN_ENTRY_GRAD_LOGPSI, ws_bytes, W);
   if (chunk < 1) return FN_ERR_WORKSPACE;
   Carver cv{(char*)ws, 0};
@@ -908,13 +966,36 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
   Bufs b;
   b.pk = cv.take((size_t)p.pk_total * p.act);
   carve_forward(p, jet ? JET : VALUE, chunk, cv, b, false);
+  const bool rescue = jet && p.rescue > 0.0f;
+  RescueBufs r;
+  if (rescue) {
+    carve_rescue(p, chunk, cv, r);
+    r.b.pk = r.pk64;
+  }
   st = pack(p, params, b.pk, s);
   if (st != FN_OK) return st;
+  if (rescue) {
+    st = pack(r.p64, params, r.pk64, s);
+    if (st != FN_OK) return st;
+  }
   for (int64_t w0 = 0; w0 < W; w0 += chunk) {
     const int64_t wc = std::min<int64_t>(chunk, W - w0);
-    st = forward(p, jet ? JET : VALUE, wc, pos + w0 * p.n3, nuc_pos, nuc_charge, params, b, sign + w0, logpsi + w0,
-                 jet ? e_loc + w0 : nullptr, e_kin ? e_kin + w0 : nullptr, e_pot ? e_pot + w0 : nullptr, s);
+    const float* x = pos + w0 * p.n3;
+    float* outs[5] = {sign + w0, logpsi + w0, jet ? e_loc + w0 : nullptr, e_kin ? e_kin + w0 : nullptr,
+                      e_pot ? e_pot + w0 : nullptr};
+    st = forward(p, jet ? JET : VALUE, wc, x, nuc_pos, nuc_charge, params, b, outs[0], outs[1], outs[2], outs[3],
+                 outs[4], s);
     if (st != FN_OK) return st;
+    if (!rescue) continue;
+    // float64 re-evaluation of the walkers of largest kappa
+    const RescueDims d = rescue_dims(p, wc);
+    FN_T(ST_RESCUE, launch_select_top(b.lnk, (int)wc, d.seg_len, d.k_seg, r.idx, s));
+    FN_T(ST_RESCUE, launch_gather_walkers(x, r.idx, (int)d.R, p.n3, r.pos_r, s));
+    st = forward(r.p64, JET, d.R, r.pos_r, nuc_pos, nuc_charge, params, r.b, r.out[0], r.out[1], r.out[2], r.out[3],
+                 r.out[4], s, ST_RESCUE);
+    if (st != FN_OK) return st;
+    const float* srcs[5] = {r.out[0], r.out[1], r.out[2], r.out[3], r.out[4]};
+    FN_T(ST_RESCUE, launch_scatter_results(r.idx, (int)d.R, outs, srcs, 5, s));
   }
   return FN_OK;
 }

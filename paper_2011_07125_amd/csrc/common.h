@@ -10,11 +10,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// bfloat16 storage type: the raw 16 bits, rounded to nearest-even from fp32
-struct bf16_t {
-  uint16_t bits;
-};
-
 __host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
   uint32_t u = __builtin_bit_cast(uint32_t, f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
@@ -34,12 +29,6 @@ __device__ inline void split_bf16(float x, uint16_t* h, uint16_t* l) {
   *l = __builtin_bit_cast(uint16_t, lb);
 }
 
-// load/store of one element of the activation type (float or bf16_t) as fp32
-__device__ inline float ld_act(const float* p) { return *p; }
-__device__ inline float ld_act(const bf16_t* p) { return bf16_bits_to_f32(p->bits); }
-__device__ inline void st_act(float* p, float v) { *p = v; }
-__device__ inline void st_act(bf16_t* p, float v) { p->bits = f32_to_bf16_bits(v); }
-
 // tanh'(u) = sech^2(u) = 4 e^{-2|u|} / (1 + e^{-2|u|})^2, free of the
 // cancellation of 1 - tanh^2(u) once tanh saturates
 __device__ inline float sech2f(float u) {
@@ -57,6 +46,14 @@ __device__ inline void tanh_sech2f(float u, float* th, float* s2) {
   const float t = -m / d;
   *th = u < 0.0f ? -t : t;
   *s2 = 4.0f * (1.0f + m) / (d * d);
+}
+__device__ inline void tanh_sech2(float u, float* th, float* s2) { tanh_sech2f(u, th, s2); }
+__device__ inline void tanh_sech2(double u, double* th, double* s2) {
+  const double m = expm1(-2.0 * fabs(u));
+  const double d = 2.0 + m;
+  const double t = -m / d;
+  *th = u < 0.0 ? -t : t;
+  *s2 = 4.0 * (1.0 + m) / (d * d);
 }
 
 template <class T> __device__ inline T wave_sum(T v) {

@@ -24,8 +24,9 @@ namespace fn {
 
 constexpr int MAXNA = 32;
 
-template <class R>
-__global__ __launch_bounds__(64) void det_kernel(const float* phi, int K, int na, int T, int n3, R* D, int dstride,
+// PT: type of the orbital jets (float, or double with R = double)
+template <class R, class PT>
+__global__ __launch_bounds__(64) void det_kernel(const PT* phi, int K, int na, int T, int n3, R* D, int dstride,
                                                  R* ainv) {
   __shared__ R LU[MAXNA * MAXNA];
   __shared__ R Bi[MAXNA * MAXNA];
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(64) void det_kernel(const float* phi, int K, int na
   const int lane = threadIdx.x;
   const int64_t mat = blockIdx.x;  // = w * K + k
   const int nsq = na * na;
-  const float* P = phi + mat * (int64_t)T * nsq;
+  const PT* P = phi + mat * (int64_t)T * nsq;
   R* out = D + mat * dstride;
 
   for (int e = lane; e < nsq; e += 64) LU[e] = (R)P[e];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(64) void det_kernel(const float* phi, int K, int na
       const int gi = e / nsq, ab = e % nsq, ar = ab / na, b = ab % na;
       const int tt = t0 + gi;
       const int row = tt < n3 ? 1 + tt : T - 1;
-      const float* M = P + (int64_t)row * nsq;
+      const PT* M = P + (int64_t)row * nsq;
       R acc = 0;
       for (int c = 0; c < na; ++c) acc += Bi[ar * na + c] * (R)M[c * na + b];
       Ys[e] = acc;
@@ -199,8 +200,8 @@ __global__ __launch_bounds__(64) void det_kernel(const float* phi, int K, int na
 // with M = W K, so that consecutive threads read consecutive addresses.
 // Gauss-Jordan elimination with partial pivoting on [B | I] gives B^-1,
 // the pivots give sign and log|det B|.
-template <class R, int NA>
-__global__ __launch_bounds__(256) void det_small_kernel(const float* phi, int64_t M, int T, int n3, R* D, int dstride,
+template <class R, int NA, class PT>
+__global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M, int T, int n3, R* D, int dstride,
                                                         R* ainv) {
   const int64_t mat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (mat >= M) return;
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void det_small_kernel(const float* phi, int64_
   R q = 0;
   for (int tt = 0; tt <= n3; ++tt) {
     const int row = tt < n3 ? 1 + tt : T - 1;
-    const float* Pm = phi + (int64_t)row * NSQ * M + mat;
+    const PT* Pm = phi + (int64_t)row * NSQ * M + mat;
     R Mt[NA][NA];
 #pragma unroll
     for (int c = 0; c < NA; ++c)
@@ -316,17 +317,17 @@ __global__ __launch_bounds__(256) void det_small_kernel(const float* phi, int64_
   out[2 + n3] = q;
 }
 
-template <class R>
-static hipError_t run_det_small(int na, const float* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
+template <class R, class PT>
+static hipError_t run_det_small(int na, const PT* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
                                 hipStream_t s) {
   const int grid = (int)((M + 255) / 256);
   switch (na) {
-    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -334,18 +335,28 @@ static hipError_t run_det_small(int na, const float* phi, int64_t M, int T, int 
 
 bool det_uses_small(int na) { return na <= DET_SMALL_MAX; }
 
-hipError_t launch_det(bool fp64, const float* phi, int W, int K, int na, int T, int n3, void* D, int dstride,
-                      void* ainv, hipStream_t s) {
+hipError_t launch_det(bool fp64, const void* phi, bool phi64, int W, int K, int na, int T, int n3, void* D,
+                      int dstride, void* ainv, hipStream_t s) {
   if (na <= 0 || W <= 0) return hipSuccess;
-  if (na > MAXNA) return hipErrorInvalidValue;
+  if (na > MAXNA || (phi64 && !fp64)) return hipErrorInvalidValue;
+  const float* pf = (const float*)phi;
+  const double* pd = (const double*)phi;
   if (det_uses_small(na)) {
     const int64_t M = (int64_t)W * K;
-    return fp64 ? run_det_small<double>(na, phi, M, T, n3, (double*)D, dstride, (double*)ainv, s)
-                : run_det_small<float>(na, phi, M, T, n3, (float*)D, dstride, (float*)ainv, s);
+    if (phi64) return run_det_small<double, double>(na, pd, M, T, n3, (double*)D, dstride, (double*)ainv, s);
+    return fp64 ? run_det_small<double, float>(na, pf, M, T, n3, (double*)D, dstride, (double*)ainv, s)
+                : run_det_small<float, float>(na, pf, M, T, n3, (float*)D, dstride, (float*)ainv, s);
   }
   const int grid = W * K;
-  if (fp64) hipLaunchKernelGGL(det_kernel<double>, dim3(grid), dim3(64), 0, s, phi, K, na, T, n3, (double*)D, dstride, (double*)ainv);
-  else hipLaunchKernelGGL(det_kernel<float>, dim3(grid), dim3(64), 0, s, phi, K, na, T, n3, (float*)D, dstride, (float*)ainv);
+  if (phi64)
+    hipLaunchKernelGGL((det_kernel<double, double>), dim3(grid), dim3(64), 0, s, pd, K, na, T, n3, (double*)D, dstride,
+                       (double*)ainv);
+  else if (fp64)
+    hipLaunchKernelGGL((det_kernel<double, float>), dim3(grid), dim3(64), 0, s, pf, K, na, T, n3, (double*)D, dstride,
+                       (double*)ainv);
+  else
+    hipLaunchKernelGGL((det_kernel<float, float>), dim3(grid), dim3(64), 0, s, pf, K, na, T, n3, (float*)D, dstride,
+                       (float*)ainv);
   return hipGetLastError();
 }
 
@@ -376,6 +387,8 @@ __global__ __launch_bounds__(64) void combine_kernel(CombineArgs a) {
   const R sgn = node ? (R)0 : (S > 0 ? (R)1 : (R)-1);
   const R rho = node ? (R)0 : ex / S;
   if (a.rho && lane < K) ((R*)a.rho)[w * K + lane] = rho;
+  // determinant-sum cancellation: kappa = max_k |P_k| / |psi|
+  if (a.ln_kappa && lane == 0) a.ln_kappa[w] = node ? INFINITY : (float)(m - logabs);
 
   double ekin = 0.0;
   if (a.jet) {

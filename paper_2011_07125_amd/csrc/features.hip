@@ -25,8 +25,9 @@ struct PackPlan {
 
 // packed[n][k] = params[src + (k - k0) * src_ld + n] (transpose) or
 // params[src + n * src_ld + (k - k0)] for k in one of the two
-// segments, 0 elsewhere; float32, or split into bfloat16 hi and lo planes
-template <bool SPLIT>
+// segments, 0 elsewhere; float32, split into bfloat16 hi and lo planes, or
+// float64
+template <int PMODE>
 __global__ void pack_weights_kernel(const float* params, void* dst, int64_t plane, PackPlan plan) {
   const int item = blockIdx.y;
   if (item >= plan.n_items) return;
@@ -37,18 +38,20 @@ __global__ void pack_weights_kernel(const float* params, void* dst, int64_t plan
     float v = 0.0f;
     if (k >= p[3] && k < p[3] + p[4]) v = params[p[5] + (p[10] ? (k - p[3]) * p[9] + n : n * p[9] + (k - p[3]))];
     else if (k >= p[6] && k < p[6] + p[7]) v = params[p[8] + (p[10] ? (k - p[6]) * p[9] + n : n * p[9] + (k - p[6]))];
-    if constexpr (SPLIT) {
+    if constexpr (PMODE == MODE_BF16X3) {
       uint16_t* d = reinterpret_cast<uint16_t*>(dst);
       const uint16_t h = f32_to_bf16_bits(v);
       d[p[0] + idx] = h;
       d[plane + p[0] + idx] = f32_to_bf16_bits(v - bf16_bits_to_f32(h));
+    } else if constexpr (PMODE == MODE_F64) {
+      reinterpret_cast<double*>(dst)[p[0] + idx] = (double)v;
     } else {
       reinterpret_cast<float*>(dst)[p[0] + idx] = v;
     }
   }
 }
 
-hipError_t launch_pack_weights(bool split, const float* params, void* dst, int64_t plane, const int64_t* plan,
+hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t plane, const int64_t* plan,
                                int n_items, hipStream_t s) {
   if (n_items > 32) return hipErrorInvalidValue;
   PackPlan pp;
@@ -56,8 +59,9 @@ hipError_t launch_pack_weights(bool split, const float* params, void* dst, int64
   for (int i = 0; i < n_items; ++i)
     for (int j = 0; j < 11; ++j) pp.it[i][j] = plan[i * 11 + j];
   dim3 grid(64, n_items);
-  if (split) hipLaunchKernelGGL(pack_weights_kernel<true>, grid, dim3(256), 0, s, params, dst, plane, pp);
-  else hipLaunchKernelGGL(pack_weights_kernel<false>, grid, dim3(256), 0, s, params, dst, plane, pp);
+  if (mode == MODE_BF16X3) hipLaunchKernelGGL(pack_weights_kernel<MODE_BF16X3>, grid, dim3(256), 0, s, params, dst, plane, pp);
+  else if (mode == MODE_F64) hipLaunchKernelGGL(pack_weights_kernel<MODE_F64>, grid, dim3(256), 0, s, params, dst, plane, pp);
+  else hipLaunchKernelGGL(pack_weights_kernel<MODE_F32>, grid, dim3(256), 0, s, params, dst, plane, pp);
   return hipGetLastError();
 }
 
@@ -65,9 +69,10 @@ hipError_t launch_pack_weights(bool split, const float* params, void* dst, int64
 // H0[(g Tp + t) ldh + f], g = w n + i: the jets of
 //   h_i = concat_I (r_i - R_I, |r_i - R_I|)
 // d/dr_i of (r_i - R_I)_c = e_c; of |r_i - R_I| = (r_i - R_I)/|r_i - R_I|;
-// Laplacian of |r_i - R_I| = 2 / |r_i - R_I|.
-template <class TA>
-__global__ void features_kernel(const float* pos, const float* nuc, int W, int n, int N, int T, int Tp, TA* H0,
+// Laplacian of |r_i - R_I| = 2 / |r_i - R_I|.  S: float or double
+// (arithmetic and storage).
+template <class S>
+__global__ void features_kernel(const float* pos, const float* nuc, int W, int n, int N, int T, int Tp, S* H0,
                                 int ldh) {
   const int64_t total = (int64_t)W * n * Tp * ldh;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
@@ -76,32 +81,32 @@ __global__ void features_kernel(const float* pos, const float* nuc, int W, int n
     const int t = (int)(row % Tp);
     const int64_t g = row / Tp;
     const int i = (int)(g % n);
-    float v = 0.0f;
+    S v = 0;
     if (f < 4 * N && t < T) {
       const int I = f >> 2, comp = f & 3;
       const float* r = pos + g * 3;
-      float d0 = r[0] - nuc[3 * I], d1 = r[1] - nuc[3 * I + 1], d2 = r[2] - nuc[3 * I + 2];
-      float dist = sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
-      float dc[3] = {d0, d1, d2};
+      const S d0 = (S)r[0] - (S)nuc[3 * I], d1 = (S)r[1] - (S)nuc[3 * I + 1], d2 = (S)r[2] - (S)nuc[3 * I + 2];
+      const S dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const S dc[3] = {d0, d1, d2};
       if (t == 0) {
         v = comp < 3 ? dc[comp] : dist;
       } else if (t == T - 1) {
-        v = comp < 3 ? 0.0f : 2.0f / dist;
+        v = comp < 3 ? (S)0 : (S)2 / dist;
       } else {
         const int jt = (t - 1) / 3, c = (t - 1) % 3;
-        if (jt == i) v = comp < 3 ? (comp == c ? 1.0f : 0.0f) : dc[c] / dist;
+        if (jt == i) v = comp < 3 ? (comp == c ? (S)1 : (S)0) : dc[c] / dist;
       }
     }
-    st_act(H0 + idx, v);
+    H0[idx] = v;
   }
 }
 
-hipError_t launch_features(bool bf16, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
+hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
                            void* H0, int ldh, hipStream_t s) {
   int64_t total = (int64_t)W * n * Tp * ldh;
   int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (grid <= 0) return hipSuccess;
-  if (bf16) hipLaunchKernelGGL(features_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (bf16_t*)H0, ldh);
+  if (f64) hipLaunchKernelGGL(features_kernel<double>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (double*)H0, ldh);
   else hipLaunchKernelGGL(features_kernel<float>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (float*)H0, ldh);
   return hipGetLastError();
 }
@@ -126,13 +131,15 @@ struct TwoElecDev {
 template <int D2> constexpr int two_e_ps_stride() { return D2 + 1; }
 inline size_t two_e_ws_offset(int slots, int ps) { return ((size_t)slots * ps + 3) / 4 * 4; }
 
-template <class TA, int D2>
+// S: float or double (arithmetic, LDS and the stored jets of g^a_i)
+template <class S, int D2>
 __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
-  extern __shared__ float sh[];
+  extern __shared__ __attribute__((aligned(16))) char sh_raw[];
+  S* sh = reinterpret_cast<S*>(sh_raw);
   constexpr int PS = two_e_ps_stride<D2>();
   const int n = a.n, R2 = a.R2, d2 = a.d2;
-  float* Ps = sh;                                                // [slots][PS]
-  float* Ws = sh + ((size_t)a.ipb * n * R2 * PS + 3) / 4 * 4;    // [D2][D2] then c[D2], 16-byte aligned
+  S* Ps = sh;                                                // [slots][PS]
+  S* Ws = sh + ((size_t)a.ipb * n * R2 * PS + 3) / 4 * 4;    // [D2][D2] then c[D2], 16-byte aligned
   const int tid = threadIdx.x;
   const int slots = a.ipb * n * R2;
   const int64_t gbase = (int64_t)blockIdx.x * a.ipb;
@@ -147,27 +154,27 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
 
   // input pair features (r_i - r_j, |r_i - r_j|) and their sparse jets
   if (live) {
-    float in[4] = {0.f, 0.f, 0.f, 0.f};
+    S in[4] = {0, 0, 0, 0};
     if (i != j) {
       const float* ri = a.pos + (w * n + i) * 3;
       const float* rj = a.pos + (w * n + j) * 3;
-      float dd[3] = {ri[0] - rj[0], ri[1] - rj[1], ri[2] - rj[2]};
-      float dist = sqrtf(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+      const S dd[3] = {(S)ri[0] - (S)rj[0], (S)ri[1] - (S)rj[1], (S)ri[2] - (S)rj[2]};
+      const S dist = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
       if (q == 0) {
         in[0] = dd[0]; in[1] = dd[1]; in[2] = dd[2]; in[3] = dist;
       } else if (q <= 6) {
         const int c = (q - 1) % 3;
-        const float sgn = q <= 3 ? 1.0f : -1.0f;  // d/dr_i or d/dr_j
-        in[0] = c == 0 ? sgn : 0.0f;
-        in[1] = c == 1 ? sgn : 0.0f;
-        in[2] = c == 2 ? sgn : 0.0f;
+        const S sgn = q <= 3 ? (S)1 : (S)-1;  // d/dr_i or d/dr_j
+        in[0] = c == 0 ? sgn : (S)0;
+        in[1] = c == 1 ? sgn : (S)0;
+        in[2] = c == 2 ? sgn : (S)0;
         in[3] = sgn * dd[c] / dist;
       } else {
-        in[3] = 4.0f / dist;  // Laplacian over r_i and r_j of |r_i - r_j|
+        in[3] = (S)4 / dist;  // Laplacian over r_i and r_j of |r_i - r_j|
       }
     }
 #pragma unroll
-    for (int k = 0; k < D2; ++k) Ps[(size_t)s * PS + k] = k < 4 ? in[k] : 0.0f;
+    for (int k = 0; k < D2; ++k) Ps[(size_t)s * PS + k] = k < 4 ? in[k] : (S)0;
   }
 
   int ein = 4;
@@ -176,7 +183,7 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
     __syncthreads();
     // dense jets of g^a_i = mean_{j in a} h_ij from the pair activations in LDS
     {
-      TA* G = reinterpret_cast<TA*>(a.G[l]);
+      S* G = reinterpret_cast<S*>(a.G[l]);
       const int ldg = a.ldg[l];
       const int T = a.T, Tp = a.Tp;
       // each thread owns one column c = (spin a, feature o) and a stride of
@@ -185,17 +192,17 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
       const bool colv = c < 2 * ein;
       const int al = colv ? c / ein : 0, o = colv ? c % ein : 0;
       const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n_dn;
-      const float inv_na = na > 0 ? 1.0f / (float)na : 0.0f;
+      const S inv_na = na > 0 ? (S)1 / (S)na : (S)0;
       for (int e = 0; e < a.ipb; ++e) {
         const int64_t ge = gbase + e;
         if (ge >= n_groups) break;
         const int ie = (int)(ge % n);
-        const float* base = Ps + (size_t)e * n * R2 * PS + o;
-        TA* Gr = G + ge * Tp * (int64_t)ldg + c;
+        const S* base = Ps + (size_t)e * n * R2 * PS + o;
+        S* Gr = G + ge * Tp * (int64_t)ldg + c;
         for (int t = tid / ldg; t < Tp; t += rstep) {
-          float v = 0.0f;
+          S v = 0;
           if (colv && na > 0 && t < T) {
-            float acc = 0.0f;
+            S acc = 0;
             if (t == 0) {
               for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2) * PS];
             } else if (t == T - 1) {
@@ -210,69 +217,75 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
             }
             v = acc * inv_na;
           }
-          st_act(Gr + (int64_t)t * ldg, v);
+          Gr[(int64_t)t * ldg] = v;
         }
       }
       if (a.h2_out[l] && R2 == 1) {
         for (int idx = tid; idx < a.ipb * n * ein; idx += blockDim.x) {
           const int e = idx / (n * ein), jj = (idx / ein) % n, o = idx % ein;
           const int64_t ge = gbase + e;
-          if (ge < n_groups) a.h2_out[l][(ge * n + jj) * ein + o] = Ps[(size_t)(e * n + jj) * PS + o];
+          if (ge < n_groups) a.h2_out[l][(ge * n + jj) * ein + o] = (float)Ps[(size_t)(e * n + jj) * PS + o];
         }
       }
     }
     if (l + 1 == a.L) break;
     // two-electron layer l: h' = tanh(h W_l + c_l) (+ h when widths match)
     for (int k = tid; k < D2 * D2 + D2; k += blockDim.x) {
-      float v = 0.0f;
+      S v = 0;
       if (k < D2 * D2) {
         const int kr = k / D2, o = k % D2;
-        if (kr < ein && o < d2) v = a.params[a.w_off[l] + kr * d2 + o];
+        if (kr < ein && o < d2) v = (S)a.params[a.w_off[l] + kr * d2 + o];
       } else if (k - D2 * D2 < d2) {
-        v = a.params[a.c_off[l] + (k - D2 * D2)];
+        v = (S)a.params[a.c_off[l] + (k - D2 * D2)];
       }
       Ws[k] = v;
     }
     __syncthreads();
-    float u[D2];
+    S u[D2];
 #pragma unroll
-    for (int o = 0; o < D2; ++o) u[o] = q == 0 ? Ws[D2 * D2 + o] : 0.0f;
+    for (int o = 0; o < D2; ++o) u[o] = q == 0 ? Ws[D2 * D2 + o] : (S)0;
     if (live) {
       for (int k = 0; k < ein; ++k) {
-        const float x = Ps[(size_t)s * PS + k];
-        const float4* wr = reinterpret_cast<const float4*>(Ws + k * D2);
+        const S x = Ps[(size_t)s * PS + k];
+        if constexpr (sizeof(S) == 4) {
+          const float4* wr = reinterpret_cast<const float4*>(Ws + k * D2);
 #pragma unroll
-        for (int o4 = 0; o4 < D2 / 4; ++o4) {
-          const float4 wv = wr[o4];
-          u[4 * o4] += x * wv.x;
-          u[4 * o4 + 1] += x * wv.y;
-          u[4 * o4 + 2] += x * wv.z;
-          u[4 * o4 + 3] += x * wv.w;
+          for (int o4 = 0; o4 < D2 / 4; ++o4) {
+            const float4 wv = wr[o4];
+            u[4 * o4] += x * wv.x;
+            u[4 * o4 + 1] += x * wv.y;
+            u[4 * o4 + 2] += x * wv.z;
+            u[4 * o4 + 3] += x * wv.w;
+          }
+        } else {
+          const S* wr = Ws + k * D2;
+#pragma unroll
+          for (int o = 0; o < D2; ++o) u[o] += x * wr[o];
         }
       }
     }
     const bool res = ein == d2;
 #pragma unroll
     for (int o = 0; o < D2; ++o) {
-      const float uo = u[o];
-      float y, dy, s2 = 0.0f;
+      const S uo = u[o];
+      S y, dy, s2 = 0;
       if (R2 == 8) {
-        const float u0 = __shfl(uo, tid & ~7, 64);
-        float sq = (q >= 1 && q <= 6) ? uo * uo : 0.0f;
+        const S u0 = __shfl(uo, tid & ~7, 64);
+        S sq = (q >= 1 && q <= 6) ? uo * uo : (S)0;
         sq += __shfl_xor(sq, 1, 64);
         sq += __shfl_xor(sq, 2, 64);
         sq += __shfl_xor(sq, 4, 64);
         s2 = sq;
-        tanh_sech2f(u0, &y, &dy);
+        tanh_sech2(u0, &y, &dy);
       } else {
-        tanh_sech2f(uo, &y, &dy);
+        tanh_sech2(uo, &y, &dy);
       }
-      float outv;
+      S outv;
       if (q == 0) outv = y;
       else if (q <= 6) outv = dy * uo;
-      else outv = dy * uo - 2.0f * y * dy * s2;
+      else outv = dy * uo - (S)2 * y * dy * s2;
       if (res && live) outv += Ps[(size_t)s * PS + o];
-      u[o] = o < d2 ? outv : 0.0f;
+      u[o] = o < d2 ? outv : (S)0;
     }
     ein = d2;
     __syncthreads();
@@ -283,24 +296,45 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
   }
 }
 
-template <class TA, int D2>
+template <class S, int D2>
 static hipError_t run_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
   const size_t shmem =
-      (two_e_ws_offset(d.ipb * d.n * d.R2, two_e_ps_stride<D2>()) + (size_t)D2 * D2 + D2) * sizeof(float);
-  hipLaunchKernelGGL((two_electron_kernel<TA, D2>), dim3(grid), dim3(256), shmem, s, d);
+      (two_e_ws_offset(d.ipb * d.n * d.R2, two_e_ps_stride<D2>()) + (size_t)D2 * D2 + D2) * sizeof(S);
+  if (shmem > 65536) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&two_electron_kernel<S, D2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+        return hipErrorInvalidValue;
+      attr_set = true;
+    }
+  }
+  hipLaunchKernelGGL((two_electron_kernel<S, D2>), dim3(grid), dim3(256), shmem, s, d);
   return hipGetLastError();
 }
 
-template <class TA>
+template <class S>
 static hipError_t pick_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
-  if (d.d2 <= 4) return run_two_e<TA, 4>(d, grid, s);
-  if (d.d2 <= 8) return run_two_e<TA, 8>(d, grid, s);
-  if (d.d2 <= 16) return run_two_e<TA, 16>(d, grid, s);
-  if (d.d2 <= 32) return run_two_e<TA, 32>(d, grid, s);
-  return run_two_e<TA, 64>(d, grid, s);
+  if (d.d2 <= 4) return run_two_e<S, 4>(d, grid, s);
+  if (d.d2 <= 8) return run_two_e<S, 8>(d, grid, s);
+  if (d.d2 <= 16) return run_two_e<S, 16>(d, grid, s);
+  if (d.d2 <= 32) return run_two_e<S, 32>(d, grid, s);
+  return run_two_e<S, 64>(d, grid, s);
 }
 
-hipError_t launch_two_electron(bool bf16, const TwoElecArgs& a, hipStream_t s) {
+// electrons per block of the two-electron stream: at most 256 slots and at
+// most 64 KiB of LDS, or one electron in up to 160 KiB (the LDS of a CU)
+// when one does not fit in 64 KiB; 0 if it does not fit at all
+int two_electron_per_block(int n, int d2, int T, int scalar_bytes) {
+  const int R2 = T > 1 ? 8 : 1;
+  const int D2p = d2 <= 4 ? 4 : d2 <= 8 ? 8 : d2 <= 16 ? 16 : d2 <= 32 ? 32 : 64;
+  const int fixed = 4 + D2p * D2p + D2p, per = n * R2 * (D2p + 1);
+  const int cap64 = (65536 / scalar_bytes - fixed) / per;
+  if (cap64 >= 1) return std::min(256 / (n * R2), cap64);
+  return (160 * 1024 / scalar_bytes - fixed) / per >= 1 ? 1 : 0;
+}
+
+hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s) {
   TwoElecDev d;
   d.pos = a.pos;
   d.params = a.params;
@@ -314,21 +348,18 @@ hipError_t launch_two_electron(bool bf16, const TwoElecArgs& a, hipStream_t s) {
   d.W = a.W; d.n = a.n; d.n_up = a.n_up; d.L = a.L; d.d2 = a.d2; d.T = a.T; d.Tp = a.Tp;
   d.R2 = a.T > 1 ? 8 : 1;
   if (a.d2 > 64 || a.n * d.R2 > 256 || a.L > 8) return hipErrorInvalidValue;
-  // electrons per block: at most 256 slots and at most 64 KiB of LDS
-  const int D2p = a.d2 <= 4 ? 4 : a.d2 <= 8 ? 8 : a.d2 <= 16 ? 16 : a.d2 <= 32 ? 32 : 64;
-  const int lds_cap = (65536 / 4 - 4 - D2p * D2p - D2p) / (a.n * d.R2 * (D2p + 1));
-  d.ipb = std::min(256 / (a.n * d.R2), lds_cap);
+  d.ipb = two_electron_per_block(a.n, a.d2, a.T, f64 ? 8 : 4);
   if (d.ipb < 1) return hipErrorInvalidValue;
   const int64_t groups = (int64_t)a.W * a.n;
   const int grid = (int)((groups + d.ipb - 1) / d.ipb);
   if (grid <= 0) return hipSuccess;
-  return bf16 ? pick_two_e<bf16_t>(d, grid, s) : pick_two_e<float>(d, grid, s);
+  return f64 ? pick_two_e<double>(d, grid, s) : pick_two_e<float>(d, grid, s);
 }
 
 // ------------------------------------------------------------ mean fields
 // Hbar[(w Tp + t)][a din_p + f] = mean_{j of spin a} H[((w n + j) Tp + t)][f]
-template <class TA>
-__global__ void meanfield_kernel(const TA* H, int ldh, int W, int n, int n_up, int Tp, int din_p, TA* Hbar) {
+template <class S>
+__global__ void meanfield_kernel(const S* H, int ldh, int W, int n, int n_up, int Tp, int din_p, S* Hbar) {
   const int64_t total = (int64_t)W * Tp * 2 * din_p;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(idx % (2 * din_p));
@@ -337,9 +368,9 @@ __global__ void meanfield_kernel(const TA* H, int ldh, int W, int n, int n_up, i
     const int64_t w = row / Tp;
     const int al = c / din_p, f = c % din_p;
     const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n - n_up;
-    float acc = 0.0f;
-    for (int j = j0; j < j0 + na; ++j) acc += ld_act(H + ((w * n + j) * Tp + t) * (int64_t)ldh + f);
-    st_act(Hbar + idx, na > 0 ? acc / (float)na : 0.0f);
+    S acc = 0;
+    for (int j = j0; j < j0 + na; ++j) acc += H[((w * n + j) * Tp + t) * (int64_t)ldh + f];
+    Hbar[idx] = na > 0 ? acc / (S)na : (S)0;
   }
 }
 
@@ -370,19 +401,24 @@ __global__ void meanfield4_kernel(const float* H, int ldh, int W, int n, int n_u
   }
 }
 
-hipError_t launch_meanfield(bool bf16, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
+hipError_t launch_meanfield(bool f64, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
                             hipStream_t s) {
   int64_t total = (int64_t)W * Tp * 2 * din_p;
   int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (grid <= 0) return hipSuccess;
-  if (!bf16 && din_p % 4 == 0 && ldh % 4 == 0) {
+  if (f64) {
+    hipLaunchKernelGGL(meanfield_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)H, ldh, W, n, n_up, Tp,
+                       din_p, (double*)Hbar);
+    return hipGetLastError();
+  }
+  if (din_p % 4 == 0 && ldh % 4 == 0) {
     const int64_t t4 = (int64_t)W * Tp * (din_p / 4);
     hipLaunchKernelGGL(meanfield4_kernel, dim3((unsigned)std::min<int64_t>((t4 + 255) / 256, 1 << 20)), dim3(256), 0, s,
                        (const float*)H, ldh, W, n, n_up, Tp, din_p, (float*)Hbar);
     return hipGetLastError();
   }
-  if (bf16) hipLaunchKernelGGL(meanfield_kernel<bf16_t>, dim3(grid), dim3(256), 0, s, (const bf16_t*)H, ldh, W, n, n_up, Tp, din_p, (bf16_t*)Hbar);
-  else hipLaunchKernelGGL(meanfield_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p, (float*)Hbar);
+  hipLaunchKernelGGL(meanfield_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p,
+                     (float*)Hbar);
   return hipGetLastError();
 }
 

@@ -10,15 +10,18 @@
 // the squared pre-activation) or the product rule with the envelope
 // without leaving the tile.
 //
-// Tile: BM rows (whole electrons) x BN columns, K step 32, 256 threads as
-// 2 x 2 wavefronts of 64, each wavefront a grid of 16x16 MFMA tiles.
-// Activations are float32 in HBM.  Two arithmetic modes:
-//   MODE_F32:   v_mfma_f32_16x16x4_f32 on the float32 operands
+// Tile: BM rows (whole electrons) x BN columns, 256 threads as 2 x 2
+// wavefronts of 64, each wavefront a grid of 16x16 MFMA tiles.  Three
+// arithmetic modes:
+//   MODE_F32:   v_mfma_f32_16x16x4_f32 on float32 operands, K step 32
 //   MODE_BF16X3: each operand split x = hi + lo into two bfloat16 (16
 //               significand bits in all) and x y ~ hi_x hi_y + hi_x lo_y +
 //               lo_x hi_y by three v_mfma_f32_16x16x32_bf16 into one
 //               float32 accumulator; the activations are split while being
-//               staged into LDS, the weights are pre-split by the packer.
+//               staged into LDS, the weights are pre-split by the packer
+//   MODE_F64:   v_mfma_f64_16x16x4_f64 on float64 operands, K step 16, with
+//               float64 activations and a float64 epilogue (the float64
+//               re-evaluation of ill-conditioned walkers)
 // Global -> register -> LDS double buffering: the next K tile is fetched
 // while the current one is multiplied.
 #include "common.h"
@@ -26,19 +29,39 @@
 
 namespace fn {
 
-template <int MODE, int BM, int BN>
-struct Smem {
+template <int MODE> struct ModeT {
+  using S = float;  // activations, accumulators and epilogue
+  using Acc = floatx4;
   static constexpr int BK = 32;
-  // fp32: one plane of floats, row stride BK+4; split bf16: hi and lo planes
-  // of bf16, row stride BK+8
-  static constexpr int LDS_K = MODE == MODE_F32 ? BK + 4 : BK + 8;
+  static constexpr int LDS_K = MODE == MODE_F32 ? BK + 4 : BK + 8;  // staged row stride (elements)
   static constexpr int ESZ = MODE == MODE_F32 ? 4 : 2;
   static constexpr int PLANES = MODE == MODE_F32 ? 1 : 2;
-  static constexpr int A_PLANE = BM * LDS_K * ESZ;
-  static constexpr int B_PLANE = BN * LDS_K * ESZ;
-  static constexpr int AB_BYTES = PLANES * (A_PLANE + B_PLANE);
-  static constexpr int LDC = BN + 4;
-  static constexpr int C_BYTES = BM * LDC * 4;
+  static constexpr int VPR_A = BK / 4;                               // 16-byte vectors per A tile row
+  static constexpr int VPR_B = MODE == MODE_F32 ? BK / 4 : BK / 8;   // 16-byte vectors per B tile row
+  static constexpr int LDC_PAD = 4;
+};
+template <> struct ModeT<MODE_F64> {
+  using S = double;
+  using Acc = doublex4;
+  static constexpr int BK = 16;
+  static constexpr int LDS_K = BK + 1;
+  static constexpr int ESZ = 8;
+  static constexpr int PLANES = 1;
+  static constexpr int VPR_A = BK / 2;
+  static constexpr int VPR_B = BK / 2;
+  static constexpr int LDC_PAD = 1;
+};
+
+template <int MODE, int BM, int BN>
+struct Smem {
+  using M = ModeT<MODE>;
+  static constexpr int BK = M::BK;
+  static constexpr int LDS_K = M::LDS_K;
+  static constexpr int A_PLANE = BM * LDS_K * M::ESZ;
+  static constexpr int B_PLANE = BN * LDS_K * M::ESZ;
+  static constexpr int AB_BYTES = M::PLANES * (A_PLANE + B_PLANE);
+  static constexpr int LDC = BN + M::LDC_PAD;
+  static constexpr int C_BYTES = BM * LDC * (int)sizeof(typename M::S);
   static constexpr int BYTES = AB_BYTES > C_BYTES ? AB_BYTES : C_BYTES;
 };
 
@@ -47,15 +70,16 @@ __device__ inline uint32_t pack2(uint16_t a, uint16_t b) { return (uint32_t)a | 
 template <int MODE, int BM, int BN, int EPI>
 __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
   using SM = Smem<MODE, BM, BN>;
+  using MT = ModeT<MODE>;
+  using S = typename MT::S;
   constexpr int BK = SM::BK;
   constexpr int LDS_K = SM::LDS_K;
   constexpr int TM = BM / 32, TN = BN / 32;
-  constexpr int VPR_A = BK / 4;                             // float4 vectors per A tile row
-  constexpr int VPR_B = MODE == MODE_F32 ? BK / 4 : BK / 8;  // 16-byte vectors per B tile row
+  constexpr int VPR_A = MT::VPR_A, VPR_B = MT::VPR_B;
   constexpr int NVA = (BM * VPR_A + 255) / 256;
   constexpr int NVB = (BN * VPR_B + 255) / 256;
   __shared__ __attribute__((aligned(16))) char smem[SM::BYTES];
-  float* Cs = reinterpret_cast<float*>(smem);
+  S* Cs = reinterpret_cast<S*>(smem);
 
   // XCD-aware tile order: the n_ntiles column tiles of one row tile are
   // given block ids that differ by multiples of 8, so they land on the same
@@ -91,17 +115,19 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
     }
   }
 
-  uint4 ra[NVA], rb[NVB], rbl[MODE == MODE_F32 ? 1 : NVB];
+  // A and B elements: S (float32 or float64); the split form reads bfloat16 B
+  constexpr int EA = 16 / (int)sizeof(S);  // A elements per 16-byte vector
+  uint4 ra[NVA], rb[NVB], rbl[MODE == MODE_BF16X3 ? NVB : 1];
   auto load = [&](int kt) {
     const int kb = kt * BK;
-    const float* src;
+    const S* src;
     int lda, kk;
     if (kb < a.ka0) {
-      src = (const float*)a.a0;
+      src = (const S*)a.a0;
       lda = a.lda0;
       kk = kb;
     } else {
-      src = (const float*)a.a1;
+      src = (const S*)a.a1;
       lda = a.lda1;
       kk = kb - a.ka0;
     }
@@ -110,7 +136,7 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       int v = tid + i * 256;
       uint4 z = {0, 0, 0, 0};
       if (v < BM * VPR_A && rowoff[i] >= 0) {
-        int kv = (v % VPR_A) * 4;
+        int kv = (v % VPR_A) * EA;
         z = *reinterpret_cast<const uint4*>(src + (size_t)rowoff[i] * lda + kk + kv);
       }
       ra[i] = z;
@@ -122,18 +148,18 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       if (v < BN * VPR_B) {
         int nn = v / VPR_B, col = n0 + nn;
         if (col < a.N) {
-          if constexpr (MODE == MODE_F32) {
-            int kv = (v % VPR_B) * 4;
-            z = *reinterpret_cast<const uint4*>((const float*)a.bt + (size_t)col * a.ldb + kb + kv);
-          } else {
+          if constexpr (MODE == MODE_BF16X3) {
             int kv = (v % VPR_B) * 8;
             z = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt + (size_t)col * a.ldb + kb + kv);
             zl = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt_lo + (size_t)col * a.ldb + kb + kv);
+          } else {
+            int kv = (v % VPR_B) * EA;
+            z = *reinterpret_cast<const uint4*>((const S*)a.bt + (size_t)col * a.ldb + kb + kv);
           }
         }
       }
       rb[i] = z;
-      if constexpr (MODE != MODE_F32) rbl[i] = zl;
+      if constexpr (MODE == MODE_BF16X3) rbl[i] = zl;
     }
   };
   auto store = [&]() {
@@ -149,6 +175,28 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       for (int i = 0; i < NVB; ++i) {
         int v = tid + i * 256;
         if (v < BN * VPR_B) *reinterpret_cast<uint4*>(Bs + (v / VPR_B) * LDS_K + (v % VPR_B) * 4) = rb[i];
+      }
+    } else if constexpr (MODE == MODE_F64) {
+      // odd row stride: 8-byte stores
+      double* As = reinterpret_cast<double*>(smem);
+      double* Bs = reinterpret_cast<double*>(smem + SM::A_PLANE);
+#pragma unroll
+      for (int i = 0; i < NVA; ++i) {
+        int v = tid + i * 256;
+        if (v < BM * VPR_A) {
+          double* d = As + (v / VPR_A) * LDS_K + (v % VPR_A) * 2;
+          d[0] = __builtin_bit_cast(double, uint2{ra[i].x, ra[i].y});
+          d[1] = __builtin_bit_cast(double, uint2{ra[i].z, ra[i].w});
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NVB; ++i) {
+        int v = tid + i * 256;
+        if (v < BN * VPR_B) {
+          double* d = Bs + (v / VPR_B) * LDS_K + (v % VPR_B) * 2;
+          d[0] = __builtin_bit_cast(double, uint2{rb[i].x, rb[i].y});
+          d[1] = __builtin_bit_cast(double, uint2{rb[i].z, rb[i].w});
+        }
       }
     } else {
       uint16_t* Ah = reinterpret_cast<uint16_t*>(smem);
@@ -181,11 +229,11 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
     }
   };
 
-  floatx4 acc[TM][TN];
+  typename MT::Acc acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TN; ++j) acc[i][j] = typename MT::Acc{0, 0, 0, 0};
 
   const int arow = wm * (BM / 2) + (lane & 15);
   const int brow = wn * (BN / 2) + (lane & 15);
@@ -197,12 +245,12 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
     store();
     __syncthreads();
     if (kt + 1 < nkt) load(kt + 1);
-    if constexpr (MODE == MODE_F32) {
-      const float* As = reinterpret_cast<const float*>(smem);
-      const float* Bs = reinterpret_cast<const float*>(smem + SM::A_PLANE);
+    if constexpr (MODE == MODE_F32 || MODE == MODE_F64) {
+      const S* As = reinterpret_cast<const S*>(smem);
+      const S* Bs = reinterpret_cast<const S*>(smem + SM::A_PLANE);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
-        float af[TM], bfr[TN];
+        S af[TM], bfr[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) af[i] = As[(arow + i * 16) * LDS_K + ks * 4 + kq];
 #pragma unroll
@@ -210,8 +258,12 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (MODE == MODE_F64)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            else
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
+          }
       }
     } else {
       const uint16_t* Ah = reinterpret_cast<const uint16_t*>(smem);
@@ -243,32 +295,34 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
   __syncthreads();
   // accumulators -> LDS tile [BM][BN]; the layer epilogue first adds the
   // per-walker mean-field term P (every jet row) and the bias (value row),
-  // all loads issued together from the accumulator layout
+  // all loads issued together from the accumulator layout.  Item r of lane
+  // (kq, c) holds row 4 kq + r of its 16x16 tile for the float32 and
+  // bfloat16 instructions, row kq + 4 r for the float64 one; column c.
   constexpr int LDC = SM::LDC;
   const int T = a.T;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = wm * (BM / 2) + i * 16 + kq * 4 + r;
+      const int row = wm * (BM / 2) + i * 16 + (MODE == MODE_F64 ? kq + 4 * r : kq * 4 + r);
       // row bookkeeping once per row (not per element)
-      const float* Prow = nullptr;
+      const S* Prow = nullptr;
       bool bias_row = false;
       if constexpr (EPI == EPI_TANHJET) {
         const int e = row / rows_per, t = row % rows_per;
         const int g = g0 + e;
-        if (g < a.n_groups && t < T) Prow = a.P + ((size_t)(g / a.n_all) * rows_per + t) * a.ldp;
+        if (g < a.n_groups && t < T) Prow = (const S*)a.P + ((size_t)(g / a.n_all) * rows_per + t) * a.ldp;
         bias_row = t == 0;
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int col = wn * (BN / 2) + j * 16 + (lane & 15);
-        float v = acc[i][j][r];
+        S v = acc[i][j][r];
         if constexpr (EPI == EPI_TANHJET) {
           const int gc = n0 + col;
           if (Prow && gc < a.N) {
             v += Prow[gc];
-            if (bias_row) v += a.bias[gc];
+            if (bias_row) v += (S)a.bias[gc];
           }
         }
         Cs[row * LDC + col] = v;
@@ -282,8 +336,8 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       int g = g0 + e, gc = n0 + col;
       if (g < a.n_groups && gc < a.N) {
         const long og = a.c_nsub ? (long)(g / a.c_nsub) * a.c_nall + a.c_eoff + (g % a.c_nsub) : (long)g;
-        float* dst = a.c + ((size_t)og * rows_per + t) * a.ldc + gc;
-        const float v = Cs[r * LDC + col];
+        S* dst = (S*)a.c + ((size_t)og * rows_per + t) * a.ldc + gc;
+        const S v = Cs[r * LDC + col];
         *dst = a.c_accum ? *dst + v : v;
       }
     }
@@ -295,48 +349,62 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       const int e = p / BN, col = p % BN;
       const int g = g0 + e, gc = n0 + col;
       if (g >= a.n_groups || gc >= a.N) continue;
-      float* Cr = Cs + (e * rows_per) * LDC + col;
-      const float u0 = Cr[0];
-      float y, dy;
-      tanh_sech2f(u0, &y, &dy);
-      if (a.pre_out) a.pre_out[(size_t)g * a.N + gc] = u0;
+      S* Cr = Cs + (e * rows_per) * LDC + col;
+      const S u0 = Cr[0];
+      S y, dy;
+      tanh_sech2(u0, &y, &dy);
+      if (a.pre_out) a.pre_out[(size_t)g * a.N + gc] = (float)u0;
       Cr[0] = y;
       if (T > 1) {
-        float s2 = 0.0f;
+        S s2 = 0;
         for (int t = 1; t < T - 1; ++t) {
-          const float u = Cr[t * LDC];
+          const S u = Cr[t * LDC];
           s2 += u * u;
         }
         for (int t = 1; t < T - 1; ++t) Cr[t * LDC] *= dy;
-        Cr[(T - 1) * LDC] = dy * Cr[(T - 1) * LDC] - 2.0f * y * dy * s2;
-        for (int t = T; t < rows_per; ++t) Cr[t * LDC] = 0.0f;
+        Cr[(T - 1) * LDC] = dy * Cr[(T - 1) * LDC] - (S)2 * y * dy * s2;
+        for (int t = T; t < rows_per; ++t) Cr[t * LDC] = 0;
       }
     }
     __syncthreads();
     // coalesced write-out of whole rows, residual added on the way
-    float* out = reinterpret_cast<float*>(a.out);
-    const float* res = reinterpret_cast<const float*>(a.a0);
-    constexpr int V4 = BN / 4;
-    for (int p = tid; p < BM * V4; p += 256) {
-      const int r = p / V4, c4 = (p % V4) * 4;
-      const int e = r / rows_per, t = r % rows_per;
-      const int g = g0 + e, gc = n0 + c4;
-      if (g >= a.n_groups || gc >= a.N) continue;
-      const size_t orow = (size_t)g * rows_per + t;
-      float4 v = *reinterpret_cast<const float4*>(Cs + r * LDC + c4);
-      if (a.res) {
-        const float4 rr = *reinterpret_cast<const float4*>(res + orow * a.lda0 + gc);
-        v.x += rr.x;
-        v.y += rr.y;
-        v.z += rr.z;
-        v.w += rr.w;
+    S* out = reinterpret_cast<S*>(a.out);
+    const S* res = reinterpret_cast<const S*>(a.a0);
+    if constexpr (MODE == MODE_F64) {
+      for (int p = tid; p < BM * BN; p += 256) {
+        const int r = p / BN, c = p % BN;
+        const int e = r / rows_per, t = r % rows_per;
+        const int g = g0 + e, gc = n0 + c;
+        if (g >= a.n_groups || gc >= a.N) continue;
+        const size_t orow = (size_t)g * rows_per + t;
+        S v = Cs[r * LDC + c];
+        if (a.res) v += res[orow * a.lda0 + gc];
+        out[orow * a.ldo + gc] = v;
       }
-      *reinterpret_cast<float4*>(out + orow * a.ldo + gc) = v;
+    } else {
+      constexpr int V4 = BN / 4;
+      for (int p = tid; p < BM * V4; p += 256) {
+        const int r = p / V4, c4 = (p % V4) * 4;
+        const int e = r / rows_per, t = r % rows_per;
+        const int g = g0 + e, gc = n0 + c4;
+        if (g >= a.n_groups || gc >= a.N) continue;
+        const size_t orow = (size_t)g * rows_per + t;
+        float4 v = *reinterpret_cast<const float4*>(Cs + r * LDC + c4);
+        if (a.res) {
+          const float4 rr = *reinterpret_cast<const float4*>(res + orow * a.lda0 + gc);
+          v.x += rr.x;
+          v.y += rr.y;
+          v.z += rr.z;
+          v.w += rr.w;
+        }
+        *reinterpret_cast<float4*>(out + orow * a.ldo + gc) = v;
+      }
     }
   } else {  // EPI_ORBITAL
     const int na = a.n_sub;
     const int nsq = na * na;
     const int Kd = a.N / na;
+    S* phi = reinterpret_cast<S*>(a.phi);
     for (int p = tid; p < E * BN; p += 256) {
       int e = p / BN, col = p % BN;
       int g = g0 + e, gc = n0 + col;
@@ -345,42 +413,42 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       const int j = a.e_off + jj;  // electron index
       const int k = gc / na, i = gc % na;
       const float* rj = a.pos + ((size_t)w * a.n_elec + j) * 3;
-      const float x0 = rj[0], x1 = rj[1], x2 = rj[2];
+      const S x0 = rj[0], x1 = rj[1], x2 = rj[2];
       // isotropic envelope sum_m pi exp(-|sigma| d) and its gradient and
       // Laplacian with respect to r_j
-      float e0 = 0.f, ex = 0.f, ey = 0.f, ez = 0.f, le = 0.f;
+      S e0 = 0, ex = 0, ey = 0, ez = 0, le = 0;
       for (int m = 0; m < a.n_nuc; ++m) {
-        float dx = x0 - a.nuc[3 * m], dyv = x1 - a.nuc[3 * m + 1], dz = x2 - a.nuc[3 * m + 2];
-        float d = sqrtf(dx * dx + dyv * dyv + dz * dz);
-        float s = fabsf(a.sigma[(size_t)gc * a.n_nuc + m]);
-        float v = a.pi[(size_t)gc * a.n_nuc + m] * expf(-s * d);
-        float inv_d = 1.0f / d;
+        const S dx = x0 - (S)a.nuc[3 * m], dyv = x1 - (S)a.nuc[3 * m + 1], dz = x2 - (S)a.nuc[3 * m + 2];
+        const S d = sqrt(dx * dx + dyv * dyv + dz * dz);
+        const S sg = fabs((S)a.sigma[(size_t)gc * a.n_nuc + m]);
+        const S v = (S)a.pi[(size_t)gc * a.n_nuc + m] * exp(-sg * d);
+        const S inv_d = (S)1 / d;
         e0 += v;
-        ex -= s * v * dx * inv_d;
-        ey -= s * v * dyv * inv_d;
-        ez -= s * v * dz * inv_d;
-        le += v * (s * s - 2.0f * s * inv_d);
+        ex -= sg * v * dx * inv_d;
+        ey -= sg * v * dyv * inv_d;
+        ez -= sg * v * dz * inv_d;
+        le += v * (sg * sg - (S)2 * sg * inv_d);
       }
-      const float* Cr = Cs + (e * rows_per) * LDC + col;
-      const float u0 = Cr[0] + a.g_orb[gc];
+      const S* Cr = Cs + (e * rows_per) * LDC + col;
+      const S u0 = Cr[0] + (S)a.g_orb[gc];
       const int64_t mat = (int64_t)w * Kd + k;
       const size_t ts = a.phi_M ? (size_t)nsq * a.phi_M : (size_t)nsq;  // stride between jet rows
-      float* ph = a.phi_M ? a.phi + (size_t)(jj * na + i) * a.phi_M + mat : a.phi + (size_t)mat * T * nsq + jj * na + i;
+      S* ph = a.phi_M ? phi + (size_t)(jj * na + i) * a.phi_M + mat : phi + (size_t)mat * T * nsq + jj * na + i;
       ph[0] = u0 * e0;
       if (a.u_out) {
         size_t o = ((size_t)(w * Kd + k) * na + jj) * na + i;
-        a.u_out[o] = u0;
-        a.env_out[o] = e0;
+        a.u_out[o] = (float)u0;
+        a.env_out[o] = (float)e0;
       }
       if (T > 1) {
         const int tj = 1 + 3 * j;
         for (int t = 1; t < T - 1; ++t) ph[(size_t)t * ts] = Cr[t * LDC] * e0;
-        const float ux = Cr[tj * LDC], uy = Cr[(tj + 1) * LDC], uz = Cr[(tj + 2) * LDC];
+        const S ux = Cr[tj * LDC], uy = Cr[(tj + 1) * LDC], uz = Cr[(tj + 2) * LDC];
         ph[(size_t)tj * ts] += u0 * ex;
         ph[(size_t)(tj + 1) * ts] += u0 * ey;
         ph[(size_t)(tj + 2) * ts] += u0 * ez;
-        const float lu = Cr[(T - 1) * LDC];
-        ph[(size_t)(T - 1) * ts] = lu * e0 + u0 * le + 2.0f * (ux * ex + uy * ey + uz * ez);
+        const S lu = Cr[(T - 1) * LDC];
+        ph[(size_t)(T - 1) * ts] = lu * e0 + u0 * le + (S)2 * (ux * ex + uy * ey + uz * ez);
       }
     }
   }
@@ -400,28 +468,37 @@ template <int MODE, int EPI>
 static hipError_t pick(const JetGemmArgs& a, hipStream_t s) {
   const bool bm96 = a.rows_per == 96;
   if (!bm96 && (128 % a.rows_per) != 0) return hipErrorInvalidValue;
-  // column tile: 128 unless 64 wastes fewer columns
-  int w128 = (a.N + 127) / 128 * 128 - a.N;
-  int w64 = (a.N + 63) / 64 * 64 - a.N;
-  const bool bn64 = a.N <= 64 || w64 < w128;
-  if (bm96) return bn64 ? run<MODE, 96, 64, EPI>(a, s) : run<MODE, 96, 128, EPI>(a, s);
-  return bn64 ? run<MODE, 128, 64, EPI>(a, s) : run<MODE, 128, 128, EPI>(a, s);
+  if constexpr (MODE == MODE_F64) {
+    // float64 tiles sized for the LDS epilogue tile (at most 50 KiB)
+    if (bm96) return run<MODE, 96, 64, EPI>(a, s);
+    if (a.rows_per == 128) return run<MODE, 128, 32, EPI>(a, s);
+    return run<MODE, 64, 64, EPI>(a, s);
+  } else {
+    // column tile: 128 unless 64 wastes fewer columns
+    int w128 = (a.N + 127) / 128 * 128 - a.N;
+    int w64 = (a.N + 63) / 64 * 64 - a.N;
+    const bool bn64 = a.N <= 64 || w64 < w128;
+    if (bm96) return bn64 ? run<MODE, 96, 64, EPI>(a, s) : run<MODE, 96, 128, EPI>(a, s);
+    return bn64 ? run<MODE, 128, 64, EPI>(a, s) : run<MODE, 128, 128, EPI>(a, s);
+  }
+}
+
+template <int MODE>
+static hipError_t pick_epi(int epi, const JetGemmArgs& a, hipStream_t s) {
+  if (epi == EPI_PLAIN) return pick<MODE, EPI_PLAIN>(a, s);
+  if (epi == EPI_TANHJET) return pick<MODE, EPI_TANHJET>(a, s);
+  return pick<MODE, EPI_ORBITAL>(a, s);
 }
 
 hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t s) {
   if (a.n_groups <= 0) return hipSuccess;
   if ((a.ka0 % 32) || (a.ka1 % 32)) return hipErrorInvalidValue;
+  if (mode == MODE_F64) return pick_epi<MODE_F64>(epi, a, s);
   // the one-electron layers take the full-width streaming kernel when their
   // shape allows it
   if (epi == EPI_TANHJET && layer_gemm_supported(a)) return launch_layer_gemm(mode, a, s);
-  if (mode == MODE_BF16X3) {
-    if (epi == EPI_PLAIN) return pick<MODE_BF16X3, EPI_PLAIN>(a, s);
-    if (epi == EPI_TANHJET) return pick<MODE_BF16X3, EPI_TANHJET>(a, s);
-    return pick<MODE_BF16X3, EPI_ORBITAL>(a, s);
-  }
-  if (epi == EPI_PLAIN) return pick<MODE_F32, EPI_PLAIN>(a, s);
-  if (epi == EPI_TANHJET) return pick<MODE_F32, EPI_TANHJET>(a, s);
-  return pick<MODE_F32, EPI_ORBITAL>(a, s);
+  if (mode == MODE_BF16X3) return pick_epi<MODE_BF16X3>(epi, a, s);
+  return pick_epi<MODE_F32>(epi, a, s);
 }
 
 }  // namespace fn

@@ -8,9 +8,10 @@
 namespace fn {
 
 enum { EPI_PLAIN = 0, EPI_TANHJET = 1, EPI_ORBITAL = 2 };
-// GEMM arithmetic: float32 MFMA, or three bfloat16 MFMA passes on operands
-// split into hi + lo parts
-enum { MODE_F32 = 0, MODE_BF16X3 = 1 };
+// GEMM arithmetic: float32 MFMA, three bfloat16 MFMA passes on operands
+// split into hi + lo parts, or float64 MFMA on float64 operands (then every
+// activation, mean-field term, orbital jet and epilogue is float64 too)
+enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_F64 = 2 };
 
 // One MFMA GEMM over rows grouped by "electron" (rows_per rows each: the
 // value row, the 3n tangent rows and the Laplacian row of a jet, padded),
@@ -19,21 +20,21 @@ enum { MODE_F32 = 0, MODE_BF16X3 = 1 };
 struct JetGemmArgs {
   const void* a0; int lda0; int ka0;  // A segment 0 (ka0 multiple of 32; elements)
   const void* a1; int lda1; int ka1;  // A segment 1 (ka1 multiple of 32, may be 0)
-  const void* bt; int ldb;            // packed weights [N][ldb], k contiguous, ldb >= ka0 + ka1
+  const void* bt; int ldb;            // packed weights [N][ldb], k contiguous, ldb >= ka0 + ka1 (mode's type)
   const void* bt_lo;                  // MODE_BF16X3: lo plane of the weights (bt holds the hi plane)
   int n_groups, rows_per, T;
   int n_sub, n_all, e_off;
   int N;
   // EPI_PLAIN: c[(og * rows_per + t) * ldc + col] (= or += when c_accum) with
   //   og = g, or (g / c_nsub) * c_nall + c_eoff + g % c_nsub when c_nsub > 0
-  float* c; int ldc;
+  void* c; int ldc;                   // float32 (float64 in MODE_F64)
   int c_nsub, c_nall, c_eoff, c_accum;
   // EPI_TANHJET: out[(g * rows_per + t) * ldo + col] (activation type), with
   //   P[((g / n_all) * rows_per + t) * ldp + col] added to every row, bias on
   //   the value row, residual from segment 0 when res != 0; pre_out[g * N + col]
   //   receives the pre-activation of the value row when not NULL
   void* out; int ldo;
-  const float* P; int ldp;
+  const void* P; int ldp;             // float32 (float64 in MODE_F64)
   const float* bias;
   int res;
   float* pre_out;
@@ -41,7 +42,7 @@ struct JetGemmArgs {
   //   w = g / n_sub, j = g % n_sub, col = k * n_sub + i
   //   or, when phi_M > 0 (matrix index fastest, for the small-matrix
   //   determinant kernel): phi[((t n_sub + j) n_sub + i) * phi_M + w * K + k]
-  float* phi;
+  void* phi;                          // float32 (float64 in MODE_F64)
   int64_t phi_M;
   const float* pos; const float* nuc; int n_nuc; int n_elec;
   const float* g_orb; const float* pi; const float* sigma;
@@ -54,10 +55,12 @@ bool layer_gemm_supported(const JetGemmArgs& a);
 hipError_t launch_layer_gemm(int mode, const JetGemmArgs& a, hipStream_t s);
 
 // ---- features and two-electron stream (features.hip)
-// split: write bfloat16 hi planes at dst and lo planes at dst + plane (elements)
-hipError_t launch_pack_weights(bool split, const float* params, void* dst, int64_t plane, const int64_t* plan,
+// mode MODE_F32 / MODE_F64: float32 / float64 weights; MODE_BF16X3:
+// bfloat16 hi planes at dst and lo planes at dst + plane (elements)
+hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t plane, const int64_t* plan,
                                int n_items, hipStream_t s);
-hipError_t launch_features(bool bf16, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
+// f64: float64 arithmetic and storage (otherwise float32)
+hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
                            void* H0, int ldh, hipStream_t s);
 struct TwoElecArgs {
   const float* pos;   // [W][n][3]
@@ -65,12 +68,14 @@ struct TwoElecArgs {
   const int64_t* w_off;  // HOST array: offsets of W_l in params, l = 0..L-2
   const int64_t* c_off;  // HOST array: offsets of c_l
   int W, n, n_up, L, d2, T, Tp;
-  void* G[8];         // G^l [(w n + i) Tp + t][ldg_l] (activation type)
+  void* G[8];         // G^l [(w n + i) Tp + t][ldg_l] (float32, or float64 with f64)
   int ldg[8];
   float* h2_out[8];   // value mode, optional: h^l_ij [w][i][j][ein_l]
 };
-hipError_t launch_two_electron(bool bf16, const TwoElecArgs& a, hipStream_t s);
-hipError_t launch_meanfield(bool bf16, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
+hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s);
+// electrons per workgroup of the two-electron stream (0: does not fit in LDS)
+int two_electron_per_block(int n, int d2, int T, int scalar_bytes);
+hipError_t launch_meanfield(bool f64, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
                             hipStream_t s);
 
 // ---- determinants and combination (det.hip)
@@ -80,16 +85,28 @@ hipError_t launch_meanfield(bool bf16, const void* H, int ldh, int W, int n, int
 // expects the matrix-index-fastest layout of the orbital jets (phi_M = W K)
 constexpr int DET_SMALL_MAX = 6;
 bool det_uses_small(int na);
-hipError_t launch_det(bool fp64, const float* phi, int W, int K, int na, int T, int n3, void* D, int dstride,
-                      void* ainv, hipStream_t s);
+// phi64: the orbital jets are float64 (requires fp64)
+hipError_t launch_det(bool fp64, const void* phi, bool phi64, int W, int K, int na, int T, int n3, void* D,
+                      int dstride, void* ainv, hipStream_t s);
 struct CombineArgs {
   const void* D[2]; int dstride; int na[2];
   int W, K, n, n3, N, jet;
   const float* pos; const float* nuc; const float* Z;
   float* sign; float* logpsi; float* e_loc; float* e_kin; float* e_pot;
   void* rho;  // optional [W][K]: rho_k = P_k / psi (value mode, adjoint)
+  float* ln_kappa;  // optional [W]: log of max_k |P_k| / |psi| (+inf at a node)
 };
 hipError_t launch_combine(bool fp64, const CombineArgs& a, hipStream_t s);
+
+// ---- float64 re-evaluation of selected walkers (rescue.hip)
+// idx[seg * k_seg + r], r < k_seg: the k_seg walkers of segment seg (walkers
+// seg * seg_len ..) with the largest key, in decreasing key order (NaN keys
+// count as +inf, ties by increasing index); seg_len <= 16384
+hipError_t launch_select_top(const float* key, int W, int seg_len, int k_seg, int32_t* idx, hipStream_t s);
+hipError_t launch_gather_walkers(const float* pos, const int32_t* idx, int R, int n3, float* pos_r, hipStream_t s);
+// out[idx[r]] = src[r] for each non-NULL (out, src) pair
+hipError_t launch_scatter_results(const int32_t* idx, int R, float* const* outs, const float* const* srcs, int n_out,
+                                  hipStream_t s);
 
 // ---- Metropolis (mcmc.hip)
 hipError_t launch_mcmc_noise(int W, int n, int n_steps, uint64_t seed, uint64_t counter, float* noise,

@@ -52,8 +52,12 @@ __device__ inline uint32_t pk2(uint16_t a, uint16_t b) { return (uint32_t)a | ((
 // consecutive rows read at one chunk index cover all banks once
 __device__ inline int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
 
-template <int MODE, int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
+// JET: the jet pass (rows_per jet rows per electron); otherwise the value
+// pass (one row per electron)
+template <int MODE, int BM, int BN, int WM, int WN, bool JET>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void layer_gemm_kernel(JetGemmArgs a,
+                                                                                                   int n_mtiles,
+                                                                                                   int n_ntiles) {
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
   constexpr int BK = C::BK, LDA = C::LDA, LDB = C::LDB, TM = C::TM, TN = C::TN, WROWS = C::WROWS;
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -64,7 +68,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   if (m_t >= n_mtiles) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int rows_per = a.rows_per;
+  const int rows_per = JET ? a.rows_per : 1;
   const int E = BM / rows_per;  // electrons per row tile
   const int g0 = m_t * E;
   const int n0 = n_t * BN;
@@ -234,15 +238,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
   for (int j = 0; j < TN; ++j) gcol[j] = n0 + wn * C::WCOLS + j * 16 + (lane & 15);
 
-  if (rows_per == 1) {
-    // value mode: every row is an electron
+  if constexpr (!JET) {
+    // value pass: every row is an electron
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int g = g0 + wm * WROWS + i * 16 + kq * 4 + r;
         if (g >= a.n_groups) continue;
-        const float* Prow = a.P + (size_t)(g / a.n_all) * a.ldp;
+        const float* Prow = (const float*)a.P + (size_t)(g / a.n_all) * a.ldp;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int gc = gcol[j];
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int tw0 = wrow0 - e_loc * rows_per;  // jet row of the wave's first row
   const int g = g0 + e_loc;
   const bool gval = g < a.n_groups;
-  const float* Pb = a.P + (size_t)(gval ? g / a.n_all : 0) * rows_per * a.ldp;
+  const float* Pb = (const float*)a.P + (size_t)(gval ? g / a.n_all : 0) * rows_per * a.ldp;
   const size_t obase = (size_t)(gval ? g : 0) * rows_per;
 
   // pre-activation u = acc + P (+ bias on the value row); partial sums of the
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
 }
 
-template <int MODE, int BM, int BN, int WM, int WN>
+template <int MODE, int BM, int BN, int WM, int WN, bool JET>
 static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
   const int E = BM / a.rows_per;
@@ -346,13 +350,13 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   const int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN, JET>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, C::BYTES) != hipSuccess)
       return hipErrorInvalidValue;
     attr_set = true;
   }
-  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN>), dim3(grid), dim3(C::NT), C::BYTES, s, a, n_mtiles,
-                     n_ntiles);
+  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN, JET>), dim3(grid), dim3(C::NT), C::BYTES, s, a,
+                     n_mtiles, n_ntiles);
   return hipGetLastError();
 }
 
@@ -360,9 +364,9 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
 // one electron (value mode: one row per electron)
 template <int MODE>
 static hipError_t pick_layer(const JetGemmArgs& a, hipStream_t s) {
-  if (a.rows_per == 96) return run_layer<MODE, 96, 128, 2, 4>(a, s);
-  if (a.rows_per == 1 || a.rows_per == 32 || a.rows_per == 64 || a.rows_per == 128)
-    return run_layer<MODE, 128, 128, 4, 2>(a, s);
+  if (a.rows_per == 1) return run_layer<MODE, 128, 128, 4, 2, false>(a, s);
+  if (a.rows_per == 96) return run_layer<MODE, 96, 128, 2, 4, true>(a, s);
+  if (a.rows_per == 32 || a.rows_per == 64 || a.rows_per == 128) return run_layer<MODE, 128, 128, 4, 2, true>(a, s);
   return hipErrorInvalidValue;
 }
 

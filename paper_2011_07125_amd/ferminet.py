@@ -16,7 +16,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libferminet.so")
 
-FN_PREC_FP32, FN_PREC_BF16, FN_PREC_FP32_FP64DET = 0, 1, 2
+FN_PREC_FP32, FN_PREC_BF16, FN_PREC_FP32_FP64DET, FN_PREC_FP64 = 0, 1, 2, 3
+PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
 FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC = 0, 1, 2, 3
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
           5: "FN_ERR_UNSUPPORTED", 6: "FN_ERR_HIP", 7: "FN_ERR_ARG"}
@@ -30,7 +31,7 @@ class FerminetError(RuntimeError):
 
 class fn_config(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("n_elec", "n_up", "n_down", "n_nuc", "n_layers", "width1", "width2",
-                                               "n_det", "precision")]
+                                               "n_det", "precision")] + [("rescue_fraction", ctypes.c_float)]
 
 
 class fn_param_block(ctypes.Structure):
@@ -80,12 +81,14 @@ def _lib():
     return _LIB
 
 
-def make_config(cfg: dict, precision=None) -> fn_config:
+def make_config(cfg: dict, precision=None, rescue: float = 0.0) -> fn_config:
+    """rescue: fraction of walkers whose local energy is re-evaluated in
+    float64 (those of largest determinant-sum cancellation)."""
     prec = cfg.get("precision", "fp32") if precision is None else precision
     if isinstance(prec, str):
-        prec = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET}[prec]
+        prec = PRECISIONS[prec]
     return fn_config(cfg["n_elec"], cfg["n_up"], cfg["n_down"], cfg["n_nuc"], cfg["n_layers"], cfg["width1"],
-                     cfg["width2"], cfg["n_det"], prec)
+                     cfg["width2"], cfg["n_det"], prec, float(rescue))
 
 
 def _check(st: int, where: str):
@@ -106,8 +109,8 @@ def param_layout(cfg: dict):
     return [(buf[i].name.decode(), buf[i].offset, buf[i].rows, buf[i].cols) for i in range(n.value)]
 
 
-def workspace_bytes(cfg: dict, chunk_walkers: int, entry: int, precision=None) -> int:
-    c = make_config(cfg, precision)
+def workspace_bytes(cfg: dict, chunk_walkers: int, entry: int, precision=None, rescue: float = 0.0) -> int:
+    c = make_config(cfg, precision, rescue)
     out = ctypes.c_size_t(0)
     _check(_lib().ferminet_workspace_bytes(ctypes.byref(c), int(chunk_walkers), int(entry), ctypes.byref(out)),
            "ferminet_workspace_bytes")
@@ -118,10 +121,11 @@ def workspace_bytes(cfg: dict, chunk_walkers: int, entry: int, precision=None) -
 _WS = {}
 
 
-def workspace(cfg: dict, W: int, entry: int, precision=None, device=None, max_chunk=None) -> torch.Tensor:
+def workspace(cfg: dict, W: int, entry: int, precision=None, device=None, max_chunk=None,
+              rescue: float = 0.0) -> torch.Tensor:
     device = torch.device("cuda") if device is None else torch.device(device)
     chunk = W if max_chunk is None else max(1, min(W, max_chunk))
-    nbytes = workspace_bytes(cfg, max(1, chunk), entry, precision)
+    nbytes = workspace_bytes(cfg, max(1, chunk), entry, precision, rescue)
     key = (device.index if device.index is not None else torch.cuda.current_device(), entry)
     buf = _WS.get(key)
     if buf is None or buf.numel() < nbytes:
@@ -169,15 +173,17 @@ def ferminet_logpsi(cfg, pos, nuc_pos, nuc_charge, params, precision=None, ws=No
 
 
 def ferminet_local_energy(cfg, pos, nuc_pos, nuc_charge, params, precision=None, ws=None, max_chunk=None,
-                          parts=True):
-    """-> dict(sign, logpsi, e_loc, e_kin, e_pot) float32 [W]."""
+                          parts=True, rescue: float = 0.0):
+    """-> dict(sign, logpsi, e_loc, e_kin, e_pot) float32 [W].  rescue: the
+    fraction of walkers (largest determinant-sum cancellation first)
+    re-evaluated in float64."""
     W = pos.shape[0]
-    c = make_config(cfg, precision)
+    c = make_config(cfg, precision, rescue)
     out = {k: torch.empty(W, dtype=torch.float32, device=pos.device) for k in ("sign", "logpsi", "e_loc")}
     if parts:
         out["e_kin"] = torch.empty(W, dtype=torch.float32, device=pos.device)
         out["e_pot"] = torch.empty(W, dtype=torch.float32, device=pos.device)
-    ws = workspace(cfg, W, FN_ENTRY_LOCAL_ENERGY, precision, pos.device, max_chunk) if ws is None else ws
+    ws = workspace(cfg, W, FN_ENTRY_LOCAL_ENERGY, precision, pos.device, max_chunk, rescue) if ws is None else ws
     st = _lib().ferminet_local_energy(ctypes.byref(c), W, _ptr(_prep(pos)), _spins(cfg), _ptr(_prep(nuc_pos)),
                                       _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(out["sign"]),
                                       _ptr(out["logpsi"]), _ptr(out["e_loc"]), _ptr(out.get("e_kin")),
