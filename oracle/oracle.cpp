@@ -14,7 +14,10 @@
 //        sum_m pi^{k,a}_{im} exp(-|sigma^{k,a}_{im}| |r_j - R_m|)   (Eq. 5,
 //     isotropic envelope of Section 3)
 //   * h^L from the permutation-equivariant one/two-electron network of
-//     the original FermiNet (readings R1-R6, listed in the design doc)
+//     the original FermiNet, which the paper does not restate: tanh
+//     layers with a residual connection when the widths match, spin-wise
+//     mean fields that include the electron itself, two-electron features
+//     (r_i - r_j, |r_i - r_j|) that are zero at i == j
 //   * E_L = psi^{-1} H psi with H from Eq. (2), evaluated as
 //       -1/2 sum_c [d^2_c log|psi| + (d_c log|psi|)^2] + V
 //     where each second derivative along one of the 3n coordinates comes
