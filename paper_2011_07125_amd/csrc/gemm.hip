@@ -300,18 +300,37 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
   // bfloat16 instructions, row kq + 4 r for the float64 one; column c.
   constexpr int LDC = SM::LDC;
   const int T = a.T;
+  S bj[TN];
+  if constexpr (EPI == EPI_TANHJET) {
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) {
+      const int gc = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+      bj[j] = gc < a.N ? (S)a.bias[gc] : (S)0;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    // the P loads of the 16-row tile are issued together (rows and columns
+    // clamped into range, masked afterwards)
+    S pv[4][TN];
+    if constexpr (EPI == EPI_TANHJET) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * (BM / 2) + i * 16 + (MODE == MODE_F64 ? kq + 4 * r : kq * 4 + r);
+        const int e = row / rows_per, t = row % rows_per;
+        const int g = min(g0 + e, a.n_groups - 1);
+        const S* Prow = (const S*)a.P + ((size_t)(g / a.n_all) * rows_per + min(t, T - 1)) * a.ldp;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) pv[r][j] = Prow[min(n0 + wn * (BN / 2) + j * 16 + (lane & 15), a.N - 1)];
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = wm * (BM / 2) + i * 16 + (MODE == MODE_F64 ? kq + 4 * r : kq * 4 + r);
-      // row bookkeeping once per row (not per element)
-      const S* Prow = nullptr;
-      bool bias_row = false;
+      bool live = false, bias_row = false;
       if constexpr (EPI == EPI_TANHJET) {
         const int e = row / rows_per, t = row % rows_per;
-        const int g = g0 + e;
-        if (g < a.n_groups && t < T) Prow = (const S*)a.P + ((size_t)(g / a.n_all) * rows_per + t) * a.ldp;
+        live = g0 + e < a.n_groups && t < T;
         bias_row = t == 0;
       }
 #pragma unroll
@@ -319,15 +338,15 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
         const int col = wn * (BN / 2) + j * 16 + (lane & 15);
         S v = acc[i][j][r];
         if constexpr (EPI == EPI_TANHJET) {
-          const int gc = n0 + col;
-          if (Prow && gc < a.N) {
-            v += Prow[gc];
-            if (bias_row) v += (S)a.bias[gc];
+          if (live && n0 + col < a.N) {
+            v += pv[r][j];
+            if (bias_row) v += bj[j];
           }
         }
         Cs[row * LDC + col] = v;
       }
     }
+  }
   __syncthreads();
   if constexpr (EPI == EPI_PLAIN) {
     for (int p = tid; p < BM * BN; p += 256) {

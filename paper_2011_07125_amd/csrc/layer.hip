@@ -86,10 +86,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     ? ((long)(g / a.n_sub) * a.n_all + a.e_off + (g % a.n_sub)) * rows_per + t
                     : -1;
   }
-  float4 ra[C::NVA];
-  uint4 rb[C::NVB], rbl[MODE == MODE_F32 ? 1 : C::NVB];
+  // two register stages in the jet pass: the loads of K steps kt+2 and
+  // kt+3 are in flight while step kt is multiplied
+  struct Regs {
+    float4 ra[C::NVA];
+    uint4 rb[C::NVB], rbl[MODE == MODE_F32 ? 1 : C::NVB];
+  };
+  Regs R0, R1;
 
-  auto gload = [&](int kt) {
+  auto gload = [&](int kt, Regs& R) {
+    float4* ra = R.ra;
+    uint4* rb = R.rb;
+    uint4* rbl = R.rbl;
     const int kb = kt * BK;
     const float* src = kb < a.ka0 ? (const float*)a.a0 : (const float*)a.a1;
     const int lda = kb < a.ka0 ? a.lda0 : a.lda1;
@@ -121,7 +129,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       if constexpr (MODE != MODE_F32) rbl[i] = zl;
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](const Regs& R, int buf) {
+    const float4* ra = R.ra;
+    const uint4* rb = R.rb;
+    const uint4* rbl = R.rbl;
     char* st = smem + buf * C::STAGE;
     if constexpr (MODE == MODE_F32) {
       float* As = reinterpret_cast<float*>(st);
@@ -177,14 +188,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int bcol = wn * C::WCOLS + (lane & 15);
   const int kq = lane >> 4;
 
-  if (nkt > 0) {
-    gload(0);
-    sstore(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nkt; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nkt) gload(kt + 1);
+  auto compute = [&](int buf) {
     const char* st = smem + buf * C::STAGE;
     if constexpr (MODE == MODE_F32) {
       const float* As = reinterpret_cast<const float*>(st);
@@ -224,40 +228,97 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
       }
     }
-    if (kt + 1 < nkt) sstore(buf ^ 1);
+  };
+
+  if constexpr (JET) {
+    if (nkt > 0) {
+      gload(0, R0);
+      sstore(R0, 0);
+    }
+    if (nkt > 1) gload(1, R1);
+    if (nkt > 2) gload(2, R0);
     __syncthreads();
+    // unrolled by two so that the register stage of each step is static:
+    // step s sits in LDS buffer s & 1; its registers were R(s & 1)
+    for (int kt = 0; kt < nkt; kt += 2) {
+      compute(0);
+      if (kt + 1 < nkt) {
+        sstore(R1, 1);
+        if (kt + 3 < nkt) gload(kt + 3, R1);
+      }
+      __syncthreads();
+      if (kt + 1 >= nkt) break;
+      compute(1);
+      if (kt + 2 < nkt) {
+        sstore(R0, 0);
+        if (kt + 4 < nkt) gload(kt + 4, R0);
+      }
+      __syncthreads();
+    }
+  } else {
+    // value pass (short K loop, wide epilogue): one register stage
+    if (nkt > 0) {
+      gload(0, R0);
+      sstore(R0, 0);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nkt; ++kt) {
+      if (kt + 1 < nkt) gload(kt + 1, R0);
+      compute(kt & 1);
+      if (kt + 1 < nkt) sstore(R0, (kt + 1) & 1);
+      __syncthreads();
+    }
   }
 
   // ---------------------------------------------------------------- epilogue
   // accumulator (i, j, r) of lane (kq, c) is tile row wm WROWS + 16 i + 4 kq + r,
   // tile column wn WCOLS + 16 j + c
   const int T = a.T;
-  float* out = reinterpret_cast<float*>(a.out);
-  const float* res = reinterpret_cast<const float*>(a.a0);
+  // output and residual never overlap (ping-pong activation buffers)
+  float* __restrict__ out = reinterpret_cast<float*>(a.out);
+  const float* __restrict__ res = reinterpret_cast<const float*>(a.a0);
   int gcol[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) gcol[j] = n0 + wn * C::WCOLS + j * 16 + (lane & 15);
 
   if constexpr (!JET) {
-    // value pass: every row is an electron
+    // value pass: every row is an electron.  Per 16-row tile the mean-field
+    // and residual loads are issued together, then the results are stored.
+    const float* __restrict__ Pv = (const float*)a.P;
+    float* __restrict__ pre = a.pre_out;
+    float bj[TN];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) bj[j] = a.bias[gcol[j]];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      float pv[4][TN], rv[4][TN];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + wm * WROWS + i * 16 + kq * 4 + r;
+        const bool ok = g < a.n_groups;
+        const float* Prow = Pv + (size_t)(ok ? g / a.n_all : 0) * a.ldp;
+        const float* rrow = res + (size_t)(ok ? g : 0) * a.lda0;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          pv[r][j] = ok ? Prow[gcol[j]] : 0.0f;
+          rv[r][j] = (ok && a.res) ? rrow[gcol[j]] : 0.0f;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int g = g0 + wm * WROWS + i * 16 + kq * 4 + r;
         if (g >= a.n_groups) continue;
-        const float* Prow = (const float*)a.P + (size_t)(g / a.n_all) * a.ldp;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int gc = gcol[j];
-          const float u0 = acc[i][j][r] + Prow[gc] + a.bias[gc];
+          const float u0 = acc[i][j][r] + pv[r][j] + bj[j];
           float y, dy;
           tanh_sech2f(u0, &y, &dy);
-          if (a.pre_out) a.pre_out[(size_t)g * a.N + gc] = u0;
-          if (a.res) y += res[(size_t)g * a.lda0 + gc];
-          out[(size_t)g * a.ldo + gc] = y;
+          if (pre) pre[(size_t)g * a.N + gc] = u0;
+          out[(size_t)g * a.ldo + gc] = y + rv[r][j];
         }
       }
+    }
     return;
   }
 
@@ -271,26 +332,37 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const size_t obase = (size_t)(gval ? g : 0) * rows_per;
 
   // pre-activation u = acc + P (+ bias on the value row); partial sums of the
-  // squared tangent rows 1..T-2
+  // squared tangent rows 1..T-2.  Per 16-row tile all P loads are issued
+  // together (rows clamped into range, then masked) before any is used.
+  float bj[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) bj[j] = a.bias[gcol[j]];
   float s2[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) s2[j] = 0.0f;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    float pv[4][TN];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int t = tw0 + i * 16 + kq * 4 + r;
-      if (gval && t < T) {
-        const float* Prow = Pb + (size_t)t * a.ldp;
+      const float* Prow = Pb + (size_t)(t < T ? t : T - 1) * a.ldp;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          float v = acc[i][j][r] + Prow[gcol[j]];
-          if (t == 0) v += a.bias[gcol[j]];
-          acc[i][j][r] = v;
-          if (t >= 1 && t <= T - 2) s2[j] += v * v;
-        }
+      for (int j = 0; j < TN; ++j) pv[r][j] = Prow[gcol[j]];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = tw0 + i * 16 + kq * 4 + r;
+      const bool live = gval && t < T;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        float v = acc[i][j][r] + (live ? pv[r][j] : 0.0f);
+        if (live && t == 0) v += bj[j];
+        acc[i][j][r] = v;
+        if (live && t >= 1 && t <= T - 2) s2[j] += v * v;
       }
     }
+  }
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     s2[j] += __shfl_xor(s2[j], 16, 64);
@@ -320,13 +392,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + gcol[j]] = u0;
   }
   if (!gval) return;
+  // per 16-row tile: all residual loads first, then the stores (one memory
+  // round trip per tile, not per element)
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    float rv[4][TN];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = tw0 + i * 16 + kq * 4 + r;
+      const float* rrow = res + (obase + t) * a.lda0;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) rv[r][j] = (a.res && t < T) ? rrow[gcol[j]] : 0.0f;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int t = tw0 + i * 16 + kq * 4 + r;
       float* orow = out + (obase + t) * a.ldo;
-      const float* rrow = (a.res && t < T) ? res + (obase + t) * a.lda0 : nullptr;
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const float v = acc[i][j][r];
@@ -335,10 +416,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         else if (t < T - 1) o = dy[j] * v;
         else if (t == T - 1) o = dy[j] * v + lapc[j];
         else o = 0.0f;
-        if (rrow) o += rrow[gcol[j]];
-        orow[gcol[j]] = o;
+        orow[gcol[j]] = o + rv[r][j];
       }
     }
+  }
 }
 
 template <int MODE, int BM, int BN, int WM, int WN, bool JET>
