@@ -119,13 +119,15 @@ typedef struct {
    * of walkers re-evaluated entirely in float64 (0: none; ignored by
    * FN_PREC_FP64 and by the other entry points).  Within each chunk of
    * the batch, in segments of at most 8192 walkers, the ceil(f * segment)
-   * walkers with the largest determinant-sum cancellation
-   * kappa = max_k |P_k| / |psi|  (P_k = det^up_k det^down_k, Eq. (4);
-   * kappa = inf at a node) are gathered, evaluated again as FN_PREC_FP64
-   * would, and their sign, log|psi|, e_loc, e_kin and e_pot replace the
-   * reduced-precision values.  Near a node of the determinant sum the
-   * rounding error of the local energy grows with kappa, so this removes
-   * the dominant error of the batch-mean energy at a fixed cost. */
+   * walkers with the largest kappa |E_L|, where
+   * kappa = max_k |P_k| / |psi| is the determinant-sum cancellation
+   * (P_k = det^up_k det^down_k, Eq. (4); infinite at a node) and E_L the
+   * reduced-precision local energy, are gathered, evaluated again as
+   * FN_PREC_FP64 would, and their sign, log|psi|, e_loc, e_kin and e_pot
+   * replace the reduced-precision values.  The relative rounding error of
+   * E_L grows with kappa near a node of the determinant sum, so kappa |E_L|
+   * ranks the walkers by their share of the batch-mean error; the
+   * re-evaluation removes the dominant part of it at a fixed cost. */
   float rescue_fraction;
 } fn_config;
 

@@ -156,7 +156,7 @@ struct Bufs {
   void* Pm;      // mean-field terms (activation type)
   void* phi[2];  // orbital jets (activation type)
   void* D[2];
-  float* lnk;    // log kappa per walker (local energy with re-evaluation), else NULL
+  float* rkey;   // rescue key per walker (local energy with re-evaluation), else NULL
   float* prop;
   float* lp_new;
   float* sg_new;
@@ -192,7 +192,7 @@ static void carve_forward(const Plan& p, Mode m, int64_t Wc, Carver& cv, Bufs& b
     b.phi[a] = cv.take((size_t)Wc * p.K * b.T * p.na(a) * p.na(a) * p.act);
     b.D[a] = cv.take((size_t)Wc * p.K * b.dstride * rb);
   }
-  b.lnk = (m == JET && p.rescue > 0.0f) ? (float*)cv.take((size_t)Wc * 4) : nullptr;
+  b.rkey = (m == JET && p.rescue > 0.0f) ? (float*)cv.take((size_t)Wc * 4) : nullptr;
   if (mcmc) {
     b.prop = (float*)cv.take((size_t)Wc * p.n3 * 4);
     b.lp_new = (float*)cv.take((size_t)Wc * 4);
@@ -289,7 +289,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
 
 // ---------------------------------------- float64 re-evaluation buffers
 // Per chunk of Wc walkers: segments of at most 8192 walkers, the k_seg
-// walkers of largest kappa of each segment, R = segments x k_seg in all.
+// walkers of largest kappa |E_L| of each segment, R = segments x k_seg in all.
 struct RescueDims {
   int seg_len, k_seg;
   int64_t R;
@@ -540,7 +540,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   cb.e_loc = e_loc;
   cb.e_kin = e_kin;
   cb.e_pot = e_pot;
-  cb.ln_kappa = m == JET ? b.lnk : nullptr;
+  cb.rescue_key = m == JET ? b.rkey : nullptr;
   FN_T(SG(ST_COMBINE), launch_combine(p.fp64, cb, s));
   return FN_OK;
 }
@@ -987,9 +987,9 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
                  outs[4], s);
     if (st != FN_OK) return st;
     if (!rescue) continue;
-    // float64 re-evaluation of the walkers of largest kappa
+    // float64 re-evaluation of the walkers of largest kappa |E_L|
     const RescueDims d = rescue_dims(p, wc);
-    FN_T(ST_RESCUE, launch_select_top(b.lnk, (int)wc, d.seg_len, d.k_seg, r.idx, s));
+    FN_T(ST_RESCUE, launch_select_top(b.rkey, (int)wc, d.seg_len, d.k_seg, r.idx, s));
     FN_T(ST_RESCUE, launch_gather_walkers(x, r.idx, (int)d.R, p.n3, r.pos_r, s));
     st = forward(r.p64, JET, d.R, r.pos_r, nuc_pos, nuc_charge, params, r.b, r.out[0], r.out[1], r.out[2], r.out[3],
                  r.out[4], s, ST_RESCUE);

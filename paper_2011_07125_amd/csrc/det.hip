@@ -387,8 +387,7 @@ __global__ __launch_bounds__(64) void combine_kernel(CombineArgs a) {
   const R sgn = node ? (R)0 : (S > 0 ? (R)1 : (R)-1);
   const R rho = node ? (R)0 : ex / S;
   if (a.rho && lane < K) ((R*)a.rho)[w * K + lane] = rho;
-  // determinant-sum cancellation: kappa = max_k |P_k| / |psi|
-  if (a.ln_kappa && lane == 0) a.ln_kappa[w] = node ? INFINITY : (float)(m - logabs);
+
 
   double ekin = 0.0;
   if (a.jet) {
@@ -452,6 +451,10 @@ __global__ __launch_bounds__(64) void combine_kernel(CombineArgs a) {
     v = wave_sum(v);
   }
   if (lane == 0) {
+    // rescue key log(kappa |E_L|), kappa = max_k |P_k| / |psi| (determinant-sum
+    // cancellation): the scale of the walker's rounding error in E_L
+    if (a.rescue_key)
+      a.rescue_key[w] = node ? INFINITY : (float)((double)(m - logabs) + log(fabs(ekin + v)));
     a.sign[w] = (float)sgn;
     a.logpsi[w] = (float)logabs;
     if (a.jet) {

@@ -94,7 +94,8 @@ struct CombineArgs {
   const float* pos; const float* nuc; const float* Z;
   float* sign; float* logpsi; float* e_loc; float* e_kin; float* e_pot;
   void* rho;  // optional [W][K]: rho_k = P_k / psi (value mode, adjoint)
-  float* ln_kappa;  // optional [W]: log of max_k |P_k| / |psi| (+inf at a node)
+  float* rescue_key;  // optional [W] (jet mode): log(kappa |E_L|) with kappa = max_k |P_k| / |psi|
+                      // (+inf at a node, NaN propagates)
 };
 hipError_t launch_combine(bool fp64, const CombineArgs& a, hipStream_t s);
 

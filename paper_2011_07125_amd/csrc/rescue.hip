@@ -6,9 +6,10 @@
 // by kappa = max_k |P_k| / |psi| in log|psi| and more strongly in its
 // derivatives, so the local energy of those walkers carries errors many
 // orders above the arithmetic's unit roundoff.  The combination kernel
-// writes log kappa per walker; the walkers with the largest kappa of each
-// segment of the batch are gathered, evaluated again entirely in float64,
-// and their outputs scattered back over the reduced-precision ones.
+// writes log(kappa |E_L|) per walker, the scale of its absolute error; the
+// walkers with the largest key in each segment of the batch are gathered,
+// evaluated again entirely in float64, and their outputs scattered back
+// over the reduced-precision ones.
 #include <climits>
 
 #include "common.h"

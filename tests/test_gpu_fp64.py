@@ -1,6 +1,6 @@
 """The float64 form of the HIP path and the float64 re-evaluation of the
-walkers of largest determinant-sum cancellation, against the FP64 CPU
-oracle on the same seeded inputs.
+walkers of largest kappa |E_L| (kappa: determinant-sum cancellation),
+against the FP64 CPU oracle on the same seeded inputs.
 
 Tolerance of the float64 form: both sides compute in float64 from the same
 float32 inputs, and the library rounds its outputs to float32, so every
@@ -115,14 +115,16 @@ def test_rescue_everything_equals_fp64_form(form):
         assert np.array_equal(gr[k], g64[k]), f"{k}: rescued {form} differs from the fp64 form"
 
 
-def test_rescue_selects_largest_kappa():
-    """The re-evaluated walkers are the batch's largest-kappa walkers: the
-    outputs of exactly k walkers change to the float64 values, and the
-    oracle's own largest-kappa walkers are among them."""
-    say("case rescue selection ne10 W=512")
-    w = I.make_workload("ne10", walkers=512)
-    frac = 0.05
-    k = int(np.ceil(frac * 512))
+def test_rescue_selects_largest_error_scale():
+    """The re-evaluated walkers are those of largest kappa |E_L|: the outputs
+    of exactly k walkers change to the float64 values, and the walkers the
+    oracle ranks highest by kappa |E_L| (its own kappa and local energy)
+    are among them."""
+    say("case rescue selection ne10 W=4096")
+    w = I.make_workload("ne10")
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "ne10_oracle.npz"))
+    frac = 0.03
+    k = int(np.ceil(frac * 4096))
     g64 = run_gpu(w, "fp64")
     gp = run_gpu(w, "bf16")
     gr = run_gpu(w, "bf16", rescue=frac)
@@ -132,14 +134,14 @@ def test_rescue_selects_largest_kappa():
     assert (same64 | sameplain).all()
     changed = np.nonzero(~sameplain)[0]
     assert len(changed) <= k
-    assert same64.sum() >= k  # the k rescued (plus walkers whose bf16 output is already the fp64 one)
-    kap = O.amplification(w["cfg"], w["pos"], w["nuc_pos"], w["params"], threads=THREADS)[1]
-    top = np.argsort(-kap)[: k // 2]
-    say(f"   k={k} changed={len(changed)} oracle top-{k // 2} kappa rescued: {int(same64[top].sum())}")
-    assert same64[top].all(), f"largest-kappa walkers not re-evaluated: {top[~same64[top]]}"
+    assert same64.sum() >= k  # the k re-evaluated (plus walkers whose bf16 output is already the fp64 one)
+    key = gold["kappa"] * np.abs(gold["e_loc"])
+    top = np.argsort(-key)[: k // 2]
+    say(f"   k={k} changed={len(changed)} oracle top-{k // 2} by kappa|E_L| re-evaluated: {int(same64[top].sum())}")
+    assert same64[top].all(), f"largest kappa|E_L| walkers not re-evaluated: {top[~same64[top]]}"
 
 
-@pytest.mark.parametrize("form,frac", [("bf16", 0.05), ("fp32", 0.02)])
+@pytest.mark.parametrize("form,frac", [("bf16", 0.03), ("fp32", 0.01)])
 def test_rescue_batch_mean_within_1mha(form, frac):
     """The Ne-like batch (4096 walkers): with the float64 re-evaluation of
     the given fraction the batch-mean local energy is within 1 mHa of the
@@ -156,7 +158,7 @@ def test_rescue_batch_mean_within_1mha(form, frac):
 
 def test_rescue_several_segments():
     """More walkers than one selection segment (8192): each segment
-    re-evaluates its own largest-kappa walkers."""
+    re-evaluates its own walkers of largest kappa |E_L|."""
     say("case rescue segments be4 W=9000")
     w = I.make_workload("be4", walkers=9000)
     frac = 0.01
@@ -177,7 +179,8 @@ def test_rescue_several_segments():
 def test_rescue_chunked():
     """A workspace sized for 100 walkers: the batch runs in chunks (of at
     least 100 walkers: the library fills the workspace) and each chunk
-    re-evaluates its own largest-kappa walkers, ceil(f x chunk) of them."""
+    re-evaluates its own walkers of largest kappa |E_L|, ceil(f x chunk) of
+    them."""
     say("case rescue chunked ne10 W=260 chunk>=100")
     w = I.make_workload("ne10", walkers=260)
     frac = 0.1
