@@ -820,7 +820,8 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     a2.d2 = p.d2;
     a2.part = b.part2;
     FN_T(ST_ADJ_TWO_E, launch_adj_two_electron(a2, s));
-    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part2, R, (int)b.p2, b.p2, b.tmp, grad + p.offW2[0], kRowChunk, s));
+    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part2, adj_two_electron_rows((int)Wc, p.n, p.d2), (int)b.p2, b.p2, b.tmp,
+                                          grad + p.offW2[0], kRowChunk, s));
   }
   return FN_OK;
 }

@@ -310,94 +310,149 @@ hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t 
 }
 
 // ------------------------------------------------- two-electron backward
-// One block per electron i of walker w.  For l = L-2 .. 0, with Ct the
-// cotangent of h^{l+1}_ij (all j):
+// One block per group of E electrons i of walker w, all n partners j: the
+// R = E n pair rows r = (i - i0) n + j.  For l = L-2 .. 0, with Ct the
+// cotangent of h^{l+1}_ij:
 //   pre = h^l_ij W_l + c_l ; cp = Ct sech^2(pre)
-//   part_W[k][o] = sum_j h^l_ij[k] cp_j[o] ; part_c[o] = sum_j cp_j[o]
+//   part_W[k][o] = sum_r h^l_r[k] cp_r[o] ; part_c[o] = sum_r cp_r[o]
 //   Ct <- cp W_l^T (+ Ct when widths match) + (1/n_a) cot g^{a(j),l}_i
-// starting from Ct = (1/n_a) cot g^{a(j),L-1}_i.  The parameter partials of
-// the block go to part[(w n + i)][...] in the layout of the W_l, c_l blocks.
-__global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a) {
-  extern __shared__ float sh[];
-  const int n = a.n, d2 = a.d2, L = a.L;
-  const int dm = d2 > 4 ? d2 : 4;
-  float* Hs = sh;             // [n][dm]   h^l_ij
-  float* Ct = Hs + n * dm;    // [n][dm]   cotangent of h^{l+1}_ij
-  float* Cp = Ct + n * dm;    // [n][dm]
-  float* Ws = Cp + n * dm;    // [dm][d2] + c[d2]
-  const int tid = threadIdx.x;
-  const int64_t g = blockIdx.x;  // w n + i
-  const int nu = a.n_up;
-  float* part = a.part + g * a.p2;
-  // Ct = mean-field cotangent of layer L-1
+// starting from Ct = (1/n_a) cot g^{a(j),L-1}_i.  The three contractions
+// run on v_mfma_f32_16x16x4_f32 over the pair rows in LDS (rows padded to
+// 16, features to DM, zeros in the padding); the parameter partials of the
+// block go to part[block][...] in the layout of the W_l, c_l blocks.
+template <int DM>
+__global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int E, int ngrp) {
+  extern __shared__ __attribute__((aligned(16))) float sh[];
+  constexpr int LD = DM + 1;  // row stride of the LDS arrays
+  const int n = a.n, d2 = a.d2, L = a.L, nu = a.n_up;
+  const int RP = round_up(E * n, 16);
+  float* Hs = sh;            // [RP][LD] h^l_ij
+  float* Ct = Hs + RP * LD;  // [RP][LD] cotangent of h^{l+1}_ij
+  float* Cp = Ct + RP * LD;  // [RP][LD] Ct sech^2(pre)
+  float* Ws = Cp + RP * LD;  // [DM][LD] W_l
+  float* cs = Ws + DM * LD;  // [DM]     c_l
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int blk = blockIdx.x;
+  const int64_t w = blk / ngrp;
+  const int i0 = (blk % ngrp) * E;
+  const int Rb = min(E, n - i0) * n;  // live pair rows
+  float* part = a.part + (int64_t)blk * a.p2;
+  const int TMr = RP / 16, TNd = DM / 16;
+
+  // mean-field cotangent (1/n_a) cot g^{a(j),l}_i of row r, feature k < ein
+  auto mf_cot = [&](int l, int ein, int r, int k) {
+    const int i = i0 + r / n, j = r % n;
+    const int al = j < nu ? 0 : 1, na = al == 0 ? nu : n - nu;
+    return a.CG[l][(w * n + i) * a.ldcg[l] + al * ein + k] / (float)na;
+  };
   {
-    const int ein = L - 1 == 0 ? 4 : d2;
-    const float* cg = a.CG[L - 1] + g * a.ldcg[L - 1];
-    for (int idx = tid; idx < n * dm; idx += blockDim.x) {
-      const int j = idx / dm, o = idx % dm;
-      const int al = j < nu ? 0 : 1, na = al == 0 ? nu : n - nu;
-      Ct[idx] = o < ein ? cg[al * ein + o] / (float)na : 0.0f;
+    const int l = L - 1, ein = l == 0 ? 4 : d2;
+    for (int idx = tid; idx < RP * DM; idx += 256) {
+      const int r = idx / DM, k = idx % DM;
+      Ct[r * LD + k] = (r < Rb && k < ein) ? mf_cot(l, ein, r, k) : 0.0f;
     }
   }
   for (int l = L - 2; l >= 0; --l) {
     const int ein = l == 0 ? 4 : d2;
+    const int ke = round_up(ein, 4), kd = round_up(d2, 4);
     __syncthreads();
-    for (int idx = tid; idx < n * dm; idx += blockDim.x) {
-      const int j = idx / dm, k = idx % dm;
-      Hs[idx] = k < ein ? a.h2[l][(g * n + j) * ein + k] : 0.0f;
-    }
-    for (int idx = tid; idx < ein * d2 + d2; idx += blockDim.x)
-      Ws[idx] = idx < ein * d2 ? a.params[a.w_off[l] + idx] : a.params[a.c_off[l] + idx - ein * d2];
-    __syncthreads();
-    // cp = Ct * sech^2(h W + c)
-    for (int idx = tid; idx < n * d2; idx += blockDim.x) {
-      const int j = idx / d2, o = idx % d2;
-      float pre = Ws[ein * d2 + o];
-      for (int k = 0; k < ein; ++k) pre += Hs[j * dm + k] * Ws[k * d2 + o];
-      Cp[j * dm + o] = Ct[j * dm + o] * sech2f(pre);
-    }
-    __syncthreads();
-    // parameter partials
-    for (int idx = tid; idx < ein * d2 + d2; idx += blockDim.x) {
-      float acc = 0.0f;
-      if (idx < ein * d2) {
-        const int k = idx / d2, o = idx % d2;
-        for (int j = 0; j < n; ++j) acc += Hs[j * dm + k] * Cp[j * dm + o];
-      } else {
-        const int o = idx - ein * d2;
-        for (int j = 0; j < n; ++j) acc += Cp[j * dm + o];
-      }
-      part[a.p_off[l] + idx] = acc;
-    }
-    // Ct <- cp W^T (+ residual) + mean-field cotangent of layer l
-    const float* cg = a.CG[l] + g * a.ldcg[l];
-    const bool res = ein == d2;
-    float newc[4];
-    int cnt = 0;
-    for (int idx = tid; idx < n * dm; idx += blockDim.x, ++cnt) {
-      const int j = idx / dm, k = idx % dm;
+    for (int idx = tid; idx < RP * DM; idx += 256) {
+      const int r = idx / DM, k = idx % DM;
       float v = 0.0f;
-      if (k < ein) {
-        for (int o = 0; o < d2; ++o) v += Cp[j * dm + o] * Ws[k * d2 + o];
-        if (res) v += Ct[idx];
-        const int al = j < nu ? 0 : 1, na = al == 0 ? nu : n - nu;
-        v += cg[al * ein + k] / (float)na;
+      if (r < Rb && k < ein) v = a.h2[l][((w * n + i0 + r / n) * n + r % n) * ein + k];
+      Hs[r * LD + k] = v;
+    }
+    for (int idx = tid; idx < DM * DM; idx += 256) {
+      const int k = idx / DM, o = idx % DM;
+      Ws[k * LD + o] = (k < ein && o < d2) ? a.params[a.w_off[l] + k * d2 + o] : 0.0f;
+    }
+    for (int o = tid; o < DM; o += 256) cs[o] = o < d2 ? a.params[a.c_off[l] + o] : 0.0f;
+    __syncthreads();
+    // cp = Ct sech^2(H W + c)   [RP x DM]
+    for (int t = wave; t < TMr * TNd; t += 4) {
+      const int tm = t / TNd, tn = t % TNd;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < ke; ks += 4)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Hs[(tm * 16 + lr) * LD + ks + lk], Ws[(ks + lk) * LD + tn * 16 + lr],
+                                                   acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = tm * 16 + 4 * lk + q, col = tn * 16 + lr;
+        Cp[row * LD + col] = Ct[row * LD + col] * sech2f(acc[q] + cs[col]);
       }
-      newc[cnt] = v;
     }
     __syncthreads();
-    cnt = 0;
-    for (int idx = tid; idx < n * dm; idx += blockDim.x, ++cnt) Ct[idx] = newc[cnt];
+    // parameter partials: H^T cp [ein x d2], column sums of cp [d2]
+    const int TMk = round_up(ein, 16) / 16;
+    for (int t = wave; t < TMk * TNd; t += 4) {
+      const int tm = t / TNd, tn = t % TNd;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < RP; ks += 4)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Hs[(ks + lk) * LD + tm * 16 + lr], Cp[(ks + lk) * LD + tn * 16 + lr],
+                                                   acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = tm * 16 + 4 * lk + q, o = tn * 16 + lr;
+        if (k < ein && o < d2) part[a.p_off[l] + k * d2 + o] = acc[q];
+      }
+    }
+    for (int o = tid; o < d2; o += 256) {
+      float sum = 0.0f;
+      for (int r = 0; r < RP; ++r) sum += Cp[r * LD + o];
+      part[a.p_off[l] + ein * d2 + o] = sum;
+    }
+    // Ct <- cp W^T (+ Ct when widths match) + mean-field cotangent of layer l
+    // (each element read and written by one lane: in place)
+    const bool res = ein == d2;
+    const int TNk = round_up(ein, 16) / 16;
+    for (int t = wave; t < TMr * TNk; t += 4) {
+      const int tm = t / TNk, tn = t % TNk;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int ks = 0; ks < kd; ks += 4)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Cp[(tm * 16 + lr) * LD + ks + lk], Ws[(tn * 16 + lr) * LD + ks + lk],
+                                                   acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = tm * 16 + 4 * lk + q, k = tn * 16 + lr;
+        float v = 0.0f;
+        if (row < Rb && k < ein) v = acc[q] + (res ? Ct[row * LD + k] : 0.0f) + mf_cot(l, ein, row, k);
+        Ct[row * LD + k] = v;
+      }
+    }
   }
+}
+
+// electrons per block of the two-electron backward: pair rows E n <= 128
+// and the four LDS arrays within 64 KiB
+static int adj2e_dm(int d2) { return d2 <= 16 ? 16 : d2 <= 32 ? 32 : 64; }
+static int adj2e_group(int n, int d2) {
+  const int dm = adj2e_dm(d2), ld = dm + 1;
+  const int rows_cap = std::min(128, (65536 / 4 - dm * ld - dm) / (3 * ld) / 16 * 16);
+  return std::max(1, std::min(n, rows_cap / n));
+}
+
+int adj_two_electron_rows(int W, int n, int d2) {
+  const int E = adj2e_group(n, d2);
+  return W * ((n + E - 1) / E);
+}
+
+template <int DM>
+static hipError_t run_adj2e(const Adj2eArgs& a, hipStream_t s) {
+  const int E = adj2e_group(a.n, a.d2), ngrp = (a.n + E - 1) / E;
+  const int RP = round_up(E * a.n, 16);
+  const size_t shmem = ((size_t)3 * RP * (DM + 1) + (size_t)DM * (DM + 1) + DM) * sizeof(float);
+  if (shmem > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((adj_two_electron_kernel<DM>), dim3((unsigned)((int64_t)a.W * ngrp)), dim3(256), shmem, s, a, E,
+                     ngrp);
+  return hipGetLastError();
 }
 
 hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s) {
   if (a.W <= 0 || a.L < 2) return hipSuccess;
-  const int dm = a.d2 > 4 ? a.d2 : 4;
-  if (a.n * dm > 4 * 256) return hipErrorInvalidValue;  // newc[] holds 4 entries per thread
-  const size_t shmem = ((size_t)3 * a.n * dm + (size_t)dm * a.d2 + a.d2) * sizeof(float);
-  hipLaunchKernelGGL(adj_two_electron_kernel, dim3((unsigned)((int64_t)a.W * a.n)), dim3(256), shmem, s, a);
-  return hipGetLastError();
+  if (a.d2 > 64) return hipErrorInvalidValue;
+  const int dm = adj2e_dm(a.d2);
+  return dm == 16 ? run_adj2e<16>(a, s) : dm == 32 ? run_adj2e<32>(a, s) : run_adj2e<64>(a, s);
 }
 
 // ----------------------------------------- energy statistics and cotangent

@@ -157,9 +157,11 @@ struct Adj2eArgs {
   const float* CG[8];          // cot g^l_i [w n + i][ldcg_l] (columns a ein_l + o)
   int ldcg[8];
   int W, n, n_up, L, d2;
-  float* part;                 // [W n][p2]
+  float* part;                 // [adj_two_electron_rows(W, n, d2)][p2]
 };
 hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s);
+// rows of parameter partials the two-electron backward writes (<= W n)
+int adj_two_electron_rows(int W, int n, int d2);
 hipError_t launch_energy_stats(const float* e, int W, double* stats, float* cot, hipStream_t s);
 hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s);
 

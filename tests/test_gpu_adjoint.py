@@ -79,6 +79,34 @@ def test_grad_logpsi_vs_oracle(name, W, form):
     check(f"{name}/{form}", g[sel], ref, amp.max(), form)
 
 
+@pytest.mark.parametrize("name,W", [("ne10", 5), ("c4h6", 2)])
+def test_two_electron_block_gradient_every_entry(name, W):
+    """Every weight and bias of the two-electron layers (the blocks the
+    pair-row backward produces, electrons grouped per workgroup) against
+    the oracle's dual numbers."""
+    say(f"case two-electron gradient block {name} W={W}")
+    w = I.make_workload(name, walkers=W)
+    cfg = w["cfg"]
+    cot = np.random.default_rng(5).normal(size=W).astype(np.float32)
+    d = F.to_device(w)
+    g = F.ferminet_grad_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"],
+                               torch.from_numpy(cot).cuda(), precision="fp32")
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    offs = I.param_offsets(cfg)
+    sel = []
+    for bname, shape, kind in I.param_blocks(cfg):
+        if bname.startswith(("W", "c")) and not bname.startswith("w_orb"):
+            o, sh = offs[bname]
+            sel += list(range(o, o + int(np.prod(sh))))
+    sel = np.array(sorted(sel), dtype=np.int64)
+    assert sel.size > 0
+    per = O.param_grad(cfg, w["pos"], w["nuc_pos"], w["params"], sel, threads=THREADS)
+    ref = (cot.astype(np.float64)[:, None] * per).sum(0)
+    amp = O.amplification(cfg, w["pos"], w["nuc_pos"], w["params"], threads=THREADS)[0]
+    check(f"{name}/two-electron block", g[sel], ref, amp.max(), "fp32")
+
+
 def test_vmc_energy_gradient_vs_oracle():
     """(1/W) sum_w (E_L,w - mean E_L) d log|psi_w| / d theta, with the
     energies from the GPU's own local energy, against the oracle's
