@@ -129,7 +129,9 @@ struct TwoElecDev {
 // odd stride D2 + 1, so the 64 slots of a wavefront reading one feature hit
 // distinct LDS banks.
 template <int D2> constexpr int two_e_ps_stride() { return D2 + 1; }
-inline size_t two_e_ws_offset(int slots, int ps) { return ((size_t)slots * ps + 3) / 4 * 4; }
+// LDS rows of the slots, padded to whole 16-row matrix tiles
+__host__ __device__ inline int two_e_rows(int slots) { return (slots + 15) / 16 * 16; }
+inline size_t two_e_ws_offset(int slots, int ps) { return ((size_t)two_e_rows(slots) * ps + 3) / 4 * 4; }
 
 // S: float or double (arithmetic, LDS and the stored jets of g^a_i)
 template <class S, int D2>
@@ -138,8 +140,8 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
   S* sh = reinterpret_cast<S*>(sh_raw);
   constexpr int PS = two_e_ps_stride<D2>();
   const int n = a.n, R2 = a.R2, d2 = a.d2;
-  S* Ps = sh;                                                // [slots][PS]
-  S* Ws = sh + ((size_t)a.ipb * n * R2 * PS + 3) / 4 * 4;    // [D2][D2] then c[D2], 16-byte aligned
+  S* Ps = sh;                                                          // [rows][PS]
+  S* Ws = sh + ((size_t)two_e_rows(a.ipb * n * R2) * PS + 3) / 4 * 4;  // [D2][D2] then c[D2], 16-byte aligned
   const int tid = threadIdx.x;
   const int slots = a.ipb * n * R2;
   const int64_t gbase = (int64_t)blockIdx.x * a.ipb;
@@ -152,7 +154,12 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
   const int i = (int)(g % n);
   const int64_t w = g / n;
 
-  // input pair features (r_i - r_j, |r_i - r_j|) and their sparse jets
+  // input pair features (r_i - r_j, |r_i - r_j|) and their sparse jets;
+  // rows of no live slot are zero
+  if (!live && s < two_e_rows(slots)) {
+#pragma unroll
+    for (int k = 0; k < D2; ++k) Ps[(size_t)s * PS + k] = (S)0;
+  }
   if (live) {
     S in[4] = {0, 0, 0, 0};
     if (i != j) {
@@ -241,57 +248,117 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
       Ws[k] = v;
     }
     __syncthreads();
-    S u[D2];
+    if constexpr (sizeof(S) == 4 && D2 >= 16) {
+      // float32: the layer product [rows x ein] x [ein x D2] on MFMA.  Each
+      // wave owns whole 16-row tiles (two pairs x 8 sparse jet rows, or 16
+      // value rows) and updates them in place after its own reads.  In the
+      // accumulator layout item r of lane (kq, c) is row 4 kq + r: jet row
+      // q = 4 (kq & 1) + r of pair kq >> 1, column c.
+      const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+      const int n_rt = two_e_rows(slots) / 16;
+      const bool res = ein == d2;
+      const S* cb = Ws + D2 * D2;
+      for (int tm = wave; tm < n_rt; tm += 4) {
+        floatx4 acc[D2 / 16];
 #pragma unroll
-    for (int o = 0; o < D2; ++o) u[o] = q == 0 ? Ws[D2 * D2 + o] : (S)0;
-    if (live) {
-      for (int k = 0; k < ein; ++k) {
-        const S x = Ps[(size_t)s * PS + k];
-        if constexpr (sizeof(S) == 4) {
-          const float4* wr = reinterpret_cast<const float4*>(Ws + k * D2);
+        for (int tn = 0; tn < D2 / 16; ++tn) acc[tn] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < ein; ks += 4) {
+          const float av = Ps[(size_t)(tm * 16 + lr) * PS + ks + lk];
 #pragma unroll
-          for (int o4 = 0; o4 < D2 / 4; ++o4) {
-            const float4 wv = wr[o4];
-            u[4 * o4] += x * wv.x;
-            u[4 * o4 + 1] += x * wv.y;
-            u[4 * o4 + 2] += x * wv.z;
-            u[4 * o4 + 3] += x * wv.w;
+          for (int tn = 0; tn < D2 / 16; ++tn)
+            acc[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Ws[(ks + lk) * D2 + tn * 16 + lr], acc[tn], 0, 0, 0);
+        }
+#pragma unroll
+        for (int tn = 0; tn < D2 / 16; ++tn) {
+          const int col = tn * 16 + lr;
+          float o4[4];
+          if (R2 == 8) {
+            const float u0 = __shfl(acc[tn][0], lane & ~16, 64) + cb[col];
+            float sq = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int q = 4 * (lk & 1) + r;
+              if (q >= 1 && q <= 6) sq += acc[tn][r] * acc[tn][r];
+            }
+            const float s2 = sq + __shfl_xor(sq, 16, 64);
+            float y, dy;
+            tanh_sech2(u0, &y, &dy);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int q = 4 * (lk & 1) + r;
+              o4[r] = q == 0 ? y : q <= 6 ? dy * acc[tn][r] : dy * acc[tn][r] - 2.0f * y * dy * s2;
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              float y, dy;
+              tanh_sech2(acc[tn][r] + cb[col], &y, &dy);
+              o4[r] = y;
+            }
           }
-        } else {
-          const S* wr = Ws + k * D2;
 #pragma unroll
-          for (int o = 0; o < D2; ++o) u[o] += x * wr[o];
+          for (int r = 0; r < 4; ++r) {
+            const size_t e = (size_t)(tm * 16 + 4 * lk + r) * PS + col;
+            float v = o4[r];
+            if (res) v += Ps[e];
+            Ps[e] = col < d2 ? v : 0.0f;
+          }
         }
       }
-    }
-    const bool res = ein == d2;
+      ein = d2;
+    } else {
+      S u[D2];
 #pragma unroll
-    for (int o = 0; o < D2; ++o) {
-      const S uo = u[o];
-      S y, dy, s2 = 0;
-      if (R2 == 8) {
-        const S u0 = __shfl(uo, tid & ~7, 64);
-        S sq = (q >= 1 && q <= 6) ? uo * uo : (S)0;
-        sq += __shfl_xor(sq, 1, 64);
-        sq += __shfl_xor(sq, 2, 64);
-        sq += __shfl_xor(sq, 4, 64);
-        s2 = sq;
-        tanh_sech2(u0, &y, &dy);
-      } else {
-        tanh_sech2(uo, &y, &dy);
+      for (int o = 0; o < D2; ++o) u[o] = q == 0 ? Ws[D2 * D2 + o] : (S)0;
+      if (live) {
+        for (int k = 0; k < ein; ++k) {
+          const S x = Ps[(size_t)s * PS + k];
+          if constexpr (sizeof(S) == 4) {
+            const float4* wr = reinterpret_cast<const float4*>(Ws + k * D2);
+#pragma unroll
+            for (int o4 = 0; o4 < D2 / 4; ++o4) {
+              const float4 wv = wr[o4];
+              u[4 * o4] += x * wv.x;
+              u[4 * o4 + 1] += x * wv.y;
+              u[4 * o4 + 2] += x * wv.z;
+              u[4 * o4 + 3] += x * wv.w;
+            }
+          } else {
+            const S* wr = Ws + k * D2;
+#pragma unroll
+            for (int o = 0; o < D2; ++o) u[o] += x * wr[o];
+          }
+        }
       }
-      S outv;
-      if (q == 0) outv = y;
-      else if (q <= 6) outv = dy * uo;
-      else outv = dy * uo - (S)2 * y * dy * s2;
-      if (res && live) outv += Ps[(size_t)s * PS + o];
-      u[o] = o < d2 ? outv : (S)0;
-    }
-    ein = d2;
-    __syncthreads();
-    if (live) {
+      const bool res = ein == d2;
 #pragma unroll
-      for (int o = 0; o < D2; ++o) Ps[(size_t)s * PS + o] = u[o];
+      for (int o = 0; o < D2; ++o) {
+        const S uo = u[o];
+        S y, dy, s2 = 0;
+        if (R2 == 8) {
+          const S u0 = __shfl(uo, tid & ~7, 64);
+          S sq = (q >= 1 && q <= 6) ? uo * uo : (S)0;
+          sq += __shfl_xor(sq, 1, 64);
+          sq += __shfl_xor(sq, 2, 64);
+          sq += __shfl_xor(sq, 4, 64);
+          s2 = sq;
+          tanh_sech2(u0, &y, &dy);
+        } else {
+          tanh_sech2(uo, &y, &dy);
+        }
+        S outv;
+        if (q == 0) outv = y;
+        else if (q <= 6) outv = dy * uo;
+        else outv = dy * uo - (S)2 * y * dy * s2;
+        if (res && live) outv += Ps[(size_t)s * PS + o];
+        u[o] = o < d2 ? outv : (S)0;
+      }
+      ein = d2;
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int o = 0; o < D2; ++o) Ps[(size_t)s * PS + o] = u[o];
+      }
     }
   }
 }
@@ -328,10 +395,11 @@ static hipError_t pick_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
 int two_electron_per_block(int n, int d2, int T, int scalar_bytes) {
   const int R2 = T > 1 ? 8 : 1;
   const int D2p = d2 <= 4 ? 4 : d2 <= 8 ? 8 : d2 <= 16 ? 16 : d2 <= 32 ? 32 : 64;
-  const int fixed = 4 + D2p * D2p + D2p, per = n * R2 * (D2p + 1);
-  const int cap64 = (65536 / scalar_bytes - fixed) / per;
-  if (cap64 >= 1) return std::min(256 / (n * R2), cap64);
-  return (160 * 1024 / scalar_bytes - fixed) / per >= 1 ? 1 : 0;
+  auto elems = [&](int ipb) { return two_e_rows(ipb * n * R2) * (D2p + 1) + 4 + D2p * D2p + D2p; };
+  int ipb = 256 / (n * R2);
+  while (ipb > 1 && elems(ipb) * scalar_bytes > 65536) --ipb;
+  if (ipb >= 1 && elems(ipb) * scalar_bytes <= 65536) return ipb;
+  return (ipb >= 1 && elems(1) * scalar_bytes <= 160 * 1024) ? 1 : 0;
 }
 
 hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s) {
