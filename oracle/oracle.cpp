@@ -12,7 +12,9 @@
 //     with the determinant weights omega_k removed as Section 3 argues)
 //   * phi^{k,a}_i(r_j) = (w^{k,a}_i . h^L_j + g^{k,a}_i) *
 //        sum_m pi^{k,a}_{im} exp(-|sigma^{k,a}_{im}| |r_j - R_m|)   (Eq. 5,
-//     isotropic envelope of Section 3)
+//     isotropic envelope of Section 3), or with a 3x3 matrix Sigma_{im}
+//     and exp(-|Sigma_{im} (r_j - R_m)|) (Eq. 5 as written: the full
+//     covariance envelope that Section 3 replaces)
 //   * h^L from the permutation-equivariant one/two-electron network of
 //     the original FermiNet, which the paper does not restate: tanh
 //     layers with a residual connection when the widths match, spin-wise
@@ -113,11 +115,13 @@ template <class S> inline S inv_(const S& x) {
 template <class S> inline S abs_(const S& x) { return val(x) < 0.0 ? -x : x; }
 
 // ------------------------------------------------------------- the shapes
+// env: 0 isotropic envelope (one sigma per orbital and nucleus), 1 full
+// covariance (a 3x3 matrix Sigma per orbital and nucleus, row-major)
 struct Cfg {
-  int n, n_up, n_dn, N, L, d1, d2, K;
+  int n, n_up, n_dn, N, L, d1, d2, K, env;
 };
 
-Cfg read_cfg(const int32_t* c) { return {c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7]}; }
+Cfg read_cfg(const int32_t* c) { return {c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7], c[8]}; }
 
 // Offsets of the parameter blocks in the flat vector.  The layout is an
 // interface fixed by the library's header; it is written out here anew.
@@ -161,7 +165,7 @@ Layout make_layout(const Cfg& c) {
   }
   for (int a = 0; a < 2; ++a) {
     Y.sg[a] = off;
-    off += (int64_t)c.K * nspin(c, a) * c.N;
+    off += (int64_t)c.K * nspin(c, a) * c.N * (c.env ? 9 : 1);
   }
   Y.total = off;
   return Y;
@@ -330,9 +334,20 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
           for (int m = 0; m < N; ++m) {
             S d[3];
             for (int x = 0; x < 3; ++x) d[x] = pos[e * 3 + x] - nuc[m * 3 + x];
-            S r = sqrt_(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            P s_abs = abs_(sg[(size_t)col * N + m]);
-            env = env + exp_(-(r * s_abs)) * pi[(size_t)col * N + m];
+            S arg;
+            if (c.env == 0) {
+              // |sigma (r - R)| = |sigma| |r - R|
+              S r = sqrt_(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+              P s_abs = abs_(sg[(size_t)col * N + m]);
+              arg = r * s_abs;
+            } else {
+              // |Sigma (r - R)|, the Euclidean norm of the 3-vector
+              const P* Sg = sg + ((size_t)col * N + m) * 9;
+              S u[3];
+              for (int x = 0; x < 3; ++x) u[x] = Sg[3 * x] * d[0] + Sg[3 * x + 1] * d[1] + Sg[3 * x + 2] * d[2];
+              arg = sqrt_(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            }
+            env = env + exp_(-arg) * pi[(size_t)col * N + m];
           }
           A[(size_t)i * na + j] = u * env;
         }
@@ -398,7 +413,7 @@ void potential(const Cfg& c, const double* pos, const double* nuc, const double*
 
 bool cfg_ok(const Cfg& c) {
   return c.n >= 1 && c.n_up >= 0 && c.n_dn >= 0 && c.n_up + c.n_dn == c.n && c.N >= 1 && c.L >= 1 && c.d1 >= 1 &&
-         c.d2 >= 1 && c.K >= 1;
+         c.d2 >= 1 && c.K >= 1 && (c.env == 0 || c.env == 1);
 }
 
 // ------------------------------------------------------------- Philox

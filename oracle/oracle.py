@@ -61,8 +61,11 @@ def _load():
 
 
 def _cfg(cfg) -> np.ndarray:
+    """[n, n_up, n_down, N, L, d1, d2, K, envelope]; envelope 0 isotropic
+    (default), 1 full covariance."""
+    env = {"isotropic": 0, "full": 1}.get(cfg.get("envelope", 0), cfg.get("envelope", 0))
     return np.array([cfg["n_elec"], cfg["n_up"], cfg["n_down"], cfg["n_nuc"], cfg["n_layers"],
-                     cfg["width1"], cfg["width2"], cfg["n_det"]], dtype=np.int32)
+                     cfg["width1"], cfg["width2"], cfg["n_det"], env], dtype=np.int32)
 
 
 def _d(a) -> np.ndarray:

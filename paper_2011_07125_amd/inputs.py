@@ -50,9 +50,15 @@ SPECS = {
 }
 
 
-def make_cfg(n_up, n_down, n_nuc, n_layers, width1, width2, n_det, precision="fp32"):
+def make_cfg(n_up, n_down, n_nuc, n_layers, width1, width2, n_det, precision="fp32", envelope="isotropic"):
+    """envelope: 'isotropic' (one sigma per orbital and nucleus, Section 3)
+    or 'full' (a 3x3 matrix Sigma per orbital and nucleus, Eq. (5))."""
     return dict(n_elec=n_up + n_down, n_up=n_up, n_down=n_down, n_nuc=n_nuc, n_layers=n_layers,
-                width1=width1, width2=width2, n_det=n_det, precision=precision)
+                width1=width1, width2=width2, n_det=n_det, precision=precision, envelope=envelope)
+
+
+def is_full_envelope(cfg):
+    return cfg.get("envelope", "isotropic") in ("full", 1)
 
 
 def param_blocks(cfg):
@@ -63,7 +69,8 @@ def param_blocks(cfg):
     for l in 0..L-2:  W{l} [ein_l][d2],             c{l} [d2]
     for spin a:       w_orb{a} [d1][K*n_a] (column k*n_a + i), g_orb{a} [K*n_a]
     for spin a:       pi{a} [K*n_a][N]
-    for spin a:       sigma{a} [K*n_a][N]
+    for spin a:       sigma{a} [K*n_a][N] (isotropic) or [K*n_a][N][3][3]
+                      (full covariance, row-major, applied as Sigma (r - R))
     with din_0 = 4N, ein_0 = 4, din_l = d1 and ein_l = d2 for l > 0.
     """
     N, L, d1, d2, K = cfg["n_nuc"], cfg["n_layers"], cfg["width1"], cfg["width2"], cfg["n_det"]
@@ -83,7 +90,8 @@ def param_blocks(cfg):
     for a in range(2):
         out.append((f"pi{a}", (K * ns[a], N), "pi"))
     for a in range(2):
-        out.append((f"sigma{a}", (K * ns[a], N), "sigma"))
+        shape = (K * ns[a], N, 3, 3) if is_full_envelope(cfg) else (K * ns[a], N)
+        out.append((f"sigma{a}", shape, "sigma"))
     return out
 
 
@@ -106,9 +114,33 @@ def init_params(cfg, rng):
             chunks.append(rng.normal(0.0, 1.0 / np.sqrt(shape[0]), size=size))
         elif kind == "bias":
             chunks.append(np.zeros(size))
+        elif kind == "sigma" and len(shape) == 4:
+            chunks.append(np.broadcast_to(np.eye(3), shape).reshape(-1))  # Sigma = I: sigma = 1
         else:
             chunks.append(np.ones(size))
     return np.concatenate(chunks).astype(np.float32)
+
+
+def full_covariance(w, noise=0.0, seed=0):
+    """The workload w with the full-covariance envelope: every isotropic
+    sigma of w becomes the matrix sigma * I (the same wavefunction), plus
+    noise * N(0, 1) per entry when noise > 0 (seeded)."""
+    cfg = dict(w["cfg"], envelope="full")
+    src = param_offsets(w["cfg"])
+    dst = param_offsets(cfg)
+    params = np.empty(dst["_total"], dtype=w["params"].dtype)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed).spawn(5)[1]))
+    for name, shape, kind in param_blocks(cfg):
+        o, sh = dst[name]
+        so, ssh = src[name]
+        block = w["params"][so:so + int(np.prod(ssh))].astype(np.float64)
+        if kind == "sigma":
+            mats = block.reshape(ssh)[..., None, None] * np.eye(3)
+            if noise > 0:
+                mats = mats + noise * rng.normal(size=mats.shape)
+            block = mats.reshape(-1)
+        params[o:o + int(np.prod(sh))] = block
+    return dict(w, cfg=cfg, params=params)
 
 
 def molecule_geometry(seed, n_carbon=4, n_hydrogen=6, box=3.0, min_sep=1.5):

@@ -559,3 +559,96 @@ def test_metropolis_replay_supplied_noise_equals_internal():
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
     assert a[3].sum() > 0
+
+
+# ------------------------------------- full-covariance envelope (Eq. (5))
+def full_workload(noise, seed=11, W=3):
+    """small_workload with the 3x3 envelope matrices of Eq. (5): sigma I
+    plus noise N(0, 1) per entry."""
+    return I.full_covariance(small_workload(seed=seed, W=W), noise=noise, seed=seed)
+
+
+def test_full_envelope_reduces_to_isotropic():
+    """Sigma = sigma I (sigma of either sign) gives exp(-|sigma| |r - R|):
+    the full form of Eq. (5) equals the isotropic form of Section 3."""
+    w = small_workload(W=4)
+    rng = np.random.default_rng(4)
+    p = w["params"].copy()
+    off, shape = I.param_offsets(w["cfg"])["sigma0"]
+    n = int(np.prod(shape))
+    p[off:off + n] *= rng.choice([-1.0, 1.0], size=n)  # negative sigmas enter through |sigma|
+    w["params"] = p
+    wf = I.full_covariance(w)
+    a = ev(w)
+    b = ev(wf)
+    for k in ("sign", "logpsi", "e_loc"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-13, atol=1e-12)
+
+
+def test_full_envelope_left_rotation_invariance():
+    """|Q Sigma d| = |Sigma d| for orthogonal Q: psi and E_L do not change
+    when every Sigma is replaced by Q Sigma (a random Q per matrix), while a
+    right rotation Sigma Q does change them (the norm acts on Sigma (r - R))."""
+    wf = full_workload(noise=0.3)
+    a = ev(wf)
+    cfg, p = wf["cfg"], wf["params"].copy()
+    rng = np.random.default_rng(7)
+    q_left, q_right = p.copy(), p.copy()
+    for a_ in range(2):
+        off, shape = I.param_offsets(cfg)[f"sigma{a_}"]
+        n = int(np.prod(shape))
+        mats = p[off:off + n].reshape(-1, 3, 3)
+        qs = np.linalg.qr(rng.normal(size=(mats.shape[0], 3, 3)))[0]
+        q_left[off:off + n] = np.einsum("mab,mbc->mac", qs, mats).reshape(-1)
+        q_right[off:off + n] = np.einsum("mab,mbc->mac", mats, qs).reshape(-1)
+    b = O.evaluate(cfg, wf["pos"], wf["nuc_pos"], wf["nuc_charge"], q_left)
+    for k in ("sign", "logpsi", "e_loc"):
+        np.testing.assert_allclose(b[k], a[k], rtol=1e-11, atol=1e-11)
+    c = O.evaluate(cfg, wf["pos"], wf["nuc_pos"], wf["nuc_charge"], q_right)
+    assert np.abs(c["logpsi"] - a["logpsi"]).max() > 1e-3
+
+
+def test_full_envelope_laplacian_vs_finite_differences():
+    """With general Sigma matrices the jet Laplacian and gradient of
+    log|psi| equal central finite differences of the value pass."""
+    w = full_workload(noise=0.4)
+    r = ev(w, grad_pos=True)
+    pos = w["pos"].astype(np.float64).reshape(3, -1)
+    n3 = pos.shape[1]
+    h = 1e-4
+    lap = np.zeros(3)
+    grad = np.zeros((3, n3))
+    for q in range(n3):
+        pp, pm = pos.copy(), pos.copy()
+        pp[:, q] += h
+        pm[:, q] -= h
+        lp = ev(w, pp.reshape(3, -1, 3), energy=False)["logpsi"]
+        lm = ev(w, pm.reshape(3, -1, 3), energy=False)["logpsi"]
+        lap += (lp - 2 * r["logpsi"] + lm) / h ** 2
+        grad[:, q] = (lp - lm) / (2 * h)
+    np.testing.assert_allclose(r["grad_pos"], grad, rtol=1e-6, atol=1e-6)  # central-difference error O(h^2)
+    kin_fd = -0.5 * (lap + (grad ** 2).sum(1))
+    np.testing.assert_allclose(r["e_kin"], kin_fd, rtol=1e-4, atol=1e-4)
+
+
+def test_full_envelope_param_gradient_vs_finite_differences():
+    """d log|psi| / d Sigma_ab (every entry of several matrices of both
+    spins) from dual numbers equals central differences."""
+    w = full_workload(noise=0.4)
+    cfg, p = w["cfg"], w["params"]
+    offs = I.param_offsets(cfg)
+    sel = []
+    for a_ in range(2):
+        off, _ = offs[f"sigma{a_}"]
+        sel += list(range(off, off + 18))  # two full matrices
+    sel += [offs["pi0"][0], offs["g_orb1"][0]]
+    sel = np.array(sel, dtype=np.int64)
+    g = O.param_grad(cfg, w["pos"], w["nuc_pos"], p, sel)
+    h = 1e-6
+    for s_i, q in enumerate(sel):
+        pp, pm = p.copy(), p.copy()
+        pp[q] += h
+        pm[q] -= h
+        fd = (O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], pp, energy=False)["logpsi"] -
+              O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], pm, energy=False)["logpsi"]) / (2 * h)
+        np.testing.assert_allclose(g[:, s_i], fd, rtol=1e-6, atol=1e-7)
