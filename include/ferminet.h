@@ -55,7 +55,8 @@
  *    for l in 0..L-2:  W_l [ein_l][d2],             then c_l [d2]
  *    for a in up, down: w_a [d1][K n_a], then g_a [K n_a]
  *    for a in up, down: pi_a [K n_a][N]
- *    for a in up, down: sigma_a [K n_a][N]
+ *    for a in up, down: sigma_a [K n_a][N] (isotropic envelope), or
+ *                       Sigma_a [K n_a][N][3][3] (full covariance, row-major)
  *    din_0 = 4N, ein_0 = 4; din_l = d1, ein_l = d2 for l > 0.
  *    The rows of V_l are ordered as f_i: [h_i | hbar^up | hbar^down |
  *    g^up_i | g^down_i].
@@ -99,6 +100,15 @@ typedef enum {
   FN_PREC_FP64 = 3
 } fn_precision;
 
+typedef enum {
+  /* exp(-|sigma_im| |r_j - R_m|): one exponent per orbital and nucleus,
+   * the simplification of Section 3 */
+  FN_ENV_ISOTROPIC = 0,
+  /* exp(-|Sigma_im (r_j - R_m)|) with a 3x3 matrix Sigma_im (row-major,
+   * applied to the column vector r_j - R_m): Eq. (5) as written */
+  FN_ENV_FULL = 1
+} fn_envelope;
+
 /* Shapes.  Limits of this build: 1 <= n_elec <= 32 with any split
  * 0 <= n_up, n_down (n_up + n_down = n_elec), 1 <= n_nuc <= 32,
  * 1 <= n_layers <= 8, width1 in [32, 1024] and a multiple of 32,
@@ -115,6 +125,7 @@ typedef struct {
   int32_t width2;    /* d2, two-electron stream width */
   int32_t n_det;     /* K, determinants */
   int32_t precision; /* fn_precision */
+  int32_t envelope;  /* fn_envelope */
   /* Local energy in the reduced-precision forms: the fraction f in [0, 1]
    * of walkers re-evaluated entirely in float64 (0: none; ignored by
    * FN_PREC_FP64 and by the other entry points).  Within each chunk of

@@ -21,6 +21,7 @@ struct Plan {
   fn_config cfg;
   int n, nu, nd, N, L, d1, d2, K, n3;
   bool bf16, fp64, f64;
+  bool env_full;  // full-covariance envelope (3x3 Sigma per orbital and nucleus)
   int mode;       // GEMM arithmetic (MODE_*)
   float rescue;   // fraction of each chunk re-evaluated in float64 (local energy)
   size_t act;     // bytes per activation element
@@ -50,6 +51,8 @@ static fn_status make_plan(const fn_config* c, Plan& p) {
       c->precision != FN_PREC_FP64)
     return FN_ERR_CONFIG;
   if (!(c->rescue_fraction >= 0.0f && c->rescue_fraction <= 1.0f)) return FN_ERR_CONFIG;
+  if (c->envelope != FN_ENV_ISOTROPIC && c->envelope != FN_ENV_FULL) return FN_ERR_CONFIG;
+  p.env_full = c->envelope == FN_ENV_FULL;
   p.bf16 = c->precision == FN_PREC_BF16;
   p.f64 = c->precision == FN_PREC_FP64;
   p.fp64 = c->precision != FN_PREC_FP32;
@@ -91,7 +94,7 @@ static fn_status make_plan(const fn_config* c, Plan& p) {
   }
   for (int a = 0; a < 2; ++a) {
     p.offsg[a] = off;
-    off += (int64_t)p.K * p.na(a) * p.N;
+    off += (int64_t)p.K * p.na(a) * p.N * (p.env_full ? 9 : 1);
   }
   p.P = off;
   // packed weights, each block 256-byte aligned
@@ -516,6 +519,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     o.g_orb = params + p.offg[a];
     o.pi = params + p.offpi[a];
     o.sigma = params + p.offsg[a];
+    o.env_full = p.env_full;
     FN_T(SG(ST_GEMM_ORB), launch_jet_gemm(p.mode, EPI_ORBITAL, o, s));
     FN_T(SG(ST_DET), launch_det(p.fp64, b.phi[a], p.f64, (int)Wc, p.K, na, T, p.n3, b.D[a], b.dstride, nullptr, s));
   }
@@ -658,6 +662,7 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
     o.g_orb = params + p.offg[a];
     o.pi = params + p.offpi[a];
     o.sigma = params + p.offsg[a];
+    o.env_full = p.env_full;
     o.u_out = b.u[a];
     o.env_out = b.env[a];
     FN_T(ST_ADJ_FWD, launch_jet_gemm(mode, EPI_ORBITAL, o, s));
@@ -749,7 +754,8 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     const int j0 = a == 0 ? 0 : p.nu;
     FN_T(ST_ADJ_ORB, launch_adj_orbital_cot(p.fp64, b.binv[a], b.rho, cot, b.u[a], b.env[a], (int)Wc, p.K, na, b.ldu,
                                             b.cot_u[a], b.cot_env[a], s));
-    FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a], (int)Wc,
+    FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a], p.env_full,
+                                         (int)Wc,
                                          p.K, na, j0, p.n, p.N, grad + p.offpi[a], grad + p.offsg[a], s));
     FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.cot_u[a], Wc * na, p.K * na, b.ldu, b.tmp, grad + p.offg[a], kRowChunk, s));
     st = atb_add(b, b.H[p.L], p.d1, 0, na, p.n, j0, b.cot_u[a], b.ldu, Wc * na, p.d1, p.K * na, grad + p.offw[a], s);
@@ -933,7 +939,7 @@ fn_status ferminet_param_layout(const fn_config* cfg, fn_param_block* out, int32
   }
   for (int a = 0; a < 2; ++a) {
     snprintf(nm, 16, "sigma%d", a);
-    add(nm, p.offsg[a], (int64_t)p.K * p.na(a), p.N);
+    add(nm, p.offsg[a], (int64_t)p.K * p.na(a), (int64_t)p.N * (p.env_full ? 9 : 1));
   }
   *n_out = (int32_t)v.size();
   if (cap < (int32_t)v.size()) return FN_ERR_ARG;

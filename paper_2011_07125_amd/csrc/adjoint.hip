@@ -76,45 +76,77 @@ __device__ inline float block_sum256(float v, float* sh) {
   return r;
 }
 
-// envelope parameters: one block per (orbital column (k,i), nucleus m):
-//   dpi    += sum_{w,j} cot_env exp(-|s| d_jm)
-//   dsigma += sum_{w,j} cot_env pi exp(-|s| d_jm) (-sign(s) d_jm)
+// envelope parameters: one block per (orbital column (k,i), nucleus m),
+// d = r_j - R_m, e = exp(-s):
+//   isotropic: s = |sigma| |d|
+//     dpi    += sum_{w,j} cot_env e
+//     dsigma += sum_{w,j} cot_env pi e (-sign(sigma) |d|)
+//   full:      s = |Sigma d| = |u|
+//     dpi          += sum_{w,j} cot_env e
+//     dSigma[a][b] += sum_{w,j} cot_env pi e (-u_a d_b / s)
+template <bool FULL>
 __global__ __launch_bounds__(256) void adj_env_grad_kernel(const float* cot_env, const float* pos, const float* nuc,
                                                            const float* pi, const float* sigma, int W, int K,
                                                            int na, int j0, int n, int N, float* dpi,
                                                            float* dsigma) {
   __shared__ float sh[4];
+  constexpr int NS = FULL ? 9 : 1;
   const int col = blockIdx.x / N, m = blockIdx.x % N;
   const int k = col / na, i = col % na;
-  const float p = pi[col * N + m], sg = sigma[col * N + m], s = fabsf(sg);
-  const float sgn = sg < 0.0f ? -1.0f : 1.0f;
-  float api = 0.0f, asg = 0.0f;
+  const float p = pi[col * N + m];
+  float M[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) M[q] = sigma[((size_t)col * N + m) * NS + q];
+  float api = 0.0f, asg[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) asg[q] = 0.0f;
   const int64_t rows = (int64_t)W * na;
   for (int64_t r = threadIdx.x; r < rows; r += 256) {
     const int j = (int)(r % na);
     const int64_t w = r / na;
     const float* x = pos + (w * n + j0 + j) * 3;
-    const float dx = x[0] - nuc[3 * m], dy = x[1] - nuc[3 * m + 1], dz = x[2] - nuc[3 * m + 2];
-    const float d = sqrtf(dx * dx + dy * dy + dz * dz);
-    const float e = expf(-s * d);
+    const float dv[3] = {x[0] - nuc[3 * m], x[1] - nuc[3 * m + 1], x[2] - nuc[3 * m + 2]};
     const float c = cot_env[((w * K + k) * na + j) * na + i];
-    api += c * e;
-    asg += c * p * e * (-sgn * d);
+    if constexpr (FULL) {
+      float u[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) u[q] = M[3 * q] * dv[0] + M[3 * q + 1] * dv[1] + M[3 * q + 2] * dv[2];
+      const float sv = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      const float e = expf(-sv);
+      api += c * e;
+      const float f = -c * p * e / sv;
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) asg[3 * q + b] += f * u[q] * dv[b];
+    } else {
+      const float s = fabsf(M[0]), sgn = M[0] < 0.0f ? -1.0f : 1.0f;
+      const float d = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      const float e = expf(-s * d);
+      api += c * e;
+      asg[0] += c * p * e * (-sgn * d);
+    }
   }
   api = block_sum256(api, sh);
-  asg = block_sum256(asg, sh);
+#pragma unroll
+  for (int q = 0; q < NS; ++q) asg[q] = block_sum256(asg[q], sh);
   if (threadIdx.x == 0) {
     dpi[col * N + m] += api;
-    dsigma[col * N + m] += asg;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) dsigma[((size_t)col * N + m) * NS + q] += asg[q];
   }
 }
 
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
-                               const float* sigma, int W, int K, int na, int j0, int n, int N, float* dpi,
+                               const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
                                float* dsigma, hipStream_t s) {
   if (na <= 0 || W <= 0) return hipSuccess;
-  hipLaunchKernelGGL(adj_env_grad_kernel, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W, K, na,
-                     j0, n, N, dpi, dsigma);
+  if (full)
+    hipLaunchKernelGGL(adj_env_grad_kernel<true>, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W,
+                       K, na, j0, n, N, dpi, dsigma);
+  else
+    hipLaunchKernelGGL(adj_env_grad_kernel<false>, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W,
+                       K, na, j0, n, N, dpi, dsigma);
   return hipGetLastError();
 }
 

@@ -433,20 +433,51 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
       const int k = gc / na, i = gc % na;
       const float* rj = a.pos + ((size_t)w * a.n_elec + j) * 3;
       const S x0 = rj[0], x1 = rj[1], x2 = rj[2];
-      // isotropic envelope sum_m pi exp(-|sigma| d) and its gradient and
-      // Laplacian with respect to r_j
+      // envelope sum_m pi exp(-s_m) and its gradient and Laplacian with
+      // respect to r_j, d = r_j - R_m:
+      //   isotropic: s = |sigma| |d|, grad s = |sigma| d / |d|,
+      //              lap s = 2 |sigma| / |d|
+      //   full:      s = |u|, u = Sigma d, grad s = Sigma^T u / s,
+      //              lap s = (tr(Sigma^T Sigma) - |grad s|^2) / s
+      //   grad e = -e grad s, lap e = e (|grad s|^2 - lap s)
       S e0 = 0, ex = 0, ey = 0, ez = 0, le = 0;
       for (int m = 0; m < a.n_nuc; ++m) {
         const S dx = x0 - (S)a.nuc[3 * m], dyv = x1 - (S)a.nuc[3 * m + 1], dz = x2 - (S)a.nuc[3 * m + 2];
-        const S d = sqrt(dx * dx + dyv * dyv + dz * dz);
-        const S sg = fabs((S)a.sigma[(size_t)gc * a.n_nuc + m]);
-        const S v = (S)a.pi[(size_t)gc * a.n_nuc + m] * exp(-sg * d);
-        const S inv_d = (S)1 / d;
-        e0 += v;
-        ex -= sg * v * dx * inv_d;
-        ey -= sg * v * dyv * inv_d;
-        ez -= sg * v * dz * inv_d;
-        le += v * (sg * sg - (S)2 * sg * inv_d);
+        const S pim = (S)a.pi[(size_t)gc * a.n_nuc + m];
+        if (a.env_full) {
+          const float* Sg = a.sigma + ((size_t)gc * a.n_nuc + m) * 9;
+          S M[9];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) M[q] = (S)Sg[q];
+          const S u0 = M[0] * dx + M[1] * dyv + M[2] * dz;
+          const S u1 = M[3] * dx + M[4] * dyv + M[5] * dz;
+          const S u2 = M[6] * dx + M[7] * dyv + M[8] * dz;
+          const S sv = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+          const S inv_s = (S)1 / sv;
+          const S g0 = (M[0] * u0 + M[3] * u1 + M[6] * u2) * inv_s;
+          const S g1 = (M[1] * u0 + M[4] * u1 + M[7] * u2) * inv_s;
+          const S g2 = (M[2] * u0 + M[5] * u1 + M[8] * u2) * inv_s;
+          S tr = 0;
+#pragma unroll
+          for (int q = 0; q < 9; ++q) tr += M[q] * M[q];
+          const S gg = g0 * g0 + g1 * g1 + g2 * g2;
+          const S v = pim * exp(-sv);
+          e0 += v;
+          ex -= v * g0;
+          ey -= v * g1;
+          ez -= v * g2;
+          le += v * (gg - (tr - gg) * inv_s);
+        } else {
+          const S d = sqrt(dx * dx + dyv * dyv + dz * dz);
+          const S sg = fabs((S)a.sigma[(size_t)gc * a.n_nuc + m]);
+          const S v = pim * exp(-sg * d);
+          const S inv_d = (S)1 / d;
+          e0 += v;
+          ex -= sg * v * dx * inv_d;
+          ey -= sg * v * dyv * inv_d;
+          ez -= sg * v * dz * inv_d;
+          le += v * (sg * sg - (S)2 * sg * inv_d);
+        }
       }
       const S* Cr = Cs + (e * rows_per) * LDC + col;
       const S u0 = Cr[0] + (S)a.g_orb[gc];

@@ -46,6 +46,7 @@ struct JetGemmArgs {
   int64_t phi_M;
   const float* pos; const float* nuc; int n_nuc; int n_elec;
   const float* g_orb; const float* pi; const float* sigma;
+  int env_full;  // sigma holds 3x3 matrices [col][m][3][3] (full covariance envelope)
   float* u_out; float* env_out;  // value mode, optional: [w][K][j][i]
 };
 
@@ -140,7 +141,7 @@ hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, 
                                   const float* env, int W, int K, int na, int ldu, float* cot_u, float* cot_env,
                                   hipStream_t s);
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
-                               const float* sigma, int W, int K, int na, int j0, int n, int N, float* dpi,
+                               const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
                                float* dsigma, hipStream_t s);
 hipError_t launch_adj_cp(const float* ch, const float* pre, int64_t total, float* cp, hipStream_t s);
 hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float* S, hipStream_t s);

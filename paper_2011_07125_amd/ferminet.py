@@ -17,6 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libferminet.so")
 
 FN_PREC_FP32, FN_PREC_BF16, FN_PREC_FP32_FP64DET, FN_PREC_FP64 = 0, 1, 2, 3
+FN_ENV_ISOTROPIC, FN_ENV_FULL = 0, 1
+ENVELOPES = {"isotropic": FN_ENV_ISOTROPIC, "full": FN_ENV_FULL}
 PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
 FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC = 0, 1, 2, 3
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
@@ -31,7 +33,7 @@ class FerminetError(RuntimeError):
 
 class fn_config(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("n_elec", "n_up", "n_down", "n_nuc", "n_layers", "width1", "width2",
-                                               "n_det", "precision")] + [("rescue_fraction", ctypes.c_float)]
+                                               "n_det", "precision", "envelope")] + [("rescue_fraction", ctypes.c_float)]
 
 
 class fn_param_block(ctypes.Structure):
@@ -87,8 +89,10 @@ def make_config(cfg: dict, precision=None, rescue: float = 0.0) -> fn_config:
     prec = cfg.get("precision", "fp32") if precision is None else precision
     if isinstance(prec, str):
         prec = PRECISIONS[prec]
+    env = cfg.get("envelope", "isotropic")
+    env = ENVELOPES[env] if isinstance(env, str) else int(env)
     return fn_config(cfg["n_elec"], cfg["n_up"], cfg["n_down"], cfg["n_nuc"], cfg["n_layers"], cfg["width1"],
-                     cfg["width2"], cfg["n_det"], prec, float(rescue))
+                     cfg["width2"], cfg["n_det"], prec, env, float(rescue))
 
 
 def _check(st: int, where: str):
