@@ -22,6 +22,16 @@ __host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
 
 // x = hi + lo with hi = bf16(x) and lo = bf16(x - hi), both rounded to
 // nearest even by the hardware conversion (v_cvt_pk_bf16_f32 on gfx950)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+// the same split for two values at once, packed (element 0 in the low half):
+// one v_cvt_pk_bf16_f32 per part
+__device__ inline void split_bf16x2(float x0, float x1, uint32_t* hi, uint32_t* lo) {
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){x0, x1}, bf16x2));
+  const float h0 = __builtin_bit_cast(float, h << 16), h1 = __builtin_bit_cast(float, h & 0xffff0000u);
+  *hi = h;
+  *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){x0 - h0, x1 - h1}, bf16x2));
+}
 __device__ inline void split_bf16(float x, uint16_t* h, uint16_t* l) {
   const __bf16 hb = (__bf16)x;
   const __bf16 lb = (__bf16)(x - (float)hb);
@@ -40,12 +50,16 @@ __device__ inline float sech2f(float u) {
 // tanh(u) and sech^2(u) from one expm1: with m = e^{-2|u|} - 1,
 //   tanh|u| = -m / (2 + m),  sech^2 u = 4 (1 + m) / (2 + m)^2
 // (no cancellation for small |u| or once tanh saturates)
+// 1 / d for d in [1, 2] is the hardware reciprocal refined by one Newton
+// step (r + r (1 - d r)), which leaves about half an ulp.
 __device__ inline void tanh_sech2f(float u, float* th, float* s2) {
   const float m = expm1f(-2.0f * fabsf(u));
   const float d = 2.0f + m;
-  const float t = -m / d;
+  float r = __builtin_amdgcn_rcpf(d);
+  r = fmaf(r, fmaf(-d, r, 1.0f), r);
+  const float t = -m * r;
   *th = u < 0.0f ? -t : t;
-  *s2 = 4.0f * (1.0f + m) / (d * d);
+  *s2 = 4.0f * (1.0f + m) * (r * r);
 }
 __device__ inline void tanh_sech2(float u, float* th, float* s2) { tanh_sech2f(u, th, s2); }
 __device__ inline void tanh_sech2(double u, double* th, double* s2) {

@@ -20,7 +20,13 @@
 //    of the electron's other waves when the jet is taller than a wave's
 //    rows).  The sum of squared tangents is reduced with cross-lane shuffles
 //    and a 4 KiB cross-wave exchange in fixed order, the tanh chain rule is
-//    applied in registers, and results go straight to HBM with the residual added.
+//    applied in registers, and results go straight to HBM with the residual added;
+//  * every global access is a raw buffer operation whose wave-uniform part
+//    (tile or electron base, jet row, K step) sits in scalar registers and
+//    whose per-lane part is one 32-bit offset computed once: the loops carry
+//    no 64-bit address arithmetic and no per-element branches, and rows past
+//    the last electron get an offset beyond the buffer range, which the
+//    hardware reads as zero.
 #include "common.h"
 #include "kernels.h"
 
@@ -43,9 +49,25 @@ struct LayerCfg {
   static constexpr int NB = MODE == MODE_F32 ? BN * BK / 4 : BN * BK / 8;  // 16-byte vectors per B plane
   static constexpr int NVB = (NB + NT - 1) / NT;
   static_assert(NT == 512 && WROWS % 16 == 0 && WCOLS % 16 == 0, "tile shape");
+  static_assert(NB % NT == 0 && BN % 128 == 0, "every B vector is loaded; N is a multiple of 128");
 };
 
 __device__ inline uint32_t pk2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// raw buffer over the 2^31 - 1 bytes from p (word 3: the gfx9 data format
+// for untyped 32-bit access); loads at offsets of 2^31 or more return zero
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7fffffff, 0x00020000);
+}
+constexpr int kOutOfRange = (int)0x80000000;
+__device__ inline float ldf(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ inline void stf(float x, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, soff, 0);
+}
 
 // element offset of 16-byte chunk c (0..3) of row r in an unpadded bfloat16
 // tile of 32-element rows: chunks are permuted by (r >> 1) & 3, so eight
@@ -66,7 +88,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int n_t = (bid / 8) % n_ntiles;
   const int m_t = (bid / (8 * n_ntiles)) * 8 + (bid % 8);
   if (m_t >= n_mtiles) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
   const int rows_per = JET ? a.rows_per : 1;
   const int E = BM / rows_per;  // electrons per row tile
@@ -74,65 +97,68 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const int n0 = n_t * BN;
   const int nkt = (a.ka0 + a.ka1) / BK;
 
-  // A loader: 8 float4 per 32-wide tile row
-  long rowoff[C::NVA];
+  // A loader: 8 float4 per 32-wide tile row, at byte offsets from the
+  // tile's first row (row numbers grow with the electron index)
+  const int q0 = g0 / a.n_sub, m0 = g0 - q0 * a.n_sub;
+  const long row0 = ((long)q0 * a.n_all + a.e_off + m0) * rows_per;
+  int voff0[C::NVA], voff1[C::NVA];
 #pragma unroll
   for (int i = 0; i < C::NVA; ++i) {
     const int v = tid + i * C::NT;
     const int r = v / (BK / 4);
     const int e = r / rows_per, t = r - e * rows_per;
     const int g = g0 + e;
-    rowoff[i] = (v < C::NA && g < a.n_groups)
-                    ? ((long)(g / a.n_sub) * a.n_all + a.e_off + (g % a.n_sub)) * rows_per + t
-                    : -1;
+    // electron g = g0 + e: g / n_sub = q0 + qe, g % n_sub = me (32-bit)
+    const int qe = (m0 + e) / a.n_sub, me = m0 + e - qe * a.n_sub;
+    const long rr = ((long)qe * a.n_all + (me - m0)) * rows_per + t;
+    const int c4 = (v % (BK / 4)) * 4;
+    const bool ok = v < C::NA && g < a.n_groups;
+    voff0[i] = ok ? (int)((rr * a.lda0 + c4) * 4) : kOutOfRange;
+    voff1[i] = ok ? (int)((rr * a.lda1 + c4) * 4) : kOutOfRange;
   }
-  // two register stages in the jet pass: the loads of K steps kt+2 and
-  // kt+3 are in flight while step kt is multiplied
+  const __amdgpu_buffer_rsrc_t rA0 = rsrc((const float*)a.a0 + row0 * a.lda0);
+  const __amdgpu_buffer_rsrc_t rA1 = rsrc(a.ka1 > 0 ? (const float*)a.a1 + row0 * a.lda1 : (const float*)a.a0);
+  // B loader: columns n0 .. n0 + BN - 1 all exist (N is a multiple of BN)
+  constexpr int ESZ = MODE == MODE_F32 ? 4 : 2;
+  constexpr int VPR = MODE == MODE_F32 ? BK / 4 : BK / 8;  // 16-byte vectors per B row
+  int voffB[C::NVB];
+#pragma unroll
+  for (int i = 0; i < C::NVB; ++i) {
+    const int v = tid + i * C::NT;
+    voffB[i] = ((v / VPR) * a.ldb + (v % VPR) * (16 / ESZ)) * ESZ;
+  }
+  const __amdgpu_buffer_rsrc_t rB = rsrc((const char*)a.bt + (size_t)n0 * a.ldb * ESZ);
+  const __amdgpu_buffer_rsrc_t rBl =
+      rsrc(MODE == MODE_F32 ? (const char*)a.bt : (const char*)a.bt_lo + (size_t)n0 * a.ldb * ESZ);
+
+  // two register stages in the split-bfloat16 jet pass: the loads of K
+  // steps kt+2 and kt+3 are in flight while step kt is multiplied
   struct Regs {
-    float4 ra[C::NVA];
-    uint4 rb[C::NVB], rbl[MODE == MODE_F32 ? 1 : C::NVB];
+    u32x4 ra[C::NVA];
+    u32x4 rb[C::NVB], rbl[MODE == MODE_F32 ? 1 : C::NVB];
   };
   Regs R0, R1;
 
   auto gload = [&](int kt, Regs& R) {
-    float4* ra = R.ra;
-    uint4* rb = R.rb;
-    uint4* rbl = R.rbl;
     const int kb = kt * BK;
-    const float* src = kb < a.ka0 ? (const float*)a.a0 : (const float*)a.a1;
-    const int lda = kb < a.ka0 ? a.lda0 : a.lda1;
-    const int kk = kb < a.ka0 ? kb : kb - a.ka0;
+    if (kb < a.ka0) {
 #pragma unroll
-    for (int i = 0; i < C::NVA; ++i) {
-      const int v = tid + i * C::NT;
-      float4 z = {0.f, 0.f, 0.f, 0.f};
-      if (rowoff[i] >= 0) z = *reinterpret_cast<const float4*>(src + (size_t)rowoff[i] * lda + kk + (v % (BK / 4)) * 4);
-      ra[i] = z;
+      for (int i = 0; i < C::NVA; ++i) R.ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA0, voff0[i], kb * 4, 0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < C::NVA; ++i)
+        R.ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA1, voff1[i], (kb - a.ka0) * 4, 0);
     }
 #pragma unroll
     for (int i = 0; i < C::NVB; ++i) {
-      const int v = tid + i * C::NT;
-      uint4 z = {0, 0, 0, 0}, zl = {0, 0, 0, 0};
-      if constexpr (MODE == MODE_F32) {
-        const int nn = v / (BK / 4), col = n0 + nn;
-        if (v < C::NB && col < a.N)
-          z = *reinterpret_cast<const uint4*>((const float*)a.bt + (size_t)col * a.ldb + kb + (v % (BK / 4)) * 4);
-      } else {
-        const int nn = v / (BK / 8), col = n0 + nn;
-        if (v < C::NB && col < a.N) {
-          const size_t off = (size_t)col * a.ldb + kb + (v % (BK / 8)) * 8;
-          z = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt + off);
-          zl = *reinterpret_cast<const uint4*>((const uint16_t*)a.bt_lo + off);
-        }
-      }
-      rb[i] = z;
-      if constexpr (MODE != MODE_F32) rbl[i] = zl;
+      R.rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rB, voffB[i], kb * ESZ, 0);
+      if constexpr (MODE != MODE_F32) R.rbl[i] = __builtin_amdgcn_raw_buffer_load_b128(rBl, voffB[i], kb * ESZ, 0);
     }
   };
   auto sstore = [&](const Regs& R, int buf) {
-    const float4* ra = R.ra;
-    const uint4* rb = R.rb;
-    const uint4* rbl = R.rbl;
+    const u32x4* ra = R.ra;
+    const u32x4* rb = R.rb;
+    const u32x4* rbl = R.rbl;
     char* st = smem + buf * C::STAGE;
     if constexpr (MODE == MODE_F32) {
       float* As = reinterpret_cast<float*>(st);
@@ -140,12 +166,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
       for (int i = 0; i < C::NVA; ++i) {
         const int v = tid + i * C::NT;
-        if (v < C::NA) *reinterpret_cast<float4*>(As + (v / (BK / 4)) * LDA + (v % (BK / 4)) * 4) = ra[i];
+        if (C::NA % C::NT == 0 || v < C::NA)
+          *reinterpret_cast<u32x4*>(As + (v / (BK / 4)) * LDA + (v % (BK / 4)) * 4) = ra[i];
       }
 #pragma unroll
       for (int i = 0; i < C::NVB; ++i) {
         const int v = tid + i * C::NT;
-        if (v < C::NB) *reinterpret_cast<uint4*>(Bs + (v / (BK / 4)) * LDB + (v % (BK / 4)) * 4) = rb[i];
+        *reinterpret_cast<u32x4*>(Bs + (v / (BK / 4)) * LDB + (v % (BK / 4)) * 4) = rb[i];
       }
     } else {
       uint16_t* Ah = reinterpret_cast<uint16_t*>(st);
@@ -155,25 +182,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
       for (int i = 0; i < C::NVA; ++i) {
         const int v = tid + i * C::NT;
-        if (v < C::NA) {
+        if (C::NA % C::NT == 0 || v < C::NA) {
           const int q = v % (BK / 4);
           const int off = swz(v / (BK / 4), q >> 1) + (q & 1) * 4;
-          uint16_t h[4], l[4];
-          split_bf16(ra[i].x, &h[0], &l[0]);
-          split_bf16(ra[i].y, &h[1], &l[1]);
-          split_bf16(ra[i].z, &h[2], &l[2]);
-          split_bf16(ra[i].w, &h[3], &l[3]);
-          *reinterpret_cast<uint2*>(Ah + off) = uint2{pk2(h[0], h[1]), pk2(h[2], h[3])};
-          *reinterpret_cast<uint2*>(Al + off) = uint2{pk2(l[0], l[1]), pk2(l[2], l[3])};
+          uint32_t h0, h1, l0, l1;
+          split_bf16x2(__uint_as_float(ra[i].x), __uint_as_float(ra[i].y), &h0, &l0);
+          split_bf16x2(__uint_as_float(ra[i].z), __uint_as_float(ra[i].w), &h1, &l1);
+          *reinterpret_cast<uint2*>(Ah + off) = uint2{h0, h1};
+          *reinterpret_cast<uint2*>(Al + off) = uint2{l0, l1};
         }
       }
 #pragma unroll
       for (int i = 0; i < C::NVB; ++i) {
         const int v = tid + i * C::NT;
-        if (v < C::NB) {
+        {
           const int off = swz(v / (BK / 8), v % (BK / 8));
-          *reinterpret_cast<uint4*>(Bh + off) = rb[i];
-          *reinterpret_cast<uint4*>(Bl + off) = rbl[i];
+          *reinterpret_cast<u32x4*>(Bh + off) = rb[i];
+          *reinterpret_cast<u32x4*>(Bl + off) = rbl[i];
         }
       }
     }
@@ -230,7 +255,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
   };
 
-  if constexpr (JET) {
+  if constexpr (JET && MODE != MODE_F32) {
     if (nkt > 0) {
       gload(0, R0);
       sstore(R0, 0);
@@ -256,7 +281,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       __syncthreads();
     }
   } else {
-    // value pass (short K loop, wide epilogue): one register stage
+    // value pass (short K loop, wide epilogue) and float32 operands (eight
+    // MFMA k-steps per K step hide the loads): one register stage
     if (nkt > 0) {
       gload(0, R0);
       sstore(R0, 0);
@@ -322,21 +348,29 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     return;
   }
 
-  // jet mode: the rows of this wave lie in one electron (rows_per % WROWS == 0)
+  // jet mode: the rows of this wave lie in one electron (rows_per % WROWS == 0).
+  // Lane (kq, c) holds rows t = tw0 + 16 i + 4 kq + r of columns
+  // wn WCOLS + 16 j + c: the (i, r) part of a row and the whole column base
+  // are wave-uniform (scalar offsets and buffer bases), 4 kq rows and c
+  // columns are the lane's own offset, and 16 j columns an immediate.
   const int wrow0 = wm * WROWS;
   const int e_loc = wrow0 / rows_per;
   const int tw0 = wrow0 - e_loc * rows_per;  // jet row of the wave's first row
   const int g = g0 + e_loc;
   const bool gval = g < a.n_groups;
-  const float* Pb = (const float*)a.P + (size_t)(gval ? g / a.n_all : 0) * rows_per * a.ldp;
+  const int cw = n0 + wn * C::WCOLS;  // first column of the wave
   const size_t obase = (size_t)(gval ? g : 0) * rows_per;
+  // the mean-field term has rows_per rows per walker (rows past T unused)
+  const __amdgpu_buffer_rsrc_t rP =
+      rsrc((const float*)a.P + (size_t)(gval ? g / a.n_all : 0) * rows_per * a.ldp + cw);
+  const __amdgpu_buffer_rsrc_t rR = rsrc(res + obase * a.lda0 + cw);
+  const __amdgpu_buffer_rsrc_t rO = rsrc(out + obase * a.ldo + cw);
+  const int c = lane & 15;
+  const int voP = (kq * 4 * a.ldp + c) * 4, voR = (kq * 4 * a.lda0 + c) * 4, voO = (kq * 4 * a.ldo + c) * 4;
 
-  // pre-activation u = acc + P (+ bias on the value row); partial sums of the
-  // squared tangent rows 1..T-2.  Per 16-row tile all P loads are issued
-  // together (rows clamped into range, then masked) before any is used.
-  float bj[TN];
-#pragma unroll
-  for (int j = 0; j < TN; ++j) bj[j] = a.bias[gcol[j]];
+  // pre-activation u = acc + P (the bias enters the value row below);
+  // partial sums of the squared tangent rows 1 .. T-2.  Per 16-row tile all
+  // P loads are issued together before any is used.
   float s2[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) s2[j] = 0.0f;
@@ -345,21 +379,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     float pv[4][TN];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int t = tw0 + i * 16 + kq * 4 + r;
-      const float* Prow = Pb + (size_t)(t < T ? t : T - 1) * a.ldp;
+      const int so = (tw0 + i * 16 + r) * a.ldp * 4;
 #pragma unroll
-      for (int j = 0; j < TN; ++j) pv[r][j] = Prow[gcol[j]];
+      for (int j = 0; j < TN; ++j) pv[r][j] = ldf(rP, voP + j * 64, so);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int t = tw0 + i * 16 + kq * 4 + r;
-      const bool live = gval && t < T;
+      const bool live = t < a.T, tangent = (i + r > 0 || t >= 1) && t <= a.T - 2;  // t >= 16 i + r
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        float v = acc[i][j][r] + (live ? pv[r][j] : 0.0f);
-        if (live && t == 0) v += bj[j];
+        const float v = acc[i][j][r] + (live ? pv[r][j] : 0.0f);
         acc[i][j][r] = v;
-        if (live && t >= 1 && t <= T - 2) s2[j] += v * v;
+        const float q = tangent ? v : 0.0f;
+        s2[j] = fmaf(q, q, s2[j]);
       }
     }
   }
@@ -371,7 +404,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // cross-wave exchange (stage buffers are free after the main loop's last barrier)
   float* red = reinterpret_cast<float*>(smem);  // [WM][BN] partial sums
   float* val = red + WM * BN;                   // [WM][BN] value rows
-  const int cl = wn * C::WCOLS + (lane & 15);
+  const int cl = wn * C::WCOLS + c;
   if (kq == 0) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
@@ -386,37 +419,36 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   for (int j = 0; j < TN; ++j) {
     float ss = 0.0f;
     for (int w = wfirst; w < wfirst + wper; ++w) ss += red[w * BN + cl + j * 16];
-    const float u0 = val[wfirst * BN + cl + j * 16];
+    const float u0 = val[wfirst * BN + cl + j * 16] + a.bias[cw + c + j * 16];
     tanh_sech2f(u0, &y[j], &dy[j]);
     lapc[j] = -2.0f * y[j] * dy[j] * ss;
-    if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + gcol[j]] = u0;
+    if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + cw + c + j * 16] = u0;
   }
   if (!gval) return;
-  // per 16-row tile: all residual loads first, then the stores (one memory
-  // round trip per tile, not per element)
+  // per 16-row tile: all residual loads first, then the stores.  Row t
+  // becomes y (t = 0), sech^2 u0 times its tangent (0 < t < T - 1), the
+  // same plus the curvature term (t = T - 1), or zero (padding, t >= T),
+  // plus the residual.
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     float rv[4][TN];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int t = tw0 + i * 16 + kq * 4 + r;
-      const float* rrow = res + (obase + t) * a.lda0;
+      const int so = (tw0 + i * 16 + r) * a.lda0 * 4;
 #pragma unroll
-      for (int j = 0; j < TN; ++j) rv[r][j] = (a.res && t < T) ? rrow[gcol[j]] : 0.0f;
+      for (int j = 0; j < TN; ++j) rv[r][j] = a.res ? ldf(rR, voR + j * 64, so) : 0.0f;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int t = tw0 + i * 16 + kq * 4 + r;
-      float* orow = out + (obase + t) * a.ldo;
+      const bool live = t < a.T, last = t == a.T - 1;
+      const bool first = i + r == 0 && t == 0, deriv = (i + r > 0 || t >= 1) && live;  // t >= 16 i + r
+      const int so = (tw0 + i * 16 + r) * a.ldo * 4;
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const float v = acc[i][j][r];
-        float o;
-        if (t == 0) o = y[j];
-        else if (t < T - 1) o = dy[j] * v;
-        else if (t == T - 1) o = dy[j] * v + lapc[j];
-        else o = 0.0f;
-        orow[gcol[j]] = o + rv[r][j];
+        const float br = (first ? y[j] : (last ? lapc[j] : 0.0f)) + (live ? rv[r][j] : 0.0f);
+        const float o = deriv ? fmaf(dy[j], acc[i][j][r], br) : br;  // selected: pad rows may hold anything
+        stf(o, rO, voO + j * 64, so);
       }
     }
   }
