@@ -61,17 +61,21 @@ def compare(name, g, o, amp, form="fp32", elog_tol=1e-5, mean_tol=1e-3, walker_t
     checked against its own bound
         sign         equal wherever u A_w < 0.1
         |d log|psi|| <= elog_tol max(1, |log|psi||) + u A_w
-        |d E_L|      <= (walker_tol + u A_w) max(1, |E_L|)
+        |d E_L|      <= (walker_tol + u A_w) max(1, |E_L|, |E_kin|)
     and the batch mean against the propagated bound
-        |d mean E_L| <= mean_tol + mean_w(u A_w max(1, |E_L|)).
-    The errors and the worst walkers are printed."""
+        |d mean E_L| <= mean_tol + mean_w(u A_w max(1, |E_L|, |E_kin|)).
+    Of the terms of the Hamiltonian (Eq. (2)) only the kinetic one passes
+    through the network; the Coulomb terms are plain functions of the
+    positions.  The absolute error of E_L is therefore that of E_kin and
+    scales with |E_kin|, which exceeds |E_L| where kinetic and potential
+    energy cancel.  The errors and the worst walkers are printed."""
     u = U_FORM[form]
     ua = u * amp
     decided = ua < 0.1
     sgn_ok = g["sign"] == o["sign"]
     dl = np.abs(g["logpsi"] - o["logpsi"])
     de = np.abs(g["e_loc"] - o["e_loc"])
-    scale_e = np.maximum(1.0, np.abs(o["e_loc"]))
+    scale_e = np.maximum(np.maximum(1.0, np.abs(o["e_loc"])), np.abs(o["e_kin"]))
     dmean = abs(g["e_loc"].mean() - o["e_loc"].mean())
     mean_bound = mean_tol + np.mean(ua * scale_e)
     worst = np.argsort(de / scale_e)[-3:][::-1]
