@@ -130,15 +130,23 @@ typedef struct {
    * of walkers re-evaluated entirely in float64 (0: none; ignored by
    * FN_PREC_FP64 and by the other entry points).  Within each chunk of
    * the batch, in segments of at most 8192 walkers, the ceil(f * segment)
-   * walkers with the largest kappa |E_L|, where
-   * kappa = max_k |P_k| / |psi| is the determinant-sum cancellation
-   * (P_k = det^up_k det^down_k, Eq. (4); infinite at a node) and E_L the
-   * reduced-precision local energy, are gathered, evaluated again as
-   * FN_PREC_FP64 would, and their sign, log|psi|, e_loc, e_kin and e_pot
-   * replace the reduced-precision values.  The relative rounding error of
-   * E_L grows with kappa near a node of the determinant sum, so kappa |E_L|
-   * ranks the walkers by their share of the batch-mean error; the
-   * re-evaluation removes the dominant part of it at a fixed cost. */
+   * walkers with the largest error scale
+   *   kappa max(1, |E_L|, |E_kin|) (1 + (u_det / u_orb) cond),
+   * where kappa = max_k |P_k| / |psi| is the determinant-sum cancellation
+   * (P_k = det^up_k det^down_k, Eq. (4); infinite at a node), E_L and E_kin
+   * the reduced-precision local and kinetic energy, cond the largest
+   * condition number cond_1 of the walker's orbital matrices, and
+   * u_det / u_orb the unit roundoff of the determinant arithmetic over that
+   * of the orbitals (2^-37 with float64 determinants of split-bfloat16
+   * orbitals, 2^-29 with float64 determinants of float32 orbitals, 1 in
+   * float32), are gathered, evaluated again as FN_PREC_FP64 would, and
+   * their sign, log|psi|, e_loc, e_kin and e_pot replace the
+   * reduced-precision values.  Rounding errors of E_L are amplified by
+   * kappa near a node of the determinant sum and, in the factorisation, by
+   * the conditioning of the orbital matrices; only the kinetic term passes
+   * through the network.  The scale ranks the walkers by their share of
+   * the batch-mean error; the re-evaluation removes the dominant part of it
+   * at a fixed cost. */
   float rescue_fraction;
 } fn_config;
 
@@ -187,7 +195,7 @@ fn_status ferminet_logpsi(const fn_config* cfg, int32_t W, const float* pos, con
  * electron coordinates, from forward-mode jets (value, 3n tangents and
  * Laplacian) carried through every layer; the potential part from the
  * electron-electron, electron-nucleus and nucleus-nucleus Coulomb sums.
- * With cfg->rescue_fraction > 0 the walkers of largest kappa are
+ * With cfg->rescue_fraction > 0 the walkers of largest error scale are
  * re-evaluated in float64 (see fn_config); the workspace then also holds
  * the float64 buffers of those walkers.
  *   sign, logpsi [W] out (as ferminet_logpsi)

@@ -180,7 +180,7 @@ struct Carver {
 static void carve_forward(const Plan& p, Mode m, int64_t Wc, Carver& cv, Bufs& b, bool mcmc) {
   b.T = m == JET ? 3 * p.n + 2 : 1;
   b.Tp = m == JET ? round_up(b.T, 32) : 1;
-  b.dstride = m == JET ? p.n3 + 4 : 2;
+  b.dstride = m == JET ? p.n3 + 5 : 2;
   const int64_t rows = Wc * p.n * b.Tp;
   b.H0 = cv.take((size_t)rows * p.dinp[0] * p.act);
   for (int l = 0; l < p.L; ++l) b.G[l] = cv.take((size_t)rows * p.gwp[l] * p.act);
@@ -292,7 +292,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
 
 // ---------------------------------------- float64 re-evaluation buffers
 // Per chunk of Wc walkers: segments of at most 8192 walkers, the k_seg
-// walkers of largest kappa |E_L| of each segment, R = segments x k_seg in all.
+// walkers of largest error scale of each segment, R = segments x k_seg in all.
 struct RescueDims {
   int seg_len, k_seg;
   int64_t R;
@@ -545,6 +545,9 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   cb.e_kin = e_kin;
   cb.e_pot = e_pot;
   cb.rescue_key = m == JET ? b.rkey : nullptr;
+  // orbitals: split bfloat16 (16 significand bits) or float32; determinants:
+  // float64 or float32
+  cb.cond_weight = (float)(std::ldexp(1.0, p.fp64 ? -53 : -24) / std::ldexp(1.0, p.mode == MODE_BF16X3 ? -16 : -24));
   FN_T(SG(ST_COMBINE), launch_combine(p.fp64, cb, s));
   return FN_OK;
 }
@@ -994,7 +997,7 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
                  outs[4], s);
     if (st != FN_OK) return st;
     if (!rescue) continue;
-    // float64 re-evaluation of the walkers of largest kappa |E_L|
+    // float64 re-evaluation of the walkers of largest error scale
     const RescueDims d = rescue_dims(p, wc);
     FN_T(ST_RESCUE, launch_select_top(b.rkey, (int)wc, d.seg_len, d.k_seg, r.idx, s));
     FN_T(ST_RESCUE, launch_gather_walkers(x, r.idx, (int)d.R, p.n3, r.pos_r, s));

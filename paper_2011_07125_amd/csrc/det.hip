@@ -7,8 +7,10 @@
 //   d_c = tr(B^-1 dB/dx_c)                 (d log|det| / dx_c)
 //   q   = sum_c tr((B^-1 dB/dx_c)^2)
 //   lap = tr(B^-1 lap(B))
-// so that lap log|det| = lap - q.  R = double in the bf16 form, float in
-// the fp32 form.
+// so that lap log|det| = lap - q, and in jet mode the condition number
+// cond_1(A) = ||B||_inf ||B^-1||_inf of the orbital matrix A = B^T (row sums
+// of B taken before the factorisation).  R = double in the bf16 form, float
+// in the fp32 form.
 //
 // The combination (one wavefront per walker) forms psi = sum_k s_k e^{l_k}
 // as a signed log-sum-exp, rho_k = P_k / psi, and
@@ -42,6 +44,15 @@ __global__ __launch_bounds__(64) void det_kernel(const PT* phi, int K, int na, i
 
   for (int e = lane; e < nsq; e += 64) LU[e] = (R)P[e];
   __syncthreads();
+  R nb = 0;  // ||B||_inf
+  if (T > 1) {
+    for (int r = lane; r < na; r += 64) {
+      R rs = 0;
+      for (int k = 0; k < na; ++k) rs += fabs(LU[r * na + k]);
+      nb = rs;
+    }
+    nb = wave_max(nb);
+  }
   bool singular = false;
   for (int c = 0; c < na; ++c) {
     if (lane == 0) {
@@ -80,7 +91,10 @@ __global__ __launch_bounds__(64) void det_kernel(const PT* phi, int K, int na, i
   }
   if (singular) {
     for (int e = lane; e < dstride; e += 64) out[e] = (R)0;
-    if (lane == 0) out[1] = -INFINITY;
+    if (lane == 0) {
+      out[1] = -INFINITY;
+      if (T > 1) out[4 + n3] = INFINITY;
+    }
     if (ainv)
       for (int e = lane; e < nsq; e += 64) ainv[mat * nsq + e] = (R)0;
     return;
@@ -122,6 +136,16 @@ __global__ __launch_bounds__(64) void det_kernel(const PT* phi, int K, int na, i
   if (ainv)
     for (int e = lane; e < nsq; e += 64) ainv[mat * nsq + e] = Bi[e];
   if (T <= 1) return;
+  {
+    R ni = 0;  // ||B^-1||_inf
+    for (int r = lane; r < na; r += 64) {
+      R rs = 0;
+      for (int k = 0; k < na; ++k) rs += fabs(Bi[r * na + k]);
+      ni = rs;
+    }
+    ni = wave_max(ni);
+    if (lane == 0) out[4 + n3] = nb * ni;
+  }
 
   // jet contractions; "tangent" index tt in [0, n3] where tt == n3 is the
   // Laplacian row (trace only)
@@ -215,6 +239,14 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
       B[j][i] = (R)phi[(int64_t)(j * NA + i) * M + mat];
       X[j][i] = j == i ? (R)1 : (R)0;
     }
+  R nb = 0;  // ||B||_inf
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    R rs = 0;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) rs += fabs(B[j][i]);
+    nb = fmax(nb, rs);
+  }
   R sg = 1, la = 0;
   bool singular = false;
 #pragma unroll
@@ -266,6 +298,7 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
   if (singular) {
     for (int e = 0; e < dstride; ++e) out[e] = (R)0;
     out[1] = -INFINITY;
+    if (T > 1) out[4 + n3] = INFINITY;
     if (ainv)
       for (int e = 0; e < NSQ; ++e) ainv[mat * NSQ + e] = (R)0;
     return;
@@ -279,6 +312,17 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
       for (int b = 0; b < NA; ++b) ainv[mat * NSQ + a * NA + b] = X[a][b];
   }
   if (T <= 1) return;
+  {
+    R ni = 0;  // ||B^-1||_inf
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      R rs = 0;
+#pragma unroll
+      for (int b = 0; b < NA; ++b) rs += fabs(X[a][b]);
+      ni = fmax(ni, rs);
+    }
+    out[4 + n3] = nb * ni;
+  }
   // d_t = tr(B^-1 M_t), q = sum_t tr((B^-1 M_t)^2), lap = tr(B^-1 lap B)
   R q = 0;
   for (int tt = 0; tt <= n3; ++tt) {
@@ -389,6 +433,14 @@ __global__ __launch_bounds__(64) void combine_kernel(CombineArgs a) {
   if (a.rho && lane < K) ((R*)a.rho)[w * K + lane] = rho;
 
 
+  // largest condition number over the walker's orbital matrices
+  R cmax = 0;
+  if (a.jet && lane < K) {
+    if (hu) cmax = Du[(w * K + lane) * ds + 4 + n3];
+    if (hd) cmax = fmax(cmax, Dd[(w * K + lane) * ds + 4 + n3]);
+  }
+  if (a.jet) cmax = wave_max(cmax);
+
   double ekin = 0.0;
   if (a.jet) {
     // sum_k rho_k sum_a (lap_a - q_a)
@@ -451,10 +503,17 @@ __global__ __launch_bounds__(64) void combine_kernel(CombineArgs a) {
     v = wave_sum(v);
   }
   if (lane == 0) {
-    // rescue key log(kappa |E_L|), kappa = max_k |P_k| / |psi| (determinant-sum
-    // cancellation): the scale of the walker's rounding error in E_L
-    if (a.rescue_key)
-      a.rescue_key[w] = node ? INFINITY : (float)((double)(m - logabs) + log(fabs(ekin + v)));
+    // rescue key: the log of the scale of the walker's rounding error in E_L,
+    //   kappa max(1, |E_L|, |E_kin|) (1 + (u_det / u_orb) cond),
+    // kappa = max_k |P_k| / |psi| (determinant-sum cancellation), E_kin the
+    // only term computed through the network, cond the largest condition
+    // number of its orbital matrices, weighted by the ratio of the unit
+    // roundoff of the determinant arithmetic to that of the orbitals
+    if (a.rescue_key) {
+      const double el = fmax(1.0, fmax(fabs(ekin + v), fabs(ekin)));
+      a.rescue_key[w] =
+          node ? INFINITY : (float)((double)(m - logabs) + log(el) + log1p((double)a.cond_weight * (double)cmax));
+    }
     a.sign[w] = (float)sgn;
     a.logpsi[w] = (float)logabs;
     if (a.jet) {

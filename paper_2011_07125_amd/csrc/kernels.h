@@ -80,7 +80,7 @@ hipError_t launch_meanfield(bool f64, const void* H, int ldh, int W, int n, int 
                             hipStream_t s);
 
 // ---- determinants and combination (det.hip)
-// D_a[(w K + k) * dstride + ...]: sign, log|det|, d_c (3n), q, lap  (jet mode)
+// D_a[(w K + k) * dstride + ...]: sign, log|det|, d_c (3n), q, lap, cond_1(A)  (jet mode)
 //                                  sign, log|det|                      (value mode)
 // matrices up to this size take the one-thread-per-matrix kernel, which
 // expects the matrix-index-fastest layout of the orbital jets (phi_M = W K)
@@ -95,8 +95,10 @@ struct CombineArgs {
   const float* pos; const float* nuc; const float* Z;
   float* sign; float* logpsi; float* e_loc; float* e_kin; float* e_pot;
   void* rho;  // optional [W][K]: rho_k = P_k / psi (value mode, adjoint)
-  float* rescue_key;  // optional [W] (jet mode): log(kappa |E_L|) with kappa = max_k |P_k| / |psi|
-                      // (+inf at a node, NaN propagates)
+  float* rescue_key;  // optional [W] (jet mode): log(kappa max(1, |E_L|, |E_kin|) (1 + cond_weight cond))
+                      // with kappa = max_k |P_k| / |psi| and cond the largest cond_1 of the
+                      // walker's orbital matrices (+inf at a node, NaN propagates)
+  float cond_weight;  // unit roundoff of the determinant arithmetic over that of the orbitals
 };
 hipError_t launch_combine(bool fp64, const CombineArgs& a, hipStream_t s);
 

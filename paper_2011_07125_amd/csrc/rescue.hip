@@ -4,12 +4,15 @@
 // Near a node of psi = sum_k P_k (Eq. (4)) the determinant terms cancel,
 // and the rounding errors of the reduced-precision network are amplified
 // by kappa = max_k |P_k| / |psi| in log|psi| and more strongly in its
-// derivatives, so the local energy of those walkers carries errors many
-// orders above the arithmetic's unit roundoff.  The combination kernel
-// writes log(kappa |E_L|) per walker, the scale of its absolute error; the
-// walkers with the largest key in each segment of the batch are gathered,
-// evaluated again entirely in float64, and their outputs scattered back
-// over the reduced-precision ones.
+// derivatives; a nearly singular orbital matrix amplifies the rounding of
+// its own factorisation by its condition number.  The local energy of
+// those walkers carries errors many orders above the arithmetic's unit
+// roundoff.  The combination kernel writes the log of each walker's error
+// scale (kappa, the kinetic-energy magnitude and the conditioning weighted
+// by the precision of the determinant arithmetic); the walkers with the
+// largest key in each segment of the batch are gathered, evaluated again
+// entirely in float64, and their outputs scattered back over the
+// reduced-precision ones.
 #include <climits>
 
 #include "common.h"

@@ -1,6 +1,9 @@
 """The float64 form of the HIP path and the float64 re-evaluation of the
-walkers of largest kappa |E_L| (kappa: determinant-sum cancellation),
-against the FP64 CPU oracle on the same seeded inputs.
+walkers of largest error scale kappa max(1, |E_L|, |E_kin|) (1 + r cond)
+(kappa: determinant-sum cancellation; cond: the largest condition number of
+the walker's orbital matrices; r: unit roundoff of the determinant
+arithmetic over that of the orbitals), against the FP64 CPU oracle on the
+same seeded inputs.
 
 Tolerance of the float64 form: both sides compute in float64 from the same
 float32 inputs, and the library rounds its outputs to float32, so every
@@ -53,7 +56,8 @@ def run_gpu(w, precision, rescue=0.0, max_chunk=None):
 
 def check_fp64(name, g, o, amp):
     scale_l = np.maximum(1.0, np.abs(o["logpsi"]))
-    scale_e = np.maximum(1.0, np.abs(o["e_loc"]))
+    # the rounding of E_L is that of its kinetic term (see test_gpu_parity.compare)
+    scale_e = np.maximum(np.maximum(1.0, np.abs(o["e_loc"])), np.abs(o["e_kin"]))
     dl = np.abs(g["logpsi"] - o["logpsi"])
     de = np.abs(g["e_loc"] - o["e_loc"])
     bl = 2.0 ** -22 * scale_l + 1e3 * U64 * amp
@@ -84,7 +88,7 @@ def test_fp64_form_full_ne10_vs_stored_oracle():
     w = I.make_workload("ne10")
     gold = np.load(os.path.join(ROOT, "tests", "golden", "ne10_oracle.npz"))
     g = run_gpu(w, "fp64")
-    o = {k: gold[k] for k in ("sign", "logpsi", "e_loc")}
+    o = {k: gold[k] for k in ("sign", "logpsi", "e_loc", "e_kin")}
     check_fp64("ne10/fp64 full", g, o, gold["amplification"])
     assert abs(g["e_loc"].mean() - o["e_loc"].mean()) < 1e-5
 
@@ -115,19 +119,23 @@ def test_rescue_everything_equals_fp64_form(form):
         assert np.array_equal(gr[k], g64[k]), f"{k}: rescued {form} differs from the fp64 form"
 
 
-def test_rescue_selects_largest_error_scale():
-    """The re-evaluated walkers are those of largest kappa |E_L|: the outputs
-    of exactly k walkers change to the float64 values, and the walkers the
-    oracle ranks highest by kappa |E_L| (its own kappa and local energy)
-    are among them."""
-    say("case rescue selection ne10 W=4096")
+# unit roundoff of the determinant arithmetic over that of the orbitals
+COND_WEIGHT = {"bf16": 2.0 ** -37, "fp32": 1.0}
+
+
+@pytest.mark.parametrize("form,frac", [("bf16", 0.03), ("fp32", 0.01)])
+def test_rescue_selects_largest_error_scale(form, frac):
+    """The re-evaluated walkers are those of largest error scale: the
+    outputs of exactly k walkers change to the float64 values, and the
+    walkers the oracle ranks highest by that scale (from its own kappa,
+    condition numbers and energies) are among them."""
+    say(f"case rescue selection ne10 W=4096 {form}")
     w = I.make_workload("ne10")
     gold = np.load(os.path.join(ROOT, "tests", "golden", "ne10_oracle.npz"))
-    frac = 0.03
     k = int(np.ceil(frac * 4096))
     g64 = run_gpu(w, "fp64")
-    gp = run_gpu(w, "bf16")
-    gr = run_gpu(w, "bf16", rescue=frac)
+    gp = run_gpu(w, form)
+    gr = run_gpu(w, form, rescue=frac)
     same64 = np.all([gr[q] == g64[q] for q in KEYS], axis=0)
     sameplain = np.all([gr[q] == gp[q] for q in KEYS], axis=0)
     # every walker is either re-evaluated or untouched
@@ -135,10 +143,11 @@ def test_rescue_selects_largest_error_scale():
     changed = np.nonzero(~sameplain)[0]
     assert len(changed) <= k
     assert same64.sum() >= k  # the k re-evaluated (plus walkers whose bf16 output is already the fp64 one)
-    key = gold["kappa"] * np.abs(gold["e_loc"])
+    scale = np.maximum(np.maximum(1.0, np.abs(gold["e_loc"])), np.abs(gold["e_kin"]))
+    key = gold["kappa"] * scale * (1.0 + COND_WEIGHT[form] * gold["cond"])
     top = np.argsort(-key)[: k // 2]
-    say(f"   k={k} changed={len(changed)} oracle top-{k // 2} by kappa|E_L| re-evaluated: {int(same64[top].sum())}")
-    assert same64[top].all(), f"largest kappa|E_L| walkers not re-evaluated: {top[~same64[top]]}"
+    say(f"   k={k} changed={len(changed)} oracle top-{k // 2} by error scale re-evaluated: {int(same64[top].sum())}")
+    assert same64[top].all(), f"walkers of largest error scale not re-evaluated: {top[~same64[top]]}"
 
 
 @pytest.mark.parametrize("form,frac", [("bf16", 0.03), ("fp32", 0.01)])
@@ -158,7 +167,7 @@ def test_rescue_batch_mean_within_1mha(form, frac):
 
 def test_rescue_several_segments():
     """More walkers than one selection segment (8192): each segment
-    re-evaluates its own walkers of largest kappa |E_L|."""
+    re-evaluates its own walkers of largest error scale."""
     say("case rescue segments be4 W=9000")
     w = I.make_workload("be4", walkers=9000)
     frac = 0.01
@@ -179,7 +188,7 @@ def test_rescue_several_segments():
 def test_rescue_chunked():
     """A workspace sized for 100 walkers: the batch runs in chunks (of at
     least 100 walkers: the library fills the workspace) and each chunk
-    re-evaluates its own walkers of largest kappa |E_L|, ceil(f x chunk) of
+    re-evaluates its own walkers of largest error scale, ceil(f x chunk) of
     them."""
     say("case rescue chunked ne10 W=260 chunk>=100")
     w = I.make_workload("ne10", walkers=260)
