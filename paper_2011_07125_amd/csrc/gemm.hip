@@ -547,6 +547,7 @@ hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t 
   // the one-electron layers take the full-width streaming kernel when their
   // shape allows it
   if (epi == EPI_TANHJET && layer_gemm_supported(a)) return launch_layer_gemm(mode, a, s);
+  if (epi == EPI_PLAIN && layer_plain_supported(a)) return launch_layer_plain(mode, a, s);
   if (mode == MODE_BF16X3) return pick_epi<MODE_BF16X3>(epi, a, s);
   return pick_epi<MODE_F32>(epi, a, s);
 }

@@ -51,9 +51,13 @@ struct JetGemmArgs {
 };
 
 hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t s);
-// full-width streaming kernel for the EPI_TANHJET layers (layer.hip)
+// full-width streaming kernel for the EPI_TANHJET layers (layer.hip), and
+// the same kernel with a plain epilogue for EPI_PLAIN products over
+// contiguous rows
 bool layer_gemm_supported(const JetGemmArgs& a);
 hipError_t launch_layer_gemm(int mode, const JetGemmArgs& a, hipStream_t s);
+bool layer_plain_supported(const JetGemmArgs& a);
+hipError_t launch_layer_plain(int mode, const JetGemmArgs& a, hipStream_t s);
 
 // ---- features and two-electron stream (features.hip)
 // mode MODE_F32 / MODE_F64: float32 / float64 weights; MODE_BF16X3:

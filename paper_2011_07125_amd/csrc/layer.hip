@@ -74,12 +74,16 @@ __device__ inline void stf(float x, __amdgpu_buffer_rsrc_t r, int voff, int soff
 // consecutive rows read at one chunk index cover all banks once
 __device__ inline int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) << 3); }
 
-// JET: the jet pass (rows_per jet rows per electron); otherwise the value
-// pass (one row per electron)
-template <int MODE, int BM, int BN, int WM, int WN, bool JET>
+// KIND_JET: the tanh layer's jet pass (rows_per jet rows per electron);
+// KIND_VALUE: its value pass (one row per electron); KIND_PLAIN: the plain
+// product c (=, or += with c_accum) over contiguous rows (rows_per = 1)
+constexpr int KIND_VALUE = 0, KIND_JET = 1, KIND_PLAIN = 2;
+
+template <int MODE, int BM, int BN, int WM, int WN, int KIND>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void layer_gemm_kernel(JetGemmArgs a,
                                                                                                    int n_mtiles,
                                                                                                    int n_ntiles) {
+  constexpr bool JET = KIND == KIND_JET;
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
   constexpr int BK = C::BK, LDA = C::LDA, LDB = C::LDB, TM = C::TM, TN = C::TN, WROWS = C::WROWS;
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -307,7 +311,35 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
   for (int j = 0; j < TN; ++j) gcol[j] = n0 + wn * C::WCOLS + j * 16 + (lane & 15);
 
-  if constexpr (!JET) {
+  if constexpr (KIND == KIND_PLAIN) {
+    // row g0 + 16 i + 4 kq + r of the wave: the lane offset carries 4 kq
+    // rows and the column, the scalar offset 16 i + r rows, the immediate
+    // 16 j columns; rows past the last one are out of range (dropped)
+    const __amdgpu_buffer_rsrc_t rC = rsrc((float*)a.c + (size_t)g0 * a.ldc + n0 + wn * C::WCOLS);
+    const int wr = wm * WROWS + kq * 4;
+    const int voC = ((wr * a.ldc) + (lane & 15)) * 4;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      float old[4][TN];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int so = (i * 16 + r) * a.ldc * 4;
+        const int vo = g0 + wr + i * 16 + r < a.n_groups ? voC : kOutOfRange;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) old[r][j] = a.c_accum ? ldf(rC, vo + j * 64, so) : 0.0f;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int so = (i * 16 + r) * a.ldc * 4;
+        const int vo = g0 + wr + i * 16 + r < a.n_groups ? voC : kOutOfRange;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) stf(acc[i][j][r] + old[r][j], rC, vo + j * 64, so);
+      }
+    }
+    return;
+  }
+
+  if constexpr (KIND == KIND_VALUE) {
     // value pass: every row is an electron.  Per 16-row tile the mean-field
     // and residual loads are issued together, then the results are stored.
     const float* __restrict__ Pv = (const float*)a.P;
@@ -454,21 +486,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   }
 }
 
-template <int MODE, int BM, int BN, int WM, int WN, bool JET>
+template <int MODE, int BM, int BN, int WM, int WN, int KIND>
 static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
-  const int E = BM / a.rows_per;
+  const int E = KIND == KIND_JET ? BM / a.rows_per : BM;
   const int n_mtiles = (a.n_groups + E - 1) / E;
   const int n_ntiles = (a.N + BN - 1) / BN;
   const int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN, JET>),
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, C::BYTES) != hipSuccess)
       return hipErrorInvalidValue;
     attr_set = true;
   }
-  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN, JET>), dim3(grid), dim3(C::NT), C::BYTES, s, a,
+  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>), dim3(grid), dim3(C::NT), C::BYTES, s, a,
                      n_mtiles, n_ntiles);
   return hipGetLastError();
 }
@@ -477,10 +509,34 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
 // one electron (value mode: one row per electron)
 template <int MODE>
 static hipError_t pick_layer(const JetGemmArgs& a, hipStream_t s) {
-  if (a.rows_per == 1) return run_layer<MODE, 128, 128, 4, 2, false>(a, s);
-  if (a.rows_per == 96) return run_layer<MODE, 96, 128, 2, 4, true>(a, s);
-  if (a.rows_per == 32 || a.rows_per == 64 || a.rows_per == 128) return run_layer<MODE, 128, 128, 4, 2, true>(a, s);
+  if (a.rows_per == 1) return run_layer<MODE, 128, 128, 4, 2, KIND_VALUE>(a, s);
+  if (a.rows_per == 96) return run_layer<MODE, 96, 128, 2, 4, KIND_JET>(a, s);
+  if (a.rows_per == 32 || a.rows_per == 64 || a.rows_per == 128)
+    return run_layer<MODE, 128, 128, 4, 2, KIND_JET>(a, s);
   return hipErrorInvalidValue;
+}
+
+// plain products whose A rows and output rows are both contiguous (no
+// electron subsets), flattened to one row per (group, jet row)
+bool layer_plain_supported(const JetGemmArgs& a) {
+  const bool flat_a = a.rows_per == 1 || (a.n_sub == a.n_all && a.e_off == 0);
+  return flat_a && a.c_nsub == 0 && a.N % 128 == 0 && a.ka0 % 32 == 0 && a.ka1 % 32 == 0 &&
+         (int64_t)a.n_groups * a.rows_per < (1LL << 31) && a.ldc >= a.N;
+}
+
+hipError_t launch_layer_plain(int mode, const JetGemmArgs& a, hipStream_t s) {
+  if (a.n_groups <= 0) return hipSuccess;
+  if (!layer_plain_supported(a)) return hipErrorInvalidValue;
+  JetGemmArgs f = a;
+  if (a.rows_per > 1) {
+    f.n_groups = a.n_groups * a.rows_per;
+    f.n_sub = f.n_all = 1;
+    f.e_off = 0;
+  }
+  f.rows_per = 1;
+  f.T = 1;
+  return mode == MODE_BF16X3 ? run_layer<MODE_BF16X3, 128, 128, 4, 2, KIND_PLAIN>(f, s)
+                             : run_layer<MODE_F32, 128, 128, 4, 2, KIND_PLAIN>(f, s);
 }
 
 bool layer_gemm_supported(const JetGemmArgs& a) {
