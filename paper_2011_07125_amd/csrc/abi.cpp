@@ -277,7 +277,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
   // X^T Y partials: splits(R) * K1 * N with K1 <= max(d1, dinp, 2 ein), N <= max(d1, K n_a)
   const int64_t k1max = std::max<int64_t>(p.d1, std::max(dmax, 2 * std::max(4, p.d2)));
   const int64_t nmax = std::max<int64_t>(p.d1, (int64_t)p.K * std::max(p.nu, p.nd));
-  const int64_t part_n = (int64_t)atb_splits(R) * k1max * nmax;
+  const int64_t part_n = atb_part_floats((int)k1max, (int)nmax);
   b.part = (float*)cv.take((size_t)part_n * 4);
   b.p2 = 0;
   for (int l = 0; l + 1 < p.L; ++l) b.p2 += (int64_t)p.ein[l] * p.d2 + p.d2;
@@ -285,7 +285,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
   // row-sum partials: column sums over R rows (d1, p2 or ldu columns) and
   // the reduction of the X^T Y partials over their splits
   const int64_t t1 = (int64_t)rowsum_chunks(R, kRowChunk) * std::max<int64_t>(std::max<int64_t>(p.d1, b.p2), b.ldu);
-  const int64_t t2 = (int64_t)rowsum_chunks(atb_splits(R), kRowChunk) * k1max * nmax;
+  const int64_t t2 = (int64_t)rowsum_chunks(atb_part_floats((int)k1max, (int)nmax) / 4096, kRowChunk) * k1max * nmax;
   b.tmp = (float*)cv.take((size_t)std::max(t1, t2) * 4);
   b.cot = (float*)cv.take((size_t)Wc * 4);
 }
@@ -712,7 +712,7 @@ static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol
   a.part = b.part;
   FN_T(ST_ADJ_REDUCE, launch_atb(a, s));
   const int64_t cols = (int64_t)K1 * N;
-  FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part, atb_splits(R), (int)cols, cols, b.tmp, dst, kRowChunk, s));
+  FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part, atb_splits(R, K1, N), (int)cols, cols, b.tmp, dst, kRowChunk, s));
   return FN_OK;
 }
 

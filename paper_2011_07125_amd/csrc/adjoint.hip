@@ -151,48 +151,86 @@ hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const flo
 }
 
 // ------------------------------------------------------------- X^T Y
-// part[split][k][nn] = sum_{r in split} X[map(r)][xcol + k] * Y[r][nn],
-// 64 x 64 tiles on v_mfma_f32_16x16x4_f32, 256 rows per split and step 16.
-constexpr int ATB_ROWS = 256;
+// part[split][k][nn] = sum_{r in split} X[map(r)][xcol + k] * Y[r][nn]:
+// 64 x 64 output tiles on v_mfma_f32_16x16x4_f32, 16 rows per step through
+// double-buffered LDS with the next step's rows loaded into registers
+// meanwhile.  The rows are cut into as many splits as bring the launch to
+// about ATB_BLOCKS workgroups, so the partials (and their reduction) stay
+// small however many rows there are.
+constexpr int ATB_BLOCKS = 1024;
 
-__global__ __launch_bounds__(256) void atb_kernel(AtbArgs a) {
-  __shared__ float Xs[16][64 + 4];
-  __shared__ float Ys[16][64 + 4];
+int atb_splits(int64_t R, int K1, int N) {
+  const int64_t tiles = (int64_t)((K1 + 63) / 64) * ((N + 63) / 64);
+  int64_t sp = (ATB_BLOCKS + tiles - 1) / tiles;
+  sp = std::min<int64_t>(sp, (R + 63) / 64);
+  return (int)std::max<int64_t>(sp, 1);
+}
+int64_t atb_part_floats(int K1max, int Nmax) {
+  return (int64_t)(ATB_BLOCKS + ((K1max + 63) / 64) * ((Nmax + 63) / 64)) * 64 * 64;
+}
+
+// VEC: K1, N, ldx, xcol, ldy multiples of 4 (one 16-byte load per operand)
+template <bool VEC>
+__global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_split) {
+  __shared__ float Xs[2][16][64 + 4];
+  __shared__ float Ys[2][16][64 + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int tk = blockIdx.x, tn = blockIdx.y, split = blockIdx.z;
   const int k0 = tk * 64, n0 = tn * 64;
-  const int64_t r_begin = (int64_t)split * ATB_ROWS;
-  const int64_t r_end = std::min<int64_t>(r_begin + ATB_ROWS, a.R);
+  const int64_t r_begin = (int64_t)split * rows_per_split;
+  const int64_t r_end = std::min<int64_t>(r_begin + rows_per_split, a.R);
   floatx4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int lr = tid / 16, lc = (tid % 16) * 4;  // loader: row 0..15, 4 columns
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += 16) {
+  const bool kin = k0 + lc < a.K1, nin = n0 + lc < a.N;
+  float xv[4], yv[4];
+  auto load = [&](int64_t r0) {
     const int64_t r = r0 + lr;
-    float xv[4] = {0.f, 0.f, 0.f, 0.f}, yv[4] = {0.f, 0.f, 0.f, 0.f};
-    if (r < r_end) {
-      const int64_t mr = a.xs ? (r / a.xs) * a.xa + a.xe + r % a.xs : r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xv[q] = yv[q] = 0.0f;
+    if (r >= r_end) return;
+    const int64_t mr = a.xs ? (int64_t)((int)r / a.xs) * a.xa + a.xe + (int)r % a.xs : r;
+    const float* xp = a.X + mr * a.ldx + a.xcol + k0 + lc;
+    const float* yp = a.Y + r * a.ldy + n0 + lc;
+    if constexpr (VEC) {
+      if (kin) {
+        const float4 v = *reinterpret_cast<const float4*>(xp);
+        xv[0] = v.x, xv[1] = v.y, xv[2] = v.z, xv[3] = v.w;
+      }
+      if (nin) {
+        const float4 v = *reinterpret_cast<const float4*>(yp);
+        yv[0] = v.x, yv[1] = v.y, yv[2] = v.z, yv[3] = v.w;
+      }
+    } else {
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (k0 + lc + q < a.K1) xv[q] = a.X[mr * a.ldx + a.xcol + k0 + lc + q];
-        if (n0 + lc + q < a.N) yv[q] = a.Y[r * a.ldy + n0 + lc + q];
+        if (k0 + lc + q < a.K1) xv[q] = xp[q];
+        if (n0 + lc + q < a.N) yv[q] = yp[q];
       }
     }
-    __syncthreads();
+  };
+  if (r_begin < r_end) load(r_begin);
+  int buf = 0;
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += 16, buf ^= 1) {
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
-      Xs[lr][lc + q] = xv[q];
-      Ys[lr][lc + q] = yv[q];
+      Xs[buf][lr][lc + q] = xv[q];
+      Ys[buf][lr][lc + q] = yv[q];
     }
     __syncthreads();
+    if (r0 + 16 < r_end) load(r0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int rr = ks * 4 + (lane >> 4);
       float af[2], bf[2];
-      for (int i = 0; i < 2; ++i) af[i] = Xs[rr][wm * 32 + i * 16 + (lane & 15)];
-      for (int j = 0; j < 2; ++j) bf[j] = Ys[rr][wn * 32 + j * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) af[i] = Xs[buf][rr][wm * 32 + i * 16 + (lane & 15)];
+      for (int j = 0; j < 2; ++j) bf[j] = Ys[buf][rr][wn * 32 + j * 16 + (lane & 15)];
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer is written next step, after this step's barrier
   }
   float* out = a.part + (int64_t)split * a.K1 * a.N;
   for (int i = 0; i < 2; ++i)
@@ -204,12 +242,15 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a) {
       }
 }
 
-int atb_splits(int64_t R) { return (int)((R + ATB_ROWS - 1) / ATB_ROWS); }
-
 hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
   if (a.R <= 0 || a.K1 <= 0 || a.N <= 0) return hipSuccess;
-  dim3 grid((a.K1 + 63) / 64, (a.N + 63) / 64, atb_splits(a.R));
-  hipLaunchKernelGGL(atb_kernel, grid, dim3(256), 0, s, a);
+  const int sp = atb_splits(a.R, a.K1, a.N);
+  const int64_t rps = ((a.R + sp - 1) / sp + 15) / 16 * 16;
+  dim3 grid((a.K1 + 63) / 64, (a.N + 63) / 64, sp);
+  const bool vec = a.K1 % 4 == 0 && a.N % 4 == 0 && a.ldx % 4 == 0 && a.xcol % 4 == 0 && a.ldy % 4 == 0 &&
+                   ((uintptr_t)a.X % 16) == 0 && ((uintptr_t)a.Y % 16) == 0;
+  if (vec) hipLaunchKernelGGL(atb_kernel<true>, grid, dim3(256), 0, s, a, rps);
+  else hipLaunchKernelGGL(atb_kernel<false>, grid, dim3(256), 0, s, a, rps);
   return hipGetLastError();
 }
 

@@ -137,7 +137,8 @@ struct AtbArgs {
   int64_t R; int K1, N;
   float* part;
 };
-int atb_splits(int64_t R);
+int atb_splits(int64_t R, int K1, int N);   // partials written by launch_atb
+int64_t atb_part_floats(int K1max, int Nmax);  // bound on splits * K1 * N over K1 <= K1max, N <= Nmax
 hipError_t launch_atb(const AtbArgs& a, hipStream_t s);
 int rowsum_chunks(int64_t rows, int chunk);
 // dst[c] += sum_r src[r * lds + c] in a fixed order (tmp: rowsum_chunks(rows, chunk) * cols floats)
