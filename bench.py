@@ -11,7 +11,7 @@ accumulation) with float64 determinants; the plain fp32 form is timed
 beside it on the same inputs.  In both, the local energy of the walkers of
 largest rounding-error scale (determinant-sum cancellation kappa times the
 kinetic-energy magnitude, and for float32 determinants the conditioning of
-the orbital matrices; 3% and 1% of the batch by default) is re-evaluated in
+the orbital matrices; 3% and 2% of the batch by default) is re-evaluated in
 float64 inside the timed step.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -191,7 +191,7 @@ def main():
                     help="skip timing the same step with the full-covariance envelope of Eq. (5)")
     ap.add_argument("--rescue-bf16", type=float, default=0.03,
                     help="fraction of walkers whose local energy is re-evaluated in float64 (bf16 form)")
-    ap.add_argument("--rescue-fp32", type=float, default=0.01, help="the same for the fp32 form")
+    ap.add_argument("--rescue-fp32", type=float, default=0.02, help="the same for the fp32 form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first launch a plain 512 MiB copy kernel three times (counter calibration)")
     args = ap.parse_args()

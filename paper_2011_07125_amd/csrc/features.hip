@@ -132,6 +132,10 @@ template <int D2> constexpr int two_e_ps_stride() { return D2 + 1; }
 // LDS rows of the slots, padded to whole 16-row matrix tiles
 __host__ __device__ inline int two_e_rows(int slots) { return (slots + 15) / 16 * 16; }
 inline size_t two_e_ws_offset(int slots, int ps) { return ((size_t)two_e_rows(slots) * ps + 3) / 4 * 4; }
+// shared rows of a g jet (value, d/dr_i x3, Laplacian in jet mode; the value
+// in value mode) and the LDS elements of their partner sums
+__host__ __device__ inline int two_e_shared_rows(int R2) { return R2 == 8 ? 5 : 1; }
+inline size_t two_e_sums_elems(int ipb, int R2, int D2) { return (size_t)ipb * two_e_shared_rows(R2) * 2 * D2; }
 
 // S: float or double (arithmetic, LDS and the stored jets of g^a_i)
 template <class S, int D2>
@@ -142,17 +146,24 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
   const int n = a.n, R2 = a.R2, d2 = a.d2;
   S* Ps = sh;                                                          // [rows][PS]
   S* Ws = sh + ((size_t)two_e_rows(a.ipb * n * R2) * PS + 3) / 4 * 4;  // [D2][D2] then c[D2], 16-byte aligned
+  S* Ss = Ws + D2 * D2 + D2;  // [ipb][shared rows][2 ein]: partner sums of the shared g rows
   const int tid = threadIdx.x;
   const int slots = a.ipb * n * R2;
-  const int64_t gbase = (int64_t)blockIdx.x * a.ipb;
-  const int64_t n_groups = (int64_t)a.W * n;
+  // electrons of the block: gbase .. gbase + ipb - 1 (W n < 2^31), the
+  // first being electron i0 of walker w0
+  const int gbase = blockIdx.x * a.ipb;
+  const int n_groups = a.W * n;
+  const int w0 = gbase / n, i0 = gbase - w0 * n;
 
+  // slot s: electron ii of the block, partner j, sparse jet row q (R2 is 8
+  // in jet mode, 1 in value mode)
   const int s = tid;
-  const bool live = s < slots && (gbase + s / (n * R2)) < n_groups;
-  const int ii = s / (n * R2), j = (s / R2) % n, q = s % R2;
-  const int64_t g = gbase + ii;
-  const int i = (int)(g % n);
-  const int64_t w = g / n;
+  const int q = R2 == 8 ? (s & 7) : 0, pr = R2 == 8 ? (s >> 3) : s;
+  const int ii = pr / n, j = pr - ii * n;
+  const bool live = s < slots && gbase + ii < n_groups;
+  const int iw = (i0 + ii) / n;  // walkers past w0
+  const int i = i0 + ii - iw * n;
+  const int64_t w = (int64_t)w0 + iw;
 
   // input pair features (r_i - r_j, |r_i - r_j|) and their sparse jets;
   // rows of no live slot are zero
@@ -188,43 +199,99 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
   const int n_up = a.n_up, n_dn = n - a.n_up;
   for (int l = 0; l < a.L; ++l) {
     __syncthreads();
-    // dense jets of g^a_i = mean_{j in a} h_ij from the pair activations in LDS
+    // dense jets of g^a_i = mean_{j in a} h_ij from the pair activations in
+    // LDS.  Row t of the jet is a shared row (the value, d/dr_i, the
+    // Laplacian: sums over the partners of spin a) or the d/dr_j row of one
+    // partner j (that pair's row alone, zero in the other spin's columns).
     {
       S* G = reinterpret_cast<S*>(a.G[l]);
       const int ldg = a.ldg[l];
       const int T = a.T, Tp = a.Tp;
-      // each thread owns one column c = (spin a, feature o) and a stride of
-      // rows: every division happens once per layer
-      const int c = tid % ldg, rstep = blockDim.x / ldg;
-      const bool colv = c < 2 * ein;
-      const int al = colv ? c / ein : 0, o = colv ? c % ein : 0;
-      const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n_dn;
-      const S inv_na = na > 0 ? (S)1 / (S)na : (S)0;
-      for (int e = 0; e < a.ipb; ++e) {
-        const int64_t ge = gbase + e;
-        if (ge >= n_groups) break;
-        const int ie = (int)(ge % n);
-        const S* base = Ps + (size_t)e * n * R2 * PS + o;
-        S* Gr = G + ge * Tp * (int64_t)ldg + c;
-        for (int t = tid / ldg; t < Tp; t += rstep) {
-          S v = 0;
-          if (colv && na > 0 && t < T) {
-            S acc = 0;
-            if (t == 0) {
-              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2) * PS];
-            } else if (t == T - 1) {
-              for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 7) * PS];
-            } else {
-              const int jt = (t - 1) / 3, cc = (t - 1) - 3 * jt;
-              if (jt == ie) {
-                for (int jj = j0; jj < j0 + na; ++jj) acc += base[(size_t)(jj * R2 + 1 + cc) * PS];
-              } else if (jt >= j0 && jt < j0 + na) {
-                acc = base[(size_t)(jt * R2 + 4 + cc) * PS];
+      const int nq = two_e_shared_rows(R2), ncol = 2 * ein;
+      const S inv_up = n_up > 0 ? (S)1 / (S)n_up : (S)0, inv_dn = n_dn > 0 ? (S)1 / (S)n_dn : (S)0;
+      // phase 1: partner sums, one (electron, shared row, column) per item,
+      // four partners per step (independent LDS reads in flight).  The item
+      // (eq = e nq + qq, c) advances by the block size with a carry: no
+      // division inside the loop.
+      {
+        int c = tid % ncol, eq = tid / ncol;
+        const int dc = blockDim.x % ncol, deq = blockDim.x / ncol;
+        while (eq < a.ipb * nq) {
+          const int e = nq == 1 ? eq : (eq * 52429) >> 18;  // eq / 5, exact for eq < 2^14
+          const int qq = eq - e * nq;
+          const int al = c >= ein, o = c - al * ein;
+          const int j0 = al == 0 ? 0 : n_up, na = al == 0 ? n_up : n_dn;
+          const int qs = qq == 4 ? 7 : qq;  // sparse jet row: value, d/dr_i x3, Laplacian
+          const S* base = Ps + ((size_t)(e * n + j0) * R2 + qs) * PS + o;
+          const size_t step = (size_t)R2 * PS;
+          S s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+          int jj = 0;
+          for (; jj + 3 < na; jj += 4) {
+            s0 += base[jj * step];
+            s1 += base[(jj + 1) * step];
+            s2 += base[(jj + 2) * step];
+            s3 += base[(jj + 3) * step];
+          }
+          for (; jj < na; ++jj) s0 += base[jj * step];
+          Ss[(size_t)eq * ncol + c] = ((s0 + s1) + (s2 + s3)) * (al == 0 ? inv_up : inv_dn);
+          c += dc;
+          eq += deq;
+          if (c >= ncol) {
+            c -= ncol;
+            ++eq;
+          }
+        }
+      }
+      __syncthreads();
+      // phase 2: four columns of one (electron e, jet row t) per item, one
+      // 16-byte store (ldg is a multiple of 32).  (e, t, c4) and the
+      // electron's index ie within its walker advance with carries.
+      {
+        const int nc4 = ldg / 4;
+        int c4 = tid % nc4, row = tid / nc4;
+        const int dc4 = blockDim.x % nc4, drow = blockDim.x / nc4;
+        int e = row / Tp, t = row - e * Tp;
+        int ie = (i0 + e) % n;
+        while (e < a.ipb) {
+          const int c0 = c4 * 4;
+          if (gbase + e < n_groups) {
+            S v[4] = {0, 0, 0, 0};
+            if (t < T) {
+              const int jt = t >= 1 ? ((t - 1) * 43691) >> 17 : -1;  // (t - 1) / 3, exact for t < 2^16
+              const int cc = t - 1 - 3 * jt;
+              const bool shared = t == 0 || t == T - 1 || jt == ie;
+              const int qq = t == 0 ? 0 : t == T - 1 ? 4 : 1 + cc;
+              const bool jt_up = jt < n_up;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                const int c = c0 + k;
+                if (c >= ncol) continue;
+                const int al = c >= ein;
+                if (shared) v[k] = Ss[(size_t)(e * nq + qq) * ncol + c];
+                else if ((al == 0) == jt_up)
+                  v[k] = Ps[((size_t)(e * n + jt) * R2 + 4 + cc) * PS + (c - al * ein)] * (al == 0 ? inv_up : inv_dn);
               }
             }
-            v = acc * inv_na;
+            S* dst = G + ((int64_t)(gbase + e) * Tp + t) * ldg + c0;
+            if constexpr (sizeof(S) == 4) {
+              *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+            } else {
+              reinterpret_cast<double2*>(dst)[0] = double2{(double)v[0], (double)v[1]};
+              reinterpret_cast<double2*>(dst)[1] = double2{(double)v[2], (double)v[3]};
+            }
           }
-          Gr[(int64_t)t * ldg] = v;
+          c4 += dc4;
+          int adv = drow;
+          if (c4 >= nc4) {
+            c4 -= nc4;
+            ++adv;
+          }
+          t += adv;
+          while (t >= Tp) {
+            t -= Tp;
+            ++e;
+            ie = ie + 1 == n ? 0 : ie + 1;
+          }
         }
       }
       if (a.h2_out[l] && R2 == 1) {
@@ -365,8 +432,9 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
 
 template <class S, int D2>
 static hipError_t run_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
-  const size_t shmem =
-      (two_e_ws_offset(d.ipb * d.n * d.R2, two_e_ps_stride<D2>()) + (size_t)D2 * D2 + D2) * sizeof(S);
+  const size_t shmem = (two_e_ws_offset(d.ipb * d.n * d.R2, two_e_ps_stride<D2>()) + (size_t)D2 * D2 + D2 +
+                        two_e_sums_elems(d.ipb, d.R2, D2)) *
+                       sizeof(S);
   if (shmem > 65536) {
     static bool attr_set = false;
     if (!attr_set) {
@@ -395,7 +463,9 @@ static hipError_t pick_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
 int two_electron_per_block(int n, int d2, int T, int scalar_bytes) {
   const int R2 = T > 1 ? 8 : 1;
   const int D2p = d2 <= 4 ? 4 : d2 <= 8 ? 8 : d2 <= 16 ? 16 : d2 <= 32 ? 32 : 64;
-  auto elems = [&](int ipb) { return two_e_rows(ipb * n * R2) * (D2p + 1) + 4 + D2p * D2p + D2p; };
+  auto elems = [&](int ipb) {
+    return (int)(two_e_rows(ipb * n * R2) * (D2p + 1) + 4 + D2p * D2p + D2p + two_e_sums_elems(ipb, R2, D2p));
+  };
   int ipb = 256 / (n * R2);
   while (ipb > 1 && elems(ipb) * scalar_bytes > 65536) --ipb;
   if (ipb >= 1 && elems(ipb) * scalar_bytes <= 65536) return ipb;
@@ -415,7 +485,7 @@ hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s) {
   }
   d.W = a.W; d.n = a.n; d.n_up = a.n_up; d.L = a.L; d.d2 = a.d2; d.T = a.T; d.Tp = a.Tp;
   d.R2 = a.T > 1 ? 8 : 1;
-  if (a.d2 > 64 || a.n * d.R2 > 256 || a.L > 8) return hipErrorInvalidValue;
+  if (a.d2 > 64 || a.n * d.R2 > 256 || a.L > 8 || (int64_t)a.W * a.n >= (1LL << 31)) return hipErrorInvalidValue;
   d.ipb = two_electron_per_block(a.n, a.d2, a.T, f64 ? 8 : 4);
   if (d.ipb < 1) return hipErrorInvalidValue;
   const int64_t groups = (int64_t)a.W * a.n;

@@ -2,7 +2,11 @@
 bench's and the tests' full-batch error reports.  Calls only oracle/ and
 the seeded input generator.
 
-    python tests/golden/make_golden.py ne10 [threads]
+    python tests/golden/make_golden.py ne10 [threads] [seed]
+
+With a seed other than the workload's own, the network parameters and the
+walkers are both drawn from that seed (an independent batch), and the file
+is named <name>_seed<seed>_oracle.npz.
 """
 import os
 import sys
@@ -17,12 +21,12 @@ from oracle import oracle as O  # noqa: E402
 from paper_2011_07125_amd import inputs as I  # noqa: E402
 
 
-def main(name, threads):
-    w = I.make_workload(name)
+def main(name, threads, seed=None):
+    w = I.make_workload(name, seed=seed)
     t = time.time()
     r = O.evaluate(w["cfg"], w["pos"], w["nuc_pos"], w["nuc_charge"], w["params"], threads=threads)
     amp, kappa, cond = O.amplification(w["cfg"], w["pos"], w["nuc_pos"], w["params"], threads=threads)
-    out = os.path.join(HERE, f"{name}_oracle.npz")
+    out = os.path.join(HERE, f"{name}_oracle.npz" if seed is None else f"{name}_seed{seed}_oracle.npz")
     np.savez_compressed(out, sign=r["sign"], logpsi=r["logpsi"], e_loc=r["e_loc"], e_kin=r["e_kin"],
                         e_pot=r["e_pot"], amplification=amp, kappa=kappa, cond=cond, seed=w["seed"],
                         walkers=w["pos"].shape[0])
@@ -30,4 +34,5 @@ def main(name, threads):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else os.cpu_count())
+    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else os.cpu_count(),
+         int(sys.argv[3]) if len(sys.argv) > 3 else None)
