@@ -424,13 +424,29 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
     const int nsq = na * na;
     const int Kd = a.N / na;
     S* phi = reinterpret_cast<S*>(a.phi);
-    for (int p = tid; p < E * BN; p += 256) {
-      int e = p / BN, col = p % BN;
-      int g = g0 + e, gc = n0 + col;
-      if (g >= a.n_groups || gc >= a.N) continue;
+    // items (electron e, orbital i, determinant k) of the tile's columns
+    // gc = k n_a + i.  With the matrix-index-fastest layout (phi_M > 0) k
+    // runs fastest, so consecutive lanes store consecutive matrices of one
+    // (jet row, electron, orbital); otherwise i runs fastest (consecutive
+    // orbitals are adjacent in memory).
+    const int k_lo = n0 / na, nk = min(Kd, (n0 + BN - 1) / na + 1) - k_lo;
+    const int per_e = na * nk;
+    for (int p = tid; p < E * per_e; p += 256) {
+      const int e = p / per_e, r = p - e * per_e;
+      int i, k;
+      if (a.phi_M) {
+        i = r / nk;
+        k = k_lo + (r - i * nk);
+      } else {
+        const int kk = r / na;
+        i = r - kk * na;
+        k = k_lo + kk;
+      }
+      const int gc = k * na + i, col = gc - n0;
+      const int g = g0 + e;
+      if (g >= a.n_groups || col < 0 || col >= BN || gc >= a.N) continue;
       const int w = g / na, jj = g % na;
       const int j = a.e_off + jj;  // electron index
-      const int k = gc / na, i = gc % na;
       const float* rj = a.pos + ((size_t)w * a.n_elec + j) * 3;
       const S x0 = rj[0], x1 = rj[1], x2 = rj[2];
       // envelope sum_m pi exp(-s_m) and its gradient and Laplacian with
