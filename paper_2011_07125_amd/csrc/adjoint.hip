@@ -404,6 +404,9 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
   float* Cp = Ct + RP * LD;  // [RP][LD] Ct sech^2(pre)
   float* Ws = Cp + RP * LD;  // [DM][LD] W_l
   float* cs = Ws + DM * LD;  // [DM]     c_l
+  float* red = cs + DM;      // [256 / DM][DM] column-sum partials
+  int* rowi = reinterpret_cast<int*>(red + 256);  // [RP] electron of pair row r (within the walker)
+  int* rowa = rowi + RP;                          // [RP] spin of the partner of pair row r
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int blk = blockIdx.x;
@@ -412,12 +415,19 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
   const int Rb = min(E, n - i0) * n;  // live pair rows
   float* part = a.part + (int64_t)blk * a.p2;
   const int TMr = RP / 16, TNd = DM / 16;
+  // pair row r = (electron i0 + r / n, partner r % n): one division per row, here
+  for (int r = tid; r < RP; r += 256) {
+    const int e = r / n;
+    rowi[r] = i0 + e;
+    rowa[r] = r - e * n < nu ? 0 : 1;
+  }
+  const float inv_u = nu > 0 ? 1.0f / (float)nu : 0.0f, inv_d = n - nu > 0 ? 1.0f / (float)(n - nu) : 0.0f;
+  __syncthreads();
 
   // mean-field cotangent (1/n_a) cot g^{a(j),l}_i of row r, feature k < ein
   auto mf_cot = [&](int l, int ein, int r, int k) {
-    const int i = i0 + r / n, j = r % n;
-    const int al = j < nu ? 0 : 1, na = al == 0 ? nu : n - nu;
-    return a.CG[l][(w * n + i) * a.ldcg[l] + al * ein + k] / (float)na;
+    const int al = rowa[r];
+    return a.CG[l][(w * n + rowi[r]) * a.ldcg[l] + al * ein + k] * (al == 0 ? inv_u : inv_d);
   };
   {
     const int l = L - 1, ein = l == 0 ? 4 : d2;
@@ -433,7 +443,7 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
     for (int idx = tid; idx < RP * DM; idx += 256) {
       const int r = idx / DM, k = idx % DM;
       float v = 0.0f;
-      if (r < Rb && k < ein) v = a.h2[l][((w * n + i0 + r / n) * n + r % n) * ein + k];
+      if (r < Rb && k < ein) v = a.h2[l][((w * n + i0) * n + r) * ein + k];
       Hs[r * LD + k] = v;
     }
     for (int idx = tid; idx < DM * DM; idx += 256) {
@@ -470,10 +480,21 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
         if (k < ein && o < d2) part[a.p_off[l] + k * d2 + o] = acc[q];
       }
     }
-    for (int o = tid; o < d2; o += 256) {
+    // column sums of cp: 256 / DM row-chunks per column, then the chunks
+    // in fixed order
+    {
+      constexpr int NCH = 256 / DM;
+      const int o = tid % DM, ch = tid / DM;
       float sum = 0.0f;
-      for (int r = 0; r < RP; ++r) sum += Cp[r * LD + o];
-      part[a.p_off[l] + ein * d2 + o] = sum;
+      for (int r = ch; r < RP; r += NCH) sum += Cp[r * LD + o];
+      red[ch * DM + o] = sum;
+      __syncthreads();
+      if (tid < d2) {
+        float tot = 0.0f;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) tot += red[c * DM + tid];
+        part[a.p_off[l] + ein * d2 + tid] = tot;
+      }
     }
     // Ct <- cp W^T (+ Ct when widths match) + mean-field cotangent of layer l
     // (each element read and written by one lane: in place)
@@ -501,7 +522,9 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
 static int adj2e_dm(int d2) { return d2 <= 16 ? 16 : d2 <= 32 ? 32 : 64; }
 static int adj2e_group(int n, int d2) {
   const int dm = adj2e_dm(d2), ld = dm + 1;
-  const int rows_cap = std::min(128, (65536 / 4 - dm * ld - dm) / (3 * ld) / 16 * 16);
+  // LDS: three [rows][ld] arrays, W and c, 256 column-sum partials and two
+  // int tables of at most 128 rows
+  const int rows_cap = std::min(128, (65536 / 4 - dm * ld - dm - 256 - 2 * 128) / (3 * ld) / 16 * 16);
   return std::max(1, std::min(n, rows_cap / n));
 }
 
@@ -514,7 +537,7 @@ template <int DM>
 static hipError_t run_adj2e(const Adj2eArgs& a, hipStream_t s) {
   const int E = adj2e_group(a.n, a.d2), ngrp = (a.n + E - 1) / E;
   const int RP = round_up(E * a.n, 16);
-  const size_t shmem = ((size_t)3 * RP * (DM + 1) + (size_t)DM * (DM + 1) + DM) * sizeof(float);
+  const size_t shmem = ((size_t)3 * RP * (DM + 1) + (size_t)DM * (DM + 1) + DM + 256 + 2 * RP) * sizeof(float);
   if (shmem > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL((adj_two_electron_kernel<DM>), dim3((unsigned)((int64_t)a.W * ngrp)), dim3(256), shmem, s, a, E,
                      ngrp);

@@ -295,10 +295,16 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
         }
       }
       if (a.h2_out[l] && R2 == 1) {
-        for (int idx = tid; idx < a.ipb * n * ein; idx += blockDim.x) {
-          const int e = idx / (n * ein), jj = (idx / ein) % n, o = idx % ein;
-          const int64_t ge = gbase + e;
-          if (ge < n_groups) a.h2_out[l][(ge * n + jj) * ein + o] = (float)Ps[(size_t)(e * n + jj) * PS + o];
+        // the block's pair activations are one contiguous run of the output
+        // ([electron][partner][ein] with slot = e n + partner); slot and
+        // feature by shifts when ein is a power of two
+        const int nval = (min(a.ipb, n_groups - gbase)) * n * ein;
+        float* dst = a.h2_out[l] + (int64_t)gbase * n * ein;
+        const bool pow2 = (ein & (ein - 1)) == 0;
+        const int sh = __builtin_ctz(ein);
+        for (int idx = tid; idx < nval; idx += blockDim.x) {
+          const int sl = pow2 ? idx >> sh : idx / ein, o = idx - sl * ein;
+          dst[idx] = (float)Ps[(size_t)sl * PS + o];
         }
       }
     }
