@@ -27,6 +27,12 @@
 //     second derivative along that single coordinate).  No multi-tangent
 //     jet algebra, no blocking, no split-form shortcuts.
 //   * d log|psi| / d theta_p, one dual-number pass per selected parameter.
+//   * for the Kronecker-factored curvature statistics (KFAC, Martens and
+//     Grosse 2015, the optimiser the paper uses): the inputs of every dense
+//     layer at every position (electron, electron pair), and the
+//     derivative of log|psi| with respect to each pre-activation at each
+//     position, one dual-number pass per (position, unit) with a unit
+//     derivative added to that pre-activation.
 //   * Metropolis sampling of psi^2 (Eq. 3), replayed from supplied noise
 //     or from the Philox4x32-10 generator (Salmon et al., SC'11).
 //
@@ -57,6 +63,12 @@ struct Jet2 {
 inline double val(double x) { return x; }
 inline double val(const Dual& x) { return x.v; }
 inline double val(const Jet2& x) { return x.v; }
+
+// a derivative of 1 in the direction a dual-number pass probes
+template <class S> inline S probe_unit();
+template <> inline double probe_unit<double>() { return 0.0; }
+template <> inline Dual probe_unit<Dual>() { return {0.0, 1.0}; }
+template <> inline Jet2 probe_unit<Jet2>() { return {0.0, 0.0, 0.0}; }
 
 template <class S> inline S cst(double c);
 template <> inline double cst<double>(double c) { return c; }
@@ -215,10 +227,24 @@ void slogdet(int n, S* a, double* sign, S* logabs) {
 //   S: type of positions and activations; P: type of the parameters.
 // pos: [n][3]; nuc: [N][3] (plain doubles: nuclei are fixed, Section 1's
 // Born-Oppenheimer setting); prm: the flat parameter vector.
+// Optional instrumentation of eval_walker: records the inputs of the dense
+// layers (values) and adds probe_unit to one pre-activation.
+//   probe kind 0: one-electron layer `layer`, electron `pos`, unit `unit`
+//   probe kind 1: two-electron layer `layer`, pair pos = i n + j, unit
+//   probe kind 2: orbital pre-envelope value u of electron `pos` (spin
+//                 implied), column `unit` = k n_a + i of that spin
+struct Taps {
+  int kind = -1, layer = 0, pos = 0, unit = 0;
+  double* rec1 = nullptr;  // [L][n][fw_max]: f_i of one-electron layer l
+  double* rec2 = nullptr;  // [L-1][n n][ein_max]: h_ij entering two-electron layer l
+  double* reco = nullptr;  // [n][d1]: h^L_j entering the orbitals
+  int fw_max = 0, ein_max = 0;
+};
+
 template <class S, class P>
 void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc, const P* prm,
                  double* sign_out, S* logabs_out, double* sk_out = nullptr, double* lk_out = nullptr,
-                 double* orb_out = nullptr) {
+                 double* orb_out = nullptr, const Taps* tp = nullptr) {
   const int n = c.n, N = c.N;
   // spin of electron j: up for j < n_up (the caller orders spins up first)
   auto spin_of = [&](int j) { return j < c.n_up ? 0 : 1; };
@@ -279,11 +305,14 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
           fvec[3 * din + a * ein + f] = nsp[a] > 0 ? s * (1.0 / nsp[a]) : cst<S>(0.0);
         }
       }
+      if (tp && tp->rec1)
+        for (int k = 0; k < fw; ++k) tp->rec1[((size_t)l * n + i) * tp->fw_max + k] = val(fvec[k]);
       for (int o = 0; o < c.d1; ++o) {
         // pre = b_o + sum_k f_k V[k][o]
         S acc = cst<S>(0.0);
         for (int k = 0; k < fw; ++k) acc = acc + fvec[k] * V[(size_t)k * c.d1 + o];
         S pre = acc + b[o];
+        if (tp && tp->kind == 0 && tp->layer == l && tp->pos == i && tp->unit == o) pre = pre + probe_unit<S>();
         S y = tanh_(pre);
         if (din == c.d1) y = y + h1[(size_t)i * din + o];
         nh1[(size_t)i * c.d1 + o] = y;
@@ -296,10 +325,14 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
           const S* x = &h2[((size_t)i * n + j) * ein];
+          if (tp && tp->rec2)
+            for (int k = 0; k < ein; ++k) tp->rec2[((size_t)l * n * n + i * n + j) * tp->ein_max + k] = val(x[k]);
           for (int o = 0; o < c.d2; ++o) {
             S acc = cst<S>(0.0);
             for (int k = 0; k < ein; ++k) acc = acc + x[k] * W2[(size_t)k * c.d2 + o];
-            S y = tanh_(acc + c2[o]);
+            S z = acc + c2[o];
+            if (tp && tp->kind == 1 && tp->layer == l && tp->pos == i * n + j && tp->unit == o) z = z + probe_unit<S>();
+            S y = tanh_(z);
             if (ein == c.d2) y = y + x[o];
             nh2[((size_t)i * n + j) * c.d2 + o] = y;
           }
@@ -311,6 +344,8 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
 
   // orbitals and determinants: A^{k,a}_{ij} = phi^{k,a}_i(r^a_j)
   const int d1 = c.d1;
+  if (tp && tp->reco)
+    for (size_t q = 0; q < (size_t)n * d1; ++q) tp->reco[q] = val(h1[q]);
   std::vector<double> sgn_k(c.K, 1.0);
   std::vector<S> log_k(c.K, cst<S>(0.0));
   int j0 = 0;
@@ -330,6 +365,7 @@ void eval_walker(const Cfg& c, const Layout& Y, const S* pos, const double* nuc,
           S u = cst<S>(0.0);
           for (int f = 0; f < d1; ++f) u = u + h1[(size_t)e * d1 + f] * wo[(size_t)f * no + col];
           u = u + go[col];
+          if (tp && tp->kind == 2 && tp->pos == e && tp->unit == col) u = u + probe_unit<S>();
           S env = cst<S>(0.0);
           for (int m = 0; m < N; ++m) {
             S d[3];
@@ -588,6 +624,86 @@ int orc_param_grad(const int32_t* cfg, int W, const double* pos, const double* n
       eval_walker<Dual, Dual>(c, Y, x.data(), nuc, th.data(), &sg, &la);
       out[(size_t)w * n_sel + s] = la.d;
     }
+  return 0;
+}
+
+// Inputs of the dense layers, per walker (values):
+//   f1 [W][L][n][fw_max]   f_i = [h_i, hbar^up, hbar^down, g^up_i, g^down_i]
+//                          of one-electron layer l (zero-padded to fw_max)
+//   f2 [W][L-1][n n][ein_max]  h_ij entering two-electron layer l
+//   fo [W][n][d1]          h^L_j entering the orbitals
+// fw_max = 3 max(din) + 2 max(ein), ein_max = max(4, d2).
+int orc_layer_inputs(const int32_t* cfg, int W, const double* pos, const double* nuc, const double* prm,
+                     int n_threads, double* f1, double* f2, double* fo) {
+  Cfg c = read_cfg(cfg);
+  if (!cfg_ok(c)) return -1;
+  Layout Y = make_layout(c);
+  const int n = c.n, nc = 3 * n;
+  const int ein_max = std::max(4, c.d2), fw_max = 3 * std::max(4 * c.N, c.d1) + 2 * ein_max;
+  const size_t s1 = (size_t)c.L * n * fw_max, s2 = (size_t)std::max(c.L - 1, 0) * n * n * ein_max;
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int w = 0; w < W; ++w) {
+    Taps tp;
+    tp.rec1 = f1 + (size_t)w * s1;
+    tp.rec2 = f2 + (size_t)w * s2;
+    tp.reco = fo + (size_t)w * n * c.d1;
+    tp.fw_max = fw_max;
+    tp.ein_max = ein_max;
+    std::fill(tp.rec1, tp.rec1 + s1, 0.0);
+    std::fill(tp.rec2, tp.rec2 + s2, 0.0);
+    double sg;
+    double la;
+    eval_walker<double, double>(c, Y, pos + (size_t)w * nc, nuc, prm, &sg, &la, nullptr, nullptr, nullptr, &tp);
+  }
+  return 0;
+}
+
+// d log|psi_w| / d z at every position and unit of one dense layer, one
+// dual-number pass each: out [W][positions][units] with
+//   kind 0: one-electron layer `layer`: n electrons x d1 units
+//   kind 1: two-electron layer `layer`: n^2 pairs (i n + j) x d2 units
+//   kind 2: orbitals of spin `layer`: its n_a electrons x K n_a columns
+int orc_preact_cotangents(const int32_t* cfg, int W, const double* pos, const double* nuc, const double* prm,
+                          int kind, int layer, int n_threads, double* out) {
+  Cfg c = read_cfg(cfg);
+  if (!cfg_ok(c)) return -1;
+  Layout Y = make_layout(c);
+  const int n = c.n, nc = 3 * n;
+  int P, U, e0 = 0;
+  if (kind == 0) {
+    if (layer < 0 || layer >= c.L) return -1;
+    P = n;
+    U = c.d1;
+  } else if (kind == 1) {
+    if (layer < 0 || layer + 1 >= c.L) return -1;
+    P = n * n;
+    U = c.d2;
+  } else if (kind == 2) {
+    if (layer < 0 || layer > 1) return -1;
+    P = nspin(c, layer);
+    U = c.K * P;
+    e0 = layer == 0 ? 0 : c.n_up;
+  } else {
+    return -1;
+  }
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1) collapse(3)
+  for (int w = 0; w < W; ++w)
+    for (int p = 0; p < P; ++p)
+      for (int u = 0; u < U; ++u) {
+        Taps tp;
+        tp.kind = kind;
+        tp.layer = layer;
+        tp.pos = kind == 2 ? e0 + p : p;
+        tp.unit = u;
+        std::vector<Dual> x(nc);
+        for (int r = 0; r < nc; ++r) x[r] = {pos[(size_t)w * nc + r], 0.0};
+        double sg;
+        Dual la;
+        eval_walker<Dual, double>(c, Y, x.data(), nuc, prm, &sg, &la, nullptr, nullptr, nullptr, &tp);
+        out[((size_t)w * P + p) * U + u] = la.d;
+      }
   return 0;
 }
 

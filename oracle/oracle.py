@@ -54,7 +54,10 @@ def _load():
         lib.orc_philox4x32_10.restype = None
         lib.orc_mcmc_noise.argtypes = [i32, i32, i32, u64, u64, P, P]
         lib.orc_mcmc.argtypes = [P, i32, P, P, P, i32, dbl, P, P, u64, u64, i32, P, P, P]
-        for f in ("orc_slogdet", "orc_eval", "orc_potential", "orc_param_grad", "orc_mcmc_noise", "orc_mcmc"):
+        lib.orc_layer_inputs.argtypes = [P, i32, P, P, P, i32, P, P, P]
+        lib.orc_preact_cotangents.argtypes = [P, i32, P, P, P, i32, i32, i32, P]
+        for f in ("orc_slogdet", "orc_eval", "orc_potential", "orc_param_grad", "orc_mcmc_noise", "orc_mcmc",
+                  "orc_layer_inputs", "orc_preact_cotangents"):
             getattr(lib, f).restype = i32
         _lib = lib
     return _lib
@@ -221,3 +224,103 @@ def mcmc(cfg, pos, nuc_pos, params, logpsi, sign, n_steps, width, noise=None, un
                           _threads(threads), _p(lp), _p(sg), _p(acc))
     assert rc == 0
     return pos, lp, sg, acc
+
+
+# ------------------------------------------------------------------ KFAC
+# Kronecker-factored curvature statistics (Martens and Grosse 2015; the
+# paper's optimiser).  For a dense layer applied at positions r of walker w
+# (electrons, electron pairs, or the electrons of one spin) with inputs
+# a_{w,r}, a~ = [a; 1] (the bias as a last input), and pre-activation
+# cotangents g_{w,r} = d log|psi_w| / d z_{w,r}:
+#     A = sum_w c_w sum_r a~ a~^T        G = sum_w c_w sum_r g g^T
+# for caller weights c_w.  sum_w c_w sum_r a~ g^T is the gradient of
+# sum_w c_w log|psi_w| with respect to [weights; bias].
+
+def _din(cfg, l):
+    return 4 * cfg["n_nuc"] if l == 0 else cfg["width1"]
+
+
+def _ein(cfg, l):
+    return 4 if l == 0 else cfg["width2"]
+
+
+def layer_inputs(cfg, pos, nuc_pos, params, threads=None):
+    """Inputs of the dense layers: (f1 [W][L][n][fw_max], f2 [W][L-1][n^2][ein_max],
+    fo [W][n][d1]); f_i zero-padded to fw_max = 3 max(din) + 2 ein_max."""
+    pos = _d(pos)
+    W, n = pos.shape[0], cfg["n_elec"]
+    L, d1 = cfg["n_layers"], cfg["width1"]
+    ein_max = max(4, cfg["width2"])
+    fw_max = 3 * max(4 * cfg["n_nuc"], d1) + 2 * ein_max
+    f1 = np.zeros((W, L, n, fw_max))
+    f2 = np.zeros((W, max(L - 1, 0), n * n, ein_max))
+    fo = np.zeros((W, n, d1))
+    rc = _load().orc_layer_inputs(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(params)), _threads(threads),
+                                  _p(f1), _p(f2), _p(fo))
+    assert rc == 0
+    return f1, f2, fo
+
+
+def preact_cotangents(cfg, pos, nuc_pos, params, kind, layer, threads=None):
+    """d log|psi_w| / d z at every (position, unit) of one dense layer,
+    [W][positions][units]: kind 0 one-electron layer (n x d1), 1
+    two-electron layer (n^2 pairs i n + j x d2), 2 orbitals of spin `layer`
+    (n_a x K n_a)."""
+    pos = _d(pos)
+    W, n = pos.shape[0], cfg["n_elec"]
+    if kind == 0:
+        P, U = n, cfg["width1"]
+    elif kind == 1:
+        P, U = n * n, cfg["width2"]
+    else:
+        P = cfg["n_up"] if layer == 0 else cfg["n_down"]
+        U = cfg["n_det"] * P
+    out = np.zeros((W, P, U))
+    rc = _load().orc_preact_cotangents(_p(_cfg(cfg)), W, _p(pos), _p(_d(nuc_pos)), _p(_d(params)), int(kind),
+                                       int(layer), _threads(threads), _p(out))
+    assert rc == 0
+    return out
+
+
+def kfac_blocks(cfg):
+    """The dense layers in order: (name, kind, layer, d_in, d_out, positions)."""
+    n, L = cfg["n_elec"], cfg["n_layers"]
+    out = []
+    for l in range(L):
+        out.append((f"layer{l}", 0, l, 3 * _din(cfg, l) + 2 * _ein(cfg, l), cfg["width1"], n))
+    for l in range(L - 1):
+        out.append((f"pair{l}", 1, l, _ein(cfg, l), cfg["width2"], n * n))
+    for a, na in enumerate((cfg["n_up"], cfg["n_down"])):
+        if na:
+            out.append((f"orbital{a}", 2, a, cfg["width1"], cfg["n_det"] * na, na))
+    return out
+
+
+def kfac_inputs_and_cotangents(cfg, pos, nuc_pos, params, threads=None):
+    """Per block: (name, a~ [W][positions][d_in + 1], g [W][positions][d_out])."""
+    f1, f2, fo = layer_inputs(cfg, pos, nuc_pos, params, threads)
+    W = f1.shape[0]
+    res = []
+    for name, kind, l, din, dout, npos in kfac_blocks(cfg):
+        if kind == 0:
+            a = f1[:, l, :, :din]
+        elif kind == 1:
+            a = f2[:, l, :, :din]
+        else:
+            j0 = 0 if l == 0 else cfg["n_up"]
+            a = fo[:, j0:j0 + npos, :]
+        at = np.concatenate([a, np.ones((W, npos, 1))], axis=2)
+        g = preact_cotangents(cfg, pos, nuc_pos, params, kind, l, threads)
+        res.append((name, at, g))
+    return res
+
+
+def kfac_factors(cfg, pos, nuc_pos, params, weights, threads=None):
+    """[(name, A, G)] with A = sum_w c_w sum_r a~ a~^T, G = sum_w c_w sum_r g g^T."""
+    c = np.asarray(weights, dtype=np.float64)
+    out = []
+    for name, at, g in kfac_inputs_and_cotangents(cfg, pos, nuc_pos, params, threads):
+        A = np.einsum("w,wri,wrj->ij", c, at, at)
+        G = np.einsum("w,wri,wrj->ij", c, g, g)
+        out.append((name, A, G))
+    return out

@@ -652,3 +652,47 @@ def test_full_envelope_param_gradient_vs_finite_differences():
         fd = (O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], pp, energy=False)["logpsi"] -
               O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], pm, energy=False)["logpsi"]) / (2 * h)
         np.testing.assert_allclose(g[:, s_i], fd, rtol=1e-6, atol=1e-7)
+
+
+def test_kfac_statistics_reproduce_the_parameter_gradient():
+    """Statistics of the Kronecker-factored curvature (Martens and Grosse
+    2015, the optimiser the paper uses).  For every dense layer, the
+    recorded inputs a~ = [a; 1] and the probed pre-activation cotangents g
+    must give sum_w c_w sum_r a~ g^T equal to the weighted gradient of
+    log|psi| with respect to that layer's [weights; bias], taken from the
+    oracle's dual-number gradient (itself pinned by finite differences in
+    test_T9): a wrong position, a transposed product or a missing bias
+    input fails.  The factors A and G are symmetric positive semi-definite."""
+    names = {"layer": ("V", "b"), "pair": ("W", "c"), "orbital": ("w_orb", "g_orb")}
+    for w in (small_workload(W=4), I.make_workload("be4", walkers=3)):
+        cfg = w["cfg"]
+        W = w["pos"].shape[0]
+        c = np.linspace(0.2, 1.0, W)
+        blocks = O.kfac_inputs_and_cotangents(cfg, w["pos"], w["nuc_pos"], w["params"])
+        assert [b[0] for b in blocks] == [b[0] for b in O.kfac_blocks(cfg)]
+        offs = I.param_offsets(cfg)
+        sel = []
+        for name, at, g in blocks:
+            kind = name.rstrip("0123456789")
+            idx = name[len(kind):]
+            ow, shw = offs[names[kind][0] + idx]
+            ob, shb = offs[names[kind][1] + idx]
+            assert ob == ow + int(np.prod(shw))  # the bias row follows the weights
+            assert at.shape[2] == shw[0] + 1 and g.shape[2] == shw[1]
+            sel.append(np.arange(ow, ob + int(np.prod(shb))))
+        grad = O.param_grad(cfg, w["pos"], w["nuc_pos"], w["params"], np.concatenate(sel))
+        ref = (c[:, None] * grad).sum(0)
+        at_ = 0
+        for name, at, g in blocks:
+            est = np.einsum("w,wri,wro->io", c, at, g).reshape(-1)
+            seg = ref[at_:at_ + est.size]
+            np.testing.assert_allclose(est, seg, rtol=1e-9, atol=1e-10 * max(1.0, np.abs(seg).max()),
+                                       err_msg=name)
+            at_ += est.size
+        for name, A, G in O.kfac_factors(cfg, w["pos"], w["nuc_pos"], w["params"], c):
+            for M in (A, G):
+                assert np.allclose(M, M.T, rtol=0, atol=1e-12 * max(1.0, np.abs(M).max()))
+                assert np.linalg.eigvalsh(M).min() >= -1e-9 * max(1.0, np.abs(M).max())
+            # the bias entry of A is sum_w c_w times the number of positions
+            npos = [b[5] for b in O.kfac_blocks(cfg) if b[0] == name][0]
+            assert abs(A[-1, -1] - c.sum() * npos) < 1e-12 * npos
