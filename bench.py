@@ -187,6 +187,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-kfac", action="store_true", help="skip timing the KFAC statistics")
     ap.add_argument("--no-full-envelope", action="store_true",
                     help="skip timing the same step with the full-covariance envelope of Eq. (5)")
     ap.add_argument("--rescue-bf16", type=float, default=0.03,
@@ -228,6 +229,23 @@ def main():
         res["full_envelope_bf16"] = {"value": W / (ms_fe * 1e-3), "ms_per_step": ms_fe,
                                      "slowdown_vs_isotropic": ms_fe / ms_bf,
                                      "stage_ms": {k: round(v[0] / 2, 4) for k, v in st_fe.items()}}
+    if grad and not args.no_kfac:
+        # KFAC statistics (A and G of every dense layer) of the same batch
+        d = F.to_device(w)
+        c = torch.full((W,), 1.0 / W, device="cuda")
+        for i in range(args.warmup):
+            F.ferminet_kfac_factors(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], c, precision="bf16")
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for i in range(args.steps):
+            F.ferminet_kfac_factors(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], c, precision="bf16")
+        t1.record()
+        torch.cuda.synchronize()
+        ms_k = t0.elapsed_time(t1) / args.steps
+        res["kfac_factors_bf16"] = {"ms_per_call": ms_k, "value": W / (ms_k * 1e-3), "unit": "walkers/s",
+                                    "floats": F.kfac_layout(cfg)[1]}
     main_fl, mf_fl = layer_flops(cfg, W, T)
     # dominant kernel: the one-electron layer GEMM of the jet pass (L
     # launches per local-energy call, layer 0 included).  Its arithmetic

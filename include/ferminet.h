@@ -161,8 +161,20 @@ typedef enum {
   FN_ENTRY_LOGPSI = 0,
   FN_ENTRY_LOCAL_ENERGY = 1,
   FN_ENTRY_GRAD_LOGPSI = 2,
-  FN_ENTRY_MCMC = 3
+  FN_ENTRY_MCMC = 3,
+  FN_ENTRY_KFAC = 4
 } fn_entry;
+
+/* One dense layer's Kronecker factors in the output of ferminet_kfac_factors. */
+typedef struct {
+  char name[16];     /* "layer0".., "pair0".., "orbital0", "orbital1" */
+  int64_t offset_A;  /* in floats: A, dim_A x dim_A row-major */
+  int64_t offset_G;  /* in floats: G, dim_G x dim_G row-major */
+  int32_t dim_A;     /* inputs + 1 (the bias input) */
+  int32_t dim_G;     /* outputs */
+  int32_t positions; /* positions per walker the layer is applied at */
+  int32_t reserved;
+} fn_kfac_block;
 
 /* Human-readable text of a status code (static storage). */
 const char* ferminet_status_string(int32_t status);
@@ -224,6 +236,39 @@ fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos,
                               const float* nuc_pos, const float* nuc_charge, const float* params,
                               const float* e_loc, double* e_stats, float* grad, void* workspace,
                               size_t workspace_bytes, hipStream_t stream);
+
+/* Statistics of the Kronecker-factored approximate curvature (KFAC,
+ * Martens and Grosse 2015), the optimiser the paper's introduction names,
+ * for every dense layer of the network.  A layer with inputs a and
+ * pre-activations z = a W + b applied at positions r of walker w (the n
+ * electrons for the one-electron layers, whose input is
+ * f_i = [h_i, hbar^up, hbar^down, g^up_i, g^down_i]; the n^2 electron pairs
+ * (i n + j) for the two-electron layers; the n_a electrons of one spin for
+ * the orbital layer of that spin, whose input is h^L_j) contributes
+ *   A = sum_w c_w sum_r a~ a~^T,   a~ = [a; 1]
+ *   G = sum_w c_w sum_r g g^T,     g = d log|psi_w| / d z_{w,r}
+ * so that sum_w c_w sum_r a~ g^T is the gradient of sum_w c_w log|psi_w|
+ * with respect to [W; b] (the weight block followed by its bias in the
+ * parameter layout).  The envelope parameters (pi, sigma) are not dense
+ * layers and have no factors.
+ *   weights  [W] float32 in: c_w (negative values count as 0)
+ *   factors  float32 out, ferminet_kfac_layout's total floats: each
+ *            block's A then G (overwritten, not accumulated)
+ * Runs the hand-written adjoint with cotangents sqrt(c_w), in the fp32 or
+ * split-bf16 form (FN_ERR_UNSUPPORTED for FN_PREC_FP64).  Uses the
+ * FN_ENTRY_KFAC workspace. */
+fn_status ferminet_kfac_factors(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                const float* nuc_pos, const float* nuc_charge, const float* params,
+                                const float* weights, float* factors, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+/* The blocks of ferminet_kfac_factors in output order: the one-electron
+ * layers, the two-electron layers, then the orbital layers of the spins
+ * that have electrons.  Writes at most cap entries to out (HOST), the
+ * block count to *n_out and the total floats to *total (HOST); FN_ERR_ARG
+ * if cap is too small. */
+fn_status ferminet_kfac_layout(const fn_config* cfg, fn_kfac_block* out, int32_t cap, int32_t* n_out,
+                               int64_t* total);
 
 /* n_steps Metropolis random-walk steps sampling psi^2 (Eq. (3)), all
  * electrons moved at once:

@@ -235,11 +235,61 @@ struct AdjBufs {
   float* cot;       // [Wc]
   int ldu;
   int64_t p2;       // two-electron parameters in all
+  // KFAC statistics (FN_ENTRY_KFAC only)
+  float* Faug;      // [R][ldf] scaled inputs a~ of one dense layer
+  int ldf;
+  float* sc;        // [Wc] sqrt(c_w)
+  int64_t kcols;    // KFAC columns of a two-electron partial row
+  int64_t ldp2;     // floats per two-electron partial row (p2 + kcols)
 };
 
 static constexpr int kRowChunk = 64;
 
-static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
+// ------------------------------------------------------------ KFAC layout
+// the dense layers: one-electron layers, two-electron layers, orbitals of
+// each spin that has electrons; each block's A then G in the output
+struct KfacBlk {
+  char name[16];
+  int kind, layer, dA, dG, npos;
+  int64_t offA, offG;
+};
+static std::vector<KfacBlk> kfac_blocks(const Plan& p, int64_t* total) {
+  std::vector<KfacBlk> v;
+  int64_t off = 0;
+  auto add = [&](const char* nm, int kind, int layer, int dA, int dG, int npos) {
+    KfacBlk k;
+    memset(&k, 0, sizeof(k));
+    snprintf(k.name, sizeof(k.name), "%s", nm);
+    k.kind = kind;
+    k.layer = layer;
+    k.dA = dA;
+    k.dG = dG;
+    k.npos = npos;
+    k.offA = off;
+    off += (int64_t)dA * dA;
+    k.offG = off;
+    off += (int64_t)dG * dG;
+    v.push_back(k);
+  };
+  char nm[16];
+  for (int l = 0; l < p.L; ++l) {
+    snprintf(nm, sizeof(nm), "layer%d", l);
+    add(nm, 0, l, 3 * p.din[l] + 2 * p.ein[l] + 1, p.d1, p.n);
+  }
+  for (int l = 0; l + 1 < p.L; ++l) {
+    snprintf(nm, sizeof(nm), "pair%d", l);
+    add(nm, 1, l, p.ein[l] + 1, p.d2, p.n * p.n);
+  }
+  for (int a = 0; a < 2; ++a)
+    if (p.na(a) > 0) {
+      snprintf(nm, sizeof(nm), "orbital%d", a);
+      add(nm, 2, a, p.d1 + 1, p.K * p.na(a), p.na(a));
+    }
+  if (total) *total = off;
+  return v;
+}
+
+static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, bool kfac = false) {
   const int64_t R = Wc * p.n;
   const size_t rb = p.fp64 ? 8 : 4;
   int dmax = 0;
@@ -275,16 +325,32 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b) {
   b.S = (float*)cv.take((size_t)Wc * p.d1 * 4);
   b.CMF = (float*)cv.take((size_t)Wc * 2 * dmax * 4);
   // X^T Y partials: splits(R) * K1 * N with K1 <= max(d1, dinp, 2 ein), N <= max(d1, K n_a)
-  const int64_t k1max = std::max<int64_t>(p.d1, std::max(dmax, 2 * std::max(4, p.d2)));
-  const int64_t nmax = std::max<int64_t>(p.d1, (int64_t)p.K * std::max(p.nu, p.nd));
+  int64_t k1max = std::max<int64_t>(p.d1, std::max(dmax, 2 * std::max(4, p.d2)));
+  int64_t nmax = std::max<int64_t>(p.d1, (int64_t)p.K * std::max(p.nu, p.nd));
+  b.kcols = 0;
+  b.ldf = 0;
+  if (kfac) {
+    // A = a~^T a~ and G = g^T g of every dense layer; two-electron blocks
+    // as extra columns of the pair partials
+    for (const KfacBlk& k : kfac_blocks(p, nullptr)) {
+      k1max = std::max<int64_t>(k1max, std::max(k.dA, k.dG));
+      nmax = std::max<int64_t>(nmax, std::max(k.dA, k.dG));
+      if (k.kind == 1) b.kcols += (int64_t)k.dA * k.dA + (int64_t)k.dG * k.dG;
+      if (k.kind != 1) b.ldf = std::max(b.ldf, round_up(k.dA, 4));
+    }
+  }
   const int64_t part_n = atb_part_floats((int)k1max, (int)nmax);
   b.part = (float*)cv.take((size_t)part_n * 4);
   b.p2 = 0;
   for (int l = 0; l + 1 < p.L; ++l) b.p2 += (int64_t)p.ein[l] * p.d2 + p.d2;
-  b.part2 = (float*)cv.take((size_t)R * std::max<int64_t>(b.p2, 1) * 4);
-  // row-sum partials: column sums over R rows (d1, p2 or ldu columns) and
-  // the reduction of the X^T Y partials over their splits
-  const int64_t t1 = (int64_t)rowsum_chunks(R, kRowChunk) * std::max<int64_t>(std::max<int64_t>(p.d1, b.p2), b.ldu);
+  b.ldp2 = b.p2 + b.kcols;
+  b.part2 = (float*)cv.take((size_t)R * std::max<int64_t>(b.ldp2, 1) * 4);
+  b.Faug = kfac ? (float*)cv.take((size_t)R * b.ldf * 4) : nullptr;
+  b.sc = kfac ? (float*)cv.take((size_t)Wc * 4) : nullptr;
+  // row-sum partials: column sums over R rows (d1, p2, KFAC or ldu columns)
+  // and the reduction of the X^T Y partials over their splits
+  const int64_t t1 = (int64_t)rowsum_chunks(R, kRowChunk) *
+                     std::max<int64_t>(std::max<int64_t>(p.d1, std::max(b.p2, b.kcols)), b.ldu);
   const int64_t t2 = (int64_t)rowsum_chunks(atb_part_floats((int)k1max, (int)nmax) / 4096, kRowChunk) * k1max * nmax;
   b.tmp = (float*)cv.take((size_t)std::max(t1, t2) * 4);
   b.cot = (float*)cv.take((size_t)Wc * 4);
@@ -331,9 +397,9 @@ static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   Carver cv{nullptr, 0};
   Bufs b;
   cv.take((size_t)p.pk_total * p.act);
-  if (entry == FN_ENTRY_GRAD_LOGPSI) {
+  if (entry == FN_ENTRY_GRAD_LOGPSI || entry == FN_ENTRY_KFAC) {
     AdjBufs ab;
-    carve_adjoint(p, Wc, cv, ab);
+    carve_adjoint(p, Wc, cv, ab, entry == FN_ENTRY_KFAC);
     return cv.used;
   }
   carve_forward(p, entry == FN_ENTRY_LOCAL_ENERGY ? JET : VALUE, Wc, cv, b, entry == FN_ENTRY_MCMC);
@@ -744,12 +810,21 @@ static fn_status gemm_cwt(const float* C, int ldc_in, int K, int64_t rows, const
 }
 
 // reverse pass of one chunk with walker cotangents cot[Wc]; adds into grad
+// (when not NULL) and, with kout, the KFAC factors of the chunk into kout
+// (the cotangents then being sqrt(c_w), held in b.sc)
 static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const float* nuc, const float* params,
-                          const float* cot, const AdjBufs& b, float* grad, hipStream_t s) {
+                          const float* cot, const AdjBufs& b, float* grad, hipStream_t s, float* kout = nullptr) {
   const int64_t R = Wc * p.n;
   fn_status st;
   float* CHc = b.CH[0];
   float* CHn = b.CH[1];
+  std::vector<KfacBlk> kb;
+  if (kout) kb = kfac_blocks(p, nullptr);
+  auto kblk = [&](int kind, int layer) -> const KfacBlk* {
+    for (const KfacBlk& k : kb)
+      if (k.kind == kind && k.layer == layer) return &k;
+    return nullptr;
+  };
   // determinants -> orbitals -> envelope
   for (int a = 0; a < 2; ++a) {
     const int na = p.na(a);
@@ -757,12 +832,24 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     const int j0 = a == 0 ? 0 : p.nu;
     FN_T(ST_ADJ_ORB, launch_adj_orbital_cot(p.fp64, b.binv[a], b.rho, cot, b.u[a], b.env[a], (int)Wc, p.K, na, b.ldu,
                                             b.cot_u[a], b.cot_env[a], s));
-    FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a], p.env_full,
-                                         (int)Wc,
-                                         p.K, na, j0, p.n, p.N, grad + p.offpi[a], grad + p.offsg[a], s));
-    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.cot_u[a], Wc * na, p.K * na, b.ldu, b.tmp, grad + p.offg[a], kRowChunk, s));
-    st = atb_add(b, b.H[p.L], p.d1, 0, na, p.n, j0, b.cot_u[a], b.ldu, Wc * na, p.d1, p.K * na, grad + p.offw[a], s);
-    if (st != FN_OK) return st;
+    if (grad) {
+      FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a],
+                                           p.env_full, (int)Wc, p.K, na, j0, p.n, p.N, grad + p.offpi[a],
+                                           grad + p.offsg[a], s));
+      FN_T(ST_ADJ_REDUCE,
+           launch_rowsum_add(b.cot_u[a], Wc * na, p.K * na, b.ldu, b.tmp, grad + p.offg[a], kRowChunk, s));
+      st = atb_add(b, b.H[p.L], p.d1, 0, na, p.n, j0, b.cot_u[a], b.ldu, Wc * na, p.d1, p.K * na, grad + p.offw[a], s);
+      if (st != FN_OK) return st;
+    }
+    if (kout) {
+      // orbital layer of spin a: G = cot_u^T cot_u, A = a~^T a~ with a~ = sqrt(c_w) [h^L_j, 1]
+      const KfacBlk* k = kblk(2, a);
+      st = atb_add(b, b.cot_u[a], b.ldu, 0, 0, 0, 0, b.cot_u[a], b.ldu, Wc * na, k->dG, k->dG, kout + k->offG, s);
+      if (st != FN_OK) return st;
+      FN_T(ST_ADJ_REDUCE, launch_kfac_aug_orbital(b.H[p.L], p.d1, p.d1, b.sc, (int)Wc, p.n, j0, na, b.ldf, b.Faug, s));
+      st = atb_add(b, b.Faug, b.ldf, 0, 0, 0, 0, b.Faug, b.ldf, Wc * na, k->dA, k->dA, kout + k->offA, s);
+      if (st != FN_OK) return st;
+    }
     // cot h^L of the electrons of spin a
     st = gemm_cwt(b.cot_u[a], b.ldu, b.ldu, Wc * na, b.wo[a], b.ldu, p.d1, CHc, p.d1, 0, na, p.n, j0, ST_ADJ_ORB, s);
     if (st != FN_OK) return st;
@@ -773,21 +860,34 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     const float* V = params + p.offV[l];
     FN_T(ST_ADJ_LAYERS, launch_adj_cp(CHc, b.PRE[l + 1], R * p.d1, b.CP, s));
     FN_T(ST_ADJ_LAYERS, launch_adj_walker_sum(b.CP, (int)Wc, p.n, p.d1, b.S, s));
-    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.CP, R, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
     const int ldh = l == 0 ? p.dinp[0] : p.d1;
-    // dA = sum h_i^T cp_i
-    st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s);
-    if (st != FN_OK) return st;
-    // dB^a = sum_w hbar^a_w^T S_w
-    for (int a = 0; a < 2; ++a) {
-      st = atb_add(b, b.Hbar[l], 2 * p.dinp[l], a * p.dinp[l], 0, 0, 0, b.S, p.d1, Wc, din, p.d1,
-                   grad + p.offV[l] + (int64_t)(din + a * din) * p.d1, s);
+    if (grad) {
+      FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.CP, R, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
+      // dA = sum h_i^T cp_i
+      st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s);
+      if (st != FN_OK) return st;
+      // dB^a = sum_w hbar^a_w^T S_w
+      for (int a = 0; a < 2; ++a) {
+        st = atb_add(b, b.Hbar[l], 2 * p.dinp[l], a * p.dinp[l], 0, 0, 0, b.S, p.d1, Wc, din, p.d1,
+                     grad + p.offV[l] + (int64_t)(din + a * din) * p.d1, s);
+        if (st != FN_OK) return st;
+      }
+      // dC = sum g_i^T cp_i (columns a ein + o)
+      st = atb_add(b, b.G[l], p.gwp[l], 0, 0, 0, 0, b.CP, p.d1, R, 2 * ein, p.d1,
+                   grad + p.offV[l] + (int64_t)3 * din * p.d1, s);
       if (st != FN_OK) return st;
     }
-    // dC = sum g_i^T cp_i (columns a ein + o)
-    st = atb_add(b, b.G[l], p.gwp[l], 0, 0, 0, 0, b.CP, p.d1, R, 2 * ein, p.d1, grad + p.offV[l] + (int64_t)3 * din * p.d1,
-                 s);
-    if (st != FN_OK) return st;
+    if (kout) {
+      // one-electron layer l: G = cp^T cp, A = a~^T a~ with
+      // a~ = sqrt(c_w) [h_i, hbar^up, hbar^down, g^up_i, g^down_i, 1]
+      const KfacBlk* k = kblk(0, l);
+      st = atb_add(b, b.CP, p.d1, 0, 0, 0, 0, b.CP, p.d1, R, k->dG, k->dG, kout + k->offG, s);
+      if (st != FN_OK) return st;
+      FN_T(ST_ADJ_REDUCE, launch_kfac_aug_layer(b.H[l], ldh, din, b.Hbar[l], p.dinp[l], b.G[l], p.gwp[l], ein, b.sc,
+                                                (int)Wc, p.n, b.ldf, b.Faug, s));
+      st = atb_add(b, b.Faug, b.ldf, 0, 0, 0, 0, b.Faug, b.ldf, R, k->dA, k->dA, kout + k->offA, s);
+      if (st != FN_OK) return st;
+    }
     // cot g^l_i = cp_i [C^up; C^down]^T  (for the two-electron stream)
     st = gemm_cwt(b.CP, p.d1, p.d1, R, V + (int64_t)3 * din * p.d1, p.d1, 2 * ein, b.CG[l], p.gwp[l], 0, 0, 0, 0,
                   ST_ADJ_LAYERS, s);
@@ -822,15 +922,29 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
       a2.ldcg[l] = p.gwp[l];
     }
     a2.p2 = b.p2;
+    a2.ldp = b.ldp2;
     a2.W = (int)Wc;
     a2.n = p.n;
     a2.n_up = p.nu;
     a2.L = p.L;
     a2.d2 = p.d2;
     a2.part = b.part2;
+    const KfacBlk* k0 = kout ? kblk(1, 0) : nullptr;
+    if (k0) {
+      // the pair blocks are contiguous in the output, A then G per layer,
+      // as the KFAC columns of the partial rows
+      a2.kfac = 1;
+      a2.sc = b.sc;
+      for (int l = 0; l + 1 < p.L; ++l) a2.k_off[l] = b.p2 + (kblk(1, l)->offA - k0->offA);
+    }
     FN_T(ST_ADJ_TWO_E, launch_adj_two_electron(a2, s));
-    FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part2, adj_two_electron_rows((int)Wc, p.n, p.d2), (int)b.p2, b.p2, b.tmp,
-                                          grad + p.offW2[0], kRowChunk, s));
+    const int rows2 = adj_two_electron_rows((int)Wc, p.n, p.d2);
+    if (grad)
+      FN_T(ST_ADJ_REDUCE,
+           launch_rowsum_add(b.part2, rows2, (int)b.p2, b.ldp2, b.tmp, grad + p.offW2[0], kRowChunk, s));
+    if (k0)
+      FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part2 + b.p2, rows2, (int)b.kcols, b.ldp2, b.tmp, kout + k0->offA,
+                                            kRowChunk, s));
   }
   return FN_OK;
 }
@@ -838,17 +952,22 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
 // the whole adjoint over all chunks: grad = sum_w cot[w] d log|psi_w| / d theta.
 // cot_all: per-walker cotangents [W], or nullptr with e_loc/stats for the
 // VMC estimator ((E_L - mean) / W, computed chunk by chunk on the device).
+// kfac_w (with kout): the KFAC statistics with walker weights kfac_w
+// instead of a gradient (grad, cot_all, e_loc and stats unused)
 static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const float* nuc_pos, const float* nuc_charge,
                              const float* params, const float* cot_all, const float* e_loc, const double* stats,
-                             float* grad, void* ws, size_t ws_bytes, hipStream_t s) {
+                             float* grad, void* ws, size_t ws_bytes, hipStream_t s, const float* kfac_w = nullptr,
+                             float* kout = nullptr) {
   // the adjoint runs in float32 / split bfloat16 only
   if (p.f64) return FN_ERR_UNSUPPORTED;
-  const int64_t chunk = max_chunk(p, FN_ENTRY_GRAD_LOGPSI, ws_bytes, W);
+  const bool kfac = kout != nullptr;
+  const int entry = kfac ? FN_ENTRY_KFAC : FN_ENTRY_GRAD_LOGPSI;
+  const int64_t chunk = max_chunk(p, entry, ws_bytes, W);
   if (chunk < 1) return FN_ERR_WORKSPACE;
   Carver cv{(char*)ws, 0};
   void* pk = cv.take((size_t)p.pk_total * p.act);
   AdjBufs b;
-  carve_adjoint(p, chunk, cv, b);
+  carve_adjoint(p, chunk, cv, b, kfac);
   fn_status st = pack(p, params, pk, s);
   if (st != FN_OK) return st;
   // orbital weights with zero-padded columns, float32, rows as stored
@@ -862,15 +981,27 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
     }
     if (!it.empty()) FN_T(ST_PACK, launch_pack_weights(false, params, b.wo[0], 0, it.data(), (int)(it.size() / 11), s));
   }
-  FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+  if (kfac) {
+    int64_t total = 0;
+    kfac_blocks(p, &total);
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(kout, total, 0.0f, s));
+  } else {
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+  }
   for (int64_t w0 = 0; w0 < W; w0 += chunk) {
     const int64_t wc = std::min<int64_t>(chunk, W - w0);
     const float* x = pos + w0 * p.n3;
     st = forward_store(p, wc, x, nuc_pos, nuc_charge, params, pk, b, s);
     if (st != FN_OK) return st;
-    const float* cot = cot_all ? cot_all + w0 : b.cot;
-    if (!cot_all) FN_T(ST_ADJ_REDUCE, launch_cot_from_stats(e_loc + w0, (int)wc, stats, W, b.cot, s));
-    st = backward(p, wc, x, nuc_pos, params, cot, b, grad, s);
+    if (kfac) {
+      // cotangents sqrt(c_w): every pre-activation cotangent then carries sqrt(c_w)
+      FN_T(ST_ADJ_REDUCE, launch_kfac_sqrt_weights(kfac_w + w0, (int)wc, b.sc, s));
+      st = backward(p, wc, x, nuc_pos, params, b.sc, b, nullptr, s, kout);
+    } else {
+      const float* cot = cot_all ? cot_all + w0 : b.cot;
+      if (!cot_all) FN_T(ST_ADJ_REDUCE, launch_cot_from_stats(e_loc + w0, (int)wc, stats, W, b.cot, s));
+      st = backward(p, wc, x, nuc_pos, params, cot, b, grad, s);
+    }
     if (st != FN_OK) return st;
   }
   return FN_OK;
@@ -955,7 +1086,7 @@ fn_status ferminet_workspace_bytes(const fn_config* cfg, int32_t chunk_walkers, 
   fn_status st = make_plan(cfg, p);
   if (st != FN_OK) return st;
   if (!bytes) return FN_ERR_NULL;
-  if (chunk_walkers < 1 || entry < 0 || entry > 3) return FN_ERR_ARG;
+  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_KFAC) return FN_ERR_ARG;
   *bytes = chunk_bytes(p, entry, chunk_walkers);
   return FN_OK;
 }
@@ -1095,6 +1226,51 @@ fn_status ferminet_grad_logpsi(const fn_config* cfg, int32_t W, const float* pos
   }
   return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, cotangent, nullptr, nullptr, grad, workspace,
                      workspace_bytes, stream);
+}
+
+fn_status ferminet_kfac_factors(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                const float* nuc_pos, const float* nuc_charge, const float* params,
+                                const float* weights, float* factors, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+  Plan p;
+  fn_status st = check_common(cfg, W, pos, spins, nuc_pos, nuc_charge, params, workspace, p);
+  if (st != FN_OK) return st;
+  if (!weights || !factors) return FN_ERR_NULL;
+  if (p.f64) return FN_ERR_UNSUPPORTED;
+  if (W == 0) {
+    int64_t total = 0;
+    kfac_blocks(p, &total);
+    const hipStream_t s = stream;
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(factors, total, 0.0f, s));
+    return FN_OK;
+  }
+  return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, nullptr, nullptr, nullptr, nullptr, workspace,
+                     workspace_bytes, stream, weights, factors);
+}
+
+fn_status ferminet_kfac_layout(const fn_config* cfg, fn_kfac_block* out, int32_t cap, int32_t* n_out,
+                               int64_t* total) {
+  Plan p;
+  fn_status st = make_plan(cfg, p);
+  if (st != FN_OK) return st;
+  if (!n_out || !total || (cap > 0 && !out)) return FN_ERR_NULL;
+  int64_t tot = 0;
+  const std::vector<KfacBlk> v = kfac_blocks(p, &tot);
+  *n_out = (int32_t)v.size();
+  *total = tot;
+  if (cap < (int32_t)v.size()) return FN_ERR_ARG;
+  for (size_t i = 0; i < v.size(); ++i) {
+    fn_kfac_block b;
+    memset(&b, 0, sizeof(b));
+    snprintf(b.name, sizeof(b.name), "%s", v[i].name);
+    b.offset_A = v[i].offA;
+    b.offset_G = v[i].offG;
+    b.dim_A = v[i].dA;
+    b.dim_G = v[i].dG;
+    b.positions = v[i].npos;
+    out[i] = b;
+  }
+  return FN_OK;
 }
 
 fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,

@@ -413,7 +413,8 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
   const int64_t w = blk / ngrp;
   const int i0 = (blk % ngrp) * E;
   const int Rb = min(E, n - i0) * n;  // live pair rows
-  float* part = a.part + (int64_t)blk * a.p2;
+  float* part = a.part + (int64_t)blk * a.ldp;
+  const float cw = a.kfac ? a.sc[w] * a.sc[w] : 0.0f;
   const int TMr = RP / 16, TNd = DM / 16;
   // pair row r = (electron i0 + r / n, partner r % n): one division per row, here
   for (int r = tid; r < RP; r += 256) {
@@ -496,6 +497,54 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
         part[a.p_off[l] + ein * d2 + tid] = tot;
       }
     }
+    if (a.kfac) {
+      // KFAC statistics of this layer: c_w [H 1]^T [H 1] and cp^T cp over
+      // the pair rows (cp already carries sqrt(c_w) through the cotangent)
+      float* kA = part + a.k_off[l];
+      float* kG = kA + (ein + 1) * (ein + 1);
+      for (int t = wave; t < TMk * TMk; t += 4) {
+        const int tm = t / TMk, tn = t % TMk;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < RP; ks += 4)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Hs[(ks + lk) * LD + tm * 16 + lr], Hs[(ks + lk) * LD + tn * 16 + lr],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = tm * 16 + 4 * lk + q, o = tn * 16 + lr;
+          if (k < ein && o < ein) kA[k * (ein + 1) + o] = cw * acc[q];
+        }
+      }
+      for (int t = wave; t < TNd * TNd; t += 4) {
+        const int tm = t / TNd, tn = t % TNd;
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < RP; ks += 4)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Cp[(ks + lk) * LD + tm * 16 + lr], Cp[(ks + lk) * LD + tn * 16 + lr],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = tm * 16 + 4 * lk + q, o = tn * 16 + lr;
+          if (k < d2 && o < d2) kG[k * d2 + o] = acc[q];
+        }
+      }
+      // the bias row and column: c_w sum_rows h, and c_w times the row count
+      {
+        constexpr int NCH = 256 / DM;
+        const int o = tid % DM, ch = tid / DM;
+        float sum = 0.0f;
+        for (int r = ch; r < RP; r += NCH) sum += Hs[r * LD + o];
+        __syncthreads();
+        red[ch * DM + o] = sum;
+        __syncthreads();
+        if (tid < ein) {
+          float tot = 0.0f;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) tot += red[c * DM + tid];
+          kA[tid * (ein + 1) + ein] = cw * tot;
+          kA[ein * (ein + 1) + tid] = cw * tot;
+        }
+        if (tid == 0) kA[ein * (ein + 1) + ein] = cw * (float)Rb;
+      }
+    }
     // Ct <- cp W^T (+ Ct when widths match) + mean-field cotangent of layer l
     // (each element read and written by one lane: in place)
     const bool res = ein == d2;
@@ -549,6 +598,70 @@ hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s) {
   if (a.d2 > 64) return hipErrorInvalidValue;
   const int dm = adj2e_dm(a.d2);
   return dm == 16 ? run_adj2e<16>(a, s) : dm == 32 ? run_adj2e<32>(a, s) : run_adj2e<64>(a, s);
+}
+
+// ---------------------------------------------------------- KFAC inputs
+__global__ void kfac_sqrt_weights_kernel(const float* c, int Wc, float* sc) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < Wc) sc[w] = sqrtf(fmaxf(c[w], 0.0f));
+}
+
+hipError_t launch_kfac_sqrt_weights(const float* c, int Wc, float* sc, hipStream_t s) {
+  if (Wc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kfac_sqrt_weights_kernel, dim3((Wc + 255) / 256), dim3(256), 0, s, c, Wc, sc);
+  return hipGetLastError();
+}
+
+// one workgroup per row r = w n + i
+__global__ __launch_bounds__(256) void kfac_aug_layer_kernel(const float* H, int ldh, int din, const float* Hbar,
+                                                             int dinp, const float* G, int ldg, int ein,
+                                                             const float* sc, int n, int ldo, float* out) {
+  const int64_t r = blockIdx.x;
+  const int w = (int)(r / n);
+  const float s = sc[w];
+  const float* h = H + r * ldh;
+  const float* hb = Hbar + (int64_t)w * 2 * dinp;
+  const float* g = G + r * ldg;
+  float* o = out + r * ldo;
+  for (int c = threadIdx.x; c < ldo; c += blockDim.x) {
+    float v = 0.0f;
+    if (c < din) v = h[c];
+    else if (c < 2 * din) v = hb[c - din];
+    else if (c < 3 * din) v = hb[dinp + c - 2 * din];
+    else if (c < 3 * din + 2 * ein) v = g[c - 3 * din];
+    else if (c == 3 * din + 2 * ein) v = 1.0f;
+    o[c] = s * v;
+  }
+}
+
+hipError_t launch_kfac_aug_layer(const float* H, int ldh, int din, const float* Hbar, int dinp, const float* G,
+                                 int ldg, int ein, const float* sc, int Wc, int n, int ldo, float* out, hipStream_t s) {
+  const int64_t R = (int64_t)Wc * n;
+  if (R <= 0) return hipSuccess;
+  if (ldo < 3 * din + 2 * ein + 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kfac_aug_layer_kernel, dim3((unsigned)R), dim3(256), 0, s, H, ldh, din, Hbar, dinp, G, ldg, ein,
+                     sc, n, ldo, out);
+  return hipGetLastError();
+}
+
+// one workgroup per row r = w n_a + j
+__global__ __launch_bounds__(256) void kfac_aug_orbital_kernel(const float* H, int ldh, int d1, const float* sc, int n,
+                                                               int j0, int na, int ldo, float* out) {
+  const int64_t r = blockIdx.x;
+  const int w = (int)(r / na), j = (int)(r - (int64_t)w * na);
+  const float s = sc[w];
+  const float* h = H + ((int64_t)w * n + j0 + j) * ldh;
+  float* o = out + r * ldo;
+  for (int c = threadIdx.x; c < ldo; c += blockDim.x) o[c] = c < d1 ? s * h[c] : (c == d1 ? s : 0.0f);
+}
+
+hipError_t launch_kfac_aug_orbital(const float* H, int ldh, int d1, const float* sc, int Wc, int n, int j0, int na,
+                                   int ldo, float* out, hipStream_t s) {
+  const int64_t R = (int64_t)Wc * na;
+  if (R <= 0) return hipSuccess;
+  if (ldo < d1 + 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kfac_aug_orbital_kernel, dim3((unsigned)R), dim3(256), 0, s, H, ldh, d1, sc, n, j0, na, ldo, out);
+  return hipGetLastError();
 }
 
 // ----------------------------------------- energy statistics and cotangent

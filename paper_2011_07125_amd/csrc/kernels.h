@@ -165,12 +165,29 @@ struct Adj2eArgs {
   const float* CG[8];          // cot g^l_i [w n + i][ldcg_l] (columns a ein_l + o)
   int ldcg[8];
   int W, n, n_up, L, d2;
-  float* part;                 // [adj_two_electron_rows(W, n, d2)][p2]
+  float* part;                 // [adj_two_electron_rows(W, n, d2)][ldp]
+  int64_t ldp;                 // floats per partial row (>= p2)
+  // KFAC statistics (kfac != 0): per partial row, for each layer l < L-1,
+  // the (ein_l + 1)^2 block sum_pairs c_w a~ a~^T (a~ = [h_ij; 1]) at column
+  // k_off[l], then the d2^2 block sum_pairs cp cp^T; sc[w] = sqrt(c_w)
+  int kfac;
+  int64_t k_off[8];
+  const float* sc;
 };
 hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s);
 // rows of parameter partials the two-electron backward writes (<= W n)
 int adj_two_electron_rows(int W, int n, int d2);
 hipError_t launch_energy_stats(const float* e, int W, double* stats, float* cot, hipStream_t s);
+// KFAC statistics: sc[w] = sqrt(max(c_w, 0)); the inputs a~ of a dense
+// layer materialised row by row and scaled by sc[w]:
+//   one-electron layer: out[w n + i] = sc[w] [h_i (din), hbar^up_w (din),
+//     hbar^down_w (din), g_i (2 ein), 1, 0 ...]   (ldo columns)
+//   orbitals of one spin: out[w n_a + j] = sc[w] [h^L_{j0 + j} (d1), 1, 0 ...]
+hipError_t launch_kfac_sqrt_weights(const float* c, int Wc, float* sc, hipStream_t s);
+hipError_t launch_kfac_aug_layer(const float* H, int ldh, int din, const float* Hbar, int dinp, const float* G,
+                                 int ldg, int ein, const float* sc, int Wc, int n, int ldo, float* out, hipStream_t s);
+hipError_t launch_kfac_aug_orbital(const float* H, int ldh, int d1, const float* sc, int Wc, int n, int j0, int na,
+                                   int ldo, float* out, hipStream_t s);
 hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s);
 
 }  // namespace fn

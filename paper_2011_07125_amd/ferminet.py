@@ -20,7 +20,7 @@ FN_PREC_FP32, FN_PREC_BF16, FN_PREC_FP32_FP64DET, FN_PREC_FP64 = 0, 1, 2, 3
 FN_ENV_ISOTROPIC, FN_ENV_FULL = 0, 1
 ENVELOPES = {"isotropic": FN_ENV_ISOTROPIC, "full": FN_ENV_FULL}
 PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
-FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC = 0, 1, 2, 3
+FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC, FN_ENTRY_KFAC = 0, 1, 2, 3, 4
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
           5: "FN_ERR_UNSUPPORTED", 6: "FN_ERR_HIP", 7: "FN_ERR_ARG"}
 
@@ -41,10 +41,16 @@ class fn_param_block(ctypes.Structure):
                 ("cols", ctypes.c_int64)]
 
 
+class fn_kfac_block(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 16), ("offset_A", ctypes.c_int64), ("offset_G", ctypes.c_int64),
+                ("dim_A", ctypes.c_int32), ("dim_G", ctypes.c_int32), ("positions", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 EXPORTS = ("ferminet_status_string", "ferminet_param_count", "ferminet_param_layout", "ferminet_workspace_bytes",
            "ferminet_logpsi", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
-           "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_stage_timing", "ferminet_stage_times",
-           "ferminet_stage_name")
+           "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
+           "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name")
 
 _LIB = None
 _LOCK = threading.Lock()
@@ -71,6 +77,8 @@ def _lib():
                 lib.ferminet_local_energy.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_grad_logpsi.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
                 lib.vmc_energy_gradient.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, sz, P]
+                lib.ferminet_kfac_factors.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
+                lib.ferminet_kfac_layout.argtypes = [C, P, i32, P, P]
                 lib.vmc_mcmc_step.argtypes = [C, i32, P, P, P, P, P, P, P, i32, f32, u64, u64, P, P, P, P, sz, P]
                 lib.vmc_mcmc_noise.argtypes = [i32, i32, i32, u64, u64, P, P, P]
                 lib.ferminet_stage_timing.argtypes = [i32]
@@ -207,6 +215,41 @@ def ferminet_grad_logpsi(cfg, pos, nuc_pos, nuc_charge, params, cotangent, preci
                                      _ptr(ws), ws.numel(), _stream())
     _check(st, "ferminet_grad_logpsi")
     return grad
+
+
+def kfac_layout(cfg):
+    """[(name, offset_A, dim_A, offset_G, dim_G, positions)] and the total floats."""
+    c = make_config(cfg, "fp32")
+    n = ctypes.c_int32(0)
+    total = ctypes.c_int64(0)
+    buf = (fn_kfac_block * 32)()
+    _check(_lib().ferminet_kfac_layout(ctypes.byref(c), buf, 32, ctypes.byref(n), ctypes.byref(total)),
+           "ferminet_kfac_layout")
+    blocks = [(buf[i].name.decode(), buf[i].offset_A, buf[i].dim_A, buf[i].offset_G, buf[i].dim_G, buf[i].positions)
+              for i in range(n.value)]
+    return blocks, int(total.value)
+
+
+def ferminet_kfac_factors(cfg, pos, nuc_pos, nuc_charge, params, weights, precision=None, ws=None, max_chunk=None):
+    """KFAC statistics of every dense layer -> flat float32 tensor in the
+    layout of kfac_layout (each block's A then G)."""
+    W = pos.shape[0]
+    c = make_config(cfg, precision)
+    _, total = kfac_layout(cfg)
+    out = torch.empty(total, dtype=torch.float32, device=pos.device)
+    ws = workspace(cfg, W, FN_ENTRY_KFAC, precision, pos.device, max_chunk) if ws is None else ws
+    st = _lib().ferminet_kfac_factors(ctypes.byref(c), W, _ptr(_prep(pos)), _spins(cfg), _ptr(_prep(nuc_pos)),
+                                      _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(_prep(weights)), _ptr(out),
+                                      _ptr(ws), ws.numel(), _stream())
+    _check(st, "ferminet_kfac_factors")
+    return out
+
+
+def kfac_split(cfg, flat):
+    """{name: (A, G)} views of the output of ferminet_kfac_factors."""
+    blocks, _ = kfac_layout(cfg)
+    return {name: (flat[oa:oa + da * da].view(da, da), flat[og:og + dg * dg].view(dg, dg))
+            for name, oa, da, og, dg, _ in blocks}
 
 
 def vmc_energy_gradient(cfg, pos, nuc_pos, nuc_charge, params, e_loc, precision=None, ws=None, max_chunk=None):
