@@ -324,3 +324,44 @@ def kfac_factors(cfg, pos, nuc_pos, params, weights, threads=None):
         G = np.einsum("w,wri,wrj->ij", c, g, g)
         out.append((name, A, G))
     return out
+
+
+def kfac_damping_pi(A, G):
+    """pi of the factored Tikhonov damping (Martens and Grosse 2015, sec. 6.3):
+    sqrt((tr A / dim A) / (tr G / dim G)), 1 when either trace vanishes."""
+    ta, tg = np.trace(A) / A.shape[0], np.trace(G) / G.shape[0]
+    return float(np.sqrt(ta / tg)) if ta > 0 and tg > 0 else 1.0
+
+
+def kfac_precondition(cfg, factors, grad, damping):
+    """The KFAC step direction: for every dense layer with factors (A, G) and
+    gradient block M = [weights; bias] ((d_in + 1) x d_out, as stored in
+    the parameter layout),
+        X = (A + pi sqrt(lambda) I)^-1 M (G + sqrt(lambda) / pi I)^-1
+    (factored Tikhonov damping); the envelope parameters keep their
+    gradient.  factors: [(name, A, G)] as kfac_factors returns them."""
+    out = np.array(grad, dtype=np.float64, copy=True)
+    offs = _kfac_param_offsets(cfg)
+    s = np.sqrt(damping)
+    for name, A, G in factors:
+        off = offs[name]
+        dA, dG = A.shape[0], G.shape[0]
+        M = out[off:off + dA * dG].reshape(dA, dG)
+        pi = kfac_damping_pi(A, G)
+        Ad = A + pi * s * np.eye(dA)
+        Gd = G + (s / pi) * np.eye(dG)
+        X = np.linalg.solve(Gd.T, np.linalg.solve(Ad, M).T).T
+        out[off:off + dA * dG] = X.reshape(-1)
+    return out
+
+
+def _kfac_param_offsets(cfg):
+    """Offset of each dense layer's [weights; bias] in the parameter layout
+    (the weight block, immediately followed by its bias)."""
+    off = param_offsets(cfg)  # V_l, b_l per layer; W_l, c_l per pair layer; w_a, g_a per spin; ...
+    L = cfg["n_layers"]
+    res = {}
+    for name, kind, l, din, dout, npos in kfac_blocks(cfg):
+        idx = 2 * l if kind == 0 else (2 * L + 2 * l if kind == 1 else 2 * L + 2 * (L - 1) + 2 * l)
+        res[name] = int(off[idx])
+    return res

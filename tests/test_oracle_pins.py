@@ -696,3 +696,43 @@ def test_kfac_statistics_reproduce_the_parameter_gradient():
             # the bias entry of A is sum_w c_w times the number of positions
             npos = [b[5] for b in O.kfac_blocks(cfg) if b[0] == name][0]
             assert abs(A[-1, -1] - c.sum() * npos) < 1e-12 * npos
+
+
+def test_kfac_precondition_is_the_kronecker_solve():
+    """The KFAC step direction (Martens and Grosse 2015; factored Tikhonov
+    damping): per dense layer, X = (A + pi s I)^-1 M (G + s / pi I)^-1 with
+    s = sqrt(lambda).  Pinned against the solve of the full Kronecker system
+    (A_d kron G_d) vec(X) = vec(M) (row-major vec, symmetric G_d) and the
+    closed form for scaled identities; the envelope parameters keep their
+    gradient."""
+    w = small_workload(W=3)
+    cfg = w["cfg"]
+    c = np.array([0.2, 0.5, 0.3])
+    facs = O.kfac_factors(cfg, w["pos"], w["nuc_pos"], w["params"], c)
+    rng = np.random.default_rng(4)
+    P = I.param_offsets(cfg)["_total"]
+    grad = rng.normal(size=P)
+    lam = 1e-2
+    upd = O.kfac_precondition(cfg, facs, grad, lam)
+    offs = O._kfac_param_offsets(cfg)
+    covered = np.zeros(P, dtype=bool)
+    for name, A, G in facs:
+        dA, dG = A.shape[0], G.shape[0]
+        off = offs[name]
+        covered[off:off + dA * dG] = True
+        pi = O.kfac_damping_pi(A, G)
+        s = np.sqrt(lam)
+        Ad, Gd = A + pi * s * np.eye(dA), G + s / pi * np.eye(dG)
+        ref = np.linalg.solve(np.kron(Ad, Gd), grad[off:off + dA * dG])
+        np.testing.assert_allclose(upd[off:off + dA * dG], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max(),
+                                   err_msg=name)
+    # envelope parameters (the only ones outside the dense layers) unchanged
+    assert np.array_equal(upd[~covered], grad[~covered])
+    assert not covered[I.param_offsets(cfg)["pi0"][0]]
+    # scaled identities: X = M / ((a + pi s)(g + s / pi)), pi = sqrt(a / g)
+    a_, g_ = 3.0, 0.5
+    fac = [(name, a_ * np.eye(A.shape[0]), g_ * np.eye(G.shape[0])) for name, A, G in facs]
+    upd2 = O.kfac_precondition(cfg, fac, grad, lam)
+    pi = np.sqrt(a_ / g_)
+    scale = 1.0 / ((a_ + pi * np.sqrt(lam)) * (g_ + np.sqrt(lam) / pi))
+    np.testing.assert_allclose(upd2[covered], grad[covered] * scale, rtol=1e-12)
