@@ -246,6 +246,18 @@ def main():
         ms_k = t0.elapsed_time(t1) / args.steps
         res["kfac_factors_bf16"] = {"ms_per_call": ms_k, "value": W / (ms_k * 1e-3), "unit": "walkers/s",
                                     "floats": F.kfac_layout(cfg)[1]}
+        # the step direction from those factors (float64 Cholesky and solves)
+        fac = F.ferminet_kfac_factors(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], c,
+                                      precision="bf16")
+        g = torch.randn(d["params"].numel(), device="cuda")
+        F.ferminet_kfac_precondition(cfg, fac, g, 1e-3)
+        torch.cuda.synchronize()
+        t0.record()
+        for i in range(3):
+            F.ferminet_kfac_precondition(cfg, fac, g, 1e-3)
+        t1.record()
+        torch.cuda.synchronize()
+        res["kfac_precondition"] = {"ms_per_call": t0.elapsed_time(t1) / 3, "damping": 1e-3}
     main_fl, mf_fl = layer_flops(cfg, W, T)
     # dominant kernel: the one-electron layer GEMM of the jet pass (L
     # launches per local-energy call, layer 0 included).  Its arithmetic

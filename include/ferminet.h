@@ -162,7 +162,8 @@ typedef enum {
   FN_ENTRY_LOCAL_ENERGY = 1,
   FN_ENTRY_GRAD_LOGPSI = 2,
   FN_ENTRY_MCMC = 3,
-  FN_ENTRY_KFAC = 4
+  FN_ENTRY_KFAC = 4,
+  FN_ENTRY_KFAC_PRECONDITION = 5 /* chunk_walkers is ignored */
 } fn_entry;
 
 /* One dense layer's Kronecker factors in the output of ferminet_kfac_factors. */
@@ -269,6 +270,24 @@ fn_status ferminet_kfac_factors(const fn_config* cfg, int32_t W, const float* po
  * if cap is too small. */
 fn_status ferminet_kfac_layout(const fn_config* cfg, fn_kfac_block* out, int32_t cap, int32_t* n_out,
                                int64_t* total);
+
+/* The KFAC step direction (Martens and Grosse 2015, factored Tikhonov
+ * damping) from the factors of ferminet_kfac_factors: for every dense layer
+ * with gradient block M = [W; b] ((dim_A) x (dim_G) floats at the weight
+ * block's offset in the parameter layout, the bias row last),
+ *   X = (A + pi s I)^-1 M (G + s / pi I)^-1,  s = sqrt(damping),
+ *   pi = sqrt((tr A / dim_A) / (tr G / dim_G))  (1 if a trace is not positive)
+ * computed in float64 (Cholesky factors of the damped factors, triangular
+ * solves); the envelope parameters (pi, sigma), which belong to no dense
+ * layer, keep their gradient.
+ *   factors  [total] float32 in (ferminet_kfac_layout)
+ *   grad     [P] float32 in; update [P] float32 out (may not alias grad)
+ *   damping  lambda > 0 and finite, else FN_ERR_ARG
+ * The factors must be positive semi-definite (as ferminet_kfac_factors
+ * returns them); the damping then makes every Cholesky pivot positive.
+ * Uses the FN_ENTRY_KFAC_PRECONDITION workspace. */
+fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors, const float* grad, float damping,
+                                     float* update, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* n_steps Metropolis random-walk steps sampling psi^2 (Eq. (3)), all
  * electrons moved at once:

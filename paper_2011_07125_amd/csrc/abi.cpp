@@ -146,7 +146,7 @@ enum Mode { VALUE = 0, JET = 1 };
 enum Stage {
   ST_PACK, ST_FEATURES, ST_TWO_E, ST_MEANFIELD, ST_GEMM_MF, ST_GEMM_LAYER, ST_GEMM_ORB, ST_DET, ST_COMBINE,
   ST_PROPOSE, ST_ACCEPT, ST_ADJ_FWD, ST_ADJ_DET, ST_ADJ_ORB, ST_ADJ_LAYERS, ST_ADJ_TWO_E, ST_ADJ_REDUCE,
-  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_COUNT
+  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_KFAC, ST_COUNT
 };
 
 struct Bufs {
@@ -393,8 +393,35 @@ static void carve_rescue(const Plan& p, int64_t Wc, Carver& cv, RescueBufs& r) {
   for (int q = 0; q < 5; ++q) r.out[q] = (float*)cv.take((size_t)d.R * 4);
 }
 
+// float64 scratch of the KFAC step direction: per dense layer the damped
+// factors and two copies of its gradient block
+static void carve_kfac_solve(const Plan& p, Carver& cv, KfacPrepArgs& a) {
+  const std::vector<KfacBlk> kb = kfac_blocks(p, nullptr);
+  a.nb = (int)kb.size();
+  char* base = cv.base;
+  auto take = [&](int64_t doubles) { return (int64_t)(((char*)cv.take((size_t)doubles * 8) - base) / 8); };
+  for (int b = 0; b < a.nb; ++b) {
+    const KfacBlk& k = kb[b];
+    a.dA[b] = k.dA;
+    a.dG[b] = k.dG;
+    a.offA[b] = k.offA;
+    a.offG[b] = k.offG;
+    a.offP[b] = k.kind == 0 ? p.offV[k.layer] : k.kind == 1 ? p.offW2[k.layer] : p.offw[k.layer];
+    a.offLA[b] = take((int64_t)k.dA * k.dA);
+    a.offLG[b] = take((int64_t)k.dG * k.dG);
+    a.offY[b] = take((int64_t)k.dA * k.dG);
+    a.offYt[b] = take((int64_t)k.dA * k.dG);
+  }
+}
+
 static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   Carver cv{nullptr, 0};
+  if (entry == FN_ENTRY_KFAC_PRECONDITION) {
+    KfacPrepArgs a;
+    Carver c0{(char*)nullptr, 0};
+    carve_kfac_solve(p, c0, a);
+    return c0.used;
+  }
   Bufs b;
   cv.take((size_t)p.pk_total * p.act);
   if (entry == FN_ENTRY_GRAD_LOGPSI || entry == FN_ENTRY_KFAC) {
@@ -437,7 +464,7 @@ static const char* kStageNames[ST_COUNT] = {
     "pack_weights", "features",  "two_electron", "meanfield",    "gemm_meanfield", "gemm_layer",
     "gemm_orbital", "det",       "combine",      "mcmc_propose", "mcmc_accept",    "adj_forward",
     "adj_det",      "adj_orbital", "adj_layers", "adj_two_electron", "adj_reduce",     "gemm_layer_value",
-    "rescue_fp64"};
+    "rescue_fp64",  "kfac_precondition"};
 static std::mutex g_time_mu;
 static bool g_timing = false;
 struct StageRec {
@@ -1086,7 +1113,7 @@ fn_status ferminet_workspace_bytes(const fn_config* cfg, int32_t chunk_walkers, 
   fn_status st = make_plan(cfg, p);
   if (st != FN_OK) return st;
   if (!bytes) return FN_ERR_NULL;
-  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_KFAC) return FN_ERR_ARG;
+  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_KFAC_PRECONDITION) return FN_ERR_ARG;
   *bytes = chunk_bytes(p, entry, chunk_walkers);
   return FN_OK;
 }
@@ -1246,6 +1273,63 @@ fn_status ferminet_kfac_factors(const fn_config* cfg, int32_t W, const float* po
   }
   return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, nullptr, nullptr, nullptr, nullptr, workspace,
                      workspace_bytes, stream, weights, factors);
+}
+
+fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors, const float* grad, float damping,
+                                     float* update, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  Plan p;
+  fn_status st = make_plan(cfg, p);
+  if (st != FN_OK) return st;
+  if (!factors || !grad || !update || !workspace) return FN_ERR_NULL;
+  if (!(damping > 0.0f) || !std::isfinite(damping)) return FN_ERR_ARG;
+  if (update == grad) return FN_ERR_ARG;
+  if (((uintptr_t)workspace & 255) != 0) return FN_ERR_WORKSPACE;
+  KfacPrepArgs a;
+  memset(&a, 0, sizeof(a));
+  Carver cv{(char*)workspace, 0};
+  carve_kfac_solve(p, cv, a);
+  if (a.nb > KFAC_MAX_BLOCKS) return FN_ERR_UNSUPPORTED;
+  if (workspace_bytes < cv.used) return FN_ERR_WORKSPACE;
+  // every dense layer's bias row directly follows its weights
+  for (int l = 0; l < p.L; ++l)
+    if (p.offb[l] != p.offV[l] + (int64_t)(3 * p.din[l] + 2 * p.ein[l]) * p.d1) return FN_ERR_CONFIG;
+  a.factors = factors;
+  a.grad = grad;
+  a.update = update;
+  a.S = (double*)workspace;
+  a.sqrt_damping = std::sqrt((double)damping);
+  const hipStream_t s = stream;
+  FN_T(ST_KFAC, launch_copy_f32(grad, update, p.P, s));
+  FN_T(ST_KFAC, launch_kfac_prep(a, s));
+  SpdBatch ch;
+  memset(&ch, 0, sizeof(ch));
+  for (int b = 0; b < a.nb; ++b) {
+    ch.n[ch.nm] = a.dA[b];
+    ch.off[ch.nm++] = a.offLA[b];
+    ch.n[ch.nm] = a.dG[b];
+    ch.off[ch.nm++] = a.offLG[b];
+  }
+  FN_T(ST_KFAC, launch_spd_cholesky(ch, a.S, s));
+  SpdBatch sa, sg;
+  memset(&sa, 0, sizeof(sa));
+  memset(&sg, 0, sizeof(sg));
+  for (int b = 0; b < a.nb; ++b) {
+    sa.n[b] = a.dA[b];
+    sa.m[b] = a.dG[b];
+    sa.off[b] = a.offLA[b];
+    sa.offB[b] = a.offY[b];
+    sg.n[b] = a.dG[b];
+    sg.m[b] = a.dA[b];
+    sg.off[b] = a.offLG[b];
+    sg.offB[b] = a.offYt[b];
+  }
+  sa.nm = sg.nm = a.nb;
+  // Y = A_d^-1 M; Yt = Y^T; Yt = G_d^-1 Yt = (Y G_d^-1)^T
+  FN_T(ST_KFAC, launch_spd_solve(sa, a.S, s));
+  FN_T(ST_KFAC, launch_kfac_transpose(a, s));
+  FN_T(ST_KFAC, launch_spd_solve(sg, a.S, s));
+  FN_T(ST_KFAC, launch_kfac_write(a, s));
+  return FN_OK;
 }
 
 fn_status ferminet_kfac_layout(const fn_config* cfg, fn_kfac_block* out, int32_t cap, int32_t* n_out,

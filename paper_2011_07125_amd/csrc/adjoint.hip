@@ -169,7 +169,9 @@ int64_t atb_part_floats(int K1max, int Nmax) {
   return (int64_t)(ATB_BLOCKS + ((K1max + 63) / 64) * ((Nmax + 63) / 64)) * 64 * 64;
 }
 
-// VEC: K1, N, ldx, xcol, ldy multiples of 4 (one 16-byte load per operand)
+// VEC: ldx, xcol, ldy multiples of 4 and 16-byte aligned bases (one 16-byte
+// load per operand; the last vector of a row is read element by element
+// when K1 or N is not a multiple of 4)
 template <bool VEC>
 __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_split) {
   __shared__ float Xs[2][16][64 + 4];
@@ -195,13 +197,19 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
     const float* xp = a.X + mr * a.ldx + a.xcol + k0 + lc;
     const float* yp = a.Y + r * a.ldy + n0 + lc;
     if constexpr (VEC) {
-      if (kin) {
+      if (k0 + lc + 3 < a.K1) {
         const float4 v = *reinterpret_cast<const float4*>(xp);
         xv[0] = v.x, xv[1] = v.y, xv[2] = v.z, xv[3] = v.w;
+      } else if (kin) {
+        for (int q = 0; q < 4; ++q)
+          if (k0 + lc + q < a.K1) xv[q] = xp[q];
       }
-      if (nin) {
+      if (n0 + lc + 3 < a.N) {
         const float4 v = *reinterpret_cast<const float4*>(yp);
         yv[0] = v.x, yv[1] = v.y, yv[2] = v.z, yv[3] = v.w;
+      } else if (nin) {
+        for (int q = 0; q < 4; ++q)
+          if (n0 + lc + q < a.N) yv[q] = yp[q];
       }
     } else {
 #pragma unroll
@@ -247,8 +255,8 @@ hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
   const int sp = atb_splits(a.R, a.K1, a.N);
   const int64_t rps = ((a.R + sp - 1) / sp + 15) / 16 * 16;
   dim3 grid((a.K1 + 63) / 64, (a.N + 63) / 64, sp);
-  const bool vec = a.K1 % 4 == 0 && a.N % 4 == 0 && a.ldx % 4 == 0 && a.xcol % 4 == 0 && a.ldy % 4 == 0 &&
-                   ((uintptr_t)a.X % 16) == 0 && ((uintptr_t)a.Y % 16) == 0;
+  const bool vec = a.ldx % 4 == 0 && a.xcol % 4 == 0 && a.ldy % 4 == 0 && ((uintptr_t)a.X % 16) == 0 &&
+                   ((uintptr_t)a.Y % 16) == 0;
   if (vec) hipLaunchKernelGGL(atb_kernel<true>, grid, dim3(256), 0, s, a, rps);
   else hipLaunchKernelGGL(atb_kernel<false>, grid, dim3(256), 0, s, a, rps);
   return hipGetLastError();

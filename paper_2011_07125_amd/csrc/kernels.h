@@ -188,6 +188,32 @@ hipError_t launch_kfac_aug_layer(const float* H, int ldh, int din, const float* 
                                  int ldg, int ein, const float* sc, int Wc, int n, int ldo, float* out, hipStream_t s);
 hipError_t launch_kfac_aug_orbital(const float* H, int ldh, int d1, const float* sc, int Wc, int n, int j0, int na,
                                    int ldo, float* out, hipStream_t s);
+
+// ---- KFAC step direction (kfac.hip), float64
+constexpr int KFAC_MAX_BLOCKS = 32, KFAC_MAX_MATS = 64;
+struct KfacPrepArgs {
+  int nb;                                           // dense layers
+  int64_t offA[KFAC_MAX_BLOCKS], offG[KFAC_MAX_BLOCKS];  // in the factors (floats)
+  int64_t offP[KFAC_MAX_BLOCKS];                    // [weights; bias] in the parameter layout
+  int64_t offLA[KFAC_MAX_BLOCKS], offLG[KFAC_MAX_BLOCKS], offY[KFAC_MAX_BLOCKS], offYt[KFAC_MAX_BLOCKS];  // in S
+  int dA[KFAC_MAX_BLOCKS], dG[KFAC_MAX_BLOCKS];
+  const float* factors;
+  const float* grad;
+  float* update;
+  double* S;
+  double sqrt_damping;
+};
+// matrices mat: n x n at S + off (row-major), right-hand sides n x m at S + offB
+struct SpdBatch {
+  int nm;
+  int n[KFAC_MAX_MATS], m[KFAC_MAX_MATS];
+  int64_t off[KFAC_MAX_MATS], offB[KFAC_MAX_MATS];
+};
+hipError_t launch_kfac_prep(const KfacPrepArgs& a, hipStream_t s);       // damped factors, M
+hipError_t launch_spd_cholesky(const SpdBatch& bt, double* S, hipStream_t s);  // in place, lower
+hipError_t launch_spd_solve(const SpdBatch& bt, double* S, hipStream_t s);     // B <- (L L^T)^-1 B
+hipError_t launch_kfac_transpose(const KfacPrepArgs& a, hipStream_t s);  // Y -> Yt
+hipError_t launch_kfac_write(const KfacPrepArgs& a, hipStream_t s);      // Yt^T -> update
 hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s);
 
 }  // namespace fn

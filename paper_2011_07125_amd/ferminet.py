@@ -21,6 +21,7 @@ FN_ENV_ISOTROPIC, FN_ENV_FULL = 0, 1
 ENVELOPES = {"isotropic": FN_ENV_ISOTROPIC, "full": FN_ENV_FULL}
 PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
 FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC, FN_ENTRY_KFAC = 0, 1, 2, 3, 4
+FN_ENTRY_KFAC_PRECONDITION = 5
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
           5: "FN_ERR_UNSUPPORTED", 6: "FN_ERR_HIP", 7: "FN_ERR_ARG"}
 
@@ -50,6 +51,7 @@ class fn_kfac_block(ctypes.Structure):
 EXPORTS = ("ferminet_status_string", "ferminet_param_count", "ferminet_param_layout", "ferminet_workspace_bytes",
            "ferminet_logpsi", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
            "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
+           "ferminet_kfac_precondition",
            "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name")
 
 _LIB = None
@@ -79,6 +81,7 @@ def _lib():
                 lib.vmc_energy_gradient.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_kfac_factors.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_kfac_layout.argtypes = [C, P, i32, P, P]
+                lib.ferminet_kfac_precondition.argtypes = [C, P, P, f32, P, P, sz, P]
                 lib.vmc_mcmc_step.argtypes = [C, i32, P, P, P, P, P, P, P, i32, f32, u64, u64, P, P, P, P, sz, P]
                 lib.vmc_mcmc_noise.argtypes = [i32, i32, i32, u64, u64, P, P, P]
                 lib.ferminet_stage_timing.argtypes = [i32]
@@ -242,6 +245,17 @@ def ferminet_kfac_factors(cfg, pos, nuc_pos, nuc_charge, params, weights, precis
                                       _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(_prep(weights)), _ptr(out),
                                       _ptr(ws), ws.numel(), _stream())
     _check(st, "ferminet_kfac_factors")
+    return out
+
+
+def ferminet_kfac_precondition(cfg, factors, grad, damping, ws=None):
+    """The KFAC step direction from the factors of ferminet_kfac_factors -> [P] float32."""
+    c = make_config(cfg, "fp32")
+    out = torch.empty_like(grad, dtype=torch.float32)
+    ws = workspace(cfg, 1, FN_ENTRY_KFAC_PRECONDITION, "fp32", grad.device) if ws is None else ws
+    st = _lib().ferminet_kfac_precondition(ctypes.byref(c), _ptr(_prep(factors)), _ptr(_prep(grad)), float(damping),
+                                           _ptr(out), _ptr(ws), ws.numel(), _stream())
+    _check(st, "ferminet_kfac_precondition")
     return out
 
 
