@@ -365,3 +365,67 @@ def _kfac_param_offsets(cfg):
         idx = 2 * l if kind == 0 else (2 * L + 2 * l if kind == 1 else 2 * L + 2 * (L - 1) + 2 * l)
         res[name] = int(off[idx])
     return res
+
+
+# ------------------------------------------------------- VMC iteration
+# One optimisation iteration of the variational energy E[E_L] under psi^2
+# (Eq. (3); Section 2 names KFAC as the optimiser but gives no settings, so
+# the following readings are stated once here):
+#  * sampling: the caller's walkers take n_steps Metropolis steps from
+#    log|psi| at the current parameters;
+#  * local energies are clipped to median +- clip_scale * mean|E_L - median|
+#    (no clipping for clip_scale <= 0) and the gradient is the energy
+#    gradient 2 sum_w (E~_w - mean E~) / W * d log|psi_w| / d theta with the
+#    clipped energies E~;
+#  * the KFAC factors are running averages F <- decay F + (1 - decay) F_batch
+#    with batch weights 1/W (decay = 0 starts them from the batch);
+#  * the step is theta <- theta - lr c X with X the damped KFAC direction of
+#    the gradient and c = min(1, sqrt(C / (lr^2 <X, g>))) (KFAC's norm
+#    constraint C; no constraint for C <= 0 or <X, g> <= 0).
+
+def clip_energies(e, clip_scale):
+    """E_L clipped to median +- clip_scale * (mean absolute deviation from
+    the median); the input itself for clip_scale <= 0."""
+    e = np.asarray(e, dtype=np.float64)
+    if clip_scale <= 0:
+        return e.copy()
+    med = np.median(e)
+    tv = np.mean(np.abs(e - med))
+    return np.clip(e, med - clip_scale * tv, med + clip_scale * tv)
+
+
+def norm_constraint_coefficient(x_dot_g, lr, norm_constraint):
+    """lr * min(1, sqrt(C / (lr^2 <X, g>))): the length of the step along X."""
+    if norm_constraint > 0 and x_dot_g > 0:
+        return lr * min(1.0, float(np.sqrt(norm_constraint / (lr * lr * x_dot_g))))
+    return lr
+
+
+def vmc_train_step(cfg, pos, nuc_pos, nuc_charge, params, factors, n_steps, width, lr, damping, norm_constraint,
+                   decay, clip_scale, noise=None, uniforms=None, seed=0, counter=0, threads=None):
+    """One VMC iteration.  factors: [(name, A, G)] running averages from the
+    previous iteration, or None (then decay is taken as 0).  Returns a dict
+    with the new pos, params and factors and the intermediate results."""
+    params = _d(params)
+    r0 = evaluate(cfg, pos, nuc_pos, nuc_charge, params, energy=False, threads=threads)
+    pos, lp, sg, acc = mcmc(cfg, pos, nuc_pos, params, r0["logpsi"], r0["sign"], n_steps, width, noise, uniforms,
+                            seed, counter, threads)
+    W = pos.shape[0]
+    r = evaluate(cfg, pos, nuc_pos, nuc_charge, params, threads=threads)
+    e = r["e_loc"]
+    ec = clip_energies(e, clip_scale)
+    c = (ec - ec.mean()) / W
+    P = param_count(cfg)
+    per = param_grad(cfg, pos, nuc_pos, params, np.arange(P), threads=threads)
+    g = 2.0 * (c @ per)
+    batch = kfac_factors(cfg, pos, nuc_pos, params, np.full(W, 1.0 / W), threads=threads)
+    if factors is None:
+        new_f = batch
+    else:
+        new_f = [(n, decay * A0 + (1 - decay) * A, decay * G0 + (1 - decay) * G)
+                 for (n, A0, G0), (_, A, G) in zip(factors, batch)]
+    X = kfac_precondition(cfg, new_f, g, damping)
+    q = float(X @ g)
+    coef = norm_constraint_coefficient(q, lr, norm_constraint)
+    return {"pos": pos, "logpsi": lp, "sign": sg, "n_accepted": acc, "e_loc": e, "e_clip": ec, "grad": g,
+            "direction": X, "x_dot_g": q, "coef": coef, "factors": new_f, "params": params - coef * X}

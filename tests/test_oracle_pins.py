@@ -736,3 +736,104 @@ def test_kfac_precondition_is_the_kronecker_solve():
     pi = np.sqrt(a_ / g_)
     scale = 1.0 / ((a_ + pi * np.sqrt(lam)) * (g_ + np.sqrt(lam) / pi))
     np.testing.assert_allclose(upd2[covered], grad[covered] * scale, rtol=1e-12)
+
+
+# ------------------------------------------------------- VMC iteration
+def test_clip_energies_hand_computed_and_equivariant():
+    """Clipping of the local energies (median +- s * mean absolute deviation
+    from the median): a hand-computed case, the identity for s <= 0, and
+    equivariance under shifts and positive scalings of the energies."""
+    e = np.array([-3.0, -1.0, 0.0, 1.0, 100.0])
+    # median 0, mean |e| = 105 / 5 = 21
+    np.testing.assert_array_equal(O.clip_energies(e, 5.0), e)
+    np.testing.assert_array_equal(O.clip_energies(e, 1.0), [-3.0, -1.0, 0.0, 1.0, 21.0])
+    np.testing.assert_array_equal(O.clip_energies(e, 0.1), [-2.1, -1.0, 0.0, 1.0, 2.1])
+    # even count: the median is the mean of the two middle values (0.5); mean |e - 0.5| = 5
+    e2 = np.array([-9.0, 0.0, 1.0, 10.0])
+    np.testing.assert_allclose(O.clip_energies(e2, 0.5), [-2.0, 0.0, 1.0, 3.0])
+    np.testing.assert_array_equal(O.clip_energies(e2, 0.0), e2)
+    rng = np.random.default_rng(2)
+    x = rng.standard_cauchy(101)
+    np.testing.assert_allclose(O.clip_energies(x + 7.5, 2.0), O.clip_energies(x, 2.0) + 7.5, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(O.clip_energies(3.0 * x, 2.0), 3.0 * O.clip_energies(x, 2.0), rtol=1e-12)
+
+
+def test_norm_constraint_coefficient_closed_form():
+    """KFAC's norm constraint: the step lr c X with c = min(1, sqrt(C /
+    (lr^2 <X, g>))) leaves (lr c)^2 <X, g> <= C, with equality when the
+    constraint is active, and is lr itself otherwise."""
+    lr = 0.05
+    assert O.norm_constraint_coefficient(0.1, lr, 1.0) == lr
+    for q in (10.0, 1e3, 1e6):
+        k = O.norm_constraint_coefficient(q, lr, 1e-3)
+        assert k < lr
+        assert abs(k * k * q - 1e-3) < 1e-15
+    assert O.norm_constraint_coefficient(5.0, lr, 0.0) == lr  # no constraint
+    assert O.norm_constraint_coefficient(-1.0, lr, 1e-3) == lr
+
+
+def test_train_step_hydrogenic_sigma_descends_exact_gradient():
+    """One electron with the network output zeroed, psi = exp(-s r),
+    walkers sampled exactly from psi^2 (no Metropolis steps): the envelope
+    exponent is not a dense-layer parameter, so its step is -lr times the
+    energy gradient, whose expectation is dE/ds = s - Z for
+    E(s) = s^2/2 - Z s (Eq. (3)).  Pins the factor 2, the sign of the
+    update and the pass-through of the envelope parameters; iterating
+    drives s to Z."""
+    Z, s = 2.0, 1.6
+    cfg = hydrogenic_cfg(1, 0)
+    rng = np.random.default_rng(12)
+    M = 6000
+
+    def sample(s_):
+        rad = rng.gamma(3.0, 1.0 / (2 * s_), size=M)
+        v = rng.normal(size=(M, 3))
+        return (v / np.linalg.norm(v, axis=1, keepdims=True) * rad[:, None])[:, None, :], rad
+
+    p = blank(cfg)
+    put(p, cfg, "g_orb0", 1.0)
+    put(p, cfg, "pi0", 1.0)
+    put(p, cfg, "sigma0", s)
+    sig = I.param_offsets(cfg)["sigma0"][0]
+    lr = 0.3
+    pos, rad = sample(s)
+    out = O.vmc_train_step(cfg, pos, np.zeros((1, 3)), [Z], p, None, 0, 0.1, lr, 1e-3, 0.0, 0.0, 0.0, threads=8)
+    assert np.array_equal(out["pos"], pos)
+    e = out["e_loc"]
+    est = 2 * np.mean((e - e.mean()) * (-rad))
+    assert abs(out["grad"][sig] - est) < 1e-9 * abs(est)
+    sd = 2 * np.std((e - e.mean()) * rad) / math.sqrt(M)
+    assert abs(out["grad"][sig] - (s - Z)) < 5 * sd
+    assert out["direction"][sig] == out["grad"][sig]
+    assert abs(out["params"][sig] - (s - lr * out["grad"][sig])) < 1e-12
+    # the network output stays zero (its gradient vanishes), so the
+    # iteration is gradient descent on E(s) and converges to s = Z
+    for _ in range(12):
+        s_ = out["params"][sig]
+        pos, rad = sample(s_)
+        out = O.vmc_train_step(cfg, pos, np.zeros((1, 3)), [Z], out["params"], out["factors"], 0, 0.1, lr, 1e-3,
+                               0.0, 0.5, 0.0, threads=8)
+    assert abs(out["params"][sig] - Z) < 0.05
+
+
+def test_train_step_descent_direction_and_running_factors():
+    """On a small two-nucleus network: the KFAC direction is a descent
+    direction (<X, g> > 0, the damped factors being positive definite), the
+    step is -lr c X with the norm constraint active or not, decay = 1 keeps
+    the previous factors and decay = 0 takes the batch's."""
+    w = small_workload(W=5)
+    cfg = w["cfg"]
+    args = (cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], w["params"])
+    free = O.vmc_train_step(*args, None, 0, 0.1, 0.02, 1e-2, 0.0, 0.0, 5.0)
+    assert free["x_dot_g"] > 0
+    assert free["coef"] == 0.02
+    np.testing.assert_allclose(free["params"], w["params"] - 0.02 * free["direction"], rtol=0, atol=1e-15)
+    cons = O.vmc_train_step(*args, None, 0, 0.1, 0.02, 1e-2, 1e-6 * free["x_dot_g"], 0.0, 5.0)
+    assert abs(cons["coef"] ** 2 * cons["x_dot_g"] - 1e-6 * free["x_dot_g"]) < 1e-9 * 1e-6 * free["x_dot_g"]
+    old = [(n, 2.0 * A + np.eye(A.shape[0]), 3.0 * G) for n, A, G in free["factors"]]
+    keep = O.vmc_train_step(*args, old, 0, 0.1, 0.02, 1e-2, 0.0, 1.0, 5.0)
+    for (n, A, G), (_, A0, G0) in zip(keep["factors"], old):
+        assert np.array_equal(A, A0) and np.array_equal(G, G0)
+    take = O.vmc_train_step(*args, old, 0, 0.1, 0.02, 1e-2, 0.0, 0.0, 5.0)
+    for (n, A, G), (_, A0, G0) in zip(take["factors"], free["factors"]):
+        assert np.array_equal(A, A0) and np.array_equal(G, G0)
