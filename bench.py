@@ -101,8 +101,8 @@ def copy_calibration(nbytes=512 << 20, reps=3):
 
 def one_step(w, d, form, state, grad, seed, counter, rescue):
     cfg = w["cfg"]
-    F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], state["logpsi"], state["sign"], 1, 0.02,
-                    seed, counter, precision=form)
+    F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], state["logpsi"], state["sign"],
+                    state["mcmc_steps"], state["mcmc_width"], seed, counter, precision=form)
     out = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
                                   parts=False, rescue=rescue)
     if grad:
@@ -111,11 +111,11 @@ def one_step(w, d, form, state, grad, seed, counter, rescue):
     return out
 
 
-def time_form(w, form, steps, warmup, grad, rescue):
+def time_form(w, form, steps, warmup, grad, rescue, mcmc_steps=1):
     d = F.to_device(w)
     cfg = w["cfg"]
     s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
-    state = {"sign": s, "logpsi": l}
+    state = {"sign": s, "logpsi": l, "mcmc_steps": mcmc_steps, "mcmc_width": w["spec"].get("mcmc_width", 0.02)}
     for i in range(warmup):
         one_step(w, d, form, state, grad, 11, i, rescue)
     torch.cuda.synchronize()
@@ -193,6 +193,8 @@ def main():
     ap.add_argument("--rescue-bf16", type=float, default=0.03,
                     help="fraction of walkers whose local energy is re-evaluated in float64 (bf16 form)")
     ap.add_argument("--rescue-fp32", type=float, default=0.02, help="the same for the fp32 form")
+    ap.add_argument("--mcmc-steps", type=int, default=None,
+                    help="Metropolis moves per step (default: the workload's own, else 1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first launch a plain 512 MiB copy kernel three times (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +209,7 @@ def main():
     cfg = w["cfg"]
     W = w["pos"].shape[0]
     T = 3 * cfg["n_elec"] + 2
+    mcmc_steps = args.mcmc_steps if args.mcmc_steps is not None else w["spec"].get("mcmc_steps", 1)
     grad = True
     try:
         F.vmc_energy_gradient(cfg, *[F.to_device(dict(w, pos=w["pos"][:2]))[k]
@@ -215,17 +218,17 @@ def main():
     except F.FerminetError:
         grad = False  # adjoint not available in this build
 
-    ms_bf, st_bf = time_form(w, "bf16", args.steps, args.warmup, grad, args.rescue_bf16)
+    ms_bf, st_bf = time_form(w, "bf16", args.steps, args.warmup, grad, args.rescue_bf16, mcmc_steps)
     res = {}
     if not args.no_fp32:
-        ms_32, st_32 = time_form(w, "fp32", args.steps, args.warmup, grad, args.rescue_fp32)
+        ms_32, st_32 = time_form(w, "fp32", args.steps, args.warmup, grad, args.rescue_fp32, mcmc_steps)
         res["fp32_form"] = {"value": W / (ms_32 * 1e-3), "ms_per_step": ms_32, "rescue_fraction": args.rescue_fp32,
                             "stage_ms": {k: round(v[0] / 2, 4) for k, v in st_32.items()}}
     if not args.no_full_envelope:
         # the same step with a general 3x3 Sigma per orbital and nucleus, the
         # envelope that Section 3 replaces by the isotropic one to save time
         wf = I.full_covariance(w, noise=0.3, seed=5)
-        ms_fe, st_fe = time_form(wf, "bf16", args.steps, args.warmup, grad, args.rescue_bf16)
+        ms_fe, st_fe = time_form(wf, "bf16", args.steps, args.warmup, grad, args.rescue_bf16, mcmc_steps)
         res["full_envelope_bf16"] = {"value": W / (ms_fe * 1e-3), "ms_per_step": ms_fe,
                                      "slowdown_vs_isotropic": ms_fe / ms_bf,
                                      "stage_ms": {k: round(v[0] / 2, 4) for k, v in st_fe.items()}}
@@ -258,6 +261,26 @@ def main():
         t1.record()
         torch.cuda.synchronize()
         res["kfac_precondition"] = {"ms_per_call": t0.elapsed_time(t1) / 3, "damping": 1e-3}
+        # one whole VMC iteration (vmc_train_step): log|psi| refresh, 10
+        # Metropolis moves, local energy, clipped-energy gradient, KFAC
+        # factors, their running average, damped direction, parameter step
+        d = F.to_device(w)
+        fac = torch.zeros(F.kfac_layout(cfg)[1], device="cuda")
+        it_args = (cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], fac, 10, 0.02, 11)
+        for i in range(args.warmup):
+            F.vmc_train_step(*it_args, 10 * i, 0.05, 1e-3, 1e-3, 0.0 if i == 0 else 0.95, 5.0, precision="bf16",
+                             rescue=args.rescue_bf16)
+        torch.cuda.synchronize()
+        t0.record()
+        n_it = max(1, args.steps // 2)
+        for i in range(n_it):
+            F.vmc_train_step(*it_args, 10 * (args.warmup + i), 0.05, 1e-3, 1e-3, 0.95, 5.0, precision="bf16",
+                             rescue=args.rescue_bf16)
+        t1.record()
+        torch.cuda.synchronize()
+        ms_it = t0.elapsed_time(t1) / n_it
+        res["vmc_iteration_bf16"] = {"ms_per_iteration": ms_it, "value": W / (ms_it * 1e-3),
+                                     "unit": "walker-iterations/s", "mcmc_steps": 10}
     main_fl, mf_fl = layer_flops(cfg, W, T)
     # dominant kernel: the one-electron layer GEMM of the jet pass (L
     # launches per local-energy call, layer 0 included).  Its arithmetic
@@ -290,7 +313,7 @@ def main():
         "config": {"workload": f"{args.workload}: Z={w['nuc_charge'].tolist()}, {cfg['n_elec']} electrons "
                                f"({cfg['n_up']} up/{cfg['n_down']} down), {W} walkers, {cfg['n_layers']} layers "
                                f"{cfg['width1']}/{cfg['width2']}, {cfg['n_det']} dets, isotropic envelope",
-                   "walkers": W, "step": "1 Metropolis move + local energy" + (" + VMC gradient" if grad else ""),
+                   "walkers": W, "step": f"{mcmc_steps} Metropolis move{'s' if mcmc_steps > 1 else ''} + local energy" + (" + VMC gradient" if grad else ""),
                    "form": "bf16x3 layer GEMMs (fp32 accumulation), fp64 determinants, fp64 re-evaluation of the "
                            f"{args.rescue_bf16:.0%} walkers of largest rounding-error scale",
                    "rescue_fraction": args.rescue_bf16,

@@ -163,8 +163,23 @@ typedef enum {
   FN_ENTRY_GRAD_LOGPSI = 2,
   FN_ENTRY_MCMC = 3,
   FN_ENTRY_KFAC = 4,
-  FN_ENTRY_KFAC_PRECONDITION = 5 /* chunk_walkers is ignored */
+  FN_ENTRY_KFAC_PRECONDITION = 5, /* chunk_walkers is ignored */
+  FN_ENTRY_TRAIN = 6              /* chunk_walkers is the batch size W (see vmc_train_step) */
 } fn_entry;
+
+/* Settings of one VMC iteration (vmc_train_step). */
+typedef struct {
+  int32_t mcmc_steps;    /* Metropolis steps before the evaluation, >= 0 */
+  float mcmc_width;      /* proposal standard deviation (bohr) */
+  uint64_t seed;         /* Philox key of the moves, as in vmc_mcmc_step */
+  uint64_t counter;      /* step counter of the first move, as in vmc_mcmc_step */
+  float learning_rate;   /* lr > 0 */
+  float damping;         /* lambda > 0 of the KFAC direction */
+  float norm_constraint; /* C of the step length; <= 0: no constraint */
+  float factor_decay;    /* running average of the KFAC factors, in [0, 1]; 0 takes the batch's */
+  float clip_scale;      /* s of the energy clipping; <= 0: no clipping */
+  int32_t reserved;
+} fn_train_options;
 
 /* One dense layer's Kronecker factors in the output of ferminet_kfac_factors. */
 typedef struct {
@@ -288,6 +303,41 @@ fn_status ferminet_kfac_layout(const fn_config* cfg, fn_kfac_block* out, int32_t
  * Uses the FN_ENTRY_KFAC_PRECONDITION workspace. */
 fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors, const float* grad, float damping,
                                      float* update, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One iteration of the variational optimisation of E[E_L] under psi^2
+ * (Eq. (3)) with KFAC (Martens and Grosse 2015), the optimiser the paper
+ * names; the paper gives no settings, so they are arguments.  In order, on
+ * the stream:
+ *   1. log|psi| of the walkers under the current parameters, then
+ *      options->mcmc_steps Metropolis moves (vmc_mcmc_step; noise and
+ *      uniforms as there, both NULL or both given);
+ *   2. the local energies e_loc [W] (float32 out; ferminet_local_energy in
+ *      cfg's form, with cfg's float64 re-evaluation fraction);
+ *   3. E~ = e_loc clipped to median +- s * mean|e_loc - median| (the median
+ *      of an even count is the mean of the two middle values; no clipping
+ *      for s <= 0) and the energy gradient
+ *        g = 2 sum_w (E~_w - mean E~) / W d log|psi_w| / d theta;
+ *   4. the KFAC factors of the batch (weights 1/W) and the running average
+ *        factors <- decay factors + (1 - decay) batch factors
+ *      (factors: [total] float32 in/out in ferminet_kfac_layout's layout;
+ *      with decay = 0 its input is not read);
+ *   5. the damped direction X (ferminet_kfac_precondition) and the step
+ *        params <- params - lr c X,  c = min(1, sqrt(C / (lr^2 <X, g>)))
+ *      (c = 1 for C <= 0 or <X, g> <= 0), params [P] float32 in/out.
+ *   stats  [8] float64 DEVICE out: mean and population variance of e_loc,
+ *          acceptance rate (accepted moves / (W mcmc_steps); 0 without
+ *          moves), median, mean |e_loc - median|, mean E~, <X, g>, lr c
+ * W >= 1 (else FN_ERR_ARG); FN_ERR_UNSUPPORTED for FN_PREC_FP64.  Options
+ * outside their ranges or not finite give FN_ERR_ARG.  The workspace holds
+ * per-walker and per-parameter buffers for the whole batch followed by the
+ * passes' own workspace: ferminet_workspace_bytes(cfg, W, FN_ENTRY_TRAIN)
+ * runs every pass in one chunk; less works down to the passes' one-walker
+ * chunks (FN_ERR_WORKSPACE otherwise, checked before anything is
+ * enqueued). */
+fn_status vmc_train_step(const fn_config* cfg, int32_t W, float* pos, const int32_t* spins, const float* nuc_pos,
+                         const float* nuc_charge, float* params, float* factors, const fn_train_options* options,
+                         const float* noise, const float* uniforms, float* e_loc, double* stats, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream);
 
 /* n_steps Metropolis random-walk steps sampling psi^2 (Eq. (3)), all
  * electrons moved at once:

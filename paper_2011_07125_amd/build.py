@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libferminet.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["gemm.hip", "layer.hip", "features.hip", "det.hip", "mcmc.hip", "adjoint.hip", "rescue.hip", "kfac.hip",
-           "abi.cpp"]
+           "train.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed-fp32 instructions are switched off for all device code
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",

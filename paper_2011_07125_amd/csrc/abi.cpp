@@ -146,7 +146,7 @@ enum Mode { VALUE = 0, JET = 1 };
 enum Stage {
   ST_PACK, ST_FEATURES, ST_TWO_E, ST_MEANFIELD, ST_GEMM_MF, ST_GEMM_LAYER, ST_GEMM_ORB, ST_DET, ST_COMBINE,
   ST_PROPOSE, ST_ACCEPT, ST_ADJ_FWD, ST_ADJ_DET, ST_ADJ_ORB, ST_ADJ_LAYERS, ST_ADJ_TWO_E, ST_ADJ_REDUCE,
-  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_KFAC, ST_COUNT
+  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_KFAC, ST_TRAIN, ST_COUNT
 };
 
 struct Bufs {
@@ -414,8 +414,39 @@ static void carve_kfac_solve(const Plan& p, Carver& cv, KfacPrepArgs& a) {
   }
 }
 
+// buffers of one VMC iteration that live across its passes (the batch of W
+// walkers; the passes take their own workspace after these)
+struct TrainBufs {
+  float *sign, *logpsi, *e_clip, *wts;
+  int32_t* n_acc;
+  double *st2, *part;
+  float *grad, *dir, *fb;
+};
+
+static void carve_train(const Plan& p, int64_t W, Carver& cv, TrainBufs& t) {
+  t.sign = (float*)cv.take(W * 4);
+  t.logpsi = (float*)cv.take(W * 4);
+  t.e_clip = (float*)cv.take(W * 4);
+  t.wts = (float*)cv.take(W * 4);
+  t.n_acc = (int32_t*)cv.take(W * 4);
+  t.st2 = (double*)cv.take(2 * 8);
+  t.part = (double*)cv.take(256 * 8);
+  t.grad = (float*)cv.take(p.P * 4);
+  t.dir = (float*)cv.take(p.P * 4);
+  int64_t total = 0;
+  kfac_blocks(p, &total);
+  t.fb = (float*)cv.take(total * 4);
+}
+
 static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   Carver cv{nullptr, 0};
+  if (entry == FN_ENTRY_TRAIN) {
+    TrainBufs t;
+    carve_train(p, Wc, cv, t);
+    size_t pass = chunk_bytes(p, FN_ENTRY_KFAC_PRECONDITION, 1);
+    for (int e = FN_ENTRY_LOGPSI; e <= FN_ENTRY_KFAC; ++e) pass = std::max(pass, chunk_bytes(p, e, Wc));
+    return cv.used + pass;
+  }
   if (entry == FN_ENTRY_KFAC_PRECONDITION) {
     KfacPrepArgs a;
     Carver c0{(char*)nullptr, 0};
@@ -464,7 +495,7 @@ static const char* kStageNames[ST_COUNT] = {
     "pack_weights", "features",  "two_electron", "meanfield",    "gemm_meanfield", "gemm_layer",
     "gemm_orbital", "det",       "combine",      "mcmc_propose", "mcmc_accept",    "adj_forward",
     "adj_det",      "adj_orbital", "adj_layers", "adj_two_electron", "adj_reduce",     "gemm_layer_value",
-    "rescue_fp64",  "kfac_precondition"};
+    "rescue_fp64",  "kfac_precondition", "train_step"};
 static std::mutex g_time_mu;
 static bool g_timing = false;
 struct StageRec {
@@ -1113,7 +1144,7 @@ fn_status ferminet_workspace_bytes(const fn_config* cfg, int32_t chunk_walkers, 
   fn_status st = make_plan(cfg, p);
   if (st != FN_OK) return st;
   if (!bytes) return FN_ERR_NULL;
-  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_KFAC_PRECONDITION) return FN_ERR_ARG;
+  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_TRAIN) return FN_ERR_ARG;
   *bytes = chunk_bytes(p, entry, chunk_walkers);
   return FN_OK;
 }
@@ -1371,6 +1402,63 @@ fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos,
   FN_T(ST_ADJ_REDUCE, launch_energy_stats(e_loc, W, e_stats, nullptr, s));
   return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, nullptr, e_loc, e_stats, grad, workspace,
                      workspace_bytes, stream);
+}
+
+fn_status vmc_train_step(const fn_config* cfg, int32_t W, float* pos, const int32_t* spins, const float* nuc_pos,
+                         const float* nuc_charge, float* params, float* factors, const fn_train_options* options,
+                         const float* noise, const float* uniforms, float* e_loc, double* stats, void* workspace,
+                         size_t workspace_bytes, hipStream_t stream) {
+  Plan p;
+  fn_status st = check_common(cfg, W, pos, spins, nuc_pos, nuc_charge, params, workspace, p);
+  if (st != FN_OK) return st;
+  if (!options || !factors || !e_loc || !stats) return FN_ERR_NULL;
+  if (W < 1) return FN_ERR_ARG;  // the batch statistics of an empty batch are undefined
+  if (p.f64) return FN_ERR_UNSUPPORTED;
+  const fn_train_options o = *options;
+  if (o.mcmc_steps < 0 || !std::isfinite(o.mcmc_width) || !(o.learning_rate > 0.0f) ||
+      !std::isfinite(o.learning_rate) || !(o.damping > 0.0f) || !std::isfinite(o.damping) ||
+      !std::isfinite(o.norm_constraint) || !(o.factor_decay >= 0.0f && o.factor_decay <= 1.0f) ||
+      !std::isfinite(o.clip_scale))
+    return FN_ERR_ARG;
+  if ((noise == nullptr) != (uniforms == nullptr)) return FN_ERR_ARG;
+  Carver cv{(char*)workspace, 0};
+  TrainBufs t;
+  carve_train(p, W, cv, t);
+  if (workspace_bytes < cv.used) return FN_ERR_WORKSPACE;
+  void* rest = (char*)workspace + cv.used;
+  const size_t rb = workspace_bytes - cv.used;
+  // every pass must fit (in chunks) before anything is enqueued
+  if (rb < chunk_bytes(p, FN_ENTRY_KFAC_PRECONDITION, 1)) return FN_ERR_WORKSPACE;
+  for (int e = FN_ENTRY_LOGPSI; e <= FN_ENTRY_KFAC; ++e)
+    if (max_chunk(p, e, rb, W) < 1) return FN_ERR_WORKSPACE;
+  int64_t total = 0;
+  kfac_blocks(p, &total);
+  const hipStream_t s = stream;
+  // log|psi| of the walkers under the current parameters, then the moves
+  st = ferminet_logpsi(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.sign, t.logpsi, rest, rb, s);
+  if (st != FN_OK) return st;
+  st = vmc_mcmc_step(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.logpsi, t.sign, o.mcmc_steps, o.mcmc_width,
+                     o.seed, o.counter, noise, uniforms, t.n_acc, rest, rb, s);
+  if (st != FN_OK) return st;
+  st = ferminet_local_energy(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.sign, t.logpsi, e_loc, nullptr,
+                             nullptr, rest, rb, s);
+  if (st != FN_OK) return st;
+  FN_T(ST_TRAIN, launch_train_energy_stats(e_loc, t.n_acc, W, o.mcmc_steps, (double)o.clip_scale, t.e_clip, stats, s));
+  // energy gradient 2 sum_w (E~_w - mean E~) / W d log|psi_w| / d theta
+  st = vmc_energy_gradient(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.e_clip, t.st2, t.grad, rest, rb, s);
+  if (st != FN_OK) return st;
+  FN_T(ST_TRAIN, launch_lincomb(t.grad, t.grad, 2.0f, 0.0f, p.P, s));
+  // running averages of the batch factors (weights 1/W)
+  FN_T(ST_TRAIN, launch_fill_f32(t.wts, W, 1.0f / (float)W, s));
+  st = ferminet_kfac_factors(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.wts, t.fb, rest, rb, s);
+  if (st != FN_OK) return st;
+  FN_T(ST_TRAIN, launch_lincomb(factors, t.fb, 1.0f - o.factor_decay, o.factor_decay, total, s));
+  st = ferminet_kfac_precondition(cfg, factors, t.grad, o.damping, t.dir, rest, rb, s);
+  if (st != FN_OK) return st;
+  FN_T(ST_TRAIN, launch_step_length(t.dir, t.grad, p.P, (double)o.learning_rate, (double)o.norm_constraint, t.part,
+                                    stats, s));
+  FN_T(ST_TRAIN, launch_apply_step(params, t.dir, p.P, stats, s));
+  return FN_OK;
 }
 
 }  // extern "C"

@@ -216,4 +216,20 @@ hipError_t launch_kfac_transpose(const KfacPrepArgs& a, hipStream_t s);  // Y ->
 hipError_t launch_kfac_write(const KfacPrepArgs& a, hipStream_t s);      // Yt^T -> update
 hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s);
 
+// ---- one VMC iteration (train.hip)
+// stats[0..5] = mean E, variance E, acceptance (sum n_acc / (W n_steps)),
+// median, mean |E - median|, mean of the clipped energies; e_clip = E
+// clipped to median +- clip_scale * that deviation (E itself if
+// clip_scale <= 0)
+hipError_t launch_train_energy_stats(const float* e, const int32_t* n_acc, int W, int n_steps, double clip_scale,
+                                     float* e_clip, double* stats, hipStream_t s);
+// y = a x + b y (y = a x when b = 0)
+hipError_t launch_lincomb(float* y, const float* x, float a, float b, int64_t n, hipStream_t s);
+// stats[6] = <x, g>, stats[7] = lr min(1, sqrt(C / (lr^2 <x, g>))) (lr when
+// C <= 0 or <x, g> <= 0); part: 256 doubles of scratch
+hipError_t launch_step_length(const float* x, const float* g, int64_t n, double lr, double norm_constraint,
+                              double* part, double* stats, hipStream_t s);
+// theta -= stats[7] x
+hipError_t launch_apply_step(float* theta, const float* x, int64_t n, const double* stats, hipStream_t s);
+
 }  // namespace fn

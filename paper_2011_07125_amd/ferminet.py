@@ -21,7 +21,7 @@ FN_ENV_ISOTROPIC, FN_ENV_FULL = 0, 1
 ENVELOPES = {"isotropic": FN_ENV_ISOTROPIC, "full": FN_ENV_FULL}
 PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
 FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC, FN_ENTRY_KFAC = 0, 1, 2, 3, 4
-FN_ENTRY_KFAC_PRECONDITION = 5
+FN_ENTRY_KFAC_PRECONDITION, FN_ENTRY_TRAIN = 5, 6
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
           5: "FN_ERR_UNSUPPORTED", 6: "FN_ERR_HIP", 7: "FN_ERR_ARG"}
 
@@ -48,10 +48,17 @@ class fn_kfac_block(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class fn_train_options(ctypes.Structure):
+    _fields_ = [("mcmc_steps", ctypes.c_int32), ("mcmc_width", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("counter", ctypes.c_uint64), ("learning_rate", ctypes.c_float), ("damping", ctypes.c_float),
+                ("norm_constraint", ctypes.c_float), ("factor_decay", ctypes.c_float),
+                ("clip_scale", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
 EXPORTS = ("ferminet_status_string", "ferminet_param_count", "ferminet_param_layout", "ferminet_workspace_bytes",
            "ferminet_logpsi", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
            "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
-           "ferminet_kfac_precondition",
+           "ferminet_kfac_precondition", "vmc_train_step",
            "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name")
 
 _LIB = None
@@ -84,6 +91,8 @@ def _lib():
                 lib.ferminet_kfac_precondition.argtypes = [C, P, P, f32, P, P, sz, P]
                 lib.vmc_mcmc_step.argtypes = [C, i32, P, P, P, P, P, P, P, i32, f32, u64, u64, P, P, P, P, sz, P]
                 lib.vmc_mcmc_noise.argtypes = [i32, i32, i32, u64, u64, P, P, P]
+                lib.vmc_train_step.argtypes = [C, i32, P, P, P, P, P, P, ctypes.POINTER(fn_train_options), P, P, P,
+                                               P, P, sz, P]
                 lib.ferminet_stage_timing.argtypes = [i32]
                 lib.ferminet_stage_times.argtypes = [P, P, i32]
                 lib.ferminet_stage_name.argtypes = [i32]
@@ -295,6 +304,30 @@ def vmc_mcmc_step(cfg, pos, nuc_pos, nuc_charge, params, logpsi, sign, n_steps, 
                               ws.numel(), _stream())
     _check(st, "vmc_mcmc_step")
     return acc
+
+
+def vmc_train_step(cfg, pos, nuc_pos, nuc_charge, params, factors, mcmc_steps, mcmc_width, seed, counter,
+                   learning_rate, damping=1e-3, norm_constraint=1e-3, factor_decay=0.95, clip_scale=5.0, noise=None,
+                   uniforms=None, precision=None, rescue=0.0, ws=None):
+    """One VMC iteration (include/ferminet.h), in place on pos, params and
+    factors (the running KFAC factors, kfac_layout's total floats).
+    Returns (e_loc [W] float32, stats [8] float64: mean and variance of
+    e_loc, acceptance rate, median, mean |e_loc - median|, mean of the
+    clipped energies, <X, g>, step length lr c)."""
+    W = pos.shape[0]
+    c = make_config(cfg, precision, rescue)
+    e = torch.empty(W, dtype=torch.float32, device=pos.device)
+    stats = torch.empty(8, dtype=torch.float64, device=pos.device)
+    o = fn_train_options(int(mcmc_steps), float(mcmc_width), int(seed), int(counter), float(learning_rate),
+                         float(damping), float(norm_constraint), float(factor_decay), float(clip_scale), 0)
+    ws = workspace(cfg, W, FN_ENTRY_TRAIN, precision, pos.device, rescue=rescue) if ws is None else ws
+    st = _lib().vmc_train_step(ctypes.byref(c), W, _ptr(_prep(pos)), _spins(cfg), _ptr(_prep(nuc_pos)),
+                               _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(_prep(factors)), ctypes.byref(o),
+                               _ptr(_prep(noise)) if noise is not None else None,
+                               _ptr(_prep(uniforms)) if uniforms is not None else None, _ptr(e), _ptr(stats),
+                               _ptr(ws), ws.numel(), _stream())
+    _check(st, "vmc_train_step")
+    return e, stats
 
 
 def vmc_mcmc_noise(W, n_elec, n_steps, seed, counter=0, device="cuda"):

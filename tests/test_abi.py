@@ -112,3 +112,43 @@ def test_entry_points_reject_bad_arguments_before_launch():
     assert h(ctypes.byref(c), 8, fake, good, fake, fake, fake, None, fake, fake, 1 << 30, None) == 1
     assert lib.vmc_mcmc_noise(-1, 4, 1, 0, 0, fake, fake, None) == 7
     assert lib.ferminet_status_string(4).decode().startswith("workspace")
+
+
+def test_train_step_rejects_bad_arguments_before_launch():
+    """vmc_train_step validates its options, the batch, the form and the
+    workspace (its per-walker and per-parameter buffers plus the passes'
+    own) before anything is enqueued."""
+    lib = _lib_or_skip()
+    c = _cfg()
+    fake = ctypes.c_void_p(1 << 40)
+    good = (ctypes.c_int32 * 4)(0, 0, 1, 1)
+
+    def opts(**kw):
+        base = dict(mcmc_steps=2, mcmc_width=0.1, seed=0, counter=0, learning_rate=0.05, damping=1e-3,
+                    norm_constraint=1e-3, factor_decay=0.95, clip_scale=5.0, reserved=0)
+        base.update(kw)
+        return F.fn_train_options(**base)
+
+    def call(W=8, o=None, cfg=c, noise=None, uni=None, nbytes=1 << 34, ws=fake):
+        o = opts() if o is None else o
+        return lib.vmc_train_step(ctypes.byref(cfg), W, fake, good, fake, fake, fake, fake, ctypes.byref(o), noise,
+                                  uni, fake, fake, ws, nbytes, None)
+
+    need = ctypes.c_size_t(0)
+    assert lib.ferminet_workspace_bytes(ctypes.byref(c), 8, F.FN_ENTRY_TRAIN, ctypes.byref(need)) == 0
+    one = ctypes.c_size_t(0)
+    assert lib.ferminet_workspace_bytes(ctypes.byref(c), 8, F.FN_ENTRY_KFAC, ctypes.byref(one)) == 0
+    assert need.value > one.value
+    assert call(W=0) == 7
+    assert call(W=-1) == 7
+    assert lib.vmc_train_step(ctypes.byref(c), 8, fake, good, fake, fake, fake, fake, None, None, None, fake, fake,
+                              fake, 1 << 34, None) == 1
+    assert call(cfg=_cfg(precision=3)) == 5
+    for bad in (dict(mcmc_steps=-1), dict(learning_rate=0.0), dict(learning_rate=float("inf")), dict(damping=0.0),
+                dict(factor_decay=1.5), dict(factor_decay=-0.1), dict(clip_scale=float("nan")),
+                dict(norm_constraint=float("inf")), dict(mcmc_width=float("nan"))):
+        assert call(o=opts(**bad)) == 7, bad
+    assert call(noise=fake) == 7
+    assert call(nbytes=1024) == 4
+    assert call(nbytes=need.value - one.value) == 4
+    assert call(ws=ctypes.c_void_p((1 << 40) + 64)) == 4

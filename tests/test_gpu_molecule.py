@@ -1,0 +1,186 @@
+"""The 30-electron, 10-nucleus molecule (the bicyclobutane stand-in of
+Table 2) at its full batch sizes, in the launch configurations the
+throughput measurement uses:
+
+  * differentiation form, 2048 walkers, fp32: the local energy and
+    d log|psi| / d theta of sampled walkers against the oracle (energies,
+    and derivatives on seeded random parameters plus the first and last
+    entry of every block), the batch statistics of the VMC gradient;
+  * a full VMC iteration, 8192 walkers: 10 Metropolis steps of width
+    0.02 bohr, then the local energy and the VMC gradient, in the bf16
+    form against the plain fp32 form on the same GPU (acceptance rate,
+    energy mean and variance, gradient), with sampled walkers of the
+    final batch against the oracle.
+
+Tolerances are those of test_gpu_parity.compare (energies) and
+test_gpu_adjoint.check (derivatives), per walker from the oracle's
+rounding amplification A_w; between the two forms the bound is the sum of
+the two forms' bounds.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2011_07125_amd import ferminet as F  # noqa: E402
+from paper_2011_07125_amd import inputs as I  # noqa: E402
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from test_gpu_parity import compare, U_FORM  # noqa: E402
+from test_gpu_adjoint import check, selection  # noqa: E402
+
+THREADS = min(16, os.cpu_count() or 1)
+RESCUE = {"bf16": 0.03, "fp32": 0.02}  # the throughput measurement's defaults
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    O.build(force=False)
+    assert torch.cuda.is_available()
+    F._lib()
+
+
+def oracle_at(w, pos):
+    return O.evaluate(w["cfg"], pos.astype(np.float64), w["nuc_pos"].astype(np.float64),
+                      w["nuc_charge"].astype(np.float64), w["params"].astype(np.float64), threads=THREADS)
+
+
+def amp_at(w, pos):
+    return O.amplification(w["cfg"], pos, w["nuc_pos"], w["params"], threads=THREADS)[0]
+
+
+def test_c4h6_differentiation_form_full_batch():
+    say("case c4h6 differentiation form W=2048 fp32")
+    w = I.make_workload("c4h6")
+    cfg = w["cfg"]
+    W = w["pos"].shape[0]
+    assert W == 2048
+    d = F.to_device(w)
+    out = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision="fp32")
+    grad, stats = F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], out["e_loc"],
+                                        precision="fp32")
+    torch.cuda.synchronize()
+    g = {k: v.double().cpu().numpy() for k, v in out.items()}
+    e = g["e_loc"]
+    st = stats.cpu().numpy()
+    say(f"   mean E_L {st[0]:.6f} variance {st[1]:.6e} |grad|inf {grad.abs().max().item():.3e}")
+    assert np.isfinite(e).all() and np.isfinite(grad.cpu().numpy()).all()
+    assert abs(st[0] - e.mean()) <= 1e-12 * W * max(1.0, np.abs(e).max())
+    assert abs(st[1] - e.var()) <= 1e-9 * max(1.0, e.var())
+
+    rng = np.random.default_rng(4)
+    idx = np.sort(rng.choice(W, 6, replace=False))
+    o = oracle_at(w, w["pos"][idx])
+    amp = amp_at(w, w["pos"][idx])
+    compare("c4h6/full batch/sampled", {k: v[idx] for k, v in g.items()}, o, amp, "fp32")
+
+    # d log|psi_w| / d theta of three sampled walkers: a one-hot cotangent
+    # over the whole batch
+    sel = selection(cfg, 4, n_pick=64)
+    per = O.param_grad(cfg, w["pos"][idx[:3]], w["nuc_pos"], w["params"], sel, threads=THREADS)
+    for j, wi in enumerate(idx[:3]):
+        cot = torch.zeros(W, device="cuda")
+        cot[wi] = 1.0
+        gw = F.ferminet_grad_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], cot, precision="fp32")
+        torch.cuda.synchronize()
+        check(f"c4h6/walker {wi}", gw.double().cpu().numpy()[sel], per[j], amp[j], "fp32")
+
+
+def _iteration(w, form):
+    cfg = w["cfg"]
+    W = w["pos"].shape[0]
+    spec = w["spec"]
+    d = F.to_device(w)
+    s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
+    acc = F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], l, s, spec["mcmc_steps"],
+                          spec["mcmc_width"], w["seed"], 0, precision=form)
+    out = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
+                                  rescue=RESCUE[form])
+    grad, stats = F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], out["e_loc"],
+                                        precision=form)
+    torch.cuda.synchronize()
+    r = {k: v.double().cpu().numpy() for k, v in out.items()}
+    r["pos"] = d["pos"].cpu().numpy()
+    r["acc"] = acc.cpu().numpy().sum() / (W * spec["mcmc_steps"])
+    r["grad"] = grad.double().cpu().numpy()
+    r["stats"] = stats.cpu().numpy()
+    r["dev"] = d
+    return r
+
+
+def test_c4h6_vmc_iteration_bf16_vs_fp32():
+    """Tolerances: acceptance, energy mean and variance between the forms
+    within the sum of the forms' bounds against the oracle (1e-3 Ha each
+    for the mean); the VMC gradient is a Monte Carlo estimate, so the
+    forms' difference is gated by the estimator's own standard error
+    (from 8 groups of walkers): half of it in L2 norm."""
+    say("case c4h6 VMC iteration W=8192 bf16 vs fp32")
+    w = I.make_workload("c4h6_vmc")
+    cfg = w["cfg"]
+    W = w["pos"].shape[0]
+    assert W == 8192
+    r = {f: _iteration(w, f) for f in ("fp32", "bf16")}
+    a, b = r["fp32"], r["bf16"]
+    same = np.all(a["pos"] == b["pos"], axis=(1, 2))
+    say(f"   acceptance fp32 {a['acc']:.5f} bf16 {b['acc']:.5f}; chains identical on {int(same.sum())} of {W} walkers")
+    say(f"   mean E_L fp32 {a['stats'][0]:.6f} bf16 {b['stats'][0]:.6f}; variance fp32 {a['stats'][1]:.6e} "
+        f"bf16 {b['stats'][1]:.6e}")
+    assert 0.5 < a["acc"] <= 1.0
+    assert np.isfinite(a["e_loc"]).all() and np.isfinite(b["e_loc"]).all()
+
+    # sampled walkers of the final fp32 batch against the oracle
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(W, 6, replace=False))
+    o = oracle_at(w, a["pos"][idx])
+    amp = amp_at(w, a["pos"][idx])
+    for f in ("fp32", "bf16"):
+        pf = r[f]["pos"][idx]
+        keep = np.all(pf == a["pos"][idx], axis=(1, 2))
+        compare(f"c4h6_vmc/{f}/sampled", {k: r[f][k][idx][keep] for k in ("sign", "logpsi", "e_loc")},
+                {k: o[k][keep] for k in ("sign", "logpsi", "e_loc", "e_kin")}, amp[keep], f)
+
+    # the two forms on the walkers whose chains took the same decisions
+    ea, eb = a["e_loc"][same], b["e_loc"][same]
+    dmean = abs(ea.mean() - eb.mean())
+    dvar = abs(ea.var() - eb.var()) / ea.var()
+    say(f"   identical chains: |d mean E_L| {dmean:.2e} Ha, rel d variance {dvar:.2e}, |d acc| "
+        f"{abs(a['acc'] - b['acc']):.2e}")
+    assert abs(a["acc"] - b["acc"]) <= 1e-3
+    assert same.mean() >= 0.99
+    assert dmean <= 2e-3
+    assert dvar <= 1e-2
+
+    # gradient: the forms' difference against the estimator's standard error
+    da = a["dev"]
+    c = (a["e_loc"] - a["e_loc"].mean()) / W
+    groups = []
+    for k in range(8):
+        ck = np.zeros(W, dtype=np.float32)
+        ck[k::8] = c[k::8]
+        gk = F.ferminet_grad_logpsi(cfg, da["pos"], da["nuc_pos"], da["nuc_charge"], da["params"],
+                                    torch.from_numpy(ck).cuda(), precision="fp32")
+        groups.append(gk.double().cpu().numpy())
+    groups = np.array(groups)
+    se = np.sqrt(8.0) * groups.std(axis=0, ddof=1)
+    # the adjoint's own rounding: both forms at the fp32 chain's positions with the same cotangents
+    cs = torch.from_numpy((c * same).astype(np.float32)).cuda()
+    g_same = {f: F.ferminet_grad_logpsi(cfg, da["pos"], da["nuc_pos"], da["nuc_charge"], da["params"], cs,
+                                        precision=f).double().cpu().numpy() for f in ("fp32", "bf16")}
+    ga, gb = a["grad"], b["grad"]
+    nse = np.linalg.norm(se)
+    d_all = np.linalg.norm(gb - ga)
+    d_adj = np.linalg.norm(g_same["bf16"] - g_same["fp32"])
+    say(f"   gradient |g|2 {np.linalg.norm(ga):.3e}, standard error |se|2 {nse:.3e}; bf16 - fp32: whole iteration "
+        f"{d_all:.3e} ({d_all / nse:.2f} se), same positions and cotangents {d_adj:.3e} ({d_adj / nse:.2f} se); "
+        f"sum of groups vs whole batch {np.linalg.norm(groups.sum(0) - ga) / np.linalg.norm(ga):.1e}")
+    assert d_all <= 0.5 * nse
