@@ -219,6 +219,197 @@ __global__ __launch_bounds__(64) void det_kernel(const PT* phi, int K, int na, i
   }
 }
 
+// Matrices of 7..16 rows: one 256-thread workgroup per matrix.  The
+// factorisation and B^-1 are as in det_kernel (rows in parallel); the
+// contractions, which carry almost all of the arithmetic (n_a^3 per
+// tangent, 3n + 1 tangents), are organised so that every jet element is
+// read from HBM once:
+//  * the tangent matrices M_t are staged into LDS MID_G at a time (rows
+//    1 .. T-1 of the matrix's jets are contiguous: one coalesced copy);
+//  * thread (slot, a, b) keeps row a of B^-1 in registers and forms
+//    Y_t[a][b] = sum_c B^-1[a][c] M_t[c][b] for the tangents t of its slot;
+//  * tr(Y_t^2) = sum_ab Y_t[a][b] Y_t[b][a] is accumulated per thread over
+//    all tangents and reduced once at the end; tr(Y_t) is summed per
+//    tangent by one thread.
+constexpr int MID_NT = 256, MID_G = 8;
+
+template <class R>
+__device__ inline R block_reduce(R v, R* red, bool is_max) {
+  v = is_max ? wave_max(v) : wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  R t = red[0];
+  for (int i = 1; i < MID_NT / 64; ++i) t = is_max ? (red[i] > t ? red[i] : t) : t + red[i];
+  return t;
+}
+
+template <class R, class PT, int NA>
+__global__ __launch_bounds__(MID_NT) void det_mid_kernel(const PT* phi, int T, int n3, R* D, int dstride, R* ainv) {
+  constexpr int NSQ = NA * NA;
+  constexpr int S = MID_NT / NSQ;  // tangent slots
+  __shared__ R LU[NSQ];
+  __shared__ R Bi[NSQ];
+  __shared__ PT Ms[MID_G * NSQ];
+  __shared__ R Ys[MID_G * NSQ];
+  __shared__ R red[MID_NT / 64];
+  __shared__ int piv[NA];
+  __shared__ int s_p;
+  const int tid = threadIdx.x;
+  const int64_t mat = blockIdx.x;
+  const PT* P = phi + mat * (int64_t)T * NSQ;
+  R* out = D + mat * dstride;
+
+  for (int e = tid; e < NSQ; e += MID_NT) LU[e] = (R)P[e];
+  __syncthreads();
+  R nb = 0;  // ||B||_inf
+  if (T > 1) {
+    R rs = 0;
+    if (tid < NA)
+      for (int k = 0; k < NA; ++k) rs += fabs(LU[tid * NA + k]);
+    nb = block_reduce(rs, red, true);
+  }
+  bool singular = false;
+  for (int c = 0; c < NA; ++c) {
+    if (tid == 0) {
+      int p = c;
+      R best = fabs(LU[c * NA + c]);
+      for (int r = c + 1; r < NA; ++r) {
+        const R m = fabs(LU[r * NA + c]);
+        if (m > best) {
+          best = m;
+          p = r;
+        }
+      }
+      s_p = best == (R)0 ? -1 : p;
+      piv[c] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p < 0) {
+      singular = true;
+      break;
+    }
+    if (p != c && tid < NA) {
+      const R t = LU[c * NA + tid];
+      LU[c * NA + tid] = LU[p * NA + tid];
+      LU[p * NA + tid] = t;
+    }
+    __syncthreads();
+    const R inv_p = (R)1 / LU[c * NA + c];
+    const int r = c + 1 + tid;
+    if (r < NA) {
+      const R f = LU[r * NA + c] * inv_p;
+      LU[r * NA + c] = f;
+      for (int k = c + 1; k < NA; ++k) LU[r * NA + k] -= f * LU[c * NA + k];
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    for (int e = tid; e < dstride; e += MID_NT) out[e] = (R)0;
+    __syncthreads();
+    if (tid == 0) {
+      out[1] = -INFINITY;
+      if (T > 1) out[4 + n3] = INFINITY;
+    }
+    if (ainv)
+      for (int e = tid; e < NSQ; e += MID_NT) ainv[mat * NSQ + e] = (R)0;
+    return;
+  }
+  if (tid == 0) {
+    R sg = 1, la = 0;
+    for (int c = 0; c < NA; ++c) {
+      if (piv[c] != c) sg = -sg;
+      const R u = LU[c * NA + c];
+      if (u < 0) sg = -sg;
+      la += log(fabs(u));
+    }
+    out[0] = sg;
+    out[1] = la;
+  }
+  if (ainv == nullptr && T <= 1) return;
+  // B^-1 column by column: thread c solves L U x = P e_c
+  if (tid < NA) {
+    const int c = tid;
+    for (int r = 0; r < NA; ++r) Bi[r * NA + c] = r == c ? (R)1 : (R)0;
+    for (int k = 0; k < NA; ++k)
+      if (piv[k] != k) {
+        const R t = Bi[k * NA + c];
+        Bi[k * NA + c] = Bi[piv[k] * NA + c];
+        Bi[piv[k] * NA + c] = t;
+      }
+    for (int r = 0; r < NA; ++r) {
+      R acc = Bi[r * NA + c];
+      for (int k = 0; k < r; ++k) acc -= LU[r * NA + k] * Bi[k * NA + c];
+      Bi[r * NA + c] = acc;
+    }
+    for (int r = NA - 1; r >= 0; --r) {
+      R acc = Bi[r * NA + c];
+      for (int k = r + 1; k < NA; ++k) acc -= LU[r * NA + k] * Bi[k * NA + c];
+      Bi[r * NA + c] = acc / LU[r * NA + r];
+    }
+  }
+  __syncthreads();
+  if (ainv)
+    for (int e = tid; e < NSQ; e += MID_NT) ainv[mat * NSQ + e] = Bi[e];
+  if (T <= 1) return;
+  {
+    R rs = 0;  // ||B^-1||_inf
+    if (tid < NA)
+      for (int k = 0; k < NA; ++k) rs += fabs(Bi[tid * NA + k]);
+    const R ni = block_reduce(rs, red, true);
+    if (tid == 0) out[4 + n3] = nb * ni;
+  }
+  const int slot = tid / NSQ, ab = tid - slot * NSQ, a = ab / NA, b = ab - a * NA;
+  const bool act = slot < S;
+  R brow[NA];
+#pragma unroll
+  for (int c = 0; c < NA; ++c) brow[c] = act ? Bi[a * NA + c] : (R)0;
+  R q_acc = 0;
+  const int nt = n3 + 1;  // the 3n tangent rows and the Laplacian row, rows 1 .. T-1
+  for (int t0 = 0; t0 < nt; t0 += MID_G) {
+    const int ng = nt - t0 < MID_G ? nt - t0 : MID_G;
+    const PT* src = P + (int64_t)(1 + t0) * NSQ;
+    for (int e = tid; e < ng * NSQ; e += MID_NT) Ms[e] = src[e];
+    __syncthreads();
+    if (act)
+      for (int g = slot; g < ng; g += S) {
+        R y = 0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c) y += brow[c] * (R)Ms[g * NSQ + c * NA + b];
+        Ys[g * NSQ + ab] = y;
+      }
+    __syncthreads();
+    if (act)
+      for (int g = slot; g < ng; g += S)
+        if (t0 + g < n3) q_acc += Ys[g * NSQ + ab] * Ys[g * NSQ + b * NA + a];
+    if (tid < ng) {
+      R d = 0;
+      for (int i = 0; i < NA; ++i) d += Ys[tid * NSQ + i * NA + i];
+      const int tt = t0 + tid;
+      out[tt < n3 ? 2 + tt : 3 + n3] = d;
+    }
+    __syncthreads();
+  }
+  const R q = block_reduce(q_acc, red, false);
+  if (tid == 0) out[2 + n3] = q;
+}
+
+template <class R, class PT>
+static hipError_t run_det_mid(int na, const PT* phi, int grid, int T, int n3, R* D, int dstride, R* ainv,
+                              hipStream_t s) {
+#define FN_MID(N)                                                                                           \
+  case N:                                                                                                  \
+    hipLaunchKernelGGL((det_mid_kernel<R, PT, N>), dim3(grid), dim3(MID_NT), 0, s, phi, T, n3, D, dstride, ainv); \
+    break;
+  switch (na) {
+    FN_MID(7) FN_MID(8) FN_MID(9) FN_MID(10) FN_MID(11) FN_MID(12) FN_MID(13) FN_MID(14) FN_MID(15) FN_MID(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef FN_MID
+  return hipGetLastError();
+}
+
 // Small matrices (n_a <= 6): one thread per matrix, everything in registers.
 // The orbital jets are stored matrix-index fastest, phi[(t n_a^2 + e) M + mat]
 // with M = W K, so that consecutive threads read consecutive addresses.
@@ -392,6 +583,13 @@ hipError_t launch_det(bool fp64, const void* phi, bool phi64, int W, int K, int 
                 : run_det_small<float, float>(na, pf, M, T, n3, (float*)D, dstride, (float*)ainv, s);
   }
   const int grid = W * K;
+  // 7..16 rows with the jet rows in their standard order (the Laplacian
+  // row directly after the 3n tangent rows)
+  if (na <= DET_MID_MAX && (T <= 1 || T == n3 + 2)) {
+    if (phi64) return run_det_mid<double, double>(na, pd, grid, T, n3, (double*)D, dstride, (double*)ainv, s);
+    return fp64 ? run_det_mid<double, float>(na, pf, grid, T, n3, (double*)D, dstride, (double*)ainv, s)
+                : run_det_mid<float, float>(na, pf, grid, T, n3, (float*)D, dstride, (float*)ainv, s);
+  }
   if (phi64)
     hipLaunchKernelGGL((det_kernel<double, double>), dim3(grid), dim3(64), 0, s, pd, K, na, T, n3, (double*)D, dstride,
                        (double*)ainv);

@@ -88,7 +88,7 @@ hipError_t launch_meanfield(bool f64, const void* H, int ldh, int W, int n, int 
 //                                  sign, log|det|                      (value mode)
 // matrices up to this size take the one-thread-per-matrix kernel, which
 // expects the matrix-index-fastest layout of the orbital jets (phi_M = W K)
-constexpr int DET_SMALL_MAX = 6;
+constexpr int DET_SMALL_MAX = 6, DET_MID_MAX = 16;
 bool det_uses_small(int na);
 // phi64: the orbital jets are float64 (requires fp64)
 hipError_t launch_det(bool fp64, const void* phi, bool phi64, int W, int K, int na, int T, int n3, void* D,
