@@ -143,8 +143,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   };
   Regs R0, R1;
 
-  auto gload = [&](int kt, Regs& R) {
-    const int kb = kt * BK;
+  // K-step order: the segment-1 steps, the segment-0 steps outside this
+  // tile's residual columns, then the residual columns [n0, n0 + BN) of
+  // segment 0 last, so that the epilogue's residual loads find them in L2
+  const int nk0 = a.ka0 / BK;
+  const int r0 = a.res ? n0 / BK : nk0;
+  const int nres = a.res ? (n0 + BN <= a.ka0 ? BN / BK : 0) : 0;
+  const int n1 = nkt - nk0, nout = nk0 - nres;
+  auto ktile = [&](int kt) {
+    if (kt < n1) return nk0 + kt;
+    kt -= n1;
+    if (kt < nout) return kt < r0 ? kt : kt + nres;
+    return r0 + (kt - nout);
+  };
+  auto gload = [&](int kt_step, Regs& R) {
+    const int kb = ktile(kt_step) * BK;
     if (kb < a.ka0) {
 #pragma unroll
       for (int i = 0; i < C::NVA; ++i) R.ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA0, voff0[i], kb * 4, 0);
