@@ -411,6 +411,8 @@ static void carve_kfac_solve(const Plan& p, Carver& cv, KfacPrepArgs& a) {
     a.offLG[b] = take((int64_t)k.dG * k.dG);
     a.offY[b] = take((int64_t)k.dA * k.dG);
     a.offYt[b] = take((int64_t)k.dA * k.dG);
+    a.offIA[b] = take((int64_t)(k.dA + 31) / 32 * 32 * 32);
+    a.offIG[b] = take((int64_t)(k.dG + 31) / 32 * 32 * 32);
   }
 }
 
@@ -1336,8 +1338,10 @@ fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors,
   memset(&ch, 0, sizeof(ch));
   for (int b = 0; b < a.nb; ++b) {
     ch.n[ch.nm] = a.dA[b];
+    ch.offI[ch.nm] = a.offIA[b];
     ch.off[ch.nm++] = a.offLA[b];
     ch.n[ch.nm] = a.dG[b];
+    ch.offI[ch.nm] = a.offIG[b];
     ch.off[ch.nm++] = a.offLG[b];
   }
   FN_T(ST_KFAC, launch_spd_cholesky(ch, a.S, s));
@@ -1348,11 +1352,15 @@ fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors,
     sa.n[b] = a.dA[b];
     sa.m[b] = a.dG[b];
     sa.off[b] = a.offLA[b];
+    sa.offI[b] = a.offIA[b];
     sa.offB[b] = a.offY[b];
+    sa.offZ[b] = a.offYt[b];  // free until the transpose
     sg.n[b] = a.dG[b];
     sg.m[b] = a.dA[b];
     sg.off[b] = a.offLG[b];
+    sg.offI[b] = a.offIG[b];
     sg.offB[b] = a.offYt[b];
+    sg.offZ[b] = a.offY[b];  // free after the transpose
   }
   sa.nm = sg.nm = a.nb;
   // Y = A_d^-1 M; Yt = Y^T; Yt = G_d^-1 Yt = (Y G_d^-1)^T

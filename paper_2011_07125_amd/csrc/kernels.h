@@ -196,6 +196,7 @@ struct KfacPrepArgs {
   int64_t offA[KFAC_MAX_BLOCKS], offG[KFAC_MAX_BLOCKS];  // in the factors (floats)
   int64_t offP[KFAC_MAX_BLOCKS];                    // [weights; bias] in the parameter layout
   int64_t offLA[KFAC_MAX_BLOCKS], offLG[KFAC_MAX_BLOCKS], offY[KFAC_MAX_BLOCKS], offYt[KFAC_MAX_BLOCKS];  // in S
+  int64_t offIA[KFAC_MAX_BLOCKS], offIG[KFAC_MAX_BLOCKS];  // inverse diagonal tiles of the factors, in S
   int dA[KFAC_MAX_BLOCKS], dG[KFAC_MAX_BLOCKS];
   const float* factors;
   const float* grad;
@@ -203,11 +204,13 @@ struct KfacPrepArgs {
   double* S;
   double sqrt_damping;
 };
-// matrices mat: n x n at S + off (row-major), right-hand sides n x m at S + offB
+// matrices mat: n x n at S + off (row-major); the inverses of the
+// triangular factor's diagonal tiles (ceil(n / 32) tiles of 32 x 32) at
+// S + offI; right-hand sides n x m at S + offB with an n x m scratch at S + offZ
 struct SpdBatch {
   int nm;
   int n[KFAC_MAX_MATS], m[KFAC_MAX_MATS];
-  int64_t off[KFAC_MAX_MATS], offB[KFAC_MAX_MATS];
+  int64_t off[KFAC_MAX_MATS], offI[KFAC_MAX_MATS], offB[KFAC_MAX_MATS], offZ[KFAC_MAX_MATS];
 };
 hipError_t launch_kfac_prep(const KfacPrepArgs& a, hipStream_t s);       // damped factors, M
 hipError_t launch_spd_cholesky(const SpdBatch& bt, double* S, hipStream_t s);  // in place, lower

@@ -20,10 +20,17 @@ namespace fn {
 constexpr int TB = 32;
 
 // ------------------------------------------------------------- set-up
-// per dense layer b: damped copies of A and G, and M, in float64
+// per dense layer b (blockIdx.x): damped copies of A and G, and M, in
+// float64; blockIdx.y takes PREP_ROWS rows of each.  Every workgroup forms
+// the two traces of its layer itself (dim_A + dim_G diagonal loads), so the
+// copies need no second launch.
+constexpr int PREP_ROWS = 8;
+
 __global__ __launch_bounds__(256) void kfac_prep_kernel(KfacPrepArgs a) {
   const int b = blockIdx.x, tid = threadIdx.x;
   const int nA = a.dA[b], nG = a.dG[b];
+  const int r0 = blockIdx.y * PREP_ROWS;
+  if (r0 >= nA && r0 >= nG) return;
   const float* A = a.factors + a.offA[b];
   const float* G = a.factors + a.offG[b];
   __shared__ double red[2][256];
@@ -47,74 +54,102 @@ __global__ __launch_bounds__(256) void kfac_prep_kernel(KfacPrepArgs a) {
   double* LA = a.S + a.offLA[b];
   double* LG = a.S + a.offLG[b];
   double* Y = a.S + a.offY[b];
-  for (int64_t e = tid; e < (int64_t)nA * nA; e += 256) {
-    const int64_t r = e / nA, c = e - r * nA;
-    LA[e] = (double)A[e] + (r == c ? dA : 0.0);
-  }
-  for (int64_t e = tid; e < (int64_t)nG * nG; e += 256) {
-    const int64_t r = e / nG, c = e - r * nG;
-    LG[e] = (double)G[e] + (r == c ? dG : 0.0);
-  }
   const float* M = a.grad + a.offP[b];
-  for (int64_t e = tid; e < (int64_t)nA * nG; e += 256) Y[e] = (double)M[e];
+  for (int r = r0; r < r0 + PREP_ROWS; ++r) {
+    if (r < nA) {
+      const size_t o = (size_t)r * nA;
+      for (int c = tid; c < nA; c += 256) LA[o + c] = (double)A[o + c] + (r == c ? dA : 0.0);
+      const size_t om = (size_t)r * nG;
+      for (int c = tid; c < nG; c += 256) Y[om + c] = (double)M[om + c];
+    }
+    if (r < nG) {
+      const size_t o = (size_t)r * nG;
+      for (int c = tid; c < nG; c += 256) LG[o + c] = (double)G[o + c] + (r == c ? dG : 0.0);
+    }
+  }
 }
 
 // ------------------------------------------------------------ Cholesky
-// the factored tile in LDS; rows and columns past n padded with identity
+// Right-looking blocked Cholesky in TB x TB tiles.  Step kb factors the
+// diagonal tile in LDS and also stores the inverse of its triangular factor
+// (bt.offI), so that the panel below it and every step of the triangular
+// solves are small matrix products instead of serial substitutions.
+
+// the factored tile (rows and columns past n padded with identity) and the
+// inverse of its lower-triangular factor
 __global__ __launch_bounds__(256) void chol_diag_kernel(SpdBatch bt, double* S, int kb) {
   const int mat = blockIdx.x, tid = threadIdx.x;
   const int n = bt.n[mat], t0 = kb * TB;
   if (t0 >= n) return;
   const int tb = min(TB, n - t0);
   double* A = S + bt.off[mat];
-  __shared__ double D[TB][TB + 1];
+  double* I = S + bt.offI[mat] + (size_t)kb * TB * TB;
+  __shared__ double D[TB][TB + 1], V[TB][TB + 1];
   for (int e = tid; e < TB * TB; e += 256) {
     const int r = e / TB, c = e % TB;
     D[r][c] = (r < tb && c < tb) ? A[(size_t)(t0 + r) * n + t0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int j = 0; j < tb; ++j) {
+  for (int j = 0; j < TB; ++j) {
     if (tid == 0) D[j][j] = sqrt(D[j][j]);
     __syncthreads();
-    for (int i = j + 1 + tid; i < tb; i += 256) D[i][j] /= D[j][j];
+    for (int i = j + 1 + tid; i < TB; i += 256) D[i][j] /= D[j][j];
     __syncthreads();
     for (int e = tid; e < TB * TB; e += 256) {
       const int i = e / TB, k = e % TB;
-      if (k > j && k <= i && i < tb) D[i][k] -= D[i][j] * D[k][j];
+      if (k > j && k <= i) D[i][k] -= D[i][j] * D[k][j];
     }
     __syncthreads();
   }
+  // V = D^-1 (lower triangular): thread c solves D v = e_c
+  if (tid < TB) {
+    const int c = tid;
+    for (int r = 0; r < TB; ++r) {
+      double x = 0.0;
+      if (r >= c) {
+        x = r == c ? 1.0 : 0.0;
+        for (int k = c; k < r; ++k) x -= D[r][k] * V[k][c];
+        x /= D[r][r];
+      }
+      V[r][c] = x;
+    }
+  }
+  __syncthreads();
   for (int e = tid; e < TB * TB; e += 256) {
     const int r = e / TB, c = e % TB;
     if (r < tb && c <= r) A[(size_t)(t0 + r) * n + t0 + c] = D[r][c];
+    I[e] = V[r][c];
   }
 }
 
-// tiles (ib, kb), ib > kb: rows of A[ib][kb] D^-T, one row per thread
-__global__ __launch_bounds__(64) void chol_panel_kernel(SpdBatch bt, double* S, int kb) {
+// tiles (ib, kb), ib > kb: L[ib][kb] = A[ib][kb] D^-T
+__global__ __launch_bounds__(256) void chol_panel_kernel(SpdBatch bt, double* S, int kb) {
   const int mat = blockIdx.x, ib = blockIdx.y, tid = threadIdx.x;
   const int n = bt.n[mat], nt = (n + TB - 1) / TB;
   if (ib <= kb || ib >= nt) return;
   const int t0 = kb * TB, r0 = ib * TB, rb = min(TB, n - r0);
   double* A = S + bt.off[mat];
-  __shared__ double D[TB][TB + 1], P[TB][TB + 1];
-  for (int e = tid; e < TB * TB; e += 64) {
+  const double* I = S + bt.offI[mat] + (size_t)kb * TB * TB;
+  __shared__ double V[TB][TB + 1], P[TB][TB + 1];
+  for (int e = tid; e < TB * TB; e += 256) {
     const int r = e / TB, c = e % TB;
-    D[r][c] = A[(size_t)(t0 + r) * n + t0 + c];  // kb < ib: the diagonal tile is whole
-    P[r][c] = r < rb ? A[(size_t)(r0 + r) * n + t0 + c] : 0.0;
+    V[r][c] = I[e];
+    P[r][c] = r < rb ? A[(size_t)(r0 + r) * n + t0 + c] : 0.0;  // kb < ib: the tile's columns are whole
   }
   __syncthreads();
-  if (tid < rb) {
-    for (int j = 0; j < TB; ++j) {
-      double s = P[tid][j];
-      for (int k = 0; k < j; ++k) s -= P[tid][k] * D[j][k];
-      P[tid][j] = s / D[j][j];
-    }
+  double out[TB * TB / 256];
+#pragma unroll
+  for (int q = 0; q < TB * TB / 256; ++q) {
+    const int e = tid + q * 256, r = e / TB, c = e % TB;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < TB; ++k) acc += P[r][k] * V[c][k];
+    out[q] = acc;
   }
-  __syncthreads();
-  for (int e = tid; e < TB * TB; e += 64) {
-    const int r = e / TB, c = e % TB;
-    if (r < rb) A[(size_t)(r0 + r) * n + t0 + c] = P[r][c];
+#pragma unroll
+  for (int q = 0; q < TB * TB / 256; ++q) {
+    const int e = tid + q * 256, r = e / TB, c = e % TB;
+    if (r < rb) A[(size_t)(r0 + r) * n + t0 + c] = out[q];
   }
 }
 
@@ -152,70 +187,67 @@ __global__ __launch_bounds__(256) void chol_update_kernel(SpdBatch bt, double* S
 }
 
 // ------------------------------------------------------------ triangular solves
-// B [n][m] row-major in place: forward L Z = B (upper = 0) or backward
-// L^T Z = B (upper = 1), step kb: the diagonal block, one column per thread
-__global__ __launch_bounds__(64) void trsm_diag_kernel(SpdBatch bt, double* S, int kb, int upper) {
-  const int mat = blockIdx.x, ct = blockIdx.y, tid = threadIdx.x;
-  const int n = bt.n[mat], m = bt.m[mat], t0 = kb * TB;
-  if (t0 >= n || ct * TB >= m) return;
-  const int tb = min(TB, n - t0), c0 = ct * TB, cb = min(TB, m - c0);
-  const double* L = S + bt.off[mat];
-  double* B = S + bt.offB[mat];
-  __shared__ double D[TB][TB + 1], Z[TB][TB + 1];
-  for (int e = tid; e < TB * TB; e += 64) {
-    const int r = e / TB, c = e % TB;
-    D[r][c] = (r < tb && c < tb && c <= r) ? L[(size_t)(t0 + r) * n + t0 + c] : 0.0;
-    Z[r][c] = (r < tb && c < cb) ? B[(size_t)(t0 + r) * m + c0 + c] : 0.0;
-  }
-  __syncthreads();
-  if (tid < cb) {
-    if (!upper) {
-      for (int r = 0; r < tb; ++r) {
-        double s = Z[r][tid];
-        for (int k = 0; k < r; ++k) s -= D[r][k] * Z[k][tid];
-        Z[r][tid] = s / D[r][r];
-      }
-    } else {
-      for (int r = tb - 1; r >= 0; --r) {
-        double s = Z[r][tid];
-        for (int k = r + 1; k < tb; ++k) s -= D[k][r] * Z[k][tid];
-        Z[r][tid] = s / D[r][r];
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < TB * TB; e += 64) {
-    const int r = e / TB, c = e % TB;
-    if (r < tb && c < cb) B[(size_t)(t0 + r) * m + c0 + c] = Z[r][c];
-  }
-}
-
-// the other row blocks after step kb: forward B[ib] -= L[ib][kb] Z[kb]
-// (ib > kb); backward B[ib] -= L[kb][ib]^T Z[kb] (ib < kb)
-__global__ __launch_bounds__(256) void trsm_update_kernel(SpdBatch bt, double* S, int kb, int upper) {
+// B [n][m] row-major, solved in place for L L^T X = B in two sweeps over the
+// row blocks, one launch per block step; bt.offZ is an n x m scratch.
+//   forward, step kb:  Z_kb = D_kb^-1 B_kb (written to the scratch by the
+//     workgroup of row block kb); every row block ib > kb forms Z_kb itself
+//     and updates B_ib -= L[ib][kb] Z_kb in place;
+//   backward, step kb: X_kb = D_kb^-T Z_kb (written to B by row block kb);
+//     every row block ib < kb forms X_kb itself and updates
+//     Z_ib -= L[kb][ib]^T X_kb in place.
+// Within a launch every workgroup reads only block kb of the sweep's input,
+// which no workgroup of that launch writes.
+__global__ __launch_bounds__(256) void trsm_step_kernel(SpdBatch bt, double* S, int kb, int upper) {
   const int mat = blockIdx.x, ib = blockIdx.y, ct = blockIdx.z, tid = threadIdx.x;
   const int n = bt.n[mat], m = bt.m[mat], nt = (n + TB - 1) / TB;
-  if (ib >= nt || kb >= nt || ct * TB >= m || (upper ? ib >= kb : ib <= kb)) return;
+  if (kb >= nt || ib >= nt || ct * TB >= m || (upper ? ib > kb : ib < kb)) return;
   const int t0 = kb * TB, r0 = ib * TB, c0 = ct * TB;
   const int tb = min(TB, n - t0), rb = min(TB, n - r0), cb = min(TB, m - c0);
   const double* L = S + bt.off[mat];
-  double* B = S + bt.offB[mat];
-  __shared__ double T[TB][TB + 1], Z[TB][TB + 1];
+  const double* I = S + bt.offI[mat] + (size_t)kb * TB * TB;
+  double* src = S + (upper ? bt.offZ[mat] : bt.offB[mat]);  // this sweep's input (updated in place)
+  double* dst = S + (upper ? bt.offB[mat] : bt.offZ[mat]);  // this sweep's output
+  __shared__ double V[TB][TB + 1], Bk[TB][TB + 1], Zk[TB][TB + 1];
   for (int e = tid; e < TB * TB; e += 256) {
     const int r = e / TB, c = e % TB;
-    // T[r][k]: the coefficient of Z[kb][k] in row r of block ib
-    if (!upper) T[r][c] = (r < rb && c < tb) ? L[(size_t)(r0 + r) * n + t0 + c] : 0.0;
-    else T[r][c] = (r < rb && c < tb) ? L[(size_t)(t0 + c) * n + r0 + r] : 0.0;
-    Z[r][c] = (r < tb && c < cb) ? B[(size_t)(t0 + r) * m + c0 + c] : 0.0;
+    // V[r][k]: the coefficient of Bk[k] in row r of the block's solution
+    V[r][c] = upper ? I[c * TB + r] : I[e];
+    Bk[r][c] = (r < tb && c < cb) ? src[(size_t)(t0 + r) * m + c0 + c] : 0.0;
   }
   __syncthreads();
+  constexpr int Q = TB * TB / 256;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = tid + q * 256, r = e / TB, c = e % TB;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < TB; ++k) acc += V[r][k] * Bk[k][c];
+    Zk[r][c] = acc;
+  }
+  __syncthreads();
+  if (ib == kb) {
+    for (int e = tid; e < TB * TB; e += 256) {
+      const int r = e / TB, c = e % TB;
+      if (r < tb && c < cb) dst[(size_t)(t0 + r) * m + c0 + c] = Zk[r][c];
+    }
+    return;
+  }
+  // T[r][k]: the coefficient of Zk[k] in row r of block ib
   for (int e = tid; e < TB * TB; e += 256) {
     const int r = e / TB, c = e % TB;
-    if (r >= rb || c >= cb) continue;
-    double s = 0.0;
+    if (!upper) V[r][c] = (r < rb && c < tb) ? L[(size_t)(r0 + r) * n + t0 + c] : 0.0;
+    else V[r][c] = (r < rb && c < tb) ? L[(size_t)(t0 + c) * n + r0 + r] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = tid + q * 256, r = e / TB, c = e % TB;
+    if (r < rb && c < cb) {
+      double acc = 0.0;
 #pragma unroll 8
-    for (int k = 0; k < TB; ++k) s += T[r][k] * Z[k][c];
-    B[(size_t)(r0 + r) * m + c0 + c] -= s;
+      for (int k = 0; k < TB; ++k) acc += V[r][k] * Zk[k][c];
+      src[(size_t)(r0 + r) * m + c0 + c] -= acc;
+    }
   }
 }
 
@@ -274,7 +306,7 @@ hipError_t launch_spd_cholesky(const SpdBatch& bt, double* S, hipStream_t s) {
   for (int kb = 0; kb < nt; ++kb) {
     hipLaunchKernelGGL(chol_diag_kernel, dim3(bt.nm), dim3(256), 0, s, bt, S, kb);
     if (kb + 1 < nt) {
-      hipLaunchKernelGGL(chol_panel_kernel, dim3(bt.nm, nt), dim3(64), 0, s, bt, S, kb);
+      hipLaunchKernelGGL(chol_panel_kernel, dim3(bt.nm, nt), dim3(256), 0, s, bt, S, kb);
       const int rem = nt - kb - 1;
       hipLaunchKernelGGL(chol_update_kernel, dim3(bt.nm, rem * (rem + 1) / 2), dim3(256), 0, s, bt, S, kb);
     }
@@ -288,20 +320,18 @@ hipError_t launch_spd_solve(const SpdBatch& bt, double* S, hipStream_t s) {
   const int nt = max_tiles(bt);
   int ct = 0;
   for (int i = 0; i < bt.nm; ++i) ct = std::max(ct, (bt.m[i] + TB - 1) / TB);
-  for (int kb = 0; kb < nt; ++kb) {
-    hipLaunchKernelGGL(trsm_diag_kernel, dim3(bt.nm, ct), dim3(64), 0, s, bt, S, kb, 0);
-    if (kb + 1 < nt) hipLaunchKernelGGL(trsm_update_kernel, dim3(bt.nm, nt, ct), dim3(256), 0, s, bt, S, kb, 0);
-  }
-  for (int kb = nt - 1; kb >= 0; --kb) {
-    hipLaunchKernelGGL(trsm_diag_kernel, dim3(bt.nm, ct), dim3(64), 0, s, bt, S, kb, 1);
-    if (kb > 0) hipLaunchKernelGGL(trsm_update_kernel, dim3(bt.nm, nt, ct), dim3(256), 0, s, bt, S, kb, 1);
-  }
+  for (int kb = 0; kb < nt; ++kb)
+    hipLaunchKernelGGL(trsm_step_kernel, dim3(bt.nm, nt, ct), dim3(256), 0, s, bt, S, kb, 0);
+  for (int kb = nt - 1; kb >= 0; --kb)
+    hipLaunchKernelGGL(trsm_step_kernel, dim3(bt.nm, nt, ct), dim3(256), 0, s, bt, S, kb, 1);
   return hipGetLastError();
 }
 
 hipError_t launch_kfac_prep(const KfacPrepArgs& a, hipStream_t s) {
   if (a.nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(kfac_prep_kernel, dim3(a.nb), dim3(256), 0, s, a);
+  int rows = 0;
+  for (int b = 0; b < a.nb; ++b) rows = std::max(rows, std::max(a.dA[b], a.dG[b]));
+  hipLaunchKernelGGL(kfac_prep_kernel, dim3(a.nb, (rows + PREP_ROWS - 1) / PREP_ROWS), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
