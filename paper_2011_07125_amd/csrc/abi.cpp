@@ -821,8 +821,12 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
 }
 
 // X^T Y over R rows added into grad[off ...] (K1 x N block, row-major)
+// sym: X and Y are the same columns (K1 == N) and dst is symmetric: only its
+// 64 x 64 tiles on and above the diagonal are accumulated (launch_sym_mirror
+// completes it once every chunk is in)
 static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol, int xs, int xa, int xe,
-                         const float* Y, int64_t ldy, int64_t R, int K1, int N, float* dst, hipStream_t s) {
+                         const float* Y, int64_t ldy, int64_t R, int K1, int N, float* dst, hipStream_t s,
+                         bool sym = false) {
   AtbArgs a;
   a.X = X;
   a.ldx = ldx;
@@ -836,9 +840,11 @@ static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol
   a.K1 = K1;
   a.N = N;
   a.part = b.part;
+  a.sym = sym ? 1 : 0;
   FN_T(ST_ADJ_REDUCE, launch_atb(a, s));
   const int64_t cols = (int64_t)K1 * N;
-  FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part, atb_splits(R, K1, N), (int)cols, cols, b.tmp, dst, kRowChunk, s));
+  FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part, atb_splits(R, K1, N), (int)cols, cols, b.tmp, dst, kRowChunk, s,
+                                        sym ? N : 0));
   return FN_OK;
 }
 
@@ -904,10 +910,11 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     if (kout) {
       // orbital layer of spin a: G = cot_u^T cot_u, A = a~^T a~ with a~ = sqrt(c_w) [h^L_j, 1]
       const KfacBlk* k = kblk(2, a);
-      st = atb_add(b, b.cot_u[a], b.ldu, 0, 0, 0, 0, b.cot_u[a], b.ldu, Wc * na, k->dG, k->dG, kout + k->offG, s);
+      st = atb_add(b, b.cot_u[a], b.ldu, 0, 0, 0, 0, b.cot_u[a], b.ldu, Wc * na, k->dG, k->dG, kout + k->offG, s,
+                   true);
       if (st != FN_OK) return st;
       FN_T(ST_ADJ_REDUCE, launch_kfac_aug_orbital(b.H[p.L], p.d1, p.d1, b.sc, (int)Wc, p.n, j0, na, b.ldf, b.Faug, s));
-      st = atb_add(b, b.Faug, b.ldf, 0, 0, 0, 0, b.Faug, b.ldf, Wc * na, k->dA, k->dA, kout + k->offA, s);
+      st = atb_add(b, b.Faug, b.ldf, 0, 0, 0, 0, b.Faug, b.ldf, Wc * na, k->dA, k->dA, kout + k->offA, s, true);
       if (st != FN_OK) return st;
     }
     // cot h^L of the electrons of spin a
@@ -941,11 +948,11 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
       // one-electron layer l: G = cp^T cp, A = a~^T a~ with
       // a~ = sqrt(c_w) [h_i, hbar^up, hbar^down, g^up_i, g^down_i, 1]
       const KfacBlk* k = kblk(0, l);
-      st = atb_add(b, b.CP, p.d1, 0, 0, 0, 0, b.CP, p.d1, R, k->dG, k->dG, kout + k->offG, s);
+      st = atb_add(b, b.CP, p.d1, 0, 0, 0, 0, b.CP, p.d1, R, k->dG, k->dG, kout + k->offG, s, true);
       if (st != FN_OK) return st;
       FN_T(ST_ADJ_REDUCE, launch_kfac_aug_layer(b.H[l], ldh, din, b.Hbar[l], p.dinp[l], b.G[l], p.gwp[l], ein, b.sc,
                                                 (int)Wc, p.n, b.ldf, b.Faug, s));
-      st = atb_add(b, b.Faug, b.ldf, 0, 0, 0, 0, b.Faug, b.ldf, R, k->dA, k->dA, kout + k->offA, s);
+      st = atb_add(b, b.Faug, b.ldf, 0, 0, 0, 0, b.Faug, b.ldf, R, k->dA, k->dA, kout + k->offA, s, true);
       if (st != FN_OK) return st;
     }
     // cot g^l_i = cp_i [C^up; C^down]^T  (for the two-electron stream)
@@ -1064,6 +1071,12 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
     }
     if (st != FN_OK) return st;
   }
+  if (kfac)  // the symmetric products formed only their upper tiles
+    for (const KfacBlk& k : kfac_blocks(p, nullptr))
+      if (k.kind != 1) {
+        FN_T(ST_ADJ_REDUCE, launch_sym_mirror(kout + k.offA, k.dA, s));
+        FN_T(ST_ADJ_REDUCE, launch_sym_mirror(kout + k.offG, k.dG, s));
+      }
   return FN_OK;
 }
 

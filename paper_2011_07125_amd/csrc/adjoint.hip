@@ -178,7 +178,15 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
   __shared__ float Ys[2][16][64 + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int tk = blockIdx.x, tn = blockIdx.y, split = blockIdx.z;
+  int tk = blockIdx.x, tn = blockIdx.y;
+  if (a.sym) {  // blockIdx.x enumerates the tiles tk <= tn, tn-major
+    const int p = blockIdx.x;
+    tn = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+    while (tn * (tn + 1) / 2 > p) --tn;
+    while ((tn + 1) * (tn + 2) / 2 <= p) ++tn;
+    tk = p - tn * (tn + 1) / 2;
+  }
+  const int split = blockIdx.z;
   const int k0 = tk * 64, n0 = tn * 64;
   const int64_t r_begin = (int64_t)split * rows_per_split;
   const int64_t r_end = std::min<int64_t>(r_begin + rows_per_split, a.R);
@@ -254,7 +262,8 @@ hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
   if (a.R <= 0 || a.K1 <= 0 || a.N <= 0) return hipSuccess;
   const int sp = atb_splits(a.R, a.K1, a.N);
   const int64_t rps = ((a.R + sp - 1) / sp + 15) / 16 * 16;
-  dim3 grid((a.K1 + 63) / 64, (a.N + 63) / 64, sp);
+  const int tkn = (a.K1 + 63) / 64;
+  dim3 grid(a.sym ? tkn * (tkn + 1) / 2 : tkn, a.sym ? 1 : (a.N + 63) / 64, sp);
   const bool vec = a.ldx % 4 == 0 && a.xcol % 4 == 0 && a.ldy % 4 == 0 && ((uintptr_t)a.X % 16) == 0 &&
                    ((uintptr_t)a.Y % 16) == 0;
   if (vec) hipLaunchKernelGGL(atb_kernel<true>, grid, dim3(256), 0, s, a, rps);
@@ -265,10 +274,14 @@ hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
 // ------------------------------------------------------------ row sums
 // pass 1: part[y][c] = sum_{r in chunk y} src[r * lds + c]
 // (four interleaved accumulators, combined in a fixed order)
+__device__ inline bool sym_lower(int c, int sym_n) {
+  return sym_n > 0 && (c / sym_n) / 64 > (c % sym_n) / 64;
+}
+
 __global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, int64_t lds, int64_t chunk,
-                                      float* part) {
+                                      float* part, int sym_n) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+  if (c >= cols || sym_lower(c, sym_n)) return;
   const int64_t r0 = (int64_t)blockIdx.y * chunk;
   const int64_t r1 = std::min<int64_t>(r0 + chunk, rows);
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
@@ -283,21 +296,23 @@ __global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, 
   part[(int64_t)blockIdx.y * cols + c] = (a0 + a1) + (a2 + a3);
 }
 // pass 2: dst[c] += sum_y part[y][c]; 64 columns x 4 slices of y per block
-__global__ __launch_bounds__(256) void rowsum_final_kernel(const float* part, int ny, int cols, float* dst) {
+__global__ __launch_bounds__(256) void rowsum_final_kernel(const float* part, int ny, int cols, float* dst,
+                                                            int sym_n) {
   __shared__ float sh[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
+  const bool skip = c >= cols || sym_lower(c, sym_n);
   float acc = 0.0f;
-  if (c < cols)
+  if (!skip)
     for (int y = sl; y < ny; y += 4) acc += part[(int64_t)y * cols + c];
   sh[sl][threadIdx.x & 63] = acc;
   __syncthreads();
-  if (sl == 0 && c < cols) dst[c] += (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+  if (sl == 0 && !skip) dst[c] += (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
 }
 
 int rowsum_chunks(int64_t rows, int chunk) { return (int)((rows + chunk - 1) / chunk); }
 
 hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
-                             int chunk, hipStream_t s) {
+                             int chunk, hipStream_t s, int sym_n) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   // at most 128 partial rows (never more than the tmp sizing of
   // rowsum_chunks(rows, chunk) assumes)
@@ -305,8 +320,24 @@ hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t l
   const int64_t ch = (rows + ny - 1) / ny;
   ny = (int)((rows + ch - 1) / ch);
   hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, ch,
-                     tmp);
-  hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 63) / 64), dim3(256), 0, s, tmp, ny, cols, dst);
+                     tmp, sym_n);
+  hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 63) / 64), dim3(256), 0, s, tmp, ny, cols, dst, sym_n);
+  return hipGetLastError();
+}
+
+__global__ void sym_mirror_kernel(float* M, int n) {
+  const int64_t total = (int64_t)n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n), c = (int)(e - (int64_t)r * n);
+    if (r / 64 > c / 64) M[e] = M[(int64_t)c * n + r];
+  }
+}
+
+hipError_t launch_sym_mirror(float* M, int n, hipStream_t s) {
+  if (n <= 64) return hipSuccess;
+  const int64_t total = (int64_t)n * n;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(sym_mirror_kernel, dim3(grid), dim3(256), 0, s, M, n);
   return hipGetLastError();
 }
 

@@ -136,14 +136,21 @@ struct AtbArgs {
   const float* Y; int64_t ldy;
   int64_t R; int K1, N;
   float* part;
+  // sym: X and Y are the same columns (K1 == N); only the output tiles on
+  // and above the diagonal (64 x 64) are formed
+  int sym;
 };
 int atb_splits(int64_t R, int K1, int N);   // partials written by launch_atb
 int64_t atb_part_floats(int K1max, int Nmax);  // bound on splits * K1 * N over K1 <= K1max, N <= Nmax
 hipError_t launch_atb(const AtbArgs& a, hipStream_t s);
 int rowsum_chunks(int64_t rows, int chunk);
 // dst[c] += sum_r src[r * lds + c] in a fixed order (tmp: rowsum_chunks(rows, chunk) * cols floats)
+// sym_n > 0: cols = sym_n^2 (an atb partial of a symmetric product); the
+// columns in 64 x 64 tiles below the diagonal are neither read nor written
 hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
-                             int chunk, hipStream_t s);
+                             int chunk, hipStream_t s, int sym_n = 0);
+// M[r][c] = M[c][r] for the 64 x 64 tiles below the diagonal of an n x n matrix
+hipError_t launch_sym_mirror(float* M, int n, hipStream_t s);
 hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, const float* cot, const float* u,
                                   const float* env, int W, int K, int na, int ldu, float* cot_u, float* cot_env,
                                   hipStream_t s);
