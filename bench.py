@@ -314,7 +314,7 @@ def main():
                                f"({cfg['n_up']} up/{cfg['n_down']} down), {W} walkers, {cfg['n_layers']} layers "
                                f"{cfg['width1']}/{cfg['width2']}, {cfg['n_det']} dets, isotropic envelope",
                    "walkers": W, "step": f"{mcmc_steps} Metropolis move{'s' if mcmc_steps > 1 else ''} + local energy" + (" + VMC gradient" if grad else ""),
-                   "form": "bf16x3 layer GEMMs (fp32 accumulation), fp64 determinants, fp64 re-evaluation of the "
+                   "form": "bf16x3 layer GEMMs (fp32 accumulation), fp32 orbital GEMM, fp64 determinants, fp64 re-evaluation of the "
                            f"{args.rescue_bf16:.0%} walkers of largest rounding-error scale",
                    "rescue_fraction": args.rescue_bf16,
                    "parallelism": "single GPU"},

@@ -87,10 +87,12 @@ typedef enum {
 typedef enum {
   /* every stage in float32 (layer GEMMs on FP32 MFMA) */
   FN_PREC_FP32 = 0,
-  /* layer and orbital GEMMs with bfloat16 operands and float32
-   * accumulation on MFMA; tanh, envelope and jet epilogues in float32;
-   * LU, log-determinant, A^-1 contractions and the determinant
-   * combination in float64 */
+  /* one- and two-electron layer GEMMs with split-bfloat16 operands (hi
+   * and lo parts, three bfloat16 MFMA products, float32 accumulation); the
+   * orbital GEMM in float32 (its rounding dominated the local-energy error
+   * of the form); tanh, envelope and jet epilogues in float32; LU,
+   * log-determinant, A^-1 contractions and the determinant combination in
+   * float64 */
   FN_PREC_BF16 = 1,
   /* float32 network and orbitals, float64 determinants and combination */
   FN_PREC_FP32_FP64DET = 2,

@@ -142,6 +142,11 @@ static int pack_plan(const Plan& p, std::vector<int64_t>& it) {
 }
 
 // ----------------------------------------------------------- workspace
+// bytes of the packed weights: the blocks in the arithmetic's type (two
+// bfloat16 planes in the split form) and, in the split form, float32 copies
+// of the orbital blocks at the same element offsets
+static size_t pk_bytes(const Plan& p) { return (size_t)p.pk_total * p.act + (p.bf16 ? (size_t)p.pk_total * 4 : 0); }
+
 enum Mode { VALUE = 0, JET = 1 };
 enum Stage {
   ST_PACK, ST_FEATURES, ST_TWO_E, ST_MEANFIELD, ST_GEMM_MF, ST_GEMM_LAYER, ST_GEMM_ORB, ST_DET, ST_COMBINE,
@@ -456,7 +461,7 @@ static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
     return c0.used;
   }
   Bufs b;
-  cv.take((size_t)p.pk_total * p.act);
+  cv.take(pk_bytes(p));
   if (entry == FN_ENTRY_GRAD_LOGPSI || entry == FN_ENTRY_KFAC) {
     AdjBufs ab;
     carve_adjoint(p, Wc, cv, ab, entry == FN_ENTRY_KFAC);
@@ -533,6 +538,11 @@ static fn_status pack(const Plan& p, const float* params, void* dst, hipStream_t
   std::vector<int64_t> it;
   int n = pack_plan(p, it);
   FN_T(ST_PACK, launch_pack_weights(p.mode, params, dst, p.pk_total, it.data(), n, s));
+  if (p.bf16) {  // float32 copies of the orbital blocks (the last items of the plan)
+    const int first = n - (p.nu > 0) - (p.nd > 0);
+    FN_T(ST_PACK, launch_pack_weights(MODE_F32, params, (char*)dst + (size_t)p.pk_total * 4, p.pk_total,
+                                      it.data() + (size_t)first * 11, n - first, s));
+  }
   return FN_OK;
 }
 
@@ -542,6 +552,17 @@ static const void* wt(const Bufs& b, const Plan& p, int64_t off, bool lo) {
   if (!p.bf16) return lo ? nullptr : (const char*)b.pk + off * p.act;
   return (const char*)b.pk + (off + (lo ? p.pk_total : 0)) * 2;
 }
+
+// the orbital layer's weights and the arithmetic of its product: in the
+// split-bfloat16 form the orbital GEMM runs in float32 from a float32 copy
+// of the orbital weights packed after the two bfloat16 planes (its rounding,
+// amplified by the cancellation in its dot products and by the conditioning
+// of the orbital matrices, dominated the local-energy error of the form)
+static const void* wt_orb(const Bufs& b, const Plan& p, int a) {
+  if (!p.bf16) return wt(b, p, p.pk_orb[a], false);
+  return (const char*)b.pk + ((size_t)p.pk_total * 4 + (size_t)p.pk_orb[a] * 4);
+}
+static int orb_mode(const Plan& p) { return p.mode == MODE_BF16X3 ? MODE_F32 : p.mode; }
 
 // forward pass over one chunk of Wc walkers.  jet: local energy; value:
 // sign and log|psi| only.  Launches are timed under their own stages, or
@@ -626,8 +647,8 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     o.a0 = Hin;
     o.lda0 = p.d1;
     o.ka0 = p.d1;
-    o.bt = wt(b, p, p.pk_orb[a], false);
-    o.bt_lo = wt(b, p, p.pk_orb[a], true);
+    o.bt = wt_orb(b, p, a);
+    o.bt_lo = nullptr;
     o.ldb = p.d1;
     o.n_groups = (int)(Wc * na);
     o.rows_per = Tp;
@@ -646,7 +667,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     o.pi = params + p.offpi[a];
     o.sigma = params + p.offsg[a];
     o.env_full = p.env_full;
-    FN_T(SG(ST_GEMM_ORB), launch_jet_gemm(p.mode, EPI_ORBITAL, o, s));
+    FN_T(SG(ST_GEMM_ORB), launch_jet_gemm(orb_mode(p), EPI_ORBITAL, o, s));
     FN_T(SG(ST_DET), launch_det(p.fp64, b.phi[a], p.f64, (int)Wc, p.K, na, T, p.n3, b.D[a], b.dstride, nullptr, s));
   }
   CombineArgs cb;
@@ -673,7 +694,9 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   cb.rescue_key = m == JET ? b.rkey : nullptr;
   // orbitals: split bfloat16 (16 significand bits) or float32; determinants:
   // float64 or float32
-  cb.cond_weight = (float)(std::ldexp(1.0, p.fp64 ? -53 : -24) / std::ldexp(1.0, p.mode == MODE_BF16X3 ? -16 : -24));
+  // unit roundoff of the determinant arithmetic over that of the orbital
+  // product (float32 in every form but the float64 one)
+  cb.cond_weight = (float)(std::ldexp(1.0, p.fp64 ? -53 : -24) / std::ldexp(1.0, -24));
   FN_T(SG(ST_COMBINE), launch_combine(p.fp64, cb, s));
   return FN_OK;
 }
@@ -772,8 +795,8 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
     o.a0 = b.H[p.L];
     o.lda0 = p.d1;
     o.ka0 = p.d1;
-    o.bt = wt(fb, p, p.pk_orb[a], false);
-    o.bt_lo = wt(fb, p, p.pk_orb[a], true);
+    o.bt = wt_orb(fb, p, a);
+    o.bt_lo = nullptr;
     o.ldb = p.d1;
     o.n_groups = (int)(Wc * na);
     o.rows_per = 1;
@@ -794,7 +817,7 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
     o.env_full = p.env_full;
     o.u_out = b.u[a];
     o.env_out = b.env[a];
-    FN_T(ST_ADJ_FWD, launch_jet_gemm(mode, EPI_ORBITAL, o, s));
+    FN_T(ST_ADJ_FWD, launch_jet_gemm(orb_mode(p), EPI_ORBITAL, o, s));
     FN_T(ST_ADJ_DET, launch_det(p.fp64, b.phi[a], false, (int)Wc, p.K, na, 1, p.n3, b.D[a], 2, b.binv[a], s));
   }
   CombineArgs cb;
@@ -1032,7 +1055,7 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
   const int64_t chunk = max_chunk(p, entry, ws_bytes, W);
   if (chunk < 1) return FN_ERR_WORKSPACE;
   Carver cv{(char*)ws, 0};
-  void* pk = cv.take((size_t)p.pk_total * p.act);
+  void* pk = cv.take(pk_bytes(p));
   AdjBufs b;
   carve_adjoint(p, chunk, cv, b, kfac);
   fn_status st = pack(p, params, pk, s);
@@ -1178,7 +1201,7 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
   if (chunk < 1) return FN_ERR_WORKSPACE;
   Carver cv{(char*)ws, 0};
   Bufs b;
-  b.pk = cv.take((size_t)p.pk_total * p.act);
+  b.pk = cv.take(pk_bytes(p));
   carve_forward(p, jet ? JET : VALUE, chunk, cv, b, false);
   const bool rescue = jet && p.rescue > 0.0f;
   RescueBufs r;
@@ -1258,7 +1281,7 @@ fn_status vmc_mcmc_step(const fn_config* cfg, int32_t W, float* pos, const int32
   }
   Carver cv{(char*)workspace, 0};
   Bufs b;
-  b.pk = cv.take((size_t)p.pk_total * p.act);
+  b.pk = cv.take(pk_bytes(p));
   carve_forward(p, VALUE, chunk, cv, b, true);
   st = pack(p, params, b.pk, stream);
   if (st != FN_OK) return st;

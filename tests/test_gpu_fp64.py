@@ -119,8 +119,9 @@ def test_rescue_everything_equals_fp64_form(form):
         assert np.array_equal(gr[k], g64[k]), f"{k}: rescued {form} differs from the fp64 form"
 
 
-# unit roundoff of the determinant arithmetic over that of the orbitals
-COND_WEIGHT = {"bf16": 2.0 ** -37, "fp32": 1.0}
+# unit roundoff of the determinant arithmetic over that of the orbital
+# product (float32 in both forms; the bf16 form's determinants are float64)
+COND_WEIGHT = {"bf16": 2.0 ** -29, "fp32": 1.0}
 
 
 @pytest.mark.parametrize("form,frac", [("bf16", 0.03), ("fp32", 0.02)])
@@ -150,13 +151,14 @@ def test_rescue_selects_largest_error_scale(form, frac):
     assert same64[top].all(), f"walkers of largest error scale not re-evaluated: {top[~same64[top]]}"
 
 
-@pytest.mark.parametrize("seed", [None, 101])
+@pytest.mark.parametrize("seed", [None, 101, 202, 303, 404])
 @pytest.mark.parametrize("form,frac", [("bf16", 0.03), ("fp32", 0.02)])
 def test_rescue_batch_mean_within_1mha(form, frac, seed):
-    """The Ne-like batch (4096 walkers), with its own seed and with an
-    independent one (other network parameters and walkers): with the
-    float64 re-evaluation of the default fraction the batch-mean local
-    energy is within 1 mHa of the oracle's."""
+    """The Ne-like batch (4096 walkers), with its own seed and with four
+    independent ones (other network parameters and walkers; seeds 303 and
+    404 were not used to choose the forms' settings): with the float64
+    re-evaluation of the default fraction the batch-mean local energy is
+    within 1 mHa of the oracle's."""
     say(f"case rescue batch mean ne10 seed={seed} {form} frac={frac}")
     w = I.make_workload("ne10", seed=seed)
     name = "ne10_oracle.npz" if seed is None else f"ne10_seed{seed}_oracle.npz"
