@@ -540,12 +540,21 @@ static hipError_t pick(const JetGemmArgs& a, hipStream_t s) {
     if (a.rows_per == 128) return run<MODE, 128, 32, EPI>(a, s);
     return run<MODE, 64, 64, EPI>(a, s);
   } else {
-    // column tile: 128 unless 64 wastes fewer columns
-    int w128 = (a.N + 127) / 128 * 128 - a.N;
-    int w64 = (a.N + 63) / 64 * 64 - a.N;
-    const bool bn64 = a.N <= 64 || w64 < w128;
-    if (bm96) return bn64 ? run<MODE, 96, 64, EPI>(a, s) : run<MODE, 96, 128, EPI>(a, s);
-    return bn64 ? run<MODE, 128, 64, EPI>(a, s) : run<MODE, 128, 128, EPI>(a, s);
+    // column tile: the one of 128, 96, 64 that wastes the fewest columns
+    // (the wider on ties); e.g. 96 for the 80 orbital columns of 16
+    // determinants of 5 electrons
+    const int w128 = (a.N + 127) / 128 * 128 - a.N;
+    const int w96 = (a.N + 95) / 96 * 96 - a.N;
+    const int w64 = (a.N + 63) / 64 * 64 - a.N;
+    const int bn = a.N <= 64 ? 64 : (w128 <= w96 && w128 <= w64) ? 128 : (w96 <= w64 ? 96 : 64);
+    if (bm96) {
+      if (bn == 128) return run<MODE, 96, 128, EPI>(a, s);
+      if (bn == 96) return run<MODE, 96, 96, EPI>(a, s);
+      return run<MODE, 96, 64, EPI>(a, s);
+    }
+    if (bn == 128) return run<MODE, 128, 128, EPI>(a, s);
+    if (bn == 96) return run<MODE, 128, 96, EPI>(a, s);
+    return run<MODE, 128, 64, EPI>(a, s);
   }
 }
 
