@@ -395,6 +395,81 @@ __global__ __launch_bounds__(MID_NT) void det_mid_kernel(const PT* phi, int T, i
   if (tid == 0) out[2 + n3] = q;
 }
 
+// Value-only determinants (sign and log|det|, no inverse) of 7..16-row
+// matrices, as the Metropolis and log|psi| passes need them: four matrices
+// per wavefront, sixteen lanes each, lane r of a group holding row r of its
+// matrix in registers.  Partial pivoting by a shuffle reduction over the
+// group (ties to the lower row, as in the LU of det_mid_kernel), the row
+// exchange and the pivot-row broadcast by shuffles; no LDS, no barriers.
+template <class R, class PT, int NA>
+__global__ __launch_bounds__(256) void det_value_kernel(const PT* phi, int64_t M, R* D, int dstride) {
+  const int lane = threadIdx.x & 63, r = lane & 15, base = lane & ~15;
+  const int64_t mat = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 4;  // uniform over the 16 lanes
+  const bool valid = mat < M;
+  const PT* P = phi + (valid ? mat : 0) * (int64_t)(NA * NA);
+  R a[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) a[k] = (valid && r < NA) ? (R)P[r * NA + k] : (R)0;
+  R sg = 1, la = 0;
+  bool singular = false;
+#pragma unroll
+  for (int c = 0; c < NA; ++c) {
+    R v = (r >= c && r < NA) ? fabs(a[c]) : (R)-1;
+    int idx = r;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      const R ov = __shfl_xor(v, off, 64);
+      const int oi = __shfl_xor(idx, off, 64);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    const int p = idx;  // the same in every lane of the group
+    if (v == (R)0) singular = true;
+    // exchange rows c and p (columns c .. NA-1; the rest is not needed)
+    const int src = base + (r == c ? p : (r == p ? c : r));
+#pragma unroll
+    for (int k = c; k < NA; ++k) a[k] = __shfl(a[k], src, 64);
+    R u[NA];
+#pragma unroll
+    for (int k = c; k < NA; ++k) u[k] = __shfl(a[k], base + c, 64);
+    const R piv = singular ? (R)1 : u[c];
+    if (p != c) sg = -sg;
+    if (piv < 0) sg = -sg;
+    la += log(fabs(piv));
+    const R inv_p = (R)1 / piv;  // the factorisation's own arithmetic (det_mid_kernel)
+    const R f = (r > c && r < NA) ? a[c] * inv_p : (R)0;
+#pragma unroll
+    for (int k = c + 1; k < NA; ++k) a[k] -= f * u[k];
+  }
+  if (valid && r == 0) {
+    R* out = D + mat * dstride;
+    if (singular) {
+      for (int e = 0; e < dstride; ++e) out[e] = (R)0;
+      out[1] = -INFINITY;
+    } else {
+      out[0] = sg;
+      out[1] = la;
+    }
+  }
+}
+
+template <class R, class PT>
+static hipError_t run_det_value(int na, const PT* phi, int64_t M, R* D, int dstride, hipStream_t s) {
+  const int grid = (int)((M * 16 + 255) / 256);
+#define FN_VAL(N)                                                                                       \
+  case N:                                                                                              \
+    hipLaunchKernelGGL((det_value_kernel<R, PT, N>), dim3(grid), dim3(256), 0, s, phi, M, D, dstride); \
+    break;
+  switch (na) {
+    FN_VAL(7) FN_VAL(8) FN_VAL(9) FN_VAL(10) FN_VAL(11) FN_VAL(12) FN_VAL(13) FN_VAL(14) FN_VAL(15) FN_VAL(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef FN_VAL
+  return hipGetLastError();
+}
+
 template <class R, class PT>
 static hipError_t run_det_mid(int na, const PT* phi, int grid, int T, int n3, R* D, int dstride, R* ainv,
                               hipStream_t s) {
@@ -585,6 +660,12 @@ hipError_t launch_det(bool fp64, const void* phi, bool phi64, int W, int K, int 
   const int grid = W * K;
   // 7..16 rows with the jet rows in their standard order (the Laplacian
   // row directly after the 3n tangent rows)
+  if (na <= DET_MID_MAX && T <= 1 && ainv == nullptr) {
+    const int64_t M = (int64_t)W * K;
+    if (phi64) return run_det_value<double, double>(na, pd, M, (double*)D, dstride, s);
+    return fp64 ? run_det_value<double, float>(na, pf, M, (double*)D, dstride, s)
+                : run_det_value<float, float>(na, pf, M, (float*)D, dstride, s);
+  }
   if (na <= DET_MID_MAX && (T <= 1 || T == n3 + 2)) {
     if (phi64) return run_det_mid<double, double>(na, pd, grid, T, n3, (double*)D, dstride, (double*)ainv, s);
     return fp64 ? run_det_mid<double, float>(na, pf, grid, T, n3, (double*)D, dstride, (double*)ainv, s)

@@ -160,18 +160,27 @@ def test_determinism_two_runs_bitwise():
             assert np.array_equal(a[k], b[k]), (prec, k)
 
 
-def test_logpsi_entry_matches_local_energy_and_oracle():
-    say("case logpsi ne10 W=64")
-    w = I.make_workload("ne10", walkers=64)
+@pytest.mark.parametrize("name,W,form", [("ne10", 64, "fp32"), ("ar18", 16, "fp32"), ("ar18", 16, "bf16"),
+                                         ("c4h6", 12, "fp32"), ("c4h6", 12, "bf16")])
+def test_logpsi_entry_matches_local_energy_and_oracle(name, W, form):
+    """The value pass (ferminet_logpsi; the Metropolis step's evaluation)
+    against the oracle and against the jet pass's log|psi|: 5, 9 and 15
+    electrons per spin, i.e. the register, value-only and LDS determinant
+    kernels."""
+    say(f"case logpsi {name} W={W} {form}")
+    w = I.make_workload(name, walkers=W)
     d = F.to_device(w)
-    s, l = F.ferminet_logpsi(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision="fp32")
-    g = run_gpu(w, "fp32")
+    s, l = F.ferminet_logpsi(w["cfg"], d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
+    g = run_gpu(w, form)
     o = run_oracle(w, energy=False)
     s, l = s.double().cpu().numpy(), l.double().cpu().numpy()
-    k = kappa_of(w)
-    assert np.array_equal(s, o["sign"])
-    assert (np.abs(l - o["logpsi"]) <= 1e-5 * np.maximum(1, np.abs(o["logpsi"])) + 64 * U_FORM["fp32"] * k).all()
-    assert np.abs(l - g["logpsi"]).max() <= 1e-5 * np.abs(l).max()
+    ua = U_FORM[form] * kappa_of(w)
+    decided = ua < 0.1
+    say(f"   max |d logpsi| vs oracle {np.abs(l - o['logpsi']).max():.2e}, vs jet pass {np.abs(l - g['logpsi']).max():.2e}")
+    assert np.array_equal(s[decided], o["sign"][decided])
+    assert (np.abs(l - o["logpsi"]) <= 1e-5 * np.maximum(1, np.abs(o["logpsi"])) + 64 * ua)[decided].all()
+    # the two passes differ only in the order of their roundings
+    assert (np.abs(l - g["logpsi"]) <= 1e-5 * np.maximum(1, np.abs(l)) + 64 * ua).all()
 
 
 def test_full_size_ne10_antisymmetry_and_samples():
