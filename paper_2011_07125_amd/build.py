@@ -37,7 +37,10 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(SRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(SRC, s))]
+    if missing:
+        raise RuntimeError(f"missing sources: {missing}")
+    srcs = list(SOURCES)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"

@@ -630,14 +630,16 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
 template <class R, class PT>
 static hipError_t run_det_small(int na, const PT* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
                                 hipStream_t s) {
-  const int grid = (int)((M + 255) / 256);
+  // one wavefront per block, so that the few thousand matrices of a
+  // float64 re-evaluation still spread over the compute units
+  const int grid = (int)((M + 63) / 64);
   switch (na) {
-    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6, PT>), dim3(grid), dim3(256), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

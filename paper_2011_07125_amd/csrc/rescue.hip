@@ -47,7 +47,7 @@ __global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int 
   for (int size = 2; size <= np; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = tid; i < np / 2; i += bs) {
-        const int lo = (i / stride) * stride * 2 + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride is a power of two
         const int hi = lo + stride;
         const bool up = (lo & size) == 0;
         const float klo = Ks[lo], khi = Ks[hi];
