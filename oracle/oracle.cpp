@@ -585,7 +585,9 @@ int orc_eval(const int32_t* cfg, int W, const double* pos, const double* nuc, co
     }
     double v[3];
     potential(c, p, nuc, Z, v);
-    double kin = -0.5 * (lap + g2);
+    // E_L = (H psi) / psi is undefined where psi = 0 exactly (the jets of a
+    // vanishing determinant carry no information): NaN
+    double kin = s == 0.0 ? std::numeric_limits<double>::quiet_NaN() : -0.5 * (lap + g2);
     double pot = v[0] + v[1] + v[2];
     if (e_kin) e_kin[w] = kin;
     if (e_pot) e_pot[w] = pot;

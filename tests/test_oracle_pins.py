@@ -837,3 +837,22 @@ def test_train_step_descent_direction_and_running_factors():
     take = O.vmc_train_step(*args, old, 0, 0.1, 0.02, 1e-2, 0.0, 0.0, 5.0)
     for (n, A, G), (_, A0, G0) in zip(take["factors"], free["factors"]):
         assert np.array_equal(A, A0) and np.array_equal(G, G0)
+
+
+def test_exact_node_gives_nan_local_energy():
+    """A spin-up orbital whose envelope coefficients pi vanish in every
+    determinant is zero at every electron (Eq. (5)), so every determinant
+    of Eq. (4), and psi, vanish exactly: sign 0, log|psi| = -inf, and the
+    local energy (H psi) / psi of Eq. (3) is undefined (NaN) while the
+    potential stays finite."""
+    w = small_workload(W=3)
+    cfg = w["cfg"]
+    p = w["params"].copy()
+    off, shape = I.param_offsets(cfg)["pi0"]
+    for k in range(cfg["n_det"]):
+        r = k * cfg["n_up"]
+        p[off + r * shape[1]: off + (r + 1) * shape[1]] = 0.0
+    r = O.evaluate(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], p)
+    assert (r["sign"] == 0).all() and (r["logpsi"] == -np.inf).all()
+    assert np.isnan(r["e_loc"]).all() and np.isnan(r["e_kin"]).all()
+    assert np.isfinite(r["e_pot"]).all()
