@@ -295,3 +295,53 @@ def test_mcmc_supplied_noise_equals_internal():
         outs.append((d["pos"].cpu().numpy(), l.cpu().numpy(), acc.cpu().numpy()))
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,W", [("be4", 8), ("ne10", 8), ("ar18", 4), ("c4h6", 4)])
+@pytest.mark.parametrize("form", ["fp32", "bf16"])
+def test_exact_node_zero_orbital(name, W, form):
+    """R13: with the envelope coefficients pi of one spin-up orbital zero in
+    every determinant, that orbital vanishes at every electron, every
+    spin-up orbital matrix has a zero column (which elimination keeps
+    exactly zero) and psi = 0 exactly: sign 0, log|psi| = -inf from the
+    value and the jet pass and a non-finite E_L, as in the oracle.  Covers
+    the singular paths of the 2, 5, 9 and 15 row determinant kernels."""
+    say(f"case exact node (zero orbital) {name} W={W} {form}")
+    w = I.make_workload(name, walkers=W)
+    cfg = w["cfg"]
+    p = w["params"].copy()
+    off, shape = I.param_offsets(cfg)["pi0"]  # [K n_up][N], row k n_up + i
+    for k in range(cfg["n_det"]):
+        r = k * cfg["n_up"]
+        p[off + r * shape[1]: off + (r + 1) * shape[1]] = 0.0
+    w2 = dict(w, params=p)
+    o = run_oracle(w2, energy=False)
+    assert (o["sign"] == 0).all() and (o["logpsi"] == -np.inf).all()
+    got = run_gpu(w2, form)
+    d = F.to_device(w2)
+    s, l = F.ferminet_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form)
+    torch.cuda.synchronize()
+    s, l = s.double().cpu().numpy(), l.double().cpu().numpy()
+    say(f"   value pass signs {np.unique(s)}, jet pass signs {np.unique(got['sign'])}, E_L {got['e_loc'][:3]}")
+    assert (s == 0).all() and (l == -np.inf).all()
+    assert (got["sign"] == 0).all() and (got["logpsi"] == -np.inf).all()
+    assert not np.isfinite(got["e_loc"]).any()
+
+
+@pytest.mark.parametrize("name,W", [("ne10", 8), ("c4h6", 4)])
+def test_coincident_electrons_leave_other_walkers_unchanged(name, W):
+    """Two same-spin electrons at one position (a node of psi, infinite pair
+    terms): that walker's E_L is not finite and every other walker of the
+    batch is bit for bit what it is without it."""
+    say(f"case coincident electrons {name} W={W}")
+    w = I.make_workload(name, walkers=W)
+    w2 = dict(w, pos=w["pos"].copy())
+    w2["pos"][1, 1] = w2["pos"][1, 0]  # electrons 0 and 1 are both spin up
+    for form in ("fp32", "bf16"):
+        ref = run_gpu(w, form)
+        got = run_gpu(w2, form)
+        say(f"   {form}: walker 1 sign {got['sign'][1]:.0f} log|psi| {got['logpsi'][1]:.3f} E_L {got['e_loc'][1]}")
+        assert not np.isfinite(got["e_loc"][1])
+        others = np.arange(W) != 1
+        for k in ("sign", "logpsi", "e_loc"):
+            assert np.array_equal(got[k][others], ref[k][others]), (form, k)
