@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -504,7 +505,7 @@ static const char* kStageNames[ST_COUNT] = {
     "adj_det",      "adj_orbital", "adj_layers", "adj_two_electron", "adj_reduce",     "gemm_layer_value",
     "rescue_fp64",  "kfac_precondition", "train_step"};
 static std::mutex g_time_mu;
-static bool g_timing = false;
+static std::atomic<bool> g_timing{false};
 struct StageRec {
   int stage;
   hipEvent_t a, b;

@@ -442,13 +442,10 @@ static hipError_t run_two_e(const TwoElecDev& d, int grid, hipStream_t s) {
                         two_e_sums_elems(d.ipb, d.R2, D2)) *
                        sizeof(S);
   if (shmem > 65536) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void*>(&two_electron_kernel<S, D2>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
-        return hipErrorInvalidValue;
-      attr_set = true;
-    }
+    // once per instantiation (a local static is initialised once, thread-safely)
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&two_electron_kernel<S, D2>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL((two_electron_kernel<S, D2>), dim3(grid), dim3(256), shmem, s, d);
   return hipGetLastError();

@@ -506,13 +506,11 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   const int n_mtiles = (a.n_groups + E - 1) / E;
   const int n_ntiles = (a.N + BN - 1) / BN;
   const int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, C::BYTES) != hipSuccess)
-      return hipErrorInvalidValue;
-    attr_set = true;
-  }
+  // once per instantiation (a local static is initialised once, thread-safely)
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, C::BYTES);
+  if (attr != hipSuccess) return hipErrorInvalidValue;
   hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>), dim3(grid), dim3(C::NT), C::BYTES, s, a,
                      n_mtiles, n_ntiles);
   return hipGetLastError();
