@@ -71,41 +71,62 @@ hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t
 // d/dr_i of (r_i - R_I)_c = e_c; of |r_i - R_I| = (r_i - R_I)/|r_i - R_I|;
 // Laplacian of |r_i - R_I| = 2 / |r_i - R_I|.  S: float or double
 // (arithmetic and storage).
+//
+// Item k of electron g is jet row t = k / nv and nucleus I = k % nv (nv =
+// ldh / 4): its four features, stored as one vector.  A block handles
+// several electrons when one electron has fewer items than threads (the
+// value pass has one row), and steps over the electrons of the batch.
 template <class S>
-__global__ void features_kernel(const float* pos, const float* nuc, int W, int n, int N, int T, int Tp, S* H0,
-                                int ldh) {
-  const int64_t total = (int64_t)W * n * Tp * ldh;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
-    const int f = (int)(idx % ldh);
-    const int64_t row = idx / ldh;
-    const int t = (int)(row % Tp);
-    const int64_t g = row / Tp;
-    const int i = (int)(g % n);
-    S v = 0;
-    if (f < 4 * N && t < T) {
-      const int I = f >> 2, comp = f & 3;
-      const float* r = pos + g * 3;
-      const S d0 = (S)r[0] - (S)nuc[3 * I], d1 = (S)r[1] - (S)nuc[3 * I + 1], d2 = (S)r[2] - (S)nuc[3 * I + 2];
-      const S dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-      const S dc[3] = {d0, d1, d2};
-      if (t == 0) {
-        v = comp < 3 ? dc[comp] : dist;
-      } else if (t == T - 1) {
-        v = comp < 3 ? (S)0 : (S)2 / dist;
+__global__ __launch_bounds__(256) void features_kernel(const float* pos, const float* nuc, int W, int n, int N, int T,
+                                                       int Tp, S* H0, int ldh) {
+  const int nv = ldh / 4, items = Tp * nv, groups = W * n;
+  const int epb = items >= (int)blockDim.x ? 1 : (int)blockDim.x / items;  // electrons per block step
+  for (int g0 = blockIdx.x * epb; g0 < groups; g0 += gridDim.x * epb) {
+    for (int q = threadIdx.x; q < epb * items; q += blockDim.x) {
+      const int e = q / items, k = q - e * items;
+      const int g = g0 + e;
+      if (g >= groups) break;  // e grows with q
+      const int t = k / nv, I = k - t * nv;
+      S v[4] = {0, 0, 0, 0};
+      if (I < N && t < T) {
+        const float* r = pos + (int64_t)g * 3;
+        const S d0 = (S)r[0] - (S)nuc[3 * I], d1 = (S)r[1] - (S)nuc[3 * I + 1], d2 = (S)r[2] - (S)nuc[3 * I + 2];
+        const S dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        const S dc[3] = {d0, d1, d2};
+        if (t == 0) {
+          v[0] = d0;
+          v[1] = d1;
+          v[2] = d2;
+          v[3] = dist;
+        } else if (t == T - 1) {
+          v[3] = (S)2 / dist;
+        } else {
+          const int jt = (t - 1) / 3, c = (t - 1) - 3 * jt;
+          if (jt == g % n) {
+            v[c] = (S)1;
+            v[3] = dc[c] / dist;
+          }
+        }
+      }
+      S* dst = H0 + ((int64_t)g * Tp + t) * ldh + 4 * I;
+      if constexpr (sizeof(S) == 4) {
+        *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
       } else {
-        const int jt = (t - 1) / 3, c = (t - 1) % 3;
-        if (jt == i) v = comp < 3 ? (comp == c ? (S)1 : (S)0) : dc[c] / dist;
+        reinterpret_cast<double2*>(dst)[0] = double2{(double)v[0], (double)v[1]};
+        reinterpret_cast<double2*>(dst)[1] = double2{(double)v[2], (double)v[3]};
       }
     }
-    H0[idx] = v;
   }
 }
 
 hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
                            void* H0, int ldh, hipStream_t s) {
-  int64_t total = (int64_t)W * n * Tp * ldh;
-  int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  if (grid <= 0) return hipSuccess;
+  const int64_t groups = (int64_t)W * n;
+  if (groups <= 0) return hipSuccess;
+  // rows of 16-byte-aligned vectors (buffers are 256-byte aligned)
+  if (groups >= (1LL << 31) || ldh % 4 != 0 || ldh < 4 * N) return hipErrorInvalidValue;
+  const int items = Tp * (ldh / 4), epb = items >= 256 ? 1 : 256 / items;
+  const int grid = (int)std::min<int64_t>((groups + epb - 1) / epb, 16384);
   if (f64) hipLaunchKernelGGL(features_kernel<double>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (double*)H0, ldh);
   else hipLaunchKernelGGL(features_kernel<float>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (float*)H0, ldh);
   return hipGetLastError();
