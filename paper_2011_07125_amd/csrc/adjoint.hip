@@ -273,13 +273,14 @@ hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
 
 // ------------------------------------------------------------ row sums
 // pass 1: part[y][c] = sum_{r in chunk y} src[r * lds + c]
-// (four interleaved accumulators, combined in a fixed order)
+// (four interleaved accumulators, combined in a fixed order); with one
+// chunk the sum is added straight into the destination (part = dst)
 __device__ inline bool sym_lower(int c, int sym_n) {
   return sym_n > 0 && (c / sym_n) / 64 > (c % sym_n) / 64;
 }
 
 __global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, int64_t lds, int64_t chunk,
-                                      float* part, int sym_n) {
+                                      float* part, int sym_n, int add) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols || sym_lower(c, sym_n)) return;
   const int64_t r0 = (int64_t)blockIdx.y * chunk;
@@ -293,7 +294,9 @@ __global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, 
     a3 += src[(r + 3) * lds + c];
   }
   for (; r < r1; ++r) a0 += src[r * lds + c];
-  part[(int64_t)blockIdx.y * cols + c] = (a0 + a1) + (a2 + a3);
+  const float v = (a0 + a1) + (a2 + a3);
+  if (add) part[c] += v;
+  else part[(int64_t)blockIdx.y * cols + c] = v;
 }
 // pass 2: dst[c] += sum_y part[y][c]; 64 columns x 4 slices of y per block
 __global__ __launch_bounds__(256) void rowsum_final_kernel(const float* part, int ny, int cols, float* dst,
@@ -319,8 +322,13 @@ hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t l
   int ny = std::min(rowsum_chunks(rows, chunk), 128);
   const int64_t ch = (rows + ny - 1) / ny;
   ny = (int)((rows + ch - 1) / ch);
+  if (ny == 1) {  // one pass, into dst
+    hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, 1), dim3(256), 0, s, src, rows, cols, lds, ch,
+                       dst, sym_n, 1);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, ch,
-                     tmp, sym_n);
+                     tmp, sym_n, 0);
   hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 63) / 64), dim3(256), 0, s, tmp, ny, cols, dst, sym_n);
   return hipGetLastError();
 }
