@@ -277,20 +277,35 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
           const int c0 = c4 * 4;
           if (gbase + e < n_groups) {
             S v[4] = {0, 0, 0, 0};
-            if (t < T) {
+            if (t < T && c0 < ncol) {
               const int jt = t >= 1 ? ((t - 1) * 43691) >> 17 : -1;  // (t - 1) / 3, exact for t < 2^16
               const int cc = t - 1 - 3 * jt;
               const bool shared = t == 0 || t == T - 1 || jt == ie;
               const int qq = t == 0 ? 0 : t == T - 1 ? 4 : 1 + cc;
               const bool jt_up = jt < n_up;
+              if (ein % 4 == 0) {
+                // the four columns lie in one spin half (ncol = 2 ein)
+                const int al = c0 >= ein;
+                if (shared) {
+                  const S* src = Ss + (size_t)(e * nq + qq) * ncol + c0;
 #pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                const int c = c0 + k;
-                if (c >= ncol) continue;
-                const int al = c >= ein;
-                if (shared) v[k] = Ss[(size_t)(e * nq + qq) * ncol + c];
-                else if ((al == 0) == jt_up)
-                  v[k] = Ps[((size_t)(e * n + jt) * R2 + 4 + cc) * PS + (c - al * ein)] * (al == 0 ? inv_up : inv_dn);
+                  for (int k = 0; k < 4; ++k) v[k] = src[k];
+                } else if ((al == 0) == jt_up) {
+                  const S* src = Ps + ((size_t)(e * n + jt) * R2 + 4 + cc) * PS + (c0 - al * ein);
+                  const S sc = al == 0 ? inv_up : inv_dn;
+#pragma unroll
+                  for (int k = 0; k < 4; ++k) v[k] = src[k] * sc;
+                }
+              } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  const int c = c0 + k;
+                  if (c >= ncol) continue;
+                  const int al = c >= ein;
+                  if (shared) v[k] = Ss[(size_t)(e * nq + qq) * ncol + c];
+                  else if ((al == 0) == jt_up)
+                    v[k] = Ps[((size_t)(e * n + jt) * R2 + 4 + cc) * PS + (c - al * ein)] * (al == 0 ? inv_up : inv_dn);
+                }
               }
             }
             S* dst = G + ((int64_t)(gbase + e) * Tp + t) * ldg + c0;
@@ -425,27 +440,64 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
         }
       }
       const bool res = ein == d2;
-#pragma unroll
-      for (int o = 0; o < D2; ++o) {
+      // the tanh chain rule of one output column: y = tanh u0 and
+      // dy = sech^2 u0 of the value row, s2 the sum of the squared tangents
+      auto chain = [&](int o, S y, S dy, S s2) {
         const S uo = u[o];
-        S y, dy, s2 = 0;
-        if (R2 == 8) {
-          const S u0 = __shfl(uo, tid & ~7, 64);
-          S sq = (q >= 1 && q <= 6) ? uo * uo : (S)0;
-          sq += __shfl_xor(sq, 1, 64);
-          sq += __shfl_xor(sq, 2, 64);
-          sq += __shfl_xor(sq, 4, 64);
-          s2 = sq;
-          tanh_sech2(u0, &y, &dy);
-        } else {
-          tanh_sech2(uo, &y, &dy);
-        }
         S outv;
         if (q == 0) outv = y;
         else if (q <= 6) outv = dy * uo;
         else outv = dy * uo - (S)2 * y * dy * s2;
         if (res && live) outv += Ps[(size_t)s * PS + o];
         u[o] = o < d2 ? outv : (S)0;
+      };
+      if constexpr (D2 % 8 == 0) {
+        if (R2 == 8) {
+          // jet rows: the eight lanes of a pair share u0 per column, so
+          // lane q evaluates the activation of column ob + q once and the
+          // pair exchanges the results by shuffles
+          const int pb = tid & ~7;
+#pragma unroll
+          for (int ob = 0; ob < D2; ob += 8) {
+            S u0q = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const S v = __shfl(u[ob + j], pb, 64);
+              if (q == j) u0q = v;
+            }
+            S yq, dyq;
+            tanh_sech2(u0q, &yq, &dyq);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int o = ob + j;
+              const S uo = u[o];
+              S sq = (q >= 1 && q <= 6) ? uo * uo : (S)0;
+              sq += __shfl_xor(sq, 1, 64);
+              sq += __shfl_xor(sq, 2, 64);
+              sq += __shfl_xor(sq, 4, 64);
+              chain(o, __shfl(yq, pb + j, 64), __shfl(dyq, pb + j, 64), sq);
+            }
+          }
+        }
+      }
+      if (D2 % 8 != 0 || R2 != 8) {
+#pragma unroll
+        for (int o = 0; o < D2; ++o) {
+          const S uo = u[o];
+          S y, dy, s2 = 0;
+          if (R2 == 8) {
+            const S u0 = __shfl(uo, tid & ~7, 64);
+            S sq = (q >= 1 && q <= 6) ? uo * uo : (S)0;
+            sq += __shfl_xor(sq, 1, 64);
+            sq += __shfl_xor(sq, 2, 64);
+            sq += __shfl_xor(sq, 4, 64);
+            s2 = sq;
+            tanh_sech2(u0, &y, &dy);
+          } else {
+            tanh_sech2(uo, &y, &dy);
+          }
+          chain(o, y, dy, s2);
+        }
       }
       ein = d2;
       __syncthreads();

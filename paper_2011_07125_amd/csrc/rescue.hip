@@ -13,69 +13,109 @@
 // largest key in each segment of the batch are gathered, evaluated again
 // entirely in float64, and their outputs scattered back over the
 // reduced-precision ones.
-#include <climits>
-
 #include "common.h"
 #include "kernels.h"
 
 namespace fn {
 
-// "a comes before b": larger key first, then smaller index
-__device__ inline bool before(float ka, int ia, float kb, int ib) { return ka > kb || (ka == kb && ia < ib); }
+// Order-preserving image of a key: a larger float gives a larger unsigned
+// integer, equal floats (-0 and +0 included) the same one, and NaN (an
+// undefined error scale) the largest of all.
+__device__ inline uint32_t rank_bits(float k) {
+  if (k != k) return 0xffffffffu;
+  const uint32_t b = k == 0.0f ? 0u : __float_as_uint(k);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
 
-// one workgroup per segment: bitonic sort of (key, index) pairs in LDS over
-// np = next power of two >= segment length, padding keys -inf
-__global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int W, int seg_len, int np, int k_seg,
+// exclusive prefix sum of one value per thread (blockDim.x = 1024) in LDS
+__device__ inline int block_exclusive_scan(int v, int* sc) {
+  const int tid = threadIdx.x;
+  sc[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int t = tid >= off ? sc[tid - off] : 0;
+    __syncthreads();
+    sc[tid] += t;
+    __syncthreads();
+  }
+  const int incl = sc[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+// One workgroup per segment of at most 8192 walkers: the k_seg walkers of
+// largest key, ties broken by the smaller index, written in index order.
+// The k_seg-th largest key is found by a radix select on its bytes (most
+// significant first, one 256-bin histogram per byte); the walkers above it,
+// and the first of those equal to it, are then compacted in index order.
+__global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int W, int seg_len, int k_seg,
                                                           int32_t* idx) {
-  extern __shared__ __attribute__((aligned(16))) char sm[];
-  float* Ks = reinterpret_cast<float*>(sm);
-  int* Is = reinterpret_cast<int*>(sm + (size_t)np * 4);
-  const int seg = blockIdx.x, tid = threadIdx.x, bs = blockDim.x;
+  __shared__ uint32_t Ks[8192];
+  __shared__ int hist[256];
+  __shared__ int sc[1024];
+  __shared__ int s_pick[2];
+  const int seg = blockIdx.x, tid = threadIdx.x;
   const int base = seg * seg_len;
   const int len = min(seg_len, W - base);
-  for (int i = tid; i < np; i += bs) {
-    if (i < len) {
-      float k = key[base + i];
-      Ks[i] = k != k ? INFINITY : k;  // NaN ranks first
-      Is[i] = base + i;
-    } else {
-      Ks[i] = -INFINITY;
-      Is[i] = INT_MAX;
-    }
-  }
+  for (int i = tid; i < len; i += 1024) Ks[i] = rank_bits(key[base + i]);
   __syncthreads();
-  for (int size = 2; size <= np; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < np / 2; i += bs) {
-        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride is a power of two
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const float klo = Ks[lo], khi = Ks[hi];
-        const int ilo = Is[lo], ihi = Is[hi];
-        const bool sw = up ? before(khi, ihi, klo, ilo) : before(klo, ilo, khi, ihi);
-        if (sw) {
-          Ks[lo] = khi;
-          Ks[hi] = klo;
-          Is[lo] = ihi;
-          Is[hi] = ilo;
-        }
-      }
-      __syncthreads();
+  uint32_t prefix = 0, mask = 0;
+  int need = min(k_seg, len);  // still to take among the keys that match prefix
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    for (int i = tid; i < len; i += 1024) {
+      const uint32_t u = Ks[i];
+      if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int above = 0, d = 255;
+      for (; d > 0 && above + hist[d] < need; --d) above += hist[d];
+      s_pick[0] = d;
+      s_pick[1] = need - above;
+    }
+    __syncthreads();
+    prefix |= (uint32_t)s_pick[0] << shift;
+    mask |= 0xffu << shift;
+    need = s_pick[1];
+    __syncthreads();
+  }
+  // prefix is the k_seg-th largest key; take every key above it and the
+  // first `need` keys equal to it.  Thread t owns indices [t per, (t+1) per).
+  const int per = (len + 1023) / 1024;
+  const int i0 = tid * per, i1 = min(i0 + per, len);
+  int n_gt = 0, n_eq = 0;
+  for (int i = i0; i < i1; ++i) {
+    const uint32_t u = Ks[i];
+    n_gt += u > prefix;
+    n_eq += u == prefix;
+  }
+  int gt = block_exclusive_scan(n_gt, sc);
+  int eq = block_exclusive_scan(n_eq, sc);
+  int32_t* out = idx + (size_t)seg * k_seg;
+  for (int i = i0; i < i1; ++i) {
+    const uint32_t u = Ks[i];
+    if (u > prefix) {
+      out[gt + min(eq, need)] = base + i;
+      ++gt;
+    } else if (u == prefix) {
+      if (eq < need) out[gt + eq] = base + i;
+      ++eq;
     }
   }
   // a segment shorter than k_seg repeats its first walker (same result twice)
-  for (int r = tid; r < k_seg; r += bs) idx[(size_t)seg * k_seg + r] = Is[r < len ? r : 0];
+  if (len < k_seg) {
+    __syncthreads();
+    for (int r = len + tid; r < k_seg; r += 1024) out[r] = base;
+  }
 }
 
 hipError_t launch_select_top(const float* key, int W, int seg_len, int k_seg, int32_t* idx, hipStream_t s) {
   if (W <= 0 || k_seg <= 0) return hipSuccess;
   if (seg_len <= 0 || seg_len > 8192 || k_seg > seg_len) return hipErrorInvalidValue;
-  int np = 1;
-  while (np < seg_len) np <<= 1;
   const int n_seg = (W + seg_len - 1) / seg_len;
-  const int threads = np / 2 < 1024 ? (np / 2 < 64 ? 64 : np / 2) : 1024;
-  hipLaunchKernelGGL(select_top_kernel, dim3(n_seg), dim3(threads), (size_t)np * 8, s, key, W, seg_len, np, k_seg,
-                     idx);
+  hipLaunchKernelGGL(select_top_kernel, dim3(n_seg), dim3(1024), 0, s, key, W, seg_len, k_seg, idx);
   return hipGetLastError();
 }
 
