@@ -613,14 +613,16 @@ __global__ __launch_bounds__(256) void adj_two_electron_kernel(Adj2eArgs a, int 
   }
 }
 
-// electrons per block of the two-electron backward: pair rows E n <= 128
-// and the four LDS arrays within 64 KiB
+// electrons per block of the two-electron backward: pair rows E n <= 64
+// (about 31 KiB of LDS for two-electron widths up to 32, so that five
+// blocks share a compute unit; 128 rows allowed three and took 25% longer)
+// and the LDS arrays within 64 KiB
 static int adj2e_dm(int d2) { return d2 <= 16 ? 16 : d2 <= 32 ? 32 : 64; }
 static int adj2e_group(int n, int d2) {
   const int dm = adj2e_dm(d2), ld = dm + 1;
   // LDS: three [rows][ld] arrays, W and c, 256 column-sum partials and two
   // int tables of at most 128 rows
-  const int rows_cap = std::min(128, (65536 / 4 - dm * ld - dm - 256 - 2 * 128) / (3 * ld) / 16 * 16);
+  const int rows_cap = std::min(64, (65536 / 4 - dm * ld - dm - 256 - 2 * 128) / (3 * ld) / 16 * 16);
   return std::max(1, std::min(n, rows_cap / n));
 }
 
