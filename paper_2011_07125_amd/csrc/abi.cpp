@@ -238,6 +238,8 @@ struct AdjBufs {
   float* tmp;
   float* part2;
   float* wo[2];     // orbital weights w_a, columns padded to ldu (float32)
+  uint16_t* pw = nullptr;  // split form: bfloat16 hi plane of the parameters, then the lo plane at pw_lo
+  int64_t pw_lo = 0;
   float* cot;       // [Wc]
   int ldu;
   int64_t p2;       // two-electron parameters in all
@@ -328,6 +330,10 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, boo
   b.CH[0] = (float*)cv.take((size_t)R * p.d1 * 4);
   b.CH[1] = (float*)cv.take((size_t)R * p.d1 * 4);
   b.CP = (float*)cv.take((size_t)R * p.d1 * 4);
+  if (p.bf16) {
+    b.pw_lo = (p.P + 7) / 8 * 8;  // 16-byte aligned lo plane
+    b.pw = (uint16_t*)cv.take((size_t)b.pw_lo * 2 * 2);
+  }
   b.S = (float*)cv.take((size_t)Wc * p.d1 * 4);
   b.CMF = (float*)cv.take((size_t)Wc * 2 * dmax * 4);
   // X^T Y partials: splits(R) * K1 * N with K1 <= max(d1, dinp, 2 ein), N <= max(d1, K n_a)
@@ -875,7 +881,7 @@ static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol
 // C [rows][K] times (rows of params) [N][ld] transposed: out[r][n] (=/+=) sum_k C[r][k] Wt[n][k]
 static fn_status gemm_cwt(const float* C, int ldc_in, int K, int64_t rows, const float* Wt, int ldw, int N,
                           float* out, int ldo, int accum, int o_nsub, int o_nall, int o_eoff, int stage,
-                          hipStream_t s) {
+                          hipStream_t s, const uint16_t* whi = nullptr, const uint16_t* wlo = nullptr) {
   JetGemmArgs g;
   memset(&g, 0, sizeof(g));
   g.a0 = C;
@@ -895,7 +901,14 @@ static fn_status gemm_cwt(const float* C, int ldc_in, int K, int64_t rows, const
   g.c_nall = o_nall;
   g.c_eoff = o_eoff;
   g.c_accum = accum;
-  FN_T(stage, launch_jet_gemm(MODE_F32, EPI_PLAIN, g, s));
+  // the split form multiplies by the bfloat16 planes of the weights where
+  // their rows are 16-byte aligned
+  const bool split = whi && wlo && ldw % 8 == 0 && (uintptr_t)whi % 16 == 0 && (uintptr_t)wlo % 16 == 0;
+  if (split) {
+    g.bt = whi;
+    g.bt_lo = wlo;
+  }
+  FN_T(stage, launch_jet_gemm(split ? MODE_BF16X3 : MODE_F32, EPI_PLAIN, g, s));
   return FN_OK;
 }
 
@@ -980,17 +993,20 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
       if (st != FN_OK) return st;
     }
     // cot g^l_i = cp_i [C^up; C^down]^T  (for the two-electron stream)
+    // the weights' bfloat16 planes at element offset o of the parameters (split form)
+    auto hi = [&](int64_t o) { return b.pw ? b.pw + p.offV[l] + o : nullptr; };
+    auto lo = [&](int64_t o) { return b.pw ? b.pw + b.pw_lo + p.offV[l] + o : nullptr; };
     st = gemm_cwt(b.CP, p.d1, p.d1, R, V + (int64_t)3 * din * p.d1, p.d1, 2 * ein, b.CG[l], p.gwp[l], 0, 0, 0, 0,
-                  ST_ADJ_LAYERS, s);
+                  ST_ADJ_LAYERS, s, hi((int64_t)3 * din * p.d1), lo((int64_t)3 * din * p.d1));
     if (st != FN_OK) return st;
     if (l == 0) break;  // the input features carry no parameters
     // cot h^l_i = cp_i A^T (+ cot h^{l+1}_i) + cot hbar^{a(i)} / n_a
     const bool res = din == p.d1;
     if (res) FN_T(ST_ADJ_LAYERS, launch_copy_f32(CHc, CHn, R * p.d1, s));
-    st = gemm_cwt(b.CP, p.d1, p.d1, R, V, p.d1, din, CHn, p.d1, res ? 1 : 0, 0, 0, 0, ST_ADJ_LAYERS, s);
+    st = gemm_cwt(b.CP, p.d1, p.d1, R, V, p.d1, din, CHn, p.d1, res ? 1 : 0, 0, 0, 0, ST_ADJ_LAYERS, s, hi(0), lo(0));
     if (st != FN_OK) return st;
     st = gemm_cwt(b.S, p.d1, p.d1, Wc, V + (int64_t)din * p.d1, p.d1, 2 * din, b.CMF, 2 * din, 0, 0, 0, 0,
-                  ST_ADJ_LAYERS, s);
+                  ST_ADJ_LAYERS, s, hi((int64_t)din * p.d1), lo((int64_t)din * p.d1));
     if (st != FN_OK) return st;
     FN_T(ST_ADJ_LAYERS, launch_adj_scatter_mf(b.CMF, (int)Wc, p.n, p.nu, din, din, CHn, p.d1, s));
     std::swap(CHc, CHn);
@@ -1061,6 +1077,9 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
   carve_adjoint(p, chunk, cv, b, kfac);
   fn_status st = pack(p, params, pk, s);
   if (st != FN_OK) return st;
+  // split form: the bfloat16 planes of the parameters for the reverse
+  // pass's cotangent products
+  if (b.pw) FN_T(ST_PACK, launch_split_planes(params, p.P, b.pw, b.pw + b.pw_lo, s));
   // orbital weights with zero-padded columns, float32, rows as stored
   {
     std::vector<int64_t> it;

@@ -649,6 +649,20 @@ hipError_t launch_adj_two_electron(const Adj2eArgs& a, hipStream_t s) {
   return dm == 16 ? run_adj2e<16>(a, s) : dm == 32 ? run_adj2e<32>(a, s) : run_adj2e<64>(a, s);
 }
 
+// hi and lo bfloat16 planes of a float32 vector (the split of the
+// split-bfloat16 products, element by element)
+__global__ void split_planes_kernel(const float* x, int64_t n, uint16_t* hi, uint16_t* lo) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    split_bf16(x[i], hi + i, lo + i);
+}
+
+hipError_t launch_split_planes(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(split_planes_kernel, dim3(grid), dim3(256), 0, s, x, n, hi, lo);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------- KFAC inputs
 __global__ void kfac_sqrt_weights_kernel(const float* c, int Wc, float* sc) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;

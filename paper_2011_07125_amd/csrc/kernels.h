@@ -147,6 +147,7 @@ int rowsum_chunks(int64_t rows, int chunk);
 // dst[c] += sum_r src[r * lds + c] in a fixed order (tmp: rowsum_chunks(rows, chunk) * cols floats)
 // sym_n > 0: cols = sym_n^2 (an atb partial of a symmetric product); the
 // columns in 64 x 64 tiles below the diagonal are neither read nor written
+hipError_t launch_split_planes(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t s);
 hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
                              int chunk, hipStream_t s, int sym_n = 0);
 // M[r][c] = M[c][r] for the 64 x 64 tiles below the diagonal of an n x n matrix
