@@ -87,12 +87,15 @@ typedef enum {
 typedef enum {
   /* every stage in float32 (layer GEMMs on FP32 MFMA) */
   FN_PREC_FP32 = 0,
-  /* one- and two-electron layer GEMMs with split-bfloat16 operands (hi
-   * and lo parts, three bfloat16 MFMA products, float32 accumulation); the
-   * orbital GEMM in float32 (its rounding dominated the local-energy error
-   * of the form); tanh, envelope and jet epilogues in float32; LU,
-   * log-determinant, A^-1 contractions and the determinant combination in
-   * float64 */
+  /* one-electron layer GEMMs and their mean-field terms with
+   * split-bfloat16 operands (hi and lo parts, three bfloat16 MFMA
+   * products, float32 accumulation); the two-electron layers and the
+   * orbital GEMM in float32 (the orbital product's rounding dominated the
+   * local-energy error of the form); tanh, envelope and jet epilogues in
+   * float32; LU, log-determinant, A^-1 contractions and the determinant
+   * combination in float64.  The parameter gradient's cotangent products
+   * through the one-electron layers use split-bfloat16 operands too; its
+   * reductions over walkers are float32 */
   FN_PREC_BF16 = 1,
   /* float32 network and orbitals, float64 determinants and combination */
   FN_PREC_FP32_FP64DET = 2,
