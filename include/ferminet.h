@@ -142,9 +142,10 @@ typedef struct {
    * the reduced-precision local and kinetic energy, cond the largest
    * condition number cond_1 of the walker's orbital matrices, and
    * u_det / u_orb the unit roundoff of the determinant arithmetic over that
-   * of the orbitals (2^-37 with float64 determinants of split-bfloat16
-   * orbitals, 2^-29 with float64 determinants of float32 orbitals, 1 in
-   * float32), are gathered, evaluated again as FN_PREC_FP64 would, and
+   * of the orbitals (2^-29 with the float64 determinants of float32
+   * orbitals of FN_PREC_BF16 and FN_PREC_FP32_FP64DET, 1 in FN_PREC_FP32;
+   * equal scales go to the smaller walker index, an undefined one first),
+   * are gathered, evaluated again as FN_PREC_FP64 would, and
    * their sign, log|psi|, e_loc, e_kin and e_pot replace the
    * reduced-precision values.  Rounding errors of E_L are amplified by
    * kappa near a node of the determinant sum and, in the factorisation, by
