@@ -94,8 +94,8 @@ typedef enum {
    * local-energy error of the form); tanh, envelope and jet epilogues in
    * float32; LU, log-determinant, A^-1 contractions and the determinant
    * combination in float64.  The parameter gradient's cotangent products
-   * through the one-electron layers use split-bfloat16 operands too; its
-   * reductions over walkers are float32 */
+   * through the one-electron and orbital layers use split-bfloat16
+   * operands too; its reductions over walkers are float32 */
   FN_PREC_BF16 = 1,
   /* float32 network and orbitals, float64 determinants and combination */
   FN_PREC_FP32_FP64DET = 2,

@@ -240,6 +240,7 @@ struct AdjBufs {
   float* wo[2];     // orbital weights w_a, columns padded to ldu (float32)
   uint16_t* pw = nullptr;  // split form: bfloat16 hi plane of the parameters, then the lo plane at pw_lo
   int64_t pw_lo = 0;
+  uint16_t* wo_pl[2] = {nullptr, nullptr};  // split form: hi then lo plane of wo[a] (d1 ldu each)
   float* cot;       // [Wc]
   int ldu;
   int64_t p2;       // two-electron parameters in all
@@ -333,6 +334,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, boo
   if (p.bf16) {
     b.pw_lo = (p.P + 7) / 8 * 8;  // 16-byte aligned lo plane
     b.pw = (uint16_t*)cv.take((size_t)b.pw_lo * 2 * 2);
+    for (int a = 0; a < 2; ++a) b.wo_pl[a] = (uint16_t*)cv.take((size_t)p.d1 * b.ldu * 2 * 2);
   }
   b.S = (float*)cv.take((size_t)Wc * p.d1 * 4);
   b.CMF = (float*)cv.take((size_t)Wc * 2 * dmax * 4);
@@ -955,7 +957,9 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
       if (st != FN_OK) return st;
     }
     // cot h^L of the electrons of spin a
-    st = gemm_cwt(b.cot_u[a], b.ldu, b.ldu, Wc * na, b.wo[a], b.ldu, p.d1, CHc, p.d1, 0, na, p.n, j0, ST_ADJ_ORB, s);
+    const uint16_t* wh = b.wo_pl[a];
+    st = gemm_cwt(b.cot_u[a], b.ldu, b.ldu, Wc * na, b.wo[a], b.ldu, p.d1, CHc, p.d1, 0, na, p.n, j0, ST_ADJ_ORB, s, wh,
+                  wh ? wh + (int64_t)p.d1 * b.ldu : nullptr);
     if (st != FN_OK) return st;
   }
   // one-electron layers, last to first
@@ -1090,6 +1094,11 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
       it.insert(it.end(), v, v + 11);
     }
     if (!it.empty()) FN_T(ST_PACK, launch_pack_weights(false, params, b.wo[0], 0, it.data(), (int)(it.size() / 11), s));
+    for (int a = 0; a < 2; ++a)
+      if (b.wo_pl[a] && p.na(a) > 0) {
+        const int64_t m = (int64_t)p.d1 * b.ldu;
+        FN_T(ST_PACK, launch_split_planes(b.wo[a], m, b.wo_pl[a], b.wo_pl[a] + m, s));
+      }
   }
   if (kfac) {
     int64_t total = 0;
