@@ -295,6 +295,127 @@ def test_two_electron_features_closed_form():
         assert abs(res["e_pot"][k] - pot) < 1e-12
 
 
+def _pair_stack_logpsi(x, wts, m, mutate=None):
+    """log|psi| of the 1 up + 1 down, L = 3, d1 = 2, d2 = 4 network of
+    test_two_electron_layer_stack_closed_form, written out by hand for this
+    case with the scalar functions of the namespace m (mpmath).  x: the six
+    coordinates.  mutate names one planted mistake: 'W0T'/'W1T' (transposed
+    pair weights), 'c0'/'c1' (dropped pair bias), 'res0'/'res1' (no pair
+    residual)."""
+    W0, c0, W1, c1, V1, b1, V2, b2, w0, w1, g0, g1, s = wts
+    if mutate == "W0T":
+        W0 = [list(r) for r in zip(*W0)]
+    if mutate == "W1T":
+        W1 = [list(r) for r in zip(*W1)]
+    if mutate == "c0":
+        c0 = [0.0] * 4
+    if mutate == "c1":
+        c1 = [0.0] * 4
+    k0 = 0 if mutate == "res0" else 1
+    k1 = 0 if mutate == "res1" else 1
+
+    def vecmat(v, M, b=None):  # v (len p) times M (p x q), plus b
+        q = len(M[0])
+        return [sum(v[i] * M[i][j] for i in range(len(v))) + (b[j] if b is not None else 0) for j in range(q)]
+
+    def th(v):
+        return [m.tanh(t) for t in v]
+
+    def add(*vs):
+        return [sum(t) for t in zip(*vs)]
+
+    def scale(a, v):
+        return [a * t for t in v]
+
+    r0 = m.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
+    r1 = m.sqrt(x[3] ** 2 + x[4] ** 2 + x[5] ** 2)
+    r01 = m.sqrt((x[0] - x[3]) ** 2 + (x[1] - x[4]) ** 2 + (x[2] - x[5]) ** 2)
+    d01 = [x[0] - x[3], x[1] - x[4], x[2] - x[5], r01]
+    d10 = [x[3] - x[0], x[4] - x[1], x[5] - x[2], r01]
+    # pair layer 0 (ein = d2 = 4: residual).  The diagonal pair feature is
+    # zero, so h_ii = tanh(c0) for both electrons.
+    P01 = add(th(vecmat(d01, W0, c0)), scale(k0, d01))
+    P10 = add(th(vecmat(d10, W0, c0)), scale(k0, d10))
+    Pd = th(c0)
+    # one-electron layer 0 has V0 = 0, b0 = 0 and no residual (4N != d1):
+    # h^1 = 0, so layer 1 sees only its pair means.  Each spin holds one
+    # electron: g^up_0 = h_00, g^down_0 = h_01, g^up_1 = h_10, g^down_1 = h_11.
+    Gu1, Gd1 = V1[6:10], V1[10:14]
+    h2_0 = th(add(vecmat(Pd, Gu1), vecmat(P01, Gd1), b1))
+    h2_1 = th(add(vecmat(P10, Gu1), vecmat(Pd, Gd1), b1))
+    # pair layer 1 on every pair, the diagonal included
+    Q01 = add(th(vecmat(P01, W1, c1)), scale(k1, P01))
+    Q10 = add(th(vecmat(P10, W1, c1)), scale(k1, P10))
+    Qd = add(th(vecmat(Pd, W1, c1)), scale(k1, Pd))
+    # one-electron layer 2: f_i = [h_i, hbar^up = h_0, hbar^down = h_1,
+    # g^up_i, g^down_i], plus the residual h_i
+    A, Bu, Bd, Gu2, Gd2 = V2[0:2], V2[2:4], V2[4:6], V2[6:10], V2[10:14]
+    mf = add(vecmat(h2_0, Bu), vecmat(h2_1, Bd))
+    h3_0 = add(th(add(vecmat(h2_0, A), mf, vecmat(Qd, Gu2), vecmat(Q01, Gd2), b2)), h2_0)
+    h3_1 = add(th(add(vecmat(h2_1, A), mf, vecmat(Q10, Gu2), vecmat(Qd, Gd2), b2)), h2_1)
+    u0 = vecmat(h3_0, w0)[0] + g0
+    u1 = vecmat(h3_1, w1)[0] + g1
+    return m.log(abs(u0)) - s * r0 + m.log(abs(u1)) - s * r1
+
+
+def test_two_electron_layer_stack_closed_form():
+    """Two electron layers feeding later one-electron layers (L = 3,
+    d2 = 4 = ein_0, so pair layer 0 carries the residual): pair layer l maps
+    h_ij to tanh(h_ij W_l + c_l) + h_ij, the pair means enter f_i of the
+    next one-electron layer (Section 3's equivariant network; its last layer
+    feeds the orbitals of Eq. (5)).  log|psi| is written out by hand for one
+    up and one down electron and evaluated in 50-digit arithmetic; its
+    Laplacian comes from central differences at that precision.  Each
+    planted mistake (a transposed W_l, a dropped c_l, a missing pair
+    residual) moves log|psi| far beyond the tolerance, so an oracle carrying
+    any of them fails."""
+    import mpmath as mpm
+    cfg = I.make_cfg(1, 1, 1, 3, 2, 4, 1)
+    rng = np.random.default_rng(21)
+    W0 = rng.normal(size=(4, 4)) * 0.6
+    c0 = rng.normal(size=4) * 0.5
+    W1 = rng.normal(size=(4, 4)) * 0.6
+    c1 = rng.normal(size=4) * 0.5
+    V1 = rng.normal(size=(14, 2)) * 0.5
+    b1 = rng.normal(size=2) * 0.3
+    V2 = rng.normal(size=(14, 2)) * 0.5
+    b2 = rng.normal(size=2) * 0.3
+    w0 = rng.normal(size=(2, 1))
+    w1 = rng.normal(size=(2, 1))
+    g0, g1, s, Z = 0.9, -0.8, 1.3, 2.0
+    p = blank(cfg)
+    for name, v in (("V1", V1), ("b1", b1), ("V2", V2), ("b2", b2), ("W0", W0), ("c0", c0), ("W1", W1),
+                    ("c1", c1), ("w_orb0", w0), ("w_orb1", w1), ("g_orb0", g0), ("g_orb1", g1), ("pi0", 1.0),
+                    ("pi1", 1.0), ("sigma0", s), ("sigma1", s)):
+        put(p, cfg, name, v)
+    wts = [a.tolist() if isinstance(a, np.ndarray) else a for a in (W0, c0, W1, c1, V1, b1, V2, b2, w0, w1)]
+    wts += [g0, g1, s]
+    pos = np.random.default_rng(22).normal(size=(8, 2, 3))
+    res = O.evaluate(cfg, pos, np.zeros((1, 3)), [Z], p)
+    with mpm.workdps(50):
+        h = mpm.mpf("1e-12")
+        for k in range(pos.shape[0]):
+            x = [mpm.mpf(float(v)) for v in pos[k].reshape(-1)]
+            f0 = _pair_stack_logpsi(x, wts, mpm)
+            lap = grad2 = mpm.mpf(0)
+            for c in range(6):
+                xp, xm = list(x), list(x)
+                xp[c] += h
+                xm[c] -= h
+                fp, fm = _pair_stack_logpsi(xp, wts, mpm), _pair_stack_logpsi(xm, wts, mpm)
+                lap += (fp - 2 * f0 + fm) / (h * h)
+                grad2 += ((fp - fm) / (2 * h)) ** 2
+            kin = float(-(lap + grad2) / 2)
+            pot = 1 / np.linalg.norm(pos[k, 0] - pos[k, 1]) - Z / np.linalg.norm(pos[k, 0]) - Z / np.linalg.norm(pos[k, 1])
+            assert abs(res["logpsi"][k] - float(f0)) < 1e-12
+            assert abs(res["e_kin"][k] - kin) < 1e-9 * max(1, abs(kin))
+            assert abs(res["e_pot"][k] - pot) < 1e-12
+        for mut in ("W0T", "c0", "res0", "W1T", "c1", "res1"):
+            gap = max(abs(float(_pair_stack_logpsi([mpm.mpf(float(v)) for v in pos[k].reshape(-1)], wts, mpm, mut))
+                          - res["logpsi"][k]) for k in range(pos.shape[0]))
+            assert gap > 1e-3, mut
+
+
 def test_residual_and_zero_layer():
     """A layer with zero weights adds tanh(b) to every feature through the
     residual: an L=2 network with V1 = 0, b1 = beta equals the L=1 network
