@@ -373,12 +373,16 @@ def _kfac_param_offsets(cfg):
 # the following readings are stated once here):
 #  * sampling: the caller's walkers take n_steps Metropolis steps from
 #    log|psi| at the current parameters;
+#  * walkers whose local energy is not finite (an exact node of psi, R13's
+#    coincident particles) take no part in what follows; W_f counts the
+#    others (the paper is silent; a single such walker would otherwise turn
+#    every statistic, the gradient and the step into NaN);
 #  * local energies are clipped to median +- clip_scale * mean|E_L - median|
 #    (no clipping for clip_scale <= 0) and the gradient is the energy
-#    gradient 2 sum_w (E~_w - mean E~) / W * d log|psi_w| / d theta with the
+#    gradient 2 sum_w (E~_w - mean E~) / W_f * d log|psi_w| / d theta with the
 #    clipped energies E~;
 #  * the KFAC factors are running averages F <- decay F + (1 - decay) F_batch
-#    with batch weights 1/W (decay = 0 starts them from the batch);
+#    with batch weights 1/W_f (decay = 0 starts them from the batch);
 #  * the step is theta <- theta - lr c X with X the damped KFAC direction of
 #    the gradient and c = min(1, sqrt(C / (lr^2 <X, g>))) (KFAC's norm
 #    constraint C; no constraint for C <= 0 or <X, g> <= 0).
@@ -413,12 +417,17 @@ def vmc_train_step(cfg, pos, nuc_pos, nuc_charge, params, factors, n_steps, widt
     W = pos.shape[0]
     r = evaluate(cfg, pos, nuc_pos, nuc_charge, params, threads=threads)
     e = r["e_loc"]
-    ec = clip_energies(e, clip_scale)
-    c = (ec - ec.mean()) / W
+    # walkers with a non-finite local energy (exact nodes, coincident
+    # particles) take no part in the statistics, the gradient or the factors
+    fin = np.isfinite(e)
+    Wf = int(fin.sum())
+    ec = e.copy()
+    ec[fin] = clip_energies(e[fin], clip_scale)
+    c = (ec[fin] - ec[fin].mean()) / Wf
     P = param_count(cfg)
-    per = param_grad(cfg, pos, nuc_pos, params, np.arange(P), threads=threads)
+    per = param_grad(cfg, pos[fin], nuc_pos, params, np.arange(P), threads=threads)
     g = 2.0 * (c @ per)
-    batch = kfac_factors(cfg, pos, nuc_pos, params, np.full(W, 1.0 / W), threads=threads)
+    batch = kfac_factors(cfg, pos[fin], nuc_pos, params, np.full(Wf, 1.0 / Wf), threads=threads)
     if factors is None:
         new_f = batch
     else:
@@ -428,4 +437,5 @@ def vmc_train_step(cfg, pos, nuc_pos, nuc_charge, params, factors, n_steps, widt
     q = float(X @ g)
     coef = norm_constraint_coefficient(q, lr, norm_constraint)
     return {"pos": pos, "logpsi": lp, "sign": sg, "n_accepted": acc, "e_loc": e, "e_clip": ec, "grad": g,
-            "direction": X, "x_dot_g": q, "coef": coef, "factors": new_f, "params": params - coef * X}
+            "direction": X, "x_dot_g": q, "coef": coef, "factors": new_f, "params": params - coef * X,
+            "left_out": W - Wf}

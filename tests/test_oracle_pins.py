@@ -977,3 +977,32 @@ def test_exact_node_gives_nan_local_energy():
     assert (r["sign"] == 0).all() and (r["logpsi"] == -np.inf).all()
     assert np.isnan(r["e_loc"]).all() and np.isnan(r["e_kin"]).all()
     assert np.isfinite(r["e_pot"]).all()
+
+
+def test_train_step_leaves_out_non_finite_energies():
+    """A walker whose local energy is not finite (here two same-spin
+    electrons at one point: the e-e term of Eq. (2) is infinite) takes no
+    part in the iteration: with no moves, the statistics, the gradient, the
+    factors and the step on the batch with that walker equal those on the
+    batch without it, and the walker is counted as left out."""
+    w = small_workload(W=6)
+    cfg = w["cfg"]
+    pos = w["pos"].astype(np.float64).copy()
+    bad = 2
+    pos[bad, 1] = pos[bad, 0]  # electrons 0 and 1 are both spin up
+    assert cfg["n_up"] >= 2
+    e = O.evaluate(cfg, pos, w["nuc_pos"], w["nuc_charge"], w["params"])["e_loc"]
+    assert not np.isfinite(e[bad]) and np.isfinite(np.delete(e, bad)).all()
+    keep = np.arange(pos.shape[0]) != bad
+    a = O.vmc_train_step(cfg, pos, w["nuc_pos"], w["nuc_charge"], w["params"], None, 0, 0.1, 0.02, 1e-2, 1e-3, 0.0,
+                         2.0)
+    b = O.vmc_train_step(cfg, pos[keep], w["nuc_pos"], w["nuc_charge"], w["params"], None, 0, 0.1, 0.02, 1e-2, 1e-3,
+                         0.0, 2.0)
+    assert a["left_out"] == 1 and b["left_out"] == 0
+    assert np.array_equal(a["e_clip"][keep], b["e_clip"])
+    for k in ("grad", "direction", "params"):
+        assert np.isfinite(a[k]).all()
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-14 * np.abs(b[k]).max())
+    for (n, A, G), (_, A0, G0) in zip(a["factors"], b["factors"]):
+        np.testing.assert_allclose(A, A0, rtol=1e-12, atol=1e-14 * np.abs(A0).max())
+        np.testing.assert_allclose(G, G0, rtol=1e-12, atol=1e-14 * np.abs(G0).max())
