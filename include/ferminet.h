@@ -239,11 +239,20 @@ fn_status ferminet_local_energy(const fn_config* cfg, int32_t W, const float* po
                                 float* logpsi, float* e_loc, float* e_kin, float* e_pot, void* workspace,
                                 size_t workspace_bytes, hipStream_t stream);
 
-/* Cotangent-weighted parameter gradient of log|psi| from a hand-written
- * adjoint (values recomputed, no tangents stored):
- *   grad[p] = sum_w cotangent[w] * d log|psi_w| / d theta_p
- *   cotangent [W] float32 in (required; FN_ERR_NULL if NULL)
- *   grad      [P] float32 out, in the parameter layout */
+/* Parameter gradient of log|psi| (Eq. (4)) from a hand-written adjoint
+ * (values recomputed, no tangents stored): the derivative that the
+ * gradient estimator of the energy of Eq. (3) and the KFAC statistics
+ * consume.
+ *   cotangent [W] float32 in, or NULL;
+ *   grad, with a cotangent: [P] float32 out, in the parameter layout,
+ *       grad[p] = sum_w cotangent[w] * d log|psi_w| / d theta_p;
+ *   grad, with cotangent NULL: [W][P] float32 out, row w holding
+ *       d log|psi_w| / d theta of walker w (W * P floats; the caller sizes
+ *       it, e.g. 4096 x 688832 floats = 11.3 GB for the Ne-like network).
+ * Each walker's sums run in a fixed order, so both forms are reproducible
+ * run to run.  FN_ERR_NULL if grad is NULL; FN_ERR_UNSUPPORTED in the
+ * FN_PREC_FP64 form.  With W = 0 the [P] form writes zeros and the [W][P]
+ * form writes nothing. */
 fn_status ferminet_grad_logpsi(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
                                const float* nuc_pos, const float* nuc_charge, const float* params,
                                const float* cotangent, float* grad, void* workspace, size_t workspace_bytes,
@@ -312,7 +321,10 @@ fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors,
 
 /* One iteration of the variational optimisation of E[E_L] under psi^2
  * (Eq. (3)) with KFAC (Martens and Grosse 2015), the optimiser the paper
- * names; the paper gives no settings, so they are arguments.  In order, on
+ * names; the paper gives no settings, so they are arguments.  Walkers whose
+ * local energy is not finite (an exact node of psi or coincident particles)
+ * are left out of steps 3 and 4: W_f below counts the others, and the
+ * statistics, the median and the clipping run over them only.  In order, on
  * the stream:
  *   1. log|psi| of the walkers under the current parameters, then
  *      options->mcmc_steps Metropolis moves (vmc_mcmc_step; noise and
@@ -322,17 +334,20 @@ fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors,
  *   3. E~ = e_loc clipped to median +- s * mean|e_loc - median| (the median
  *      of an even count is the mean of the two middle values; no clipping
  *      for s <= 0) and the energy gradient
- *        g = 2 sum_w (E~_w - mean E~) / W d log|psi_w| / d theta;
- *   4. the KFAC factors of the batch (weights 1/W) and the running average
+ *        g = 2 sum_w (E~_w - mean E~) / W_f d log|psi_w| / d theta;
+ *   4. the KFAC factors of the batch (weights 1/W_f) and the running average
  *        factors <- decay factors + (1 - decay) batch factors
  *      (factors: [total] float32 in/out in ferminet_kfac_layout's layout;
  *      with decay = 0 its input is not read);
  *   5. the damped direction X (ferminet_kfac_precondition) and the step
  *        params <- params - lr c X,  c = min(1, sqrt(C / (lr^2 <X, g>)))
  *      (c = 1 for C <= 0 or <X, g> <= 0), params [P] float32 in/out.
- *   stats  [8] float64 DEVICE out: mean and population variance of e_loc,
+ *   stats  [9] float64 DEVICE out: mean and population variance of e_loc,
  *          acceptance rate (accepted moves / (W mcmc_steps); 0 without
- *          moves), median, mean |e_loc - median|, mean E~, <X, g>, lr c
+ *          moves), median, mean |e_loc - median|, mean E~, <X, g>, lr c,
+ *          and the number of walkers left out (W - W_f).  With W_f = 0 the
+ *          energy statistics are NaN, the gradient and the batch factors
+ *          are zero and the parameters do not change.
  * W >= 1 (else FN_ERR_ARG); FN_ERR_UNSUPPORTED for FN_PREC_FP64.  Options
  * outside their ranges or not finite give FN_ERR_ARG.  The workspace holds
  * per-walker and per-parameter buffers for the whole batch followed by the

@@ -371,18 +371,25 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, boo
 }
 
 // ---------------------------------------- float64 re-evaluation buffers
-// Per chunk of Wc walkers: segments of at most 8192 walkers, the k_seg
-// walkers of largest error scale of each segment, R = segments x k_seg in all.
+// Per chunk of Wc walkers: segments of at most 8192 walkers; each segment
+// of len walkers re-evaluates its ceil(f len) walkers of largest error
+// scale.  Every segment but the last is full (k_seg each); the last takes
+// k_last.  R = (segments - 1) k_seg + k_last in all.
 struct RescueDims {
-  int seg_len, k_seg;
+  int seg_len, k_seg, k_last;
   int64_t R;
 };
+static int rescue_count(float f, int64_t len) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(len, (int64_t)std::ceil((double)f * (double)len)));
+}
 static RescueDims rescue_dims(const Plan& p, int64_t Wc) {
-  RescueDims d{0, 0, 0};
+  RescueDims d{0, 0, 0, 0};
   if (p.rescue <= 0.0f || Wc < 1) return d;
   d.seg_len = (int)std::min<int64_t>(Wc, 8192);
-  d.k_seg = std::max(1, std::min(d.seg_len, (int)std::ceil((double)p.rescue * d.seg_len)));
-  d.R = (Wc + d.seg_len - 1) / d.seg_len * d.k_seg;
+  const int64_t n_seg = (Wc + d.seg_len - 1) / d.seg_len;
+  d.k_seg = rescue_count(p.rescue, d.seg_len);
+  d.k_last = rescue_count(p.rescue, Wc - (n_seg - 1) * d.seg_len);
+  d.R = (n_seg - 1) * d.k_seg + d.k_last;
   return d;
 }
 
@@ -433,9 +440,9 @@ static void carve_kfac_solve(const Plan& p, Carver& cv, KfacPrepArgs& a) {
 // buffers of one VMC iteration that live across its passes (the batch of W
 // walkers; the passes take their own workspace after these)
 struct TrainBufs {
-  float *sign, *logpsi, *e_clip, *wts;
+  float *sign, *logpsi, *e_clip, *wts, *cot;
   int32_t* n_acc;
-  double *st2, *part;
+  double* part;
   float *grad, *dir, *fb;
 };
 
@@ -444,8 +451,8 @@ static void carve_train(const Plan& p, int64_t W, Carver& cv, TrainBufs& t) {
   t.logpsi = (float*)cv.take(W * 4);
   t.e_clip = (float*)cv.take(W * 4);
   t.wts = (float*)cv.take(W * 4);
+  t.cot = (float*)cv.take(W * 4);
   t.n_acc = (int32_t*)cv.take(W * 4);
-  t.st2 = (double*)cv.take(2 * 8);
   t.part = (double*)cv.take(256 * 8);
   t.grad = (float*)cv.take(p.P * 4);
   t.dir = (float*)cv.take(p.P * 4);
@@ -856,9 +863,11 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
 // sym: X and Y are the same columns (K1 == N) and dst is symmetric: only its
 // 64 x 64 tiles on and above the diagonal are accumulated (launch_sym_mirror
 // completes it once every chunk is in)
+// gld > 0: per walker instead, seg rows per walker, walker q's product
+// added at dst + q gld
 static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol, int xs, int xa, int xe,
                          const float* Y, int64_t ldy, int64_t R, int K1, int N, float* dst, hipStream_t s,
-                         bool sym = false) {
+                         bool sym = false, int64_t gld = 0, int seg = 0) {
   AtbArgs a;
   a.X = X;
   a.ldx = ldx;
@@ -873,6 +882,13 @@ static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol
   a.N = N;
   a.part = b.part;
   a.sym = sym ? 1 : 0;
+  if (gld > 0) {
+    a.dst = dst;
+    a.dst_ld = gld;
+    a.seg = seg;
+    FN_T(ST_ADJ_REDUCE, launch_atb(a, s));
+    return FN_OK;
+  }
   FN_T(ST_ADJ_REDUCE, launch_atb(a, s));
   const int64_t cols = (int64_t)K1 * N;
   FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.part, atb_splits(R, K1, N), (int)cols, cols, b.tmp, dst, kRowChunk, s,
@@ -916,9 +932,11 @@ static fn_status gemm_cwt(const float* C, int ldc_in, int K, int64_t rows, const
 
 // reverse pass of one chunk with walker cotangents cot[Wc]; adds into grad
 // (when not NULL) and, with kout, the KFAC factors of the chunk into kout
-// (the cotangents then being sqrt(c_w), held in b.sc)
+// (the cotangents then being sqrt(c_w), held in b.sc).  gld > 0: grad holds
+// one gradient per walker of the chunk, walker q's at grad + q gld.
 static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const float* nuc, const float* params,
-                          const float* cot, const AdjBufs& b, float* grad, hipStream_t s, float* kout = nullptr) {
+                          const float* cot, const AdjBufs& b, float* grad, hipStream_t s, float* kout = nullptr,
+                          int64_t gld = 0) {
   const int64_t R = Wc * p.n;
   fn_status st;
   float* CHc = b.CH[0];
@@ -940,10 +958,14 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     if (grad) {
       FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a],
                                            p.env_full, (int)Wc, p.K, na, j0, p.n, p.N, grad + p.offpi[a],
-                                           grad + p.offsg[a], s));
-      FN_T(ST_ADJ_REDUCE,
-           launch_rowsum_add(b.cot_u[a], Wc * na, p.K * na, b.ldu, b.tmp, grad + p.offg[a], kRowChunk, s));
-      st = atb_add(b, b.H[p.L], p.d1, 0, na, p.n, j0, b.cot_u[a], b.ldu, Wc * na, p.d1, p.K * na, grad + p.offw[a], s);
+                                           grad + p.offsg[a], s, gld));
+      if (gld > 0)
+        FN_T(ST_ADJ_REDUCE, launch_rowsum_seg_add(b.cot_u[a], Wc * na, na, p.K * na, b.ldu, grad + p.offg[a], gld, s));
+      else
+        FN_T(ST_ADJ_REDUCE,
+             launch_rowsum_add(b.cot_u[a], Wc * na, p.K * na, b.ldu, b.tmp, grad + p.offg[a], kRowChunk, s));
+      st = atb_add(b, b.H[p.L], p.d1, 0, na, p.n, j0, b.cot_u[a], b.ldu, Wc * na, p.d1, p.K * na, grad + p.offw[a], s,
+                   false, gld, na);
       if (st != FN_OK) return st;
     }
     if (kout) {
@@ -970,19 +992,22 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     FN_T(ST_ADJ_LAYERS, launch_adj_walker_sum(b.CP, (int)Wc, p.n, p.d1, b.S, s));
     const int ldh = l == 0 ? p.dinp[0] : p.d1;
     if (grad) {
-      FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.CP, R, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
+      if (gld > 0)
+        FN_T(ST_ADJ_REDUCE, launch_rowsum_seg_add(b.CP, R, p.n, p.d1, p.d1, grad + p.offb[l], gld, s));
+      else
+        FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.CP, R, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
       // dA = sum h_i^T cp_i
-      st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s);
+      st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s, false, gld, p.n);
       if (st != FN_OK) return st;
       // dB^a = sum_w hbar^a_w^T S_w
       for (int a = 0; a < 2; ++a) {
         st = atb_add(b, b.Hbar[l], 2 * p.dinp[l], a * p.dinp[l], 0, 0, 0, b.S, p.d1, Wc, din, p.d1,
-                     grad + p.offV[l] + (int64_t)(din + a * din) * p.d1, s);
+                     grad + p.offV[l] + (int64_t)(din + a * din) * p.d1, s, false, gld, 1);
         if (st != FN_OK) return st;
       }
       // dC = sum g_i^T cp_i (columns a ein + o)
       st = atb_add(b, b.G[l], p.gwp[l], 0, 0, 0, 0, b.CP, p.d1, R, 2 * ein, p.d1,
-                   grad + p.offV[l] + (int64_t)3 * din * p.d1, s);
+                   grad + p.offV[l] + (int64_t)3 * din * p.d1, s, false, gld, p.n);
       if (st != FN_OK) return st;
     }
     if (kout) {
@@ -1050,7 +1075,10 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     }
     FN_T(ST_ADJ_TWO_E, launch_adj_two_electron(a2, s));
     const int rows2 = adj_two_electron_rows((int)Wc, p.n, p.d2);
-    if (grad)
+    if (grad && gld > 0)
+      FN_T(ST_ADJ_REDUCE, launch_rowsum_seg_add(b.part2, rows2, (int)(rows2 / Wc), (int)b.p2, b.ldp2,
+                                                grad + p.offW2[0], gld, s));
+    else if (grad)
       FN_T(ST_ADJ_REDUCE,
            launch_rowsum_add(b.part2, rows2, (int)b.p2, b.ldp2, b.tmp, grad + p.offW2[0], kRowChunk, s));
     if (k0)
@@ -1068,7 +1096,7 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
 static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const float* nuc_pos, const float* nuc_charge,
                              const float* params, const float* cot_all, const float* e_loc, const double* stats,
                              float* grad, void* ws, size_t ws_bytes, hipStream_t s, const float* kfac_w = nullptr,
-                             float* kout = nullptr) {
+                             float* kout = nullptr, bool per_walker = false) {
   // the adjoint runs in float32 / split bfloat16 only
   if (p.f64) return FN_ERR_UNSUPPORTED;
   const bool kfac = kout != nullptr;
@@ -1105,7 +1133,7 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
     kfac_blocks(p, &total);
     FN_T(ST_ADJ_REDUCE, launch_fill_f32(kout, total, 0.0f, s));
   } else {
-    FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, per_walker ? (int64_t)W * p.P : p.P, 0.0f, s));
   }
   for (int64_t w0 = 0; w0 < W; w0 += chunk) {
     const int64_t wc = std::min<int64_t>(chunk, W - w0);
@@ -1116,6 +1144,11 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
       // cotangents sqrt(c_w): every pre-activation cotangent then carries sqrt(c_w)
       FN_T(ST_ADJ_REDUCE, launch_kfac_sqrt_weights(kfac_w + w0, (int)wc, b.sc, s));
       st = backward(p, wc, x, nuc_pos, params, b.sc, b, nullptr, s, kout);
+    } else if (per_walker) {
+      // d log|psi_w| / d theta of every walker: unit cotangents, one
+      // gradient row [P] per walker
+      FN_T(ST_ADJ_REDUCE, launch_fill_f32(b.cot, wc, 1.0f, s));
+      st = backward(p, wc, x, nuc_pos, params, b.cot, b, grad + w0 * p.P, s, nullptr, p.P);
     } else {
       const float* cot = cot_all ? cot_all + w0 : b.cot;
       if (!cot_all) FN_T(ST_ADJ_REDUCE, launch_cot_from_stats(e_loc + w0, (int)wc, stats, W, b.cot, s));
@@ -1255,7 +1288,7 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
     if (!rescue) continue;
     // float64 re-evaluation of the walkers of largest error scale
     const RescueDims d = rescue_dims(p, wc);
-    FN_T(ST_RESCUE, launch_select_top(b.rkey, (int)wc, d.seg_len, d.k_seg, r.idx, s));
+    FN_T(ST_RESCUE, launch_select_top(b.rkey, (int)wc, d.seg_len, d.k_seg, d.k_last, r.idx, s));
     FN_T(ST_RESCUE, launch_gather_walkers(x, r.idx, (int)d.R, p.n3, r.pos_r, s));
     st = forward(r.p64, JET, d.R, r.pos_r, nuc_pos, nuc_charge, params, r.b, r.out[0], r.out[1], r.out[2], r.out[3],
                  r.out[4], s, ST_RESCUE);
@@ -1343,14 +1376,16 @@ fn_status ferminet_grad_logpsi(const fn_config* cfg, int32_t W, const float* pos
   Plan p;
   fn_status st = check_common(cfg, W, pos, spins, nuc_pos, nuc_charge, params, workspace, p);
   if (st != FN_OK) return st;
-  if (!cotangent || !grad) return FN_ERR_NULL;
+  if (!grad) return FN_ERR_NULL;
   if (W == 0) {
-    const hipStream_t s = stream;
-    FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+    if (cotangent) {
+      const hipStream_t s = stream;
+      FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+    }
     return FN_OK;
   }
   return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, cotangent, nullptr, nullptr, grad, workspace,
-                     workspace_bytes, stream);
+                     workspace_bytes, stream, nullptr, nullptr, cotangent == nullptr);
 }
 
 fn_status ferminet_kfac_factors(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
@@ -1516,13 +1551,15 @@ fn_status vmc_train_step(const fn_config* cfg, int32_t W, float* pos, const int3
   st = ferminet_local_energy(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.sign, t.logpsi, e_loc, nullptr,
                              nullptr, rest, rb, s);
   if (st != FN_OK) return st;
-  FN_T(ST_TRAIN, launch_train_energy_stats(e_loc, t.n_acc, W, o.mcmc_steps, (double)o.clip_scale, t.e_clip, stats, s));
-  // energy gradient 2 sum_w (E~_w - mean E~) / W d log|psi_w| / d theta
-  st = vmc_energy_gradient(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.e_clip, t.st2, t.grad, rest, rb, s);
+  // energy statistics over the walkers with a finite local energy, the
+  // cotangents 2 (E~_w - mean E~) / W_f and the KFAC batch weights 1 / W_f
+  // (both 0 for the others)
+  FN_T(ST_TRAIN, launch_train_energy_stats(e_loc, t.n_acc, W, o.mcmc_steps, (double)o.clip_scale, t.e_clip, t.cot,
+                                           t.wts, stats, s));
+  // energy gradient 2 sum_w (E~_w - mean E~) / W_f d log|psi_w| / d theta
+  st = ferminet_grad_logpsi(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.cot, t.grad, rest, rb, s);
   if (st != FN_OK) return st;
-  FN_T(ST_TRAIN, launch_lincomb(t.grad, t.grad, 2.0f, 0.0f, p.P, s));
-  // running averages of the batch factors (weights 1/W)
-  FN_T(ST_TRAIN, launch_fill_f32(t.wts, W, 1.0f / (float)W, s));
+  // running averages of the batch factors
   st = ferminet_kfac_factors(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.wts, t.fb, rest, rb, s);
   if (st != FN_OK) return st;
   FN_T(ST_TRAIN, launch_lincomb(factors, t.fb, 1.0f - o.factor_decay, o.factor_decay, total, s));

@@ -25,7 +25,9 @@ namespace fn {
 
 // ---------------------------------------------- determinant / orbital cotangents
 // cot_u[(w na + j) * ldu + k na + i] = c_w rho_k Binv[w][k][i][j] env[w][k][j][i]
-// (zero in the padding columns), cot_env[w][k][j][i] = c_w rho_k Binv[..][i][j] u[..]
+// (zero in the padding columns), cot_env[w][k][j][i] = c_w rho_k Binv[..][i][j] u[..];
+// a walker with c_w = 0 contributes exact zeros (also where rho or Binv is
+// not finite, at a node of psi)
 template <class R>
 __global__ void adj_orbital_cot_kernel(const R* binv, const R* rho, const float* cot, const float* u,
                                        const float* env, int W, int K, int na, int ldu, float* cot_u,
@@ -41,10 +43,11 @@ __global__ void adj_orbital_cot_kernel(const R* binv, const R* rho, const float*
     if (col < K * na) {
       const int k = col / na, i = col % na;
       const int64_t m = w * K + k;
-      const R cb = (R)cot[w] * rho[m] * binv[m * nsq + i * na + j];
+      const R cw = (R)cot[w];
+      const R cb = cw == (R)0 ? (R)0 : cw * rho[m] * binv[m * nsq + i * na + j];
       const int64_t e = m * nsq + j * na + i;
-      cu = (float)(cb * (R)env[e]);
-      cot_env[e] = (float)(cb * (R)u[e]);
+      cu = cw == (R)0 ? 0.0f : (float)(cb * (R)env[e]);
+      cot_env[e] = cw == (R)0 ? 0.0f : (float)(cb * (R)u[e]);
     }
     cot_u[idx] = cu;
   }
@@ -137,10 +140,73 @@ __global__ __launch_bounds__(256) void adj_env_grad_kernel(const float* cot_env,
   }
 }
 
+// per walker (one thread per walker, orbital column and nucleus, the sum
+// over the walker's electrons j of spin a in order):
+//   dpi[w ld + col N + m] += sum_j cot_env e, dsigma likewise
+template <bool FULL>
+__global__ void adj_env_grad_walker_kernel(const float* cot_env, const float* pos, const float* nuc, const float* pi,
+                                           const float* sigma, int W, int K, int na, int j0, int n, int N,
+                                           float* dpi, float* dsigma, int64_t ld) {
+  constexpr int NS = FULL ? 9 : 1;
+  const int64_t total = (int64_t)W * K * na * N;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int cm = (int)(t % ((int64_t)K * na * N));
+    const int64_t w = t / ((int64_t)K * na * N);
+    const int col = cm / N, m = cm % N;
+    const int k = col / na, i = col % na;
+    const float p = pi[col * N + m];
+    float M[NS], asg[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      M[q] = sigma[((size_t)col * N + m) * NS + q];
+      asg[q] = 0.0f;
+    }
+    float api = 0.0f;
+    for (int j = 0; j < na; ++j) {
+      const float* x = pos + (w * n + j0 + j) * 3;
+      const float dv[3] = {x[0] - nuc[3 * m], x[1] - nuc[3 * m + 1], x[2] - nuc[3 * m + 2]};
+      const float c = cot_env[((w * K + k) * na + j) * na + i];
+      if constexpr (FULL) {
+        float u[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] = M[3 * q] * dv[0] + M[3 * q + 1] * dv[1] + M[3 * q + 2] * dv[2];
+        const float sv = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        const float e = expf(-sv);
+        api += c * e;
+        const float f = -c * p * e / sv;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) asg[3 * q + b] += f * u[q] * dv[b];
+      } else {
+        const float sa = fabsf(M[0]), sgn = M[0] < 0.0f ? -1.0f : 1.0f;
+        const float d = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        const float e = expf(-sa * d);
+        api += c * e;
+        asg[0] += c * p * e * (-sgn * d);
+      }
+    }
+    dpi[w * ld + col * N + m] += api;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) dsigma[w * ld + ((int64_t)col * N + m) * NS + q] += asg[q];
+  }
+}
+
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
                                const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
-                               float* dsigma, hipStream_t s) {
+                               float* dsigma, hipStream_t s, int64_t walker_ld) {
   if (na <= 0 || W <= 0) return hipSuccess;
+  if (walker_ld > 0) {
+    const int64_t total = (int64_t)W * K * na * N;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    if (full)
+      hipLaunchKernelGGL(adj_env_grad_walker_kernel<true>, dim3(grid), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma,
+                         W, K, na, j0, n, N, dpi, dsigma, walker_ld);
+    else
+      hipLaunchKernelGGL(adj_env_grad_walker_kernel<false>, dim3(grid), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma,
+                         W, K, na, j0, n, N, dpi, dsigma, walker_ld);
+    return hipGetLastError();
+  }
   if (full)
     hipLaunchKernelGGL(adj_env_grad_kernel<true>, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W,
                        K, na, j0, n, N, dpi, dsigma);
@@ -186,9 +252,11 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
     while ((tn + 1) * (tn + 2) / 2 <= p) ++tn;
     tk = p - tn * (tn + 1) / 2;
   }
-  const int split = blockIdx.z;
   const int k0 = tk * 64, n0 = tn * 64;
-  const int64_t r_begin = (int64_t)split * rows_per_split;
+  // per-walker mode: the z index runs over the walkers (segments of seg rows)
+  const int64_t n_split = a.dst ? a.R / a.seg : (int64_t)gridDim.z;
+  for (int64_t split = blockIdx.z; split < n_split; split += gridDim.z) {
+  const int64_t r_begin = split * rows_per_split;
   const int64_t r_end = std::min<int64_t>(r_begin + rows_per_split, a.R);
   floatx4 acc[2][2];
   for (int i = 0; i < 2; ++i)
@@ -248,7 +316,23 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
     }
     // the other buffer is written next step, after this step's barrier
   }
-  float* out = a.part + (int64_t)split * a.K1 * a.N;
+  if (a.dst) {
+    // one walker's product: each element has one owner, so += does not race
+    float* out = a.dst + split * a.dst_ld;
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + wm * 32 + i * 16 + (lane >> 4) * 4 + q;
+          const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
+          if (k < a.K1 && nn < a.N) out[(int64_t)k * a.N + nn] += acc[i][j][q];
+        }
+    // the LDS buffers are rewritten by the next walker's first step
+    __syncthreads();
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    continue;
+  }
+  float* out = a.part + split * a.K1 * a.N;
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int q = 0; q < 4; ++q) {
@@ -256,12 +340,14 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
         const int nn = n0 + wn * 32 + j * 16 + (lane & 15);
         if (k < a.K1 && nn < a.N) out[(int64_t)k * a.N + nn] = acc[i][j][q];
       }
+  }
 }
 
 hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
   if (a.R <= 0 || a.K1 <= 0 || a.N <= 0) return hipSuccess;
-  const int sp = atb_splits(a.R, a.K1, a.N);
-  const int64_t rps = ((a.R + sp - 1) / sp + 15) / 16 * 16;
+  if (a.dst && (a.seg <= 0 || a.R % a.seg != 0 || a.sym)) return hipErrorInvalidValue;
+  const int sp = a.dst ? (int)std::min<int64_t>(a.R / a.seg, 32768) : atb_splits(a.R, a.K1, a.N);
+  const int64_t rps = a.dst ? a.seg : ((a.R + sp - 1) / sp + 15) / 16 * 16;
   const int tkn = (a.K1 + 63) / 64;
   dim3 grid(a.sym ? tkn * (tkn + 1) / 2 : tkn, a.sym ? 1 : (a.N + 63) / 64, sp);
   const bool vec = a.ldx % 4 == 0 && a.xcol % 4 == 0 && a.ldy % 4 == 0 && ((uintptr_t)a.X % 16) == 0 &&
@@ -313,6 +399,29 @@ __global__ __launch_bounds__(256) void rowsum_final_kernel(const float* part, in
 }
 
 int rowsum_chunks(int64_t rows, int chunk) { return (int)((rows + chunk - 1) / chunk); }
+
+// per walker: dst[q dst_ld + c] += sum of the seg rows of segment q, in row order
+__global__ void rowsum_seg_kernel(const float* src, int64_t n_seg, int seg, int cols, int64_t lds, float* dst,
+                                  int64_t dst_ld) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  for (int64_t q = blockIdx.y; q < n_seg; q += gridDim.y) {
+    const float* p = src + q * seg * lds + c;
+    float v = 0.0f;
+    for (int r = 0; r < seg; ++r) v += p[(int64_t)r * lds];
+    dst[q * dst_ld + c] += v;
+  }
+}
+
+hipError_t launch_rowsum_seg_add(const float* src, int64_t rows, int seg, int cols, int64_t lds, float* dst,
+                                 int64_t dst_ld, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (seg <= 0 || rows % seg != 0) return hipErrorInvalidValue;
+  const int64_t n_seg = rows / seg;
+  hipLaunchKernelGGL(rowsum_seg_kernel, dim3((cols + 255) / 256, (unsigned)std::min<int64_t>(n_seg, 32768)), dim3(256),
+                     0, s, src, n_seg, seg, cols, lds, dst, dst_ld);
+  return hipGetLastError();
+}
 
 hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
                              int chunk, hipStream_t s, int sym_n) {

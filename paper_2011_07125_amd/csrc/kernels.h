@@ -107,10 +107,12 @@ struct CombineArgs {
 hipError_t launch_combine(bool fp64, const CombineArgs& a, hipStream_t s);
 
 // ---- float64 re-evaluation of selected walkers (rescue.hip)
-// idx[seg * k_seg + r], r < k_seg: the k_seg walkers of segment seg (walkers
-// seg * seg_len ..) with the largest key, in decreasing key order (NaN keys
-// count as +inf, ties by increasing index); seg_len <= 16384
-hipError_t launch_select_top(const float* key, int W, int seg_len, int k_seg, int32_t* idx, hipStream_t s);
+// idx[seg * k_seg + r], r < k: the k walkers of segment seg (walkers
+// seg * seg_len ..) with the largest key, in increasing index order (NaN keys
+// count as +inf, ties to the smaller index); k = k_seg in every full segment
+// and k_last in the last one; seg_len <= 8192
+hipError_t launch_select_top(const float* key, int W, int seg_len, int k_seg, int k_last, int32_t* idx,
+                             hipStream_t s);
 hipError_t launch_gather_walkers(const float* pos, const int32_t* idx, int R, int n3, float* pos_r, hipStream_t s);
 // out[idx[r]] = src[r] for each non-NULL (out, src) pair
 hipError_t launch_scatter_results(const int32_t* idx, int R, float* const* outs, const float* const* srcs, int n_out,
@@ -139,6 +141,12 @@ struct AtbArgs {
   // sym: X and Y are the same columns (K1 == N); only the output tiles on
   // and above the diagonal (64 x 64) are formed
   int sym;
+  // per-walker mode (dst != NULL): the rows are cut into R / seg segments of
+  // seg rows (one walker each) and segment q adds its product into
+  // dst + q * dst_ld (part and sym unused)
+  float* dst = nullptr;
+  int64_t dst_ld = 0;
+  int seg = 0;
 };
 int atb_splits(int64_t R, int K1, int N);   // partials written by launch_atb
 int64_t atb_part_floats(int K1max, int Nmax);  // bound on splits * K1 * N over K1 <= K1max, N <= Nmax
@@ -150,14 +158,20 @@ int rowsum_chunks(int64_t rows, int chunk);
 hipError_t launch_split_planes(const float* x, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t s);
 hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t lds, float* tmp, float* dst,
                              int chunk, hipStream_t s, int sym_n = 0);
+// per walker: dst[q * dst_ld + c] += sum_{r < seg} src[(q seg + r) * lds + c]
+// for the R / seg segments q (one walker each)
+hipError_t launch_rowsum_seg_add(const float* src, int64_t rows, int seg, int cols, int64_t lds, float* dst,
+                                 int64_t dst_ld, hipStream_t s);
 // M[r][c] = M[c][r] for the 64 x 64 tiles below the diagonal of an n x n matrix
 hipError_t launch_sym_mirror(float* M, int n, hipStream_t s);
 hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, const float* cot, const float* u,
                                   const float* env, int W, int K, int na, int ldu, float* cot_u, float* cot_env,
                                   hipStream_t s);
+// dpi, dsigma += the envelope-parameter gradient summed over the W walkers,
+// or (walker_ld > 0) per walker at dpi + w walker_ld, dsigma + w walker_ld
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
                                const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
-                               float* dsigma, hipStream_t s);
+                               float* dsigma, hipStream_t s, int64_t walker_ld = 0);
 hipError_t launch_adj_cp(const float* ch, const float* pre, int64_t total, float* cp, hipStream_t s);
 hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float* S, hipStream_t s);
 hipError_t launch_adj_scatter_mf(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh,
@@ -228,12 +242,14 @@ hipError_t launch_kfac_write(const KfacPrepArgs& a, hipStream_t s);      // Yt^T
 hipError_t launch_cot_from_stats(const float* e, int Wc, const double* stats, int W_total, float* cot, hipStream_t s);
 
 // ---- one VMC iteration (train.hip)
-// stats[0..5] = mean E, variance E, acceptance (sum n_acc / (W n_steps)),
-// median, mean |E - median|, mean of the clipped energies; e_clip = E
-// clipped to median +- clip_scale * that deviation (E itself if
-// clip_scale <= 0)
+// Over the W_f walkers with a finite E: stats[0..5] = mean E, variance E,
+// acceptance (sum n_acc / (W n_steps), all walkers), median, mean
+// |E - median|, mean of the clipped energies; stats[8] = W - W_f; e_clip =
+// E clipped to median +- clip_scale * that deviation (E itself if
+// clip_scale <= 0 or E is not finite); cot = 2 (e_clip - mean e_clip) / W_f
+// and wts = 1 / W_f for finite E, both 0 otherwise
 hipError_t launch_train_energy_stats(const float* e, const int32_t* n_acc, int W, int n_steps, double clip_scale,
-                                     float* e_clip, double* stats, hipStream_t s);
+                                     float* e_clip, float* cot, float* wts, double* stats, hipStream_t s);
 // y = a x + b y (y = a x when b = 0)
 hipError_t launch_lincomb(float* y, const float* x, float a, float b, int64_t n, hipStream_t s);
 // stats[6] = <x, g>, stats[7] = lr min(1, sqrt(C / (lr^2 <x, g>))) (lr when

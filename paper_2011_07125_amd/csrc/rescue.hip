@@ -43,13 +43,14 @@ __device__ inline int block_exclusive_scan(int v, int* sc) {
   return incl - v;
 }
 
-// One workgroup per segment of at most 8192 walkers: the k_seg walkers of
-// largest key, ties broken by the smaller index, written in index order.
+// One workgroup per segment of at most 8192 walkers: the k walkers of
+// largest key (k_seg in every full segment, k_last in the last one), ties
+// broken by the smaller index, written in index order at seg * k_seg.
 // The k_seg-th largest key is found by a radix select on its bytes (most
 // significant first, one 256-bin histogram per byte); the walkers above it,
 // and the first of those equal to it, are then compacted in index order.
 __global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int W, int seg_len, int k_seg,
-                                                          int32_t* idx) {
+                                                          int k_last, int32_t* idx) {
   __shared__ uint32_t Ks[8192];
   __shared__ int hist[256];
   __shared__ int sc[1024];
@@ -57,10 +58,11 @@ __global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int 
   const int seg = blockIdx.x, tid = threadIdx.x;
   const int base = seg * seg_len;
   const int len = min(seg_len, W - base);
+  const int k = seg == (int)gridDim.x - 1 ? k_last : k_seg;  // k <= len (host)
   for (int i = tid; i < len; i += 1024) Ks[i] = rank_bits(key[base + i]);
   __syncthreads();
   uint32_t prefix = 0, mask = 0;
-  int need = min(k_seg, len);  // still to take among the keys that match prefix
+  int need = k;  // still to take among the keys that match prefix
   for (int shift = 24; shift >= 0; shift -= 8) {
     if (tid < 256) hist[tid] = 0;
     __syncthreads();
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int 
     need = s_pick[1];
     __syncthreads();
   }
-  // prefix is the k_seg-th largest key; take every key above it and the
+  // prefix is the k-th largest key; take every key above it and the
   // first `need` keys equal to it.  Thread t owns indices [t per, (t+1) per).
   const int per = (len + 1023) / 1024;
   const int i0 = tid * per, i1 = min(i0 + per, len);
@@ -104,18 +106,15 @@ __global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int 
       ++eq;
     }
   }
-  // a segment shorter than k_seg repeats its first walker (same result twice)
-  if (len < k_seg) {
-    __syncthreads();
-    for (int r = len + tid; r < k_seg; r += 1024) out[r] = base;
-  }
 }
 
-hipError_t launch_select_top(const float* key, int W, int seg_len, int k_seg, int32_t* idx, hipStream_t s) {
+hipError_t launch_select_top(const float* key, int W, int seg_len, int k_seg, int k_last, int32_t* idx,
+                             hipStream_t s) {
   if (W <= 0 || k_seg <= 0) return hipSuccess;
   if (seg_len <= 0 || seg_len > 8192 || k_seg > seg_len) return hipErrorInvalidValue;
   const int n_seg = (W + seg_len - 1) / seg_len;
-  hipLaunchKernelGGL(select_top_kernel, dim3(n_seg), dim3(1024), 0, s, key, W, seg_len, k_seg, idx);
+  if (k_last < 1 || k_last > W - (n_seg - 1) * seg_len || k_last > k_seg) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(select_top_kernel, dim3(n_seg), dim3(1024), 0, s, key, W, seg_len, k_seg, k_last, idx);
   return hipGetLastError();
 }
 

@@ -10,7 +10,9 @@
 //     the float32 energies: four 8-bit digit passes, each a 256-bin LDS
 //     histogram of the keys that match the digits chosen so far;
 //   * the mean absolute deviation from the median and the clipped energies
-//     min(max(E, med - s tv), med + s tv), in float64 before rounding.
+//     min(max(E, med - s tv), med + s tv), in float64 before rounding;
+//   * the gradient cotangents and the KFAC batch weights of the walkers;
+// all over the walkers whose local energy is finite.
 #include "common.h"
 #include "kernels.h"
 
@@ -41,13 +43,14 @@ __device__ double block_sum(double v, double* red) {
   return t;
 }
 
-// the k-th smallest (0-based) of e[0..W)
+// the k-th smallest (0-based) of the finite values of e[0..W)
 __device__ float select_kth(const float* e, int W, uint32_t k, uint32_t* hist, uint32_t* bc) {
   uint32_t prefix = 0, mask = 0;
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int b = threadIdx.x; b < 256; b += kStatThreads) hist[b] = 0;
     __syncthreads();
     for (int w = threadIdx.x; w < W; w += kStatThreads) {
+      if (!isfinite(e[w])) continue;
       const uint32_t key = order_key(e[w]);
       if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
     }
@@ -73,42 +76,64 @@ __device__ float select_kth(const float* e, int W, uint32_t k, uint32_t* hist, u
   return key_float(prefix);
 }
 
+// Walkers whose local energy is not finite (an exact node, coincident
+// particles) are left out of the iteration: every statistic runs over the
+// W_f finite energies, the gradient cotangents are
+//   cot_w = 2 (E~_w - mean E~) / W_f   (0 for the others)
+// and the KFAC batch weights 1 / W_f (0 for the others).  With no finite
+// energy every cotangent and weight is 0 and the statistics are NaN.
 __global__ __launch_bounds__(kStatThreads) void train_energy_stats_kernel(const float* e, const int32_t* n_acc, int W,
                                                                           int n_steps, double clip_scale,
-                                                                          float* e_clip, double* stats) {
+                                                                          float* e_clip, float* cot, float* wts,
+                                                                          double* stats) {
   __shared__ double red[kStatThreads / 64];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t bc[2];
   const int tid = threadIdx.x;
-  double s = 0.0;
-  for (int w = tid; w < W; w += kStatThreads) s += (double)e[w];
-  const double mean = block_sum(s, red) / (double)W;
+  double s = 0.0, nf = 0.0;
+  for (int w = tid; w < W; w += kStatThreads)
+    if (isfinite(e[w])) {
+      s += (double)e[w];
+      nf += 1.0;
+    }
+  const double Wf = block_sum(nf, red);
+  const double mean = block_sum(s, red) / Wf;
   double v = 0.0;
-  for (int w = tid; w < W; w += kStatThreads) {
-    const double d = (double)e[w] - mean;
-    v += d * d;
-  }
-  const double var = block_sum(v, red) / (double)W;
+  for (int w = tid; w < W; w += kStatThreads)
+    if (isfinite(e[w])) {
+      const double d = (double)e[w] - mean;
+      v += d * d;
+    }
+  const double var = block_sum(v, red) / Wf;
   double a = 0.0;
   for (int w = tid; w < W; w += kStatThreads) a += (double)n_acc[w];
   const double acc = block_sum(a, red);
-  const float lo_k = select_kth(e, W, (uint32_t)(W - 1) / 2, hist, bc);
-  const float hi_k = select_kth(e, W, (uint32_t)W / 2, hist, bc);
-  const double med = 0.5 * ((double)lo_k + (double)hi_k);
+  const uint32_t nfi = (uint32_t)Wf;
+  double med = NAN;
+  if (nfi > 0) {
+    const float lo_k = select_kth(e, W, (nfi - 1) / 2, hist, bc);
+    const float hi_k = select_kth(e, W, nfi / 2, hist, bc);
+    med = 0.5 * ((double)lo_k + (double)hi_k);
+  }
   double t = 0.0;
-  for (int w = tid; w < W; w += kStatThreads) t += fabs((double)e[w] - med);
-  const double tv = block_sum(t, red) / (double)W;
+  for (int w = tid; w < W; w += kStatThreads)
+    if (isfinite(e[w])) t += fabs((double)e[w] - med);
+  const double tv = block_sum(t, red) / Wf;
   const bool clip = clip_scale > 0.0;
   const double lo = med - clip_scale * tv, hi = med + clip_scale * tv;
   double c = 0.0;
   for (int w = tid; w < W; w += kStatThreads) {
     const double x = (double)e[w];
-    // comparisons, not fmin/fmax, so that a NaN energy (psi = 0) stays NaN
-    const float y = clip ? (float)(x < lo ? lo : (x > hi ? hi : x)) : e[w];
+    const float y = clip && isfinite(e[w]) ? (float)(x < lo ? lo : (x > hi ? hi : x)) : e[w];
     e_clip[w] = y;
-    c += (double)y;
+    if (isfinite(e[w])) c += (double)y;
   }
-  const double cmean = block_sum(c, red) / (double)W;
+  const double cmean = block_sum(c, red) / Wf;
+  for (int w = tid; w < W; w += kStatThreads) {
+    const bool f = isfinite(e[w]);
+    cot[w] = f ? (float)(2.0 * ((double)e_clip[w] - cmean) / Wf) : 0.0f;
+    wts[w] = f ? (float)(1.0 / Wf) : 0.0f;
+  }
   if (tid == 0) {
     stats[0] = mean;
     stats[1] = var;
@@ -116,14 +141,15 @@ __global__ __launch_bounds__(kStatThreads) void train_energy_stats_kernel(const 
     stats[3] = med;
     stats[4] = tv;
     stats[5] = cmean;
+    stats[8] = (double)W - Wf;
   }
 }
 
 hipError_t launch_train_energy_stats(const float* e, const int32_t* n_acc, int W, int n_steps, double clip_scale,
-                                     float* e_clip, double* stats, hipStream_t s) {
+                                     float* e_clip, float* cot, float* wts, double* stats, hipStream_t s) {
   if (W <= 0) return hipSuccess;
   hipLaunchKernelGGL(train_energy_stats_kernel, dim3(1), dim3(kStatThreads), 0, s, e, n_acc, W, n_steps, clip_scale,
-                     e_clip, stats);
+                     e_clip, cot, wts, stats);
   return hipGetLastError();
 }
 

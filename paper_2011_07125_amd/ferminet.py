@@ -217,13 +217,16 @@ def ferminet_local_energy(cfg, pos, nuc_pos, nuc_charge, params, precision=None,
 
 
 def ferminet_grad_logpsi(cfg, pos, nuc_pos, nuc_charge, params, cotangent, precision=None, ws=None, max_chunk=None):
-    """sum_w cotangent[w] d log|psi_w| / d theta -> [P] float32."""
+    """sum_w cotangent[w] d log|psi_w| / d theta -> [P] float32; with
+    cotangent None, d log|psi_w| / d theta of every walker -> [W][P]."""
     W = pos.shape[0]
     c = make_config(cfg, precision)
-    grad = torch.empty(params.numel(), dtype=torch.float32, device=pos.device)
+    shape = (params.numel(),) if cotangent is not None else (W, params.numel())
+    grad = torch.empty(shape, dtype=torch.float32, device=pos.device)
     ws = workspace(cfg, W, FN_ENTRY_GRAD_LOGPSI, precision, pos.device, max_chunk) if ws is None else ws
     st = _lib().ferminet_grad_logpsi(ctypes.byref(c), W, _ptr(_prep(pos)), _spins(cfg), _ptr(_prep(nuc_pos)),
-                                     _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(_prep(cotangent)), _ptr(grad),
+                                     _ptr(_prep(nuc_charge)), _ptr(_prep(params)),
+                                     _ptr(_prep(cotangent)) if cotangent is not None else None, _ptr(grad),
                                      _ptr(ws), ws.numel(), _stream())
     _check(st, "ferminet_grad_logpsi")
     return grad
@@ -311,13 +314,14 @@ def vmc_train_step(cfg, pos, nuc_pos, nuc_charge, params, factors, mcmc_steps, m
                    uniforms=None, precision=None, rescue=0.0, ws=None):
     """One VMC iteration (include/ferminet.h), in place on pos, params and
     factors (the running KFAC factors, kfac_layout's total floats).
-    Returns (e_loc [W] float32, stats [8] float64: mean and variance of
+    Returns (e_loc [W] float32, stats [9] float64: mean and variance of
     e_loc, acceptance rate, median, mean |e_loc - median|, mean of the
-    clipped energies, <X, g>, step length lr c)."""
+    clipped energies, <X, g>, step length lr c, walkers left out for a
+    non-finite local energy)."""
     W = pos.shape[0]
     c = make_config(cfg, precision, rescue)
     e = torch.empty(W, dtype=torch.float32, device=pos.device)
-    stats = torch.empty(8, dtype=torch.float64, device=pos.device)
+    stats = torch.empty(9, dtype=torch.float64, device=pos.device)
     o = fn_train_options(int(mcmc_steps), float(mcmc_width), int(seed), int(counter), float(learning_rate),
                          float(damping), float(norm_constraint), float(factor_decay), float(clip_scale), 0)
     ws = workspace(cfg, W, FN_ENTRY_TRAIN, precision, pos.device, rescue=rescue) if ws is None else ws

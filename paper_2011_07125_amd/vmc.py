@@ -65,7 +65,7 @@ def train(cfg, pos, nuc_pos, nuc_charge, params, iterations, precision="bf16", m
         counter += mcmc_steps
         st = st.cpu().tolist()
         rec = {"t": t, "energy": st[0], "variance": st[1], "acceptance": st[2], "width": width, "lr": lr,
-               "step": st[7]}
+               "step": st[7], "left_out": int(st[8])}
         history.append(rec)
         acc_sum += st[2]
         if adapt_every and (t + 1) % adapt_every == 0:

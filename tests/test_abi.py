@@ -109,7 +109,8 @@ def test_entry_points_reject_bad_arguments_before_launch():
     assert g(ctypes.byref(c), 8, fake, good, fake, fake, fake, fake, fake, 1, 0.1, 0, 0, fake, None, fake, fake,
              1 << 30, None) == 7
     h = lib.ferminet_grad_logpsi
-    assert h(ctypes.byref(c), 8, fake, good, fake, fake, fake, None, fake, fake, 1 << 30, None) == 1
+    assert h(ctypes.byref(c), 8, fake, good, fake, fake, fake, fake, None, fake, 1 << 30, None) == 1  # NULL grad
+    assert h(ctypes.byref(c), 8, fake, good, fake, fake, fake, None, None, fake, 1 << 30, None) == 1
     assert lib.vmc_mcmc_noise(-1, 4, 1, 0, 0, fake, fake, None) == 7
     assert lib.ferminet_status_string(4).decode().startswith("workspace")
 

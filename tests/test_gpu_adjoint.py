@@ -160,3 +160,41 @@ def test_grad_chunked_equals_single_pass_and_is_deterministic():
     assert torch.equal(a, b)
     # chunks change the order of the sums over walkers only
     assert torch.allclose(a, c, rtol=1e-4, atol=1e-6 * a.abs().max().item())
+
+
+@pytest.mark.parametrize("name,W,form", [("be4", 48, "fp32"), ("ne10", 8, "fp32"), ("ne10", 8, "bf16"),
+                                         ("c4h6", 3, "fp32")])
+def test_per_walker_gradient_vs_oracle(name, W, form):
+    """cotangent NULL: d log|psi_w| / d theta of every walker ([W][P]) on a
+    seeded subset of 64 parameters plus the first and last entry of every
+    block, walker by walker against the oracle's dual numbers (each walker
+    against its own amplification); the cotangent-weighted sum of the rows
+    equals the [P] form; a chunked call gives the same rows bit for bit."""
+    say(f"case per-walker gradient {name} W={W} {form}")
+    w = I.make_workload(name, walkers=W)
+    cfg = w["cfg"]
+    d = F.to_device(w)
+    G = F.ferminet_grad_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], None, precision=form)
+    Gc = F.ferminet_grad_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], None, precision=form,
+                                max_chunk=max(1, W // 3))
+    cot = np.random.default_rng(7).normal(size=W).astype(np.float32)
+    g = F.ferminet_grad_logpsi(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"],
+                               torch.from_numpy(cot).cuda(), precision=form)
+    torch.cuda.synchronize()
+    assert tuple(G.shape) == (W, F.param_count(cfg))
+    assert torch.equal(G, Gc)
+    G = G.double().cpu().numpy()
+    assert np.isfinite(G).all()
+    sel = selection(cfg, w["seed"], n_pick=64)
+    per = O.param_grad(cfg, w["pos"], w["nuc_pos"], w["params"], sel, threads=THREADS)
+    amp = O.amplification(cfg, w["pos"], w["nuc_pos"], w["params"], threads=THREADS)[0]
+    for k in range(W):
+        check(f"{name}/{form}/walker {k}", G[k, sel], per[k], amp[k], form)
+    # the weighted sum of the rows against the [P] form (float32 sums in
+    # another order: relative to the largest term)
+    ref = cot.astype(np.float64) @ G
+    gd = g.double().cpu().numpy()
+    scale = (np.abs(cot)[:, None] * np.abs(G)).sum(0).max()
+    err = np.abs(gd - ref).max() / scale
+    say(f"   sum over walkers vs the [P] form: max error {err:.2e} of the largest term sum")
+    assert err <= 1e-5

@@ -170,11 +170,14 @@ def test_rescue_batch_mean_within_1mha(form, frac, seed):
     assert err <= 1e-3
 
 
-def test_rescue_several_segments():
+@pytest.mark.parametrize("W", [8193, 9000])
+def test_rescue_several_segments(W):
     """More walkers than one selection segment (8192): each segment
-    re-evaluates its own walkers of largest error scale."""
-    say("case rescue segments be4 W=9000")
-    w = I.make_workload("be4", walkers=9000)
+    re-evaluates its own ceil(f x segment) walkers of largest error scale,
+    the short last segment included (1 walker of the 1-walker tail of 8193,
+    9 of the 808-walker tail of 9000 at f = 0.01)."""
+    say(f"case rescue segments be4 W={W}")
+    w = I.make_workload("be4", walkers=W)
     frac = 0.01
     g64 = run_gpu(w, "fp64")
     gp = run_gpu(w, "fp32")
@@ -182,12 +185,12 @@ def test_rescue_several_segments():
     same64 = np.all([gr[q] == g64[q] for q in KEYS], axis=0)
     sameplain = np.all([gr[q] == gp[q] for q in KEYS], axis=0)
     assert (same64 | sameplain).all()
-    k_seg = int(np.ceil(frac * 8192))
-    for lo, hi in ((0, 8192), (8192, 9000)):
+    for lo, hi in ((0, 8192), (8192, W)):
+        k = int(np.ceil(frac * (hi - lo)))
         changed = int((~sameplain[lo:hi]).sum())
-        say(f"   segment [{lo}, {hi}): changed {changed} (k_seg {k_seg})")
-        assert changed <= k_seg
-        assert same64[lo:hi].sum() >= min(k_seg, hi - lo)
+        say(f"   segment [{lo}, {hi}): changed {changed} (k {k})")
+        assert changed <= k
+        assert same64[lo:hi].sum() >= k
 
 
 def test_rescue_chunked():

@@ -202,3 +202,47 @@ def test_short_optimisation_lowers_the_energy():
     for t in (0, 50, 100, 200, 299):
         say(f"   t={t} E={e[t]:.4f} var={v[t]:.3f} step={hist[t]['step']:.2e}")
     assert last < first - 5 * err
+
+
+def test_train_step_leaves_out_non_finite_energy():
+    """One walker of the two-nucleus network with two same-spin electrons at
+    one point (an infinite e-e term, a non-finite local energy): the
+    iteration leaves it out, as the oracle does, so the parameters stay
+    finite and the step equals the step on the batch without it; the left
+    out walker is counted in stats[8]."""
+    say("case train step with a non-finite local energy two_nuclei W=12")
+    w = two_nuclei(W=12)
+    cfg = w["cfg"]
+    bad = 4
+    w["pos"][bad, 1] = w["pos"][bad, 0]
+    keep = np.arange(12) != bad
+    lr, lam, clip = 0.05, 1e-3, 2.0
+    o = O.vmc_train_step(cfg, w["pos"], w["nuc_pos"], w["nuc_charge"], w["params"], None, 0, 0.1, lr, lam, 0.0, 0.0,
+                         clip, threads=THREADS)
+    assert o["left_out"] == 1
+    res = {}
+    for name, sub in (("with", np.arange(12)), ("without", np.nonzero(keep)[0])):
+        ws = dict(w, pos=w["pos"][sub])
+        d = F.to_device(ws)
+        _, total = F.kfac_layout(cfg)
+        fac = torch.zeros(total, device="cuda")
+        e, st = F.vmc_train_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], fac, 0, 0.1, 0, 0, lr,
+                                 lam, 0.0, 0.0, clip, precision="fp32")
+        torch.cuda.synchronize()
+        res[name] = (e.double().cpu().numpy(), st.cpu().numpy(), d["params"].double().cpu().numpy())
+    e1, st1, th1 = res["with"]
+    e2, st2, th2 = res["without"]
+    step1, step2 = th1 - w["params"], th2 - w["params"]
+    step_o = o["params"] - w["params"].astype(np.float64)
+    rel = np.linalg.norm(step1 - step2) / np.linalg.norm(step2)
+    rel_o = np.linalg.norm(step1 - step_o) / np.linalg.norm(step_o)
+    say(f"   E_L of the walker {e1[bad]}; left out {st1[8]:.0f} / {st2[8]:.0f}; mean E {st1[0]:.6f} vs {st2[0]:.6f} "
+        f"(oracle {np.mean(o['e_loc'][keep]):.6f}); step rel diff to the batch without it {rel:.2e}, to the oracle "
+        f"{rel_o:.2e}")
+    assert not np.isfinite(e1[bad])
+    assert st1[8] == 1 and st2[8] == 0
+    assert np.isfinite(th1).all() and np.isfinite(st1[:8]).all()
+    assert np.array_equal(e1[keep], e2)
+    assert abs(st1[0] - st2[0]) <= 1e-12 * abs(st2[0]) and abs(st1[3] - st2[3]) <= 1e-12 * abs(st2[3])
+    assert rel <= 1e-5
+    assert rel_o <= 1e-2
