@@ -7,12 +7,14 @@ a Metropolis move of every walker (log|psi| of the proposal), the local
 energy (sign, log|psi|, kinetic energy from the jets, Coulomb potential)
 and the VMC energy gradient from the hand-written adjoint.  The headline
 form runs the layer GEMMs in split bfloat16 (three bf16 MFMA passes, fp32
-accumulation) with float64 determinants; the plain fp32 form is timed
-beside it on the same inputs.  In both, the local energy of the walkers of
-largest rounding-error scale (determinant-sum cancellation kappa times the
-kinetic-energy magnitude, and for float32 determinants the conditioning of
-the orbital matrices; 3% and 2% of the batch by default) is re-evaluated in
-float64 inside the timed step.  Prints one JSON line.
+accumulation) with float64 determinants; the FP32 form (fp32 layer and
+orbital products, float64 determinants) is timed beside it on the same
+inputs, and the all-fp32 form (float32 determinants too) for context.  In
+each, the local energy of the walkers of largest rounding-error scale
+(determinant-sum cancellation kappa times the kinetic-energy magnitude,
+and for float32 determinants the conditioning of the orbital matrices) is
+re-evaluated in float64 inside the timed step, at the workload's fraction
+(3% of the Ne-like batch in both forms).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -251,9 +253,12 @@ def main():
     ap.add_argument("--no-kfac", action="store_true", help="skip timing the KFAC statistics")
     ap.add_argument("--no-full-envelope", action="store_true",
                     help="skip timing the same step with the full-covariance envelope of Eq. (5)")
-    ap.add_argument("--rescue-bf16", type=float, default=0.03,
-                    help="fraction of walkers whose local energy is re-evaluated in float64 (bf16 form)")
-    ap.add_argument("--rescue-fp32", type=float, default=0.02, help="the same for the fp32 form")
+    ap.add_argument("--rescue-bf16", type=float, default=None,
+                    help="fraction of walkers whose local energy is re-evaluated in float64 (bf16 form; default: "
+                         "the workload's own, inputs.RESCUE)")
+    ap.add_argument("--rescue-fp32", type=float, default=None, help="the same for the fp32 form")
+    ap.add_argument("--no-pure-fp32", action="store_true",
+                    help="skip timing the fp32 form with float32 determinants")
     ap.add_argument("--mcmc-steps", type=int, default=None,
                     help="Metropolis moves per step (default: the workload's own, else 1)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -268,6 +273,10 @@ def main():
         copy_calibration()
     w = I.make_workload(args.workload)
     cfg = w["cfg"]
+    if args.rescue_bf16 is None:
+        args.rescue_bf16 = I.RESCUE[args.workload]["bf16"]
+    if args.rescue_fp32 is None:
+        args.rescue_fp32 = I.RESCUE[args.workload]["fp32_fp64det"]
     W = w["pos"].shape[0]
     T = 3 * cfg["n_elec"] + 2
     mcmc_steps = args.mcmc_steps if args.mcmc_steps is not None else w["spec"].get("mcmc_steps", 1)
@@ -282,9 +291,18 @@ def main():
     ms_bf, st_bf = time_form(w, "bf16", args.steps, args.warmup, grad, args.rescue_bf16, mcmc_steps)
     res = {}
     if not args.no_fp32:
-        ms_32, st_32 = time_form(w, "fp32", args.steps, args.warmup, grad, args.rescue_fp32, mcmc_steps)
+        # the FP32 form: every layer and orbital product in float32, the
+        # determinants in float64 like the bf16 form's, so that the two
+        # forms differ in the layer products only
+        ms_32, st_32 = time_form(w, "fp32_fp64det", args.steps, args.warmup, grad, args.rescue_fp32, mcmc_steps)
         res["fp32_form"] = {"value": W / (ms_32 * 1e-3), "ms_per_step": ms_32, "rescue_fraction": args.rescue_fp32,
+                            "form": "fp32 layer and orbital GEMMs (fp32 MFMA), fp64 determinants",
+                            "bf16_speedup": ms_32 / ms_bf,
                             "stage_ms": {k: round(v[0] / 2, 4) for k, v in st_32.items()}}
+    if not args.no_pure_fp32:
+        ms_p, _ = time_form(w, "fp32", args.steps, args.warmup, grad, args.rescue_fp32, mcmc_steps)
+        res["fp32_pure_form"] = {"value": W / (ms_p * 1e-3), "ms_per_step": ms_p, "rescue_fraction": args.rescue_fp32,
+                                 "form": "everything in fp32, determinants included (timing only)"}
     if not args.no_full_envelope:
         # the same step with a general 3x3 Sigma per orbital and nucleus, the
         # envelope that Section 3 replaces by the isotropic one to save time
@@ -370,11 +388,11 @@ def main():
                      "ceiling_basis": "algorithmic MFMA FLOPs of the step (local energy, Metropolis value passes, "
                                       "adjoint as three value passes) at the 2.5 PFLOP/s dense bf16 peak"}}
     golden = os.path.join(ROOT, "tests", "golden", f"{args.workload}_oracle.npz")
-    if os.path.exists(golden) and not args.no_accuracy and "pos" not in np.load(golden):
+    if os.path.exists(golden) and not args.no_accuracy and "pos" not in np.load(golden).files:
         res["accuracy_bf16"] = accuracy(w, "bf16", golden, args.rescue_bf16)
         res["accuracy_bf16"]["reeval_share_of_step"] = st_bf.get("rescue_fp64", (0.0, 1))[0] / 2 / ms_bf
         if not args.no_fp32:
-            res["accuracy_fp32"] = accuracy(w, "fp32", golden, args.rescue_fp32)
+            res["accuracy_fp32"] = accuracy(w, "fp32_fp64det", golden, args.rescue_fp32)
             res["accuracy_fp32"]["reeval_share_of_step"] = st_32.get("rescue_fp64", (0.0, 1))[0] / 2 / ms_32
     line = {
         "metric": "walker local-energy evals/sec (Ne-like, 16 dets) BF16+adjoint vs FP32 at <=1 mHa",

@@ -49,6 +49,21 @@ SPECS = {
                      mcmc_steps=10, mcmc_width=0.02),
 }
 
+# Fraction of each batch whose local energy the throughput measurement and
+# the accuracy gate re-evaluate in float64, per workload and form: "bf16"
+# (split-bf16 layer products, fp32 orbital product, fp64 determinants) and
+# "fp32_fp64det" (fp32 layer and orbital products, fp64 determinants).
+# The bf16 form on the 30-electron molecule (c4h6) does not reach a 1 mHa
+# batch mean at any fraction tried up to 20%; that workload's stated form is
+# fp32.
+RESCUE = {
+    "be4": {"bf16": 0.03, "fp32_fp64det": 0.02},
+    "ne10": {"bf16": 0.03, "fp32_fp64det": 0.03},
+    "ar18": {"bf16": 0.05, "fp32_fp64det": 0.03},
+    "c4h6": {"bf16": 0.05, "fp32_fp64det": 0.10},
+    "c4h6_vmc": {"bf16": 0.03, "fp32_fp64det": 0.03},
+}
+
 
 def make_cfg(n_up, n_down, n_nuc, n_layers, width1, width2, n_det, precision="fp32", envelope="isotropic"):
     """envelope: 'isotropic' (one sigma per orbital and nucleus, Section 3)
