@@ -153,8 +153,20 @@ def workspace(cfg: dict, W: int, entry: int, precision=None, device=None, max_ch
     key = (device.index if device.index is not None else torch.cuda.current_device(), entry)
     buf = _WS.get(key)
     if buf is None or buf.numel() < nbytes:
+        # the outgrown buffer goes first, and its memory back to the device
+        # (a batch of the 30-electron molecule takes about 100 GB), so that
+        # the larger one is not refused for want of a contiguous block
         _WS.pop(key, None)
-        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        del buf
+        torch.cuda.empty_cache()
+        try:
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        except torch.OutOfMemoryError:
+            # the other entry points' buffers on this device give way
+            for k in [k for k in _WS if k[0] == key[0]]:
+                del _WS[k]
+            torch.cuda.empty_cache()
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
         _WS[key] = buf
     # exactly the requested size, so that a smaller max_chunk takes effect
     return buf[:nbytes]
@@ -162,6 +174,7 @@ def workspace(cfg: dict, W: int, entry: int, precision=None, device=None, max_ch
 
 def release_workspaces():
     _WS.clear()
+    torch.cuda.empty_cache()
 
 
 def _ptr(t):

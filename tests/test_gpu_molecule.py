@@ -48,6 +48,8 @@ def _setup():
     O.build(force=False)
     assert torch.cuda.is_available()
     F._lib()
+    yield
+    F.release_workspaces()  # the workspaces of these batches run to about 100 GB
 
 
 def oracle_at(w, pos):
