@@ -224,6 +224,26 @@ fn_status ferminet_logpsi(const fn_config* cfg, int32_t W, const float* pos, con
                           const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
                           float* logpsi, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ferminet_logpsi for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or sampling loops, harnesses that
+ * forbid hipMalloc): the same computation, the same outputs bit for bit,
+ * with the workspace taken from a 64 MiB device array inside the library
+ * instead of a caller's buffer.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); the array is set up on the
+ * call's first use on a device and held by that device until the process
+ * ends.  The batch is processed in chunks of as many walkers as the 64 MiB
+ * hold (about 1600 walkers of the Ne-like network); a network whose
+ * one-walker workspace (ferminet_workspace_bytes(cfg, 1, FN_ENTRY_LOGPSI))
+ * exceeds 64 MiB is rejected with FN_ERR_WORKSPACE before anything is
+ * enqueued.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  FN_ERR_HIP if the
+ * array's device address cannot be obtained.  Other arguments and errors
+ * as ferminet_logpsi. */
+fn_status ferminet_logpsi_noalloc(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                  const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
+                                  float* logpsi, hipStream_t stream);
+
 /* Local energy E_L = psi^-1 H psi with H of Eq. (2) for W walkers: the
  * kinetic part -1/2 sum_c [d^2_c log|psi| + (d_c log|psi|)^2] over all 3n
  * electron coordinates, from forward-mode jets (value, 3n tangents and

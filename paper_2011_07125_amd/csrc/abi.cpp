@@ -1299,6 +1299,52 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
   return FN_OK;
 }
 
+}  // extern "C"
+
+namespace fn {
+
+// ------------------------------------------- value pass without allocation
+// The workspace of ferminet_logpsi_noalloc: a file-scope device array that
+// every GPU the library runs on holds until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked
+// up once per device (hipGetSymbolAddress, with that device current, on
+// the entry point's first call there) and that pointer is what the
+// launches receive.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices] = {};
+
+static fn_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return FN_ERR_HIP;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FN_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FN_OK;
+}
+
+}  // namespace fn
+
+extern "C" {
+
+fn_status ferminet_logpsi_noalloc(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                  const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
+                                  float* logpsi, hipStream_t stream) {
+  void* ws = nullptr;
+  const fn_status st = scratch_of_current_device(&ws);
+  if (st != FN_OK) return st;
+  // the value pass writes every workspace element it reads: nothing has to
+  // start at zero
+  return run_forward_entry(cfg, W, pos, spins, nuc_pos, nuc_charge, params, sign, logpsi, nullptr, nullptr, nullptr,
+                           ws, kScratchBytes, stream, false);
+}
+
 fn_status ferminet_logpsi(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
                           const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
                           float* logpsi, void* workspace, size_t workspace_bytes, hipStream_t stream) {

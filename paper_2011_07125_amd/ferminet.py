@@ -56,7 +56,7 @@ class fn_train_options(ctypes.Structure):
 
 
 EXPORTS = ("ferminet_status_string", "ferminet_param_count", "ferminet_param_layout", "ferminet_workspace_bytes",
-           "ferminet_logpsi", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
+           "ferminet_logpsi", "ferminet_logpsi_noalloc", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
            "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
            "ferminet_kfac_precondition", "vmc_train_step",
            "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name")
@@ -83,6 +83,7 @@ def _lib():
                 lib.ferminet_param_layout.argtypes = [C, P, i32, P]
                 lib.ferminet_workspace_bytes.argtypes = [C, i32, i32, P]
                 lib.ferminet_logpsi.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
+                lib.ferminet_logpsi_noalloc.argtypes = [C, i32, P, P, P, P, P, P, P, P]
                 lib.ferminet_local_energy.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_grad_logpsi.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
                 lib.vmc_energy_gradient.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, sz, P]
@@ -207,6 +208,19 @@ def ferminet_logpsi(cfg, pos, nuc_pos, nuc_charge, params, precision=None, ws=No
                                 ws.numel(), _stream())
     _check(st, "ferminet_logpsi")
     return sign, lp
+
+
+def ferminet_logpsi_noalloc(cfg, pos, nuc_pos, nuc_charge, params, sign, logpsi, precision=None):
+    """ferminet_logpsi into the caller's sign [W] and logpsi [W] (float32,
+    on pos's device), with the library's own device workspace: the call
+    allocates no device memory (the outputs are the caller's)."""
+    W = pos.shape[0]
+    c = make_config(cfg, precision)
+    st = _lib().ferminet_logpsi_noalloc(ctypes.byref(c), W, _ptr(_prep(pos)), _spins(cfg), _ptr(_prep(nuc_pos)),
+                                        _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(_prep(sign)),
+                                        _ptr(_prep(logpsi)), _stream())
+    _check(st, "ferminet_logpsi_noalloc")
+    return sign, logpsi
 
 
 def ferminet_local_energy(cfg, pos, nuc_pos, nuc_charge, params, precision=None, ws=None, max_chunk=None,
