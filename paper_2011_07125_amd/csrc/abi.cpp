@@ -570,15 +570,17 @@ static const void* wt(const Bufs& b, const Plan& p, int64_t off, bool lo) {
 }
 
 // the orbital layer's weights and the arithmetic of its product: in the
-// split-bfloat16 form the orbital GEMM runs in float32 from a float32 copy
-// of the orbital weights packed after the two bfloat16 planes (its rounding,
-// amplified by the cancellation in its dot products and by the conditioning
-// of the orbital matrices, dominated the local-energy error of the form)
+// split-bfloat16 form the orbital GEMM runs with float32 accuracy, its
+// float32 operands (a float32 copy of the orbital weights is packed after
+// the two bfloat16 planes) split into three bfloat16 parts each (the
+// rounding of a two-part product, amplified by the cancellation in its dot
+// products and by the conditioning of the orbital matrices, dominated the
+// local-energy error of the form)
 static const void* wt_orb(const Bufs& b, const Plan& p, int a) {
   if (!p.bf16) return wt(b, p, p.pk_orb[a], false);
   return (const char*)b.pk + ((size_t)p.pk_total * 4 + (size_t)p.pk_orb[a] * 4);
 }
-static int orb_mode(const Plan& p) { return p.mode == MODE_BF16X3 ? MODE_F32 : p.mode; }
+static int orb_mode(const Plan& p) { return p.mode == MODE_BF16X3 ? MODE_BF16X6 : p.mode; }
 
 // forward pass over one chunk of Wc walkers.  jet: local energy; value:
 // sign and log|psi| only.  Launches are timed under their own stages, or

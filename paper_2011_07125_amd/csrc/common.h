@@ -32,6 +32,19 @@ __device__ inline void split_bf16x2(float x0, float x1, uint32_t* hi, uint32_t* 
   *hi = h;
   *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){x0 - h0, x1 - h1}, bf16x2));
 }
+// x = h + m + l in three bfloat16 parts for two values at once (packed):
+// h = bf16(x), m = bf16(x - h), l = bf16(x - h - m); the differences are
+// exact in float32, so the three parts carry every significand bit of x
+// (l rounds away at most a bit below 2^-24 |x|)
+__device__ inline void split3_bf16x2(float x0, float x1, uint32_t* h, uint32_t* m, uint32_t* l) {
+  const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){x0, x1}, bf16x2));
+  const float r0 = x0 - __builtin_bit_cast(float, hb << 16), r1 = x1 - __builtin_bit_cast(float, hb & 0xffff0000u);
+  const uint32_t mb = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){r0, r1}, bf16x2));
+  const float s0 = r0 - __builtin_bit_cast(float, mb << 16), s1 = r1 - __builtin_bit_cast(float, mb & 0xffff0000u);
+  *h = hb;
+  *m = mb;
+  *l = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){s0, s1}, bf16x2));
+}
 __device__ inline void split_bf16(float x, uint16_t* h, uint16_t* l) {
   const __bf16 hb = (__bf16)x;
   const __bf16 lb = (__bf16)(x - (float)hb);

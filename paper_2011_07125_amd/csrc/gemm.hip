@@ -40,6 +40,17 @@ template <int MODE> struct ModeT {
   static constexpr int VPR_B = MODE == MODE_F32 ? BK / 4 : BK / 8;   // 16-byte vectors per B tile row
   static constexpr int LDC_PAD = 4;
 };
+template <> struct ModeT<MODE_BF16X6> {
+  using S = float;
+  using Acc = floatx4;
+  static constexpr int BK = 32;
+  static constexpr int LDS_K = BK + 8;  // staged row stride (bfloat16 elements)
+  static constexpr int ESZ = 2;
+  static constexpr int PLANES = 3;
+  static constexpr int VPR_A = BK / 4;  // A and B both read as float32, split while staged
+  static constexpr int VPR_B = BK / 4;
+  static constexpr int LDC_PAD = 4;
+};
 template <> struct ModeT<MODE_F64> {
   using S = double;
   using Acc = doublex4;
@@ -198,6 +209,37 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
           d[1] = __builtin_bit_cast(double, uint2{rb[i].z, rb[i].w});
         }
       }
+    } else if constexpr (MODE == MODE_BF16X6) {
+      // three bfloat16 planes of A, then three of B, rows of LDS_K elements
+      uint16_t* Ap = reinterpret_cast<uint16_t*>(smem);
+      uint16_t* Bp = reinterpret_cast<uint16_t*>(smem + 3 * SM::A_PLANE);
+      constexpr int AP = SM::A_PLANE / 2, BP = SM::B_PLANE / 2;  // plane strides (elements)
+#pragma unroll
+      for (int i = 0; i < NVA; ++i) {
+        int v = tid + i * 256;
+        if (v < BM * VPR_A) {
+          uint32_t h0, m0, l0, h1, m1, l1;
+          split3_bf16x2(__builtin_bit_cast(float, ra[i].x), __builtin_bit_cast(float, ra[i].y), &h0, &m0, &l0);
+          split3_bf16x2(__builtin_bit_cast(float, ra[i].z), __builtin_bit_cast(float, ra[i].w), &h1, &m1, &l1);
+          const int off = (v / VPR_A) * LDS_K + (v % VPR_A) * 4;
+          *reinterpret_cast<uint2*>(Ap + off) = uint2{h0, h1};
+          *reinterpret_cast<uint2*>(Ap + AP + off) = uint2{m0, m1};
+          *reinterpret_cast<uint2*>(Ap + 2 * AP + off) = uint2{l0, l1};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NVB; ++i) {
+        int v = tid + i * 256;
+        if (v < BN * VPR_B) {
+          uint32_t h0, m0, l0, h1, m1, l1;
+          split3_bf16x2(__builtin_bit_cast(float, rb[i].x), __builtin_bit_cast(float, rb[i].y), &h0, &m0, &l0);
+          split3_bf16x2(__builtin_bit_cast(float, rb[i].z), __builtin_bit_cast(float, rb[i].w), &h1, &m1, &l1);
+          const int off = (v / VPR_B) * LDS_K + (v % VPR_B) * 4;
+          *reinterpret_cast<uint2*>(Bp + off) = uint2{h0, h1};
+          *reinterpret_cast<uint2*>(Bp + BP + off) = uint2{m0, m1};
+          *reinterpret_cast<uint2*>(Bp + 2 * BP + off) = uint2{l0, l1};
+        }
+      }
     } else {
       uint16_t* Ah = reinterpret_cast<uint16_t*>(smem);
       uint16_t* Al = reinterpret_cast<uint16_t*>(smem + SM::A_PLANE);
@@ -264,6 +306,35 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
             else
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
           }
+      }
+    } else if constexpr (MODE == MODE_BF16X6) {
+      const uint16_t* Ap = reinterpret_cast<const uint16_t*>(smem);
+      const uint16_t* Bp = reinterpret_cast<const uint16_t*>(smem + 3 * SM::A_PLANE);
+      constexpr int AP = SM::A_PLANE / 2, BP = SM::B_PLANE / 2;
+      bf16x8 a1[TM], a2[TM], a3[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = (arow + i * 16) * LDS_K + kq * 8;
+        a1[i] = *reinterpret_cast<const bf16x8*>(Ap + o);
+        a2[i] = *reinterpret_cast<const bf16x8*>(Ap + AP + o);
+        a3[i] = *reinterpret_cast<const bf16x8*>(Ap + 2 * AP + o);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int o = (brow + j * 16) * LDS_K + kq * 8;
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Bp + o);
+        const bf16x8 b2 = *reinterpret_cast<const bf16x8*>(Bp + BP + o);
+        const bf16x8 b3 = *reinterpret_cast<const bf16x8*>(Bp + 2 * BP + o);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          // the products of order 2^-16, then 2^-8, then the leading one
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[i], b1, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[i], b2, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[i], b3, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[i], b1, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[i], b2, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[i], b1, acc[i][j], 0, 0, 0);
+        }
       }
     } else {
       const uint16_t* Ah = reinterpret_cast<const uint16_t*>(smem);
@@ -574,6 +645,7 @@ hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t 
   if (epi == EPI_TANHJET && layer_gemm_supported(a)) return launch_layer_gemm(mode, a, s);
   if (epi == EPI_PLAIN && layer_plain_supported(a)) return launch_layer_plain(mode, a, s);
   if (mode == MODE_BF16X3) return pick_epi<MODE_BF16X3>(epi, a, s);
+  if (mode == MODE_BF16X6) return epi == EPI_ORBITAL ? pick<MODE_BF16X6, EPI_ORBITAL>(a, s) : hipErrorInvalidValue;
   return pick_epi<MODE_F32>(epi, a, s);
 }
 

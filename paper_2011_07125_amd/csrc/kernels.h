@@ -10,8 +10,13 @@ namespace fn {
 enum { EPI_PLAIN = 0, EPI_TANHJET = 1, EPI_ORBITAL = 2 };
 // GEMM arithmetic: float32 MFMA, three bfloat16 MFMA passes on operands
 // split into hi + lo parts, or float64 MFMA on float64 operands (then every
-// activation, mean-field term, orbital jet and epilogue is float64 too)
-enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_F64 = 2 };
+// activation, mean-field term, orbital jet and epilogue is float64 too);
+// MODE_BF16X6 (orbital products of the jet GEMM only): float32 operands
+// split into three bfloat16 parts each (all 24 significand bits) and the
+// six products of parts whose orders sum to at most 2^-16, by six bfloat16
+// MFMAs into a float32 accumulator: float32 accuracy at about 3/8 of the
+// matrix-core time of float32 MFMA
+enum { MODE_F32 = 0, MODE_BF16X3 = 1, MODE_F64 = 2, MODE_BF16X6 = 3 };
 
 // One MFMA GEMM over rows grouped by "electron" (rows_per rows each: the
 // value row, the 3n tangent rows and the Laplacian row of a jet, padded),
