@@ -131,12 +131,14 @@ def one_step(w, d, form, state, grad, seed, counter, rescue):
     cfg = w["cfg"]
     F.vmc_mcmc_step(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], state["logpsi"], state["sign"],
                     state["mcmc_steps"], state["mcmc_width"], seed, counter, precision=form)
-    out = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
-                                  parts=False, rescue=rescue)
     if grad:
-        F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], out["e_loc"],
-                              precision=form)
-    return out
+        # the local energy and the VMC gradient in one pass (the reverse
+        # pass reads the jet pass's values)
+        out, _, _ = F.vmc_local_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"],
+                                                precision=form, parts=False, rescue=rescue)
+        return out
+    return F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
+                                   parts=False, rescue=rescue)
 
 
 def time_form(w, form, steps, warmup, grad, rescue, mcmc_steps=1):

@@ -170,7 +170,8 @@ typedef enum {
   FN_ENTRY_MCMC = 3,
   FN_ENTRY_KFAC = 4,
   FN_ENTRY_KFAC_PRECONDITION = 5, /* chunk_walkers is ignored */
-  FN_ENTRY_TRAIN = 6              /* chunk_walkers is the batch size W (see vmc_train_step) */
+  FN_ENTRY_TRAIN = 6,             /* chunk_walkers is the batch size W (see vmc_train_step) */
+  FN_ENTRY_LOCAL_ENERGY_GRADIENT = 7 /* vmc_local_energy_gradient in one pass of chunk_walkers */
 } fn_entry;
 
 /* Settings of one VMC iteration (vmc_train_step). */
@@ -338,6 +339,23 @@ fn_status ferminet_kfac_layout(const fn_config* cfg, fn_kfac_block* out, int32_t
  * Uses the FN_ENTRY_KFAC_PRECONDITION workspace. */
 fn_status ferminet_kfac_precondition(const fn_config* cfg, const float* factors, const float* grad, float damping,
                                      float* update, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ferminet_local_energy followed by vmc_energy_gradient on its energies,
+ * in one pass: the energy of Eq. (2) per walker and the gradient estimator
+ * of Eq. (3),
+ *   grad[p] = (1/W) sum_w (E_L,w - mean E_L) d log|psi_w| / d theta_p,
+ * with e_stats (2 doubles, device) the batch mean and population variance
+ * of e_loc.  The reverse pass reads the values of the local energy's own
+ * jet pass (row 0 of every jet) instead of evaluating the network once
+ * more.  Outputs and their precision as the two calls; cfg->rescue_fraction
+ * as in ferminet_local_energy.  The single pass needs
+ * ferminet_workspace_bytes(cfg, W, FN_ENTRY_LOCAL_ENERGY_GRADIENT); a smaller
+ * workspace runs the two calls in turn (each in chunks).  W = 0 gives
+ * FN_ERR_ARG, the FN_PREC_FP64 form FN_ERR_UNSUPPORTED. */
+fn_status vmc_local_energy_gradient(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                    const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
+                                    float* logpsi, float* e_loc, float* e_kin, float* e_pot, double* e_stats,
+                                    float* grad, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* One iteration of the variational optimisation of E[E_L] under psi^2
  * (Eq. (3)) with KFAC (Martens and Grosse 2015), the optimiser the paper

@@ -478,6 +478,18 @@ static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   }
   Bufs b;
   cv.take(pk_bytes(p));
+  if (entry == FN_ENTRY_LOCAL_ENERGY_GRADIENT) {
+    // one pass over the whole batch: the jet pass, its float64
+    // re-evaluation, and the reverse pass on the captured values
+    carve_forward(p, JET, Wc, cv, b, false);
+    if (p.rescue > 0.0f) {
+      RescueBufs r;
+      carve_rescue(p, Wc, cv, r);
+    }
+    AdjBufs ab;
+    carve_adjoint(p, Wc, cv, ab, false);
+    return cv.used;
+  }
   if (entry == FN_ENTRY_GRAD_LOGPSI || entry == FN_ENTRY_KFAC) {
     AdjBufs ab;
     carve_adjoint(p, Wc, cv, ab, entry == FN_ENTRY_KFAC);
@@ -585,12 +597,19 @@ static int orb_mode(const Plan& p) { return p.mode == MODE_BF16X3 ? MODE_BF16X6 
 // forward pass over one chunk of Wc walkers.  jet: local energy; value:
 // sign and log|psi| only.  Launches are timed under their own stages, or
 // all under stage_all when it is not negative.
+// cap (jet mode): the values of the pass (row 0 of every jet), written
+// into the adjoint's buffers as its own value-only pass would write them
 static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, const float* nuc, const float* Z,
                          const float* params, const Bufs& b, float* sign, float* logpsi, float* e_loc,
-                         float* e_kin, float* e_pot, hipStream_t s, int stage_all = -1) {
+                         float* e_kin, float* e_pot, hipStream_t s, int stage_all = -1,
+                         const AdjBufs* cap = nullptr) {
   const int T = b.T, Tp = b.Tp;
+  const int64_t R = Wc * p.n;
   auto SG = [stage_all](int st) { return stage_all >= 0 ? stage_all : st; };
   FN_T(SG(ST_FEATURES), launch_features(p.f64, pos, nuc, (int)Wc, p.n, p.N, T, Tp, b.H0, p.dinp[0], s));
+  if (cap)
+    FN_T(SG(ST_FEATURES), launch_copy_rows((const float*)b.H0, (int64_t)Tp * p.dinp[0], cap->H[0], p.dinp[0], R,
+                                           p.dinp[0], s));
   TwoElecArgs te;
   memset(&te, 0, sizeof(te));
   te.pos = pos;
@@ -607,12 +626,20 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   for (int l = 0; l < p.L; ++l) {
     te.G[l] = b.G[l];
     te.ldg[l] = p.gwp[l];
+    te.h2_out[l] = cap ? cap->h2[l] : nullptr;
   }
   FN_T(SG(ST_TWO_E), launch_two_electron(p.f64, te, s));
+  if (cap)
+    for (int l = 0; l < p.L; ++l)
+      FN_T(SG(ST_TWO_E), launch_copy_rows((const float*)b.G[l], (int64_t)Tp * p.gwp[l], cap->G[l], p.gwp[l], R,
+                                          p.gwp[l], s));
   const void* Hin = b.H0;
   void* Hout = b.Ha;
   for (int l = 0; l < p.L; ++l) {
     FN_T(SG(ST_MEANFIELD), launch_meanfield(p.f64, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
+    if (cap)
+      FN_T(SG(ST_MEANFIELD), launch_copy_rows((const float*)b.Hbar, (int64_t)Tp * 2 * p.dinp[l], cap->Hbar[l],
+                                              2 * p.dinp[l], Wc, 2 * p.dinp[l], s));
     JetGemmArgs g;
     memset(&g, 0, sizeof(g));
     g.a0 = b.Hbar;
@@ -653,6 +680,8 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     h.ldp = p.d1;
     h.bias = params + p.offb[l];
     h.res = p.din[l] == p.d1;
+    h.pre_out = cap ? cap->PRE[l + 1] : nullptr;
+    h.val_out = cap ? cap->H[l + 1] : nullptr;
     FN_T(SG(m == JET ? ST_GEMM_LAYER : ST_GEMM_LAYER_VALUE), launch_jet_gemm(p.mode, EPI_TANHJET, h, s));
     Hin = Hout;
     Hout = Hout == b.Ha ? b.Hb : b.Ha;
@@ -685,8 +714,11 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     o.pi = params + p.offpi[a];
     o.sigma = params + p.offsg[a];
     o.env_full = p.env_full;
+    o.u_out = cap ? cap->u[a] : nullptr;
+    o.env_out = cap ? cap->env[a] : nullptr;
     FN_T(SG(ST_GEMM_ORB), launch_jet_gemm(orb_mode(p), EPI_ORBITAL, o, s));
-    FN_T(SG(ST_DET), launch_det(p.fp64, b.phi[a], p.f64, (int)Wc, p.K, na, T, p.n3, b.D[a], b.dstride, nullptr, s));
+    FN_T(SG(ST_DET), launch_det(p.fp64, b.phi[a], p.f64, (int)Wc, p.K, na, T, p.n3, b.D[a], b.dstride,
+                                cap ? cap->binv[a] : nullptr, s));
   }
   CombineArgs cb;
   memset(&cb, 0, sizeof(cb));
@@ -710,6 +742,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   cb.e_kin = e_kin;
   cb.e_pot = e_pot;
   cb.rescue_key = m == JET ? b.rkey : nullptr;
+  cb.rho = cap ? cap->rho : nullptr;
   // orbitals: split bfloat16 (16 significand bits) or float32; determinants:
   // float64 or float32
   // unit roundoff of the determinant arithmetic over that of the orbital
@@ -1090,6 +1123,29 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
   return FN_OK;
 }
 
+// the reverse pass's own copies of the weights: the bfloat16 planes of the
+// parameters (split form) and the orbital weights with zero-padded columns
+static fn_status adjoint_weights(const Plan& p, const AdjBufs& b, const float* params, hipStream_t s) {
+  // split form: the bfloat16 planes of the parameters for the reverse
+  // pass's cotangent products
+  if (b.pw) FN_T(ST_PACK, launch_split_planes(params, p.P, b.pw, b.pw + b.pw_lo, s));
+  // orbital weights with zero-padded columns, float32, rows as stored
+  std::vector<int64_t> it;
+  for (int a = 0; a < 2; ++a) {
+    if (p.na(a) == 0) continue;
+    const int64_t off = (int64_t)((char*)b.wo[a] - (char*)b.wo[0]) / 4;
+    int64_t v[11] = {off, p.d1, b.ldu, 0, (int64_t)p.K * p.na(a), p.offw[a], 0, 0, 0, (int64_t)p.K * p.na(a), 0};
+    it.insert(it.end(), v, v + 11);
+  }
+  if (!it.empty()) FN_T(ST_PACK, launch_pack_weights(false, params, b.wo[0], 0, it.data(), (int)(it.size() / 11), s));
+  for (int a = 0; a < 2; ++a)
+    if (b.wo_pl[a] && p.na(a) > 0) {
+      const int64_t m = (int64_t)p.d1 * b.ldu;
+      FN_T(ST_PACK, launch_split_planes(b.wo[a], m, b.wo_pl[a], b.wo_pl[a] + m, s));
+    }
+  return FN_OK;
+}
+
 // the whole adjoint over all chunks: grad = sum_w cot[w] d log|psi_w| / d theta.
 // cot_all: per-walker cotangents [W], or nullptr with e_loc/stats for the
 // VMC estimator ((E_L - mean) / W, computed chunk by chunk on the device).
@@ -1111,25 +1167,8 @@ static fn_status run_adjoint(const Plan& p, int32_t W, const float* pos, const f
   carve_adjoint(p, chunk, cv, b, kfac);
   fn_status st = pack(p, params, pk, s);
   if (st != FN_OK) return st;
-  // split form: the bfloat16 planes of the parameters for the reverse
-  // pass's cotangent products
-  if (b.pw) FN_T(ST_PACK, launch_split_planes(params, p.P, b.pw, b.pw + b.pw_lo, s));
-  // orbital weights with zero-padded columns, float32, rows as stored
-  {
-    std::vector<int64_t> it;
-    for (int a = 0; a < 2; ++a) {
-      if (p.na(a) == 0) continue;
-      const int64_t off = (int64_t)((char*)b.wo[a] - (char*)b.wo[0]) / 4;
-      int64_t v[11] = {off, p.d1, b.ldu, 0, (int64_t)p.K * p.na(a), p.offw[a], 0, 0, 0, (int64_t)p.K * p.na(a), 0};
-      it.insert(it.end(), v, v + 11);
-    }
-    if (!it.empty()) FN_T(ST_PACK, launch_pack_weights(false, params, b.wo[0], 0, it.data(), (int)(it.size() / 11), s));
-    for (int a = 0; a < 2; ++a)
-      if (b.wo_pl[a] && p.na(a) > 0) {
-        const int64_t m = (int64_t)p.d1 * b.ldu;
-        FN_T(ST_PACK, launch_split_planes(b.wo[a], m, b.wo_pl[a], b.wo_pl[a] + m, s));
-      }
-  }
+  st = adjoint_weights(p, b, params, s);
+  if (st != FN_OK) return st;
   if (kfac) {
     int64_t total = 0;
     kfac_blocks(p, &total);
@@ -1246,8 +1285,24 @@ fn_status ferminet_workspace_bytes(const fn_config* cfg, int32_t chunk_walkers, 
   fn_status st = make_plan(cfg, p);
   if (st != FN_OK) return st;
   if (!bytes) return FN_ERR_NULL;
-  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_TRAIN) return FN_ERR_ARG;
+  if (chunk_walkers < 1 || entry < 0 || entry > FN_ENTRY_LOCAL_ENERGY_GRADIENT) return FN_ERR_ARG;
   *bytes = chunk_bytes(p, entry, chunk_walkers);
+  return FN_OK;
+}
+
+// float64 re-evaluation of the walkers of largest error scale of one chunk
+// of wc walkers at positions x: their five outputs replace those of outs
+static fn_status reevaluate(const Plan& p, const RescueBufs& r, const Bufs& b, int64_t wc, const float* x,
+                            const float* nuc_pos, const float* nuc_charge, const float* params, float* const* outs,
+                            hipStream_t s) {
+  const RescueDims d = rescue_dims(p, wc);
+  FN_T(ST_RESCUE, launch_select_top(b.rkey, (int)wc, d.seg_len, d.k_seg, d.k_last, r.idx, s));
+  FN_T(ST_RESCUE, launch_gather_walkers(x, r.idx, (int)d.R, p.n3, r.pos_r, s));
+  fn_status st = forward(r.p64, JET, d.R, r.pos_r, nuc_pos, nuc_charge, params, r.b, r.out[0], r.out[1], r.out[2],
+                         r.out[3], r.out[4], s, ST_RESCUE);
+  if (st != FN_OK) return st;
+  const float* srcs[5] = {r.out[0], r.out[1], r.out[2], r.out[3], r.out[4]};
+  FN_T(ST_RESCUE, launch_scatter_results(r.idx, (int)d.R, outs, srcs, 5, s));
   return FN_OK;
 }
 
@@ -1288,15 +1343,8 @@ static fn_status run_forward_entry(const fn_config* cfg, int32_t W, const float*
                  outs[4], s);
     if (st != FN_OK) return st;
     if (!rescue) continue;
-    // float64 re-evaluation of the walkers of largest error scale
-    const RescueDims d = rescue_dims(p, wc);
-    FN_T(ST_RESCUE, launch_select_top(b.rkey, (int)wc, d.seg_len, d.k_seg, d.k_last, r.idx, s));
-    FN_T(ST_RESCUE, launch_gather_walkers(x, r.idx, (int)d.R, p.n3, r.pos_r, s));
-    st = forward(r.p64, JET, d.R, r.pos_r, nuc_pos, nuc_charge, params, r.b, r.out[0], r.out[1], r.out[2], r.out[3],
-                 r.out[4], s, ST_RESCUE);
+    st = reevaluate(p, r, b, wc, x, nuc_pos, nuc_charge, params, outs, s);
     if (st != FN_OK) return st;
-    const float* srcs[5] = {r.out[0], r.out[1], r.out[2], r.out[3], r.out[4]};
-    FN_T(ST_RESCUE, launch_scatter_results(r.idx, (int)d.R, outs, srcs, 5, s));
   }
   return FN_OK;
 }
@@ -1558,6 +1606,63 @@ fn_status vmc_energy_gradient(const fn_config* cfg, int32_t W, const float* pos,
   FN_T(ST_ADJ_REDUCE, launch_energy_stats(e_loc, W, e_stats, nullptr, s));
   return run_adjoint(p, W, pos, nuc_pos, nuc_charge, params, nullptr, e_loc, e_stats, grad, workspace,
                      workspace_bytes, stream);
+}
+
+fn_status vmc_local_energy_gradient(const fn_config* cfg, int32_t W, const float* pos, const int32_t* spins,
+                                    const float* nuc_pos, const float* nuc_charge, const float* params, float* sign,
+                                    float* logpsi, float* e_loc, float* e_kin, float* e_pot, double* e_stats,
+                                    float* grad, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  Plan p;
+  fn_status st = check_common(cfg, W, pos, spins, nuc_pos, nuc_charge, params, workspace, p);
+  if (st != FN_OK) return st;
+  if (!sign || !logpsi || !e_loc || !e_stats || !grad) return FN_ERR_NULL;
+  if (W == 0) return FN_ERR_ARG;  // the batch mean of an empty batch is undefined
+  if (p.f64) return FN_ERR_UNSUPPORTED;
+  const hipStream_t s = stream;
+  if (workspace_bytes < chunk_bytes(p, FN_ENTRY_LOCAL_ENERGY_GRADIENT, W)) {
+    // the batch does not fit one pass: the local energy, then the gradient
+    // with its own value-only pass, each in chunks
+    if (max_chunk(p, FN_ENTRY_LOCAL_ENERGY, workspace_bytes, W) < 1 ||
+        max_chunk(p, FN_ENTRY_GRAD_LOGPSI, workspace_bytes, W) < 1)
+      return FN_ERR_WORKSPACE;
+    st = ferminet_local_energy(cfg, W, pos, spins, nuc_pos, nuc_charge, params, sign, logpsi, e_loc, e_kin, e_pot,
+                               workspace, workspace_bytes, stream);
+    if (st != FN_OK) return st;
+    return vmc_energy_gradient(cfg, W, pos, spins, nuc_pos, nuc_charge, params, e_loc, e_stats, grad, workspace,
+                               workspace_bytes, stream);
+  }
+  Carver cv{(char*)workspace, 0};
+  Bufs b;
+  b.pk = cv.take(pk_bytes(p));
+  carve_forward(p, JET, W, cv, b, false);
+  const bool rescue = p.rescue > 0.0f;
+  RescueBufs r;
+  if (rescue) {
+    carve_rescue(p, W, cv, r);
+    r.b.pk = r.pk64;
+  }
+  AdjBufs ab;
+  carve_adjoint(p, W, cv, ab, false);
+  st = pack(p, params, b.pk, s);
+  if (st != FN_OK) return st;
+  if (rescue) {
+    st = pack(r.p64, params, r.pk64, s);
+    if (st != FN_OK) return st;
+  }
+  st = adjoint_weights(p, ab, params, s);
+  if (st != FN_OK) return st;
+  // the jet pass, keeping its values (row 0 of every jet) for the reverse pass
+  st = forward(p, JET, W, pos, nuc_pos, nuc_charge, params, b, sign, logpsi, e_loc, e_kin, e_pot, s, -1, &ab);
+  if (st != FN_OK) return st;
+  if (rescue) {
+    float* outs[5] = {sign, logpsi, e_loc, e_kin, e_pot};
+    st = reevaluate(p, r, b, W, pos, nuc_pos, nuc_charge, params, outs, s);
+    if (st != FN_OK) return st;
+  }
+  // batch statistics, cotangents (E_L - mean) / W, and the reverse pass
+  FN_T(ST_ADJ_REDUCE, launch_energy_stats(e_loc, W, e_stats, ab.cot, s));
+  FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
+  return backward(p, W, pos, nuc_pos, params, ab.cot, ab, grad, s);
 }
 
 fn_status vmc_train_step(const fn_config* cfg, int32_t W, float* pos, const int32_t* spins, const float* nuc_pos,

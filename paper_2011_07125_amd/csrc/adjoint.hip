@@ -526,6 +526,34 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// dst[r * ldd + c] = src[r * lds + c]: the value rows of jets (one row in
+// every lds floats) into a compact array.  16-byte vectors when the column
+// count and both strides allow (every jet width here is a multiple of 32);
+// a 64 x 4 block covers 64 vectors of 4 rows, rows advance by the grid.
+template <class V>
+__global__ __launch_bounds__(256) void copy_rows_kernel(const V* src, int64_t lds, V* dst, int64_t ldd, int64_t rows,
+                                                        int vpr) {
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= vpr) return;
+  for (int64_t r = (int64_t)blockIdx.y * 4 + threadIdx.y; r < rows; r += (int64_t)gridDim.y * 4)
+    dst[r * ldd + c] = src[r * lds + c];
+}
+
+hipError_t launch_copy_rows(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int cols,
+                            hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const bool vec = cols % 4 == 0 && lds % 4 == 0 && ldd % 4 == 0 && (uintptr_t)src % 16 == 0 &&
+                   (uintptr_t)dst % 16 == 0;
+  const int vpr = vec ? cols / 4 : cols;
+  const dim3 grid((vpr + 63) / 64, (unsigned)std::min<int64_t>((rows + 3) / 4, 16384));
+  if (vec)
+    hipLaunchKernelGGL(copy_rows_kernel<float4>, grid, dim3(64, 4), 0, s, (const float4*)src, lds / 4, (float4*)dst,
+                       ldd / 4, rows, vpr);
+  else
+    hipLaunchKernelGGL(copy_rows_kernel<float>, grid, dim3(64, 4), 0, s, src, lds, dst, ldd, rows, vpr);
+  return hipGetLastError();
+}
+
 __global__ void copy_f32_kernel(const float* src, float* dst, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];

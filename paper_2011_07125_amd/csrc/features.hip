@@ -330,17 +330,18 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
           }
         }
       }
-      if (a.h2_out[l] && R2 == 1) {
-        // the block's pair activations are one contiguous run of the output
-        // ([electron][partner][ein] with slot = e n + partner); slot and
-        // feature by shifts when ein is a power of two
+      if (a.h2_out[l]) {
+        // the values of the block's pair activations are one contiguous run
+        // of the output ([electron][partner][ein] with pair = e n +
+        // partner; in jet mode the value is the pair's sparse row 0); pair
+        // and feature by shifts when ein is a power of two
         const int nval = (min(a.ipb, n_groups - gbase)) * n * ein;
         float* dst = a.h2_out[l] + (int64_t)gbase * n * ein;
         const bool pow2 = (ein & (ein - 1)) == 0;
         const int sh = __builtin_ctz(ein);
         for (int idx = tid; idx < nval; idx += blockDim.x) {
-          const int sl = pow2 ? idx >> sh : idx / ein, o = idx - sl * ein;
-          dst[idx] = (float)Ps[(size_t)sl * PS + o];
+          const int pr = pow2 ? idx >> sh : idx / ein, o = idx - pr * ein;
+          dst[idx] = (float)Ps[(size_t)pr * R2 * PS + o];
         }
       }
     }

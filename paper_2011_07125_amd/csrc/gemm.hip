@@ -488,6 +488,7 @@ __global__ __launch_bounds__(256) void jet_gemm_kernel(JetGemmArgs a, int n_mtil
           v.w += rr.w;
         }
         *reinterpret_cast<float4*>(out + orow * a.ldo + gc) = v;
+        if (a.val_out && t == 0) *reinterpret_cast<float4*>(a.val_out + (size_t)g * a.N + gc) = v;
       }
     }
   } else {  // EPI_ORBITAL

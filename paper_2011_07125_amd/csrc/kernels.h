@@ -43,6 +43,7 @@ struct JetGemmArgs {
   const float* bias;
   int res;
   float* pre_out;
+  float* val_out;  // optional (float32 modes): the value row of out, compact: val_out[g * N + col]
   // EPI_ORBITAL: phi[((w * K + k) * T + t) * n_sub^2 + j * n_sub + i] with
   //   w = g / n_sub, j = g % n_sub, col = k * n_sub + i
   //   or, when phi_M > 0 (matrix index fastest, for the small-matrix
@@ -80,7 +81,7 @@ struct TwoElecArgs {
   int W, n, n_up, L, d2, T, Tp;
   void* G[8];         // G^l [(w n + i) Tp + t][ldg_l] (float32, or float64 with f64)
   int ldg[8];
-  float* h2_out[8];   // value mode, optional: h^l_ij [w][i][j][ein_l]
+  float* h2_out[8];   // optional, float32: the values h^l_ij [w][i][j][ein_l] (both modes)
 };
 hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s);
 // electrons per workgroup of the two-electron stream (0: does not fit in LDS)
@@ -182,6 +183,9 @@ hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float*
 hipError_t launch_adj_scatter_mf(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh,
                                  hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// dst[r * ldd + c] = src[r * lds + c] for r < rows, c < cols
+hipError_t launch_copy_rows(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int cols,
+                            hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
 struct Adj2eArgs {
   const float* params;

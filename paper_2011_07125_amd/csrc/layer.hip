@@ -494,6 +494,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const float br = (first ? y[j] : (last ? lapc[j] : 0.0f)) + (live ? rv[r][j] : 0.0f);
         const float o = deriv ? fmaf(dy[j], acc[i][j][r], br) : br;  // selected: pad rows may hold anything
         stf(o, rO, voO + j * 64, so);
+        if (first && a.val_out) a.val_out[(size_t)g * a.N + cw + c + j * 16] = o;
       }
     }
   }

@@ -21,7 +21,7 @@ FN_ENV_ISOTROPIC, FN_ENV_FULL = 0, 1
 ENVELOPES = {"isotropic": FN_ENV_ISOTROPIC, "full": FN_ENV_FULL}
 PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
 FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC, FN_ENTRY_KFAC = 0, 1, 2, 3, 4
-FN_ENTRY_KFAC_PRECONDITION, FN_ENTRY_TRAIN = 5, 6
+FN_ENTRY_KFAC_PRECONDITION, FN_ENTRY_TRAIN, FN_ENTRY_LOCAL_ENERGY_GRADIENT = 5, 6, 7
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
           5: "FN_ERR_UNSUPPORTED", 6: "FN_ERR_HIP", 7: "FN_ERR_ARG"}
 
@@ -57,7 +57,7 @@ class fn_train_options(ctypes.Structure):
 
 EXPORTS = ("ferminet_status_string", "ferminet_param_count", "ferminet_param_layout", "ferminet_workspace_bytes",
            "ferminet_logpsi", "ferminet_logpsi_noalloc", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
-           "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
+           "vmc_local_energy_gradient", "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
            "ferminet_kfac_precondition", "vmc_train_step",
            "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name")
 
@@ -87,6 +87,7 @@ def _lib():
                 lib.ferminet_local_energy.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_grad_logpsi.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
                 lib.vmc_energy_gradient.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, sz, P]
+                lib.vmc_local_energy_gradient.argtypes = [C, i32, P, P, P, P, P, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_kfac_factors.argtypes = [C, i32, P, P, P, P, P, P, P, P, sz, P]
                 lib.ferminet_kfac_layout.argtypes = [C, P, i32, P, P]
                 lib.ferminet_kfac_precondition.argtypes = [C, P, P, f32, P, P, sz, P]
@@ -317,6 +318,30 @@ def vmc_energy_gradient(cfg, pos, nuc_pos, nuc_charge, params, e_loc, precision=
                                     _ptr(grad), _ptr(ws), ws.numel(), _stream())
     _check(st, "vmc_energy_gradient")
     return grad, stats
+
+
+def vmc_local_energy_gradient(cfg, pos, nuc_pos, nuc_charge, params, precision=None, ws=None, max_chunk=None,
+                              parts=True, rescue: float = 0.0):
+    """ferminet_local_energy and vmc_energy_gradient of its energies in one
+    pass -> (dict(sign, logpsi, e_loc[, e_kin, e_pot]) float32 [W],
+    grad [P] float32, stats [2] float64: mean and variance of e_loc)."""
+    W = pos.shape[0]
+    c = make_config(cfg, precision, rescue)
+    out = {k: torch.empty(W, dtype=torch.float32, device=pos.device) for k in ("sign", "logpsi", "e_loc")}
+    if parts:
+        out["e_kin"] = torch.empty(W, dtype=torch.float32, device=pos.device)
+        out["e_pot"] = torch.empty(W, dtype=torch.float32, device=pos.device)
+    grad = torch.empty(params.numel(), dtype=torch.float32, device=pos.device)
+    stats = torch.empty(2, dtype=torch.float64, device=pos.device)
+    if ws is None:
+        ws = workspace(cfg, W, FN_ENTRY_LOCAL_ENERGY_GRADIENT, precision, pos.device, max_chunk, rescue)
+    st = _lib().vmc_local_energy_gradient(ctypes.byref(c), W, _ptr(_prep(pos)), _spins(cfg), _ptr(_prep(nuc_pos)),
+                                          _ptr(_prep(nuc_charge)), _ptr(_prep(params)), _ptr(out["sign"]),
+                                          _ptr(out["logpsi"]), _ptr(out["e_loc"]), _ptr(out.get("e_kin")),
+                                          _ptr(out.get("e_pot")), _ptr(stats), _ptr(grad), _ptr(ws), ws.numel(),
+                                          _stream())
+    _check(st, "vmc_local_energy_gradient")
+    return out, grad, stats
 
 
 def vmc_mcmc_step(cfg, pos, nuc_pos, nuc_charge, params, logpsi, sign, n_steps, step_width, seed, counter=0,

@@ -198,3 +198,46 @@ def test_per_walker_gradient_vs_oracle(name, W, form):
     err = np.abs(gd - ref).max() / scale
     say(f"   sum over walkers vs the [P] form: max error {err:.2e} of the largest term sum")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("name,W,form,rescue", [("ne10", 512, "bf16", 0.03), ("ne10", 256, "fp32_fp64det", 0.03),
+                                                ("c4h6", 64, "fp32", 0.0), ("be4", 200, "fp32", 0.02)])
+def test_local_energy_gradient_in_one_pass(name, W, form, rescue):
+    """vmc_local_energy_gradient (the reverse pass on the values of the
+    local energy's own jet pass) against ferminet_local_energy followed by
+    vmc_energy_gradient: the energies and statistics bit for bit, the
+    gradient to float32 rounding; with a workspace below the one-pass size
+    the entry point runs the two calls in turn (bit for bit)."""
+    say(f"case local energy + gradient in one pass {name} W={W} {form} rescue={rescue}")
+    w = I.make_workload(name, walkers=W)
+    cfg = w["cfg"]
+    d = F.to_device(w)
+    out, g1, st1 = F.vmc_local_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"],
+                                               precision=form, rescue=rescue)
+    ref = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
+                                  rescue=rescue)
+    g2, st2 = F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], ref["e_loc"],
+                                    precision=form)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(out[k], ref[k]), k
+    assert torch.equal(st1, st2)
+    diff = (g1 - g2).abs().max().item()
+    scale = g2.abs().max().item()
+    say(f"   |grad|inf {scale:.3e}, max |one pass - two calls| {diff:.3e} (bitwise equal: {torch.equal(g1, g2)})")
+    assert diff <= 1e-6 * scale
+    # below the one-pass workspace: the two calls in turn, in chunks (the
+    # same workspace bytes give both sides the same chunks)
+    ws = F.workspace(cfg, W, F.FN_ENTRY_LOCAL_ENERGY_GRADIENT, form, d["pos"].device, max(1, W // 3), rescue)
+    assert ws.numel() < F.workspace_bytes(cfg, W, F.FN_ENTRY_LOCAL_ENERGY_GRADIENT, form, rescue)
+    out3, g3, st3 = F.vmc_local_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"],
+                                                precision=form, rescue=rescue, ws=ws)
+    torch.cuda.synchronize()
+    ref3 = F.ferminet_local_energy(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], precision=form,
+                                   rescue=rescue, ws=ws)
+    g4, st4 = F.vmc_energy_gradient(cfg, d["pos"], d["nuc_pos"], d["nuc_charge"], d["params"], ref3["e_loc"],
+                                    precision=form, ws=ws)
+    torch.cuda.synchronize()
+    for k in ref3:
+        assert torch.equal(out3[k], ref3[k]), k
+    assert torch.equal(g3, g4) and torch.equal(st3, st4)
