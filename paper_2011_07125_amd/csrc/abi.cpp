@@ -461,6 +461,30 @@ static void carve_train(const Plan& p, int64_t W, Carver& cv, TrainBufs& t) {
   t.fb = (float*)cv.take(total * 4);
 }
 
+// One pass over a batch of Wc walkers: the packed weights, the jet pass,
+// its float64 re-evaluation and the reverse pass's buffers (with the KFAC
+// statistics' buffers when kfac), which the jet pass fills with its values.
+struct OnePass {
+  Bufs b;
+  RescueBufs r;
+  AdjBufs ab;
+};
+static void carve_one_pass(const Plan& p, int64_t Wc, Carver& cv, OnePass& o, bool kfac) {
+  o.b.pk = cv.take(pk_bytes(p));
+  carve_forward(p, JET, Wc, cv, o.b, false);
+  if (p.rescue > 0.0f) {
+    carve_rescue(p, Wc, cv, o.r);
+    o.r.b.pk = o.r.pk64;
+  }
+  carve_adjoint(p, Wc, cv, o.ab, kfac);
+}
+static size_t one_pass_bytes(const Plan& p, int64_t Wc, bool kfac) {
+  Carver cv{nullptr, 0};
+  OnePass o;
+  carve_one_pass(p, Wc, cv, o, kfac);
+  return cv.used;
+}
+
 static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   Carver cv{nullptr, 0};
   if (entry == FN_ENTRY_TRAIN) {
@@ -468,6 +492,8 @@ static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
     carve_train(p, Wc, cv, t);
     size_t pass = chunk_bytes(p, FN_ENTRY_KFAC_PRECONDITION, 1);
     for (int e = FN_ENTRY_LOGPSI; e <= FN_ENTRY_KFAC; ++e) pass = std::max(pass, chunk_bytes(p, e, Wc));
+    // the local energy, gradient and KFAC statistics of the batch in one pass
+    pass = std::max(pass, one_pass_bytes(p, Wc, true));
     return cv.used + pass;
   }
   if (entry == FN_ENTRY_KFAC_PRECONDITION) {
@@ -478,18 +504,7 @@ static size_t chunk_bytes(const Plan& p, int entry, int64_t Wc) {
   }
   Bufs b;
   cv.take(pk_bytes(p));
-  if (entry == FN_ENTRY_LOCAL_ENERGY_GRADIENT) {
-    // one pass over the whole batch: the jet pass, its float64
-    // re-evaluation, and the reverse pass on the captured values
-    carve_forward(p, JET, Wc, cv, b, false);
-    if (p.rescue > 0.0f) {
-      RescueBufs r;
-      carve_rescue(p, Wc, cv, r);
-    }
-    AdjBufs ab;
-    carve_adjoint(p, Wc, cv, ab, false);
-    return cv.used;
-  }
+  if (entry == FN_ENTRY_LOCAL_ENERGY_GRADIENT) return one_pass_bytes(p, Wc, false);
   if (entry == FN_ENTRY_GRAD_LOGPSI || entry == FN_ENTRY_KFAC) {
     AdjBufs ab;
     carve_adjoint(p, Wc, cv, ab, entry == FN_ENTRY_KFAC);
@@ -1291,6 +1306,33 @@ fn_status ferminet_workspace_bytes(const fn_config* cfg, int32_t chunk_walkers, 
 }
 
 // float64 re-evaluation of the walkers of largest error scale of one chunk
+static fn_status reevaluate(const Plan& p, const RescueBufs& r, const Bufs& b, int64_t wc, const float* x,
+                            const float* nuc_pos, const float* nuc_charge, const float* params, float* const* outs,
+                            hipStream_t s);
+
+// the jet pass of a one-pass layout over all W walkers (its values kept in
+// o.ab for the reverse pass) and the float64 re-evaluation; outs: sign,
+// logpsi, e_loc, e_kin, e_pot (the last two may be NULL)
+static fn_status one_pass_forward(const Plan& p, int64_t W, const float* pos, const float* nuc_pos,
+                                  const float* nuc_charge, const float* params, const OnePass& o, float* const* outs,
+                                  hipStream_t s) {
+  fn_status st = pack(p, params, o.b.pk, s);
+  if (st != FN_OK) return st;
+  const bool rescue = p.rescue > 0.0f;
+  if (rescue) {
+    st = pack(o.r.p64, params, o.r.pk64, s);
+    if (st != FN_OK) return st;
+  }
+  st = adjoint_weights(p, o.ab, params, s);
+  if (st != FN_OK) return st;
+  st = forward(p, JET, W, pos, nuc_pos, nuc_charge, params, o.b, outs[0], outs[1], outs[2], outs[3], outs[4], s, -1,
+               &o.ab);
+  if (st != FN_OK) return st;
+  if (rescue) return reevaluate(p, o.r, o.b, W, pos, nuc_pos, nuc_charge, params, outs, s);
+  return FN_OK;
+}
+
+// float64 re-evaluation of the walkers of largest error scale of one chunk
 // of wc walkers at positions x: their five outputs replace those of outs
 static fn_status reevaluate(const Plan& p, const RescueBufs& r, const Bufs& b, int64_t wc, const float* x,
                             const float* nuc_pos, const float* nuc_charge, const float* params, float* const* outs,
@@ -1632,33 +1674,12 @@ fn_status vmc_local_energy_gradient(const fn_config* cfg, int32_t W, const float
                                workspace_bytes, stream);
   }
   Carver cv{(char*)workspace, 0};
-  Bufs b;
-  b.pk = cv.take(pk_bytes(p));
-  carve_forward(p, JET, W, cv, b, false);
-  const bool rescue = p.rescue > 0.0f;
-  RescueBufs r;
-  if (rescue) {
-    carve_rescue(p, W, cv, r);
-    r.b.pk = r.pk64;
-  }
-  AdjBufs ab;
-  carve_adjoint(p, W, cv, ab, false);
-  st = pack(p, params, b.pk, s);
+  OnePass o;
+  carve_one_pass(p, W, cv, o, false);
+  float* outs[5] = {sign, logpsi, e_loc, e_kin, e_pot};
+  st = one_pass_forward(p, W, pos, nuc_pos, nuc_charge, params, o, outs, s);
   if (st != FN_OK) return st;
-  if (rescue) {
-    st = pack(r.p64, params, r.pk64, s);
-    if (st != FN_OK) return st;
-  }
-  st = adjoint_weights(p, ab, params, s);
-  if (st != FN_OK) return st;
-  // the jet pass, keeping its values (row 0 of every jet) for the reverse pass
-  st = forward(p, JET, W, pos, nuc_pos, nuc_charge, params, b, sign, logpsi, e_loc, e_kin, e_pot, s, -1, &ab);
-  if (st != FN_OK) return st;
-  if (rescue) {
-    float* outs[5] = {sign, logpsi, e_loc, e_kin, e_pot};
-    st = reevaluate(p, r, b, W, pos, nuc_pos, nuc_charge, params, outs, s);
-    if (st != FN_OK) return st;
-  }
+  const AdjBufs& ab = o.ab;
   // batch statistics, cotangents (E_L - mean) / W, and the reverse pass
   FN_T(ST_ADJ_REDUCE, launch_energy_stats(e_loc, W, e_stats, ab.cot, s));
   FN_T(ST_ADJ_REDUCE, launch_fill_f32(grad, p.P, 0.0f, s));
@@ -1701,20 +1722,46 @@ fn_status vmc_train_step(const fn_config* cfg, int32_t W, float* pos, const int3
   st = vmc_mcmc_step(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.logpsi, t.sign, o.mcmc_steps, o.mcmc_width,
                      o.seed, o.counter, noise, uniforms, t.n_acc, rest, rb, s);
   if (st != FN_OK) return st;
-  st = ferminet_local_energy(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.sign, t.logpsi, e_loc, nullptr,
-                             nullptr, rest, rb, s);
-  if (st != FN_OK) return st;
-  // energy statistics over the walkers with a finite local energy, the
-  // cotangents 2 (E~_w - mean E~) / W_f and the KFAC batch weights 1 / W_f
-  // (both 0 for the others)
-  FN_T(ST_TRAIN, launch_train_energy_stats(e_loc, t.n_acc, W, o.mcmc_steps, (double)o.clip_scale, t.e_clip, t.cot,
-                                           t.wts, stats, s));
-  // energy gradient 2 sum_w (E~_w - mean E~) / W_f d log|psi_w| / d theta
-  st = ferminet_grad_logpsi(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.cot, t.grad, rest, rb, s);
-  if (st != FN_OK) return st;
+  if (rb >= one_pass_bytes(p, W, true)) {
+    // one pass: the local energy's jet pass keeps its values for the two
+    // reverse passes (energy gradient and KFAC statistics)
+    Carver cp{(char*)rest, 0};
+    OnePass op;
+    carve_one_pass(p, W, cp, op, true);
+    float* outs[5] = {t.sign, t.logpsi, e_loc, nullptr, nullptr};
+    st = one_pass_forward(p, W, pos, nuc_pos, nuc_charge, params, op, outs, s);
+    if (st != FN_OK) return st;
+    FN_T(ST_TRAIN, launch_train_energy_stats(e_loc, t.n_acc, W, o.mcmc_steps, (double)o.clip_scale, t.e_clip,
+                                             t.cot, t.wts, stats, s));
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(t.grad, p.P, 0.0f, s));
+    st = backward(p, W, pos, nuc_pos, params, t.cot, op.ab, t.grad, s);
+    if (st != FN_OK) return st;
+    FN_T(ST_ADJ_REDUCE, launch_fill_f32(t.fb, total, 0.0f, s));
+    FN_T(ST_ADJ_REDUCE, launch_kfac_sqrt_weights(t.wts, W, op.ab.sc, s));
+    st = backward(p, W, pos, nuc_pos, params, op.ab.sc, op.ab, nullptr, s, t.fb);
+    if (st != FN_OK) return st;
+    for (const KfacBlk& k : kfac_blocks(p, nullptr))
+      if (k.kind != 1) {
+        FN_T(ST_ADJ_REDUCE, launch_sym_mirror(t.fb + k.offA, k.dA, s));
+        FN_T(ST_ADJ_REDUCE, launch_sym_mirror(t.fb + k.offG, k.dG, s));
+      }
+  } else {
+    st = ferminet_local_energy(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.sign, t.logpsi, e_loc, nullptr,
+                               nullptr, rest, rb, s);
+    if (st != FN_OK) return st;
+    // energy statistics over the walkers with a finite local energy, the
+    // cotangents 2 (E~_w - mean E~) / W_f and the KFAC batch weights 1 / W_f
+    // (both 0 for the others)
+    FN_T(ST_TRAIN, launch_train_energy_stats(e_loc, t.n_acc, W, o.mcmc_steps, (double)o.clip_scale, t.e_clip,
+                                             t.cot, t.wts, stats, s));
+    // energy gradient 2 sum_w (E~_w - mean E~) / W_f d log|psi_w| / d theta
+    st = ferminet_grad_logpsi(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.cot, t.grad, rest, rb, s);
+    if (st != FN_OK) return st;
+    // the batch factors
+    st = ferminet_kfac_factors(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.wts, t.fb, rest, rb, s);
+    if (st != FN_OK) return st;
+  }
   // running averages of the batch factors
-  st = ferminet_kfac_factors(cfg, W, pos, spins, nuc_pos, nuc_charge, params, t.wts, t.fb, rest, rb, s);
-  if (st != FN_OK) return st;
   FN_T(ST_TRAIN, launch_lincomb(factors, t.fb, 1.0f - o.factor_decay, o.factor_decay, total, s));
   st = ferminet_kfac_precondition(cfg, factors, t.grad, o.damping, t.dir, rest, rb, s);
   if (st != FN_OK) return st;
