@@ -440,6 +440,18 @@ fn_status ferminet_stage_timing(int32_t enable);
 int32_t ferminet_stage_times(double* total_ms, int32_t* count, int32_t cap);
 const char* ferminet_stage_name(int32_t stage);
 
+/* ---- execution options (process-wide) ----
+ * FN_OPT_FUSED_MEANFIELD (default 1): where the layer shape allows it
+ * (equal spin groups of at most 5 electrons, jets of at most 32 rows,
+ * float32 and split-bf16 forms) the jet layer kernel also forms the spin
+ * means of its output that the next layer reads (the mean field of Sec. 3),
+ * instead of a separate pass over the layer output; 0 always runs the
+ * separate pass.  Both give the same bits.  ferminet_set_option sets value
+ * (0 or 1) for later calls and returns FN_ERR_ARG for an unknown option or
+ * value; set it while no call is running. */
+typedef enum { FN_OPT_FUSED_MEANFIELD = 1 } fn_option;
+fn_status ferminet_set_option(int32_t option, int32_t value);
+
 #ifdef __cplusplus
 }
 #endif

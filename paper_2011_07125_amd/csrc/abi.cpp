@@ -609,6 +609,9 @@ static const void* wt_orb(const Bufs& b, const Plan& p, int a) {
 }
 static int orb_mode(const Plan& p) { return p.mode == MODE_BF16X3 ? MODE_BF16X6 : p.mode; }
 
+// FN_OPT_FUSED_MEANFIELD
+static std::atomic<bool> g_fused_meanfield{true};
+
 // forward pass over one chunk of Wc walkers.  jet: local energy; value:
 // sign and log|psi| only.  Launches are timed under their own stages, or
 // all under stage_all when it is not negative.
@@ -650,8 +653,10 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
                                           p.gwp[l], s));
   const void* Hin = b.H0;
   void* Hout = b.Ha;
+  bool hbar_ready = false;  // the previous layer's kernel wrote the spin means of Hin
   for (int l = 0; l < p.L; ++l) {
-    FN_T(SG(ST_MEANFIELD), launch_meanfield(p.f64, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
+    if (!hbar_ready)
+      FN_T(SG(ST_MEANFIELD), launch_meanfield(p.f64, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
     if (cap)
       FN_T(SG(ST_MEANFIELD), launch_copy_rows((const float*)b.Hbar, (int64_t)Tp * 2 * p.dinp[l], cap->Hbar[l],
                                               2 * p.dinp[l], Wc, 2 * p.dinp[l], s));
@@ -697,6 +702,17 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     h.res = p.din[l] == p.d1;
     h.pre_out = cap ? cap->PRE[l + 1] : nullptr;
     h.val_out = cap ? cap->H[l + 1] : nullptr;
+    // the spin means of this layer's output, for the next layer, from the
+    // layer kernel itself where its shape allows
+    hbar_ready = false;
+    if (l + 1 < p.L && !p.f64 && g_fused_meanfield.load()) {
+      h.mf_out = (float*)b.Hbar;
+      h.mf_ld = 2 * p.dinp[l + 1];
+      h.mf_half = p.dinp[l + 1];
+      h.mf_na = p.nu;
+      hbar_ready = layer_mf_supported(h);
+      if (!hbar_ready) h.mf_out = nullptr;
+    }
     FN_T(SG(m == JET ? ST_GEMM_LAYER : ST_GEMM_LAYER_VALUE), launch_jet_gemm(p.mode, EPI_TANHJET, h, s));
     Hin = Hout;
     Hout = Hout == b.Ha ? b.Hb : b.Ha;
@@ -1774,6 +1790,12 @@ fn_status vmc_train_step(const fn_config* cfg, int32_t W, float* pos, const int3
 }  // extern "C"
 
 extern "C" {
+
+fn_status ferminet_set_option(int32_t option, int32_t value) {
+  if (option != FN_OPT_FUSED_MEANFIELD || (value != 0 && value != 1)) return FN_ERR_ARG;
+  fn::g_fused_meanfield.store(value != 0);
+  return FN_OK;
+}
 
 fn_status ferminet_stage_timing(int32_t enable) {
   std::lock_guard<std::mutex> g(fn::g_time_mu);

@@ -590,27 +590,40 @@ __global__ void meanfield_kernel(const S* H, int ldh, int W, int n, int n_up, in
 }
 
 // float32 version: one thread per 4 consecutive features of one (walker,
-// jet row), both spins, 16-byte loads (din_p and ldh multiples of 4)
+// jet row), both spins, 16-byte loads (din_p and ldh multiples of 4).  A
+// thread's loads are issued eight at a time before any is added, so that
+// eight are in flight per thread; the sums still take j in order.  I is the
+// item index type (32-bit when the item count allows).
+template <class I>
 __global__ void meanfield4_kernel(const float* H, int ldh, int W, int n, int n_up, int Tp, int din_p, float* Hbar) {
-  const int q4 = din_p / 4;
-  const int64_t total = (int64_t)W * Tp * q4;
+  const I q4 = (I)(din_p / 4);
+  const I total = (I)W * (I)Tp * q4;
   const float iu = n_up > 0 ? 1.0f / (float)n_up : 0.0f;
   const float id = n - n_up > 0 ? 1.0f / (float)(n - n_up) : 0.0f;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t js = (int64_t)Tp * ldh;  // electron stride
+  for (I idx = (I)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (I)gridDim.x * blockDim.x) {
     const int f = (int)(idx % q4) * 4;
-    const int64_t row = idx / q4;  // w Tp + t
-    const int t = (int)(row % Tp);
-    const int64_t w = row / Tp;
+    const I row = idx / q4;  // w Tp + t
+    const int t = (int)(row % (I)Tp);
+    const int64_t w = (int64_t)(row / (I)Tp);
+    const float* src = H + (w * n * Tp + t) * (int64_t)ldh + f;
     float4 su = {0.f, 0.f, 0.f, 0.f}, sd = {0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < n; ++j) {
-      const float4 v = *reinterpret_cast<const float4*>(H + ((w * n + j) * Tp + t) * (int64_t)ldh + f);
-      float4& s = j < n_up ? su : sd;
-      s.x += v.x;
-      s.y += v.y;
-      s.z += v.z;
-      s.w += v.w;
+    for (int j0 = 0; j0 < n; j0 += 8) {
+      float4 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        v[k] = j0 + k < n ? *reinterpret_cast<const float4*>(src + (j0 + k) * js) : float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (j0 + k >= n) break;
+        float4& s = j0 + k < n_up ? su : sd;
+        s.x += v[k].x;
+        s.y += v[k].y;
+        s.z += v[k].z;
+        s.w += v[k].w;
+      }
     }
-    float* o = Hbar + row * 2 * din_p + f;
+    float* o = Hbar + (int64_t)row * 2 * din_p + f;
     *reinterpret_cast<float4*>(o) = float4{su.x * iu, su.y * iu, su.z * iu, su.w * iu};
     *reinterpret_cast<float4*>(o + din_p) = float4{sd.x * id, sd.y * id, sd.z * id, sd.w * id};
   }
@@ -628,8 +641,13 @@ hipError_t launch_meanfield(bool f64, const void* H, int ldh, int W, int n, int 
   }
   if (din_p % 4 == 0 && ldh % 4 == 0) {
     const int64_t t4 = (int64_t)W * Tp * (din_p / 4);
-    hipLaunchKernelGGL(meanfield4_kernel, dim3((unsigned)std::min<int64_t>((t4 + 255) / 256, 1 << 20)), dim3(256), 0, s,
-                       (const float*)H, ldh, W, n, n_up, Tp, din_p, (float*)Hbar);
+    const dim3 grid4((unsigned)std::min<int64_t>((t4 + 255) / 256, 1 << 20));
+    if (t4 + (int64_t)grid4.x * 256 < (1LL << 32))
+      hipLaunchKernelGGL(meanfield4_kernel<uint32_t>, grid4, dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p,
+                         (float*)Hbar);
+    else
+      hipLaunchKernelGGL(meanfield4_kernel<int64_t>, grid4, dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p,
+                         (float*)Hbar);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(meanfield_kernel<float>, dim3(grid), dim3(256), 0, s, (const float*)H, ldh, W, n, n_up, Tp, din_p,

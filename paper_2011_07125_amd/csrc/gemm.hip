@@ -619,6 +619,23 @@ static hipError_t pick(const JetGemmArgs& a, hipStream_t s) {
     const int w96 = (a.N + 95) / 96 * 96 - a.N;
     const int w64 = (a.N + 63) / 64 * 64 - a.N;
     const int bn = a.N <= 64 ? 64 : (w128 <= w96 && w128 <= w64) ? 128 : (w96 <= w64 ? 96 : 64);
+    if (a.rows_per == 1) {
+      // value pass (one row per electron): row tiles of 128, 64 or 32 rows,
+      // the largest that still gives the launch about 1024 workgroups
+      const int64_t nt = (a.N + bn - 1) / bn;
+      const int bm = (int64_t)(a.n_groups + 127) / 128 * nt >= 1024 ? 128
+                     : (int64_t)(a.n_groups + 63) / 64 * nt >= 1024 ? 64 : 32;
+      if (bm == 64) {
+        if (bn == 128) return run<MODE, 64, 128, EPI>(a, s);
+        if (bn == 96) return run<MODE, 64, 96, EPI>(a, s);
+        return run<MODE, 64, 64, EPI>(a, s);
+      }
+      if (bm == 32) {
+        if (bn == 128) return run<MODE, 32, 128, EPI>(a, s);
+        if (bn == 96) return run<MODE, 32, 96, EPI>(a, s);
+        return run<MODE, 32, 64, EPI>(a, s);
+      }
+    }
     if (bm96) {
       if (bn == 128) return run<MODE, 96, 128, EPI>(a, s);
       if (bn == 96) return run<MODE, 96, 96, EPI>(a, s);
@@ -640,6 +657,7 @@ static hipError_t pick_epi(int epi, const JetGemmArgs& a, hipStream_t s) {
 hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t s) {
   if (a.n_groups <= 0) return hipSuccess;
   if ((a.ka0 % 32) || (a.ka1 % 32)) return hipErrorInvalidValue;
+  if (a.mf_out && (mode == MODE_F64 || epi != EPI_TANHJET || !layer_mf_supported(a))) return hipErrorInvalidValue;
   if (mode == MODE_F64) return pick_epi<MODE_F64>(epi, a, s);
   // the one-electron layers take the full-width streaming kernel when their
   // shape allows it

@@ -44,6 +44,11 @@ struct JetGemmArgs {
   int res;
   float* pre_out;
   float* val_out;  // optional (float32 modes): the value row of out, compact: val_out[g * N + col]
+  // optional (float32 modes, layer_mf_supported): the spin means of out,
+  //   mf_out[((g / n_all) * rows_per + t) * mf_ld + a * mf_half + col] =
+  //   mean over the mf_na electrons of spin a of the walker of out's row t
+  //   (n_all = 2 mf_na electrons per walker, spin up first)
+  float* mf_out; int mf_ld; int mf_half; int mf_na;
   // EPI_ORBITAL: phi[((w * K + k) * T + t) * n_sub^2 + j * n_sub + i] with
   //   w = g / n_sub, j = g % n_sub, col = k * n_sub + i
   //   or, when phi_M > 0 (matrix index fastest, for the small-matrix
@@ -61,6 +66,9 @@ hipError_t launch_jet_gemm(int mode, int epi, const JetGemmArgs& a, hipStream_t 
 // the same kernel with a plain epilogue for EPI_PLAIN products over
 // contiguous rows
 bool layer_gemm_supported(const JetGemmArgs& a);
+// the jet layer can also write the spin means of its output (mf_out): equal
+// spin groups of at most 5 electrons, 32 jet rows, all electrons in the rows
+bool layer_mf_supported(const JetGemmArgs& a);
 hipError_t launch_layer_gemm(int mode, const JetGemmArgs& a, hipStream_t s);
 bool layer_plain_supported(const JetGemmArgs& a);
 hipError_t launch_layer_plain(int mode, const JetGemmArgs& a, hipStream_t s);

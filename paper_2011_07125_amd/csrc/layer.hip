@@ -10,6 +10,11 @@
 //    number of waves per electron) x BN = 128 columns; the column tiles of
 //    one row tile are issued back to back on the same XCD, so the repeated
 //    read of the activations is served by that XCD's L2;
+//  * for small atoms (equal spin groups of at most five electrons, 32 jet
+//    rows) a workgroup instead owns one spin group of one walker, one wave
+//    row per electron, and also writes the group's mean of its output rows:
+//    the mean field the next layer reads (Sec. 3) is formed from the tile in
+//    LDS instead of by a separate pass that reads every layer output again;
 //  * in the split-bfloat16 form each activation element is split into hi/lo
 //    parts once, by the thread that stages it into LDS (hardware
 //    round-to-nearest-even conversion); the bfloat16 tiles are stored without
@@ -48,8 +53,8 @@ struct LayerCfg {
   static constexpr int NVA = (NA + NT - 1) / NT;
   static constexpr int NB = MODE == MODE_F32 ? BN * BK / 4 : BN * BK / 8;  // 16-byte vectors per B plane
   static constexpr int NVB = (NB + NT - 1) / NT;
-  static_assert(NT == 512 && WROWS % 16 == 0 && WCOLS % 16 == 0, "tile shape");
-  static_assert(NB % NT == 0 && BN % 128 == 0, "every B vector is loaded; N is a multiple of 128");
+  static_assert(NT <= 1024 && WROWS % 16 == 0 && WCOLS % 16 == 0, "tile shape");
+  static_assert(BN % 128 == 0, "N is a multiple of 128");
 };
 
 __device__ inline uint32_t pk2(uint16_t a, uint16_t b) { return (uint32_t)a | ((uint32_t)b << 16); }
@@ -77,13 +82,16 @@ __device__ inline int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 1) & 3)) 
 // KIND_JET: the tanh layer's jet pass (rows_per jet rows per electron);
 // KIND_VALUE: its value pass (one row per electron); KIND_PLAIN: the plain
 // product c (=, or += with c_accum) over contiguous rows (rows_per = 1)
-constexpr int KIND_VALUE = 0, KIND_JET = 1, KIND_PLAIN = 2;
+// KIND_JET_MF: the jet pass over tiles of one spin group each (WM
+// electrons of 32 jet rows, one wave row per electron) that also writes the
+// group's mean of the output rows (mf_out)
+constexpr int KIND_VALUE = 0, KIND_JET = 1, KIND_PLAIN = 2, KIND_JET_MF = 3;
 
 template <int MODE, int BM, int BN, int WM, int WN, int KIND>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void layer_gemm_kernel(JetGemmArgs a,
-                                                                                                   int n_mtiles,
-                                                                                                   int n_ntiles) {
-  constexpr bool JET = KIND == KIND_JET;
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(WM * WN >= 8 ? 4 : 2, 8))) void
+layer_gemm_kernel(
+    JetGemmArgs a, int n_mtiles, int n_ntiles) {
+  constexpr bool JET = KIND == KIND_JET || KIND == KIND_JET_MF;
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
   constexpr int BK = C::BK, LDA = C::LDA, LDB = C::LDB, TM = C::TM, TN = C::TN, WROWS = C::WROWS;
   extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -129,7 +137,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
   for (int i = 0; i < C::NVB; ++i) {
     const int v = tid + i * C::NT;
-    voffB[i] = ((v / VPR) * a.ldb + (v % VPR) * (16 / ESZ)) * ESZ;
+    voffB[i] = C::NB % C::NT == 0 || v < C::NB ? ((v / VPR) * a.ldb + (v % VPR) * (16 / ESZ)) * ESZ : kOutOfRange;
   }
   const __amdgpu_buffer_rsrc_t rB = rsrc((const char*)a.bt + (size_t)n0 * a.ldb * ESZ);
   const __amdgpu_buffer_rsrc_t rBl =
@@ -189,7 +197,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
       for (int i = 0; i < C::NVB; ++i) {
         const int v = tid + i * C::NT;
-        *reinterpret_cast<u32x4*>(Bs + (v / (BK / 4)) * LDB + (v % (BK / 4)) * 4) = rb[i];
+        if (C::NB % C::NT == 0 || v < C::NB)
+          *reinterpret_cast<u32x4*>(Bs + (v / (BK / 4)) * LDB + (v % (BK / 4)) * 4) = rb[i];
       }
     } else {
       uint16_t* Ah = reinterpret_cast<uint16_t*>(st);
@@ -212,7 +221,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 #pragma unroll
       for (int i = 0; i < C::NVB; ++i) {
         const int v = tid + i * C::NT;
-        {
+        if (C::NB % C::NT == 0 || v < C::NB) {
           const int off = swz(v / (BK / 8), v % (BK / 8));
           *reinterpret_cast<u32x4*>(Bh + off) = rb[i];
           *reinterpret_cast<u32x4*>(Bl + off) = rbl[i];
@@ -469,7 +478,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     lapc[j] = -2.0f * y[j] * dy[j] * ss;
     if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + cw + c + j * 16] = u0;
   }
-  if (!gval) return;
+  // spin-group tiles: every electron of the tile exists (the host checks
+  // it), and the output tile is staged in LDS over the exchange buffer once
+  // every wave has read it
+  float* mfs = reinterpret_cast<float*>(smem);  // [BM][BN]
+  if constexpr (KIND == KIND_JET_MF) __syncthreads();
+  else if (!gval) return;
   // per 16-row tile: all residual loads first, then the stores.  Row t
   // becomes y (t = 0), sech^2 u0 times its tangent (0 < t < T - 1), the
   // same plus the curvature term (t = T - 1), or zero (padding, t >= T),
@@ -495,7 +509,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const float o = deriv ? fmaf(dy[j], acc[i][j][r], br) : br;  // selected: pad rows may hold anything
         stf(o, rO, voO + j * 64, so);
         if (first && a.val_out) a.val_out[(size_t)g * a.N + cw + c + j * 16] = o;
+        if constexpr (KIND == KIND_JET_MF) mfs[(wrow0 + i * 16 + kq * 4 + r) * BN + cl + j * 16] = o;
       }
+    }
+  }
+  if constexpr (KIND == KIND_JET_MF) {
+    // the group's mean of each output row: electrons in order, then times
+    // 1 / WM (the summation order and scaling of the separate mean-field
+    // pass, so both give the same bits)
+    __syncthreads();
+    const int wk = m_t >> 1, al = m_t & 1;  // tile m_t: spin group al of walker wk
+    const float inv = 1.0f / (float)WM;
+    float* dst = a.mf_out + (size_t)wk * rows_per * a.mf_ld + al * a.mf_half + n0;
+    for (int q = tid; q < rows_per * (BN / 4); q += C::NT) {
+      const int t = q / (BN / 4), c4 = (q % (BN / 4)) * 4;
+      float4 sm = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int e = 0; e < WM; ++e) {
+        const float4 v = *reinterpret_cast<const float4*>(mfs + (e * rows_per + t) * BN + c4);
+        sm.x += v.x;
+        sm.y += v.y;
+        sm.z += v.z;
+        sm.w += v.w;
+      }
+      *reinterpret_cast<float4*>(dst + (size_t)t * a.mf_ld + c4) = float4{sm.x * inv, sm.y * inv, sm.z * inv, sm.w * inv};
     }
   }
 }
@@ -503,16 +540,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 template <int MODE, int BM, int BN, int WM, int WN, int KIND>
 static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
-  const int E = KIND == KIND_JET ? BM / a.rows_per : BM;
+  // the spin-group tiles stage their output tile in LDS
+  constexpr int BYTES = KIND == KIND_JET_MF && BM * BN * 4 > C::BYTES ? BM * BN * 4 : C::BYTES;
+  const int E = KIND == KIND_JET || KIND == KIND_JET_MF ? BM / a.rows_per : BM;
   const int n_mtiles = (a.n_groups + E - 1) / E;
   const int n_ntiles = (a.N + BN - 1) / BN;
   const int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
   // once per instantiation (a local static is initialised once, thread-safely)
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, C::BYTES);
+      hipFuncAttributeMaxDynamicSharedMemorySize, BYTES);
   if (attr != hipSuccess) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>), dim3(grid), dim3(C::NT), C::BYTES, s, a,
+  hipLaunchKernelGGL((layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>), dim3(grid), dim3(C::NT), BYTES, s, a,
                      n_mtiles, n_ntiles);
   return hipGetLastError();
 }
@@ -521,7 +560,24 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
 // one electron (value mode: one row per electron)
 template <int MODE>
 static hipError_t pick_layer(const JetGemmArgs& a, hipStream_t s) {
-  if (a.rows_per == 1) return run_layer<MODE, 128, 128, 4, 2, KIND_VALUE>(a, s);
+  if (a.rows_per == 1) {
+    // value pass: 64-row tiles when 128-row tiles give the launch fewer
+    // than about 1024 workgroups
+    const int64_t nt = (a.N + 127) / 128;
+    if ((int64_t)(a.n_groups + 127) / 128 * nt < 1024) return run_layer<MODE, 64, 128, 4, 2, KIND_VALUE>(a, s);
+    return run_layer<MODE, 128, 128, 4, 2, KIND_VALUE>(a, s);
+  }
+  if (a.mf_out) {
+    // one spin group of mf_na electrons per tile, one wave row per electron
+    switch (a.mf_na) {
+      case 1: return run_layer<MODE, 32, 128, 1, 2, KIND_JET_MF>(a, s);
+      case 2: return run_layer<MODE, 64, 128, 2, 2, KIND_JET_MF>(a, s);
+      case 3: return run_layer<MODE, 96, 128, 3, 2, KIND_JET_MF>(a, s);
+      case 4: return run_layer<MODE, 128, 128, 4, 2, KIND_JET_MF>(a, s);
+      case 5: return run_layer<MODE, 160, 128, 5, 2, KIND_JET_MF>(a, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.rows_per == 96) return run_layer<MODE, 96, 128, 2, 4, KIND_JET>(a, s);
   if (a.rows_per == 32 || a.rows_per == 64 || a.rows_per == 128)
     return run_layer<MODE, 128, 128, 4, 2, KIND_JET>(a, s);
@@ -557,9 +613,15 @@ bool layer_gemm_supported(const JetGemmArgs& a) {
   return (rp == 1 ? a.T == 1 : tall && a.T <= rp) && a.N % 128 == 0 && a.ka0 % 32 == 0 && a.ka1 % 32 == 0;
 }
 
+bool layer_mf_supported(const JetGemmArgs& a) {
+  return layer_gemm_supported(a) && a.rows_per == 32 && a.mf_na >= 1 && a.mf_na <= 5 && a.n_all == 2 * a.mf_na &&
+         a.n_sub == a.n_all && a.e_off == 0 && a.n_groups % a.n_all == 0 && a.mf_ld % 4 == 0 && a.mf_half % 4 == 0 &&
+         a.mf_half >= a.N && a.mf_ld >= 2 * a.mf_half;
+}
+
 hipError_t launch_layer_gemm(int mode, const JetGemmArgs& a, hipStream_t s) {
   if (a.n_groups <= 0) return hipSuccess;
-  if (!layer_gemm_supported(a)) return hipErrorInvalidValue;
+  if (!layer_gemm_supported(a) || (a.mf_out && !layer_mf_supported(a))) return hipErrorInvalidValue;
   return mode == MODE_BF16X3 ? pick_layer<MODE_BF16X3>(a, s) : pick_layer<MODE_F32>(a, s);
 }
 

@@ -22,6 +22,7 @@ ENVELOPES = {"isotropic": FN_ENV_ISOTROPIC, "full": FN_ENV_FULL}
 PRECISIONS = {"fp32": FN_PREC_FP32, "bf16": FN_PREC_BF16, "fp32_fp64det": FN_PREC_FP32_FP64DET, "fp64": FN_PREC_FP64}
 FN_ENTRY_LOGPSI, FN_ENTRY_LOCAL_ENERGY, FN_ENTRY_GRAD_LOGPSI, FN_ENTRY_MCMC, FN_ENTRY_KFAC = 0, 1, 2, 3, 4
 FN_ENTRY_KFAC_PRECONDITION, FN_ENTRY_TRAIN, FN_ENTRY_LOCAL_ENERGY_GRADIENT = 5, 6, 7
+FN_OPT_FUSED_MEANFIELD = 1
 STATUS = {0: "FN_OK", 1: "FN_ERR_NULL", 2: "FN_ERR_CONFIG", 3: "FN_ERR_SPINS", 4: "FN_ERR_WORKSPACE",
           5: "FN_ERR_UNSUPPORTED", 6: "FN_ERR_HIP", 7: "FN_ERR_ARG"}
 
@@ -59,7 +60,7 @@ EXPORTS = ("ferminet_status_string", "ferminet_param_count", "ferminet_param_lay
            "ferminet_logpsi", "ferminet_logpsi_noalloc", "ferminet_local_energy", "ferminet_grad_logpsi", "vmc_energy_gradient",
            "vmc_local_energy_gradient", "vmc_mcmc_step", "vmc_mcmc_noise", "ferminet_kfac_factors", "ferminet_kfac_layout",
            "ferminet_kfac_precondition", "vmc_train_step",
-           "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name")
+           "ferminet_stage_timing", "ferminet_stage_times", "ferminet_stage_name", "ferminet_set_option")
 
 _LIB = None
 _LOCK = threading.Lock()
@@ -98,6 +99,7 @@ def _lib():
                 lib.ferminet_stage_timing.argtypes = [i32]
                 lib.ferminet_stage_times.argtypes = [P, P, i32]
                 lib.ferminet_stage_name.argtypes = [i32]
+                lib.ferminet_set_option.argtypes = [i32, i32]
                 for f in EXPORTS[2:]:
                     getattr(lib, f).restype = i32
                 lib.ferminet_stage_name.restype = ctypes.c_char_p
@@ -392,6 +394,13 @@ def vmc_mcmc_noise(W, n_elec, n_steps, seed, counter=0, device="cuda"):
     _check(_lib().vmc_mcmc_noise(W, n_elec, n_steps, int(seed), int(counter), _ptr(noise), _ptr(uni), _stream()),
            "vmc_mcmc_noise")
     return noise, uni
+
+
+def set_option(option: int, value: int):
+    """ferminet_set_option: a process-wide execution option for later calls
+    (FN_OPT_FUSED_MEANFIELD: 1 forms the spin means in the layer kernel where
+    the shape allows, 0 runs the separate pass; same bits)."""
+    _check(_lib().ferminet_set_option(int(option), int(value)), "ferminet_set_option")
 
 
 def stage_timing(enable: bool):

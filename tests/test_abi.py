@@ -113,6 +113,12 @@ def test_entry_points_reject_bad_arguments_before_launch():
     assert h(ctypes.byref(c), 8, fake, good, fake, fake, fake, None, None, fake, 1 << 30, None) == 1
     assert lib.vmc_mcmc_noise(-1, 4, 1, 0, 0, fake, fake, None) == 7
     assert lib.ferminet_status_string(4).decode().startswith("workspace")
+    # execution options: unknown option or value rejected; both values of
+    # FN_OPT_FUSED_MEANFIELD accepted (the default, 1, is restored)
+    assert lib.ferminet_set_option(99, 1) == 7
+    assert lib.ferminet_set_option(F.FN_OPT_FUSED_MEANFIELD, 2) == 7
+    assert lib.ferminet_set_option(F.FN_OPT_FUSED_MEANFIELD, 0) == 0
+    assert lib.ferminet_set_option(F.FN_OPT_FUSED_MEANFIELD, 1) == 0
 
 
 def test_train_step_rejects_bad_arguments_before_launch():

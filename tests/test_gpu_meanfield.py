@@ -1,0 +1,68 @@
+"""The spin means of the mean field (Sec. 3) formed in the jet layer kernel
+(FN_OPT_FUSED_MEANFIELD = 1, the default) against the separate mean-field
+pass (FN_OPT_FUSED_MEANFIELD = 0): the two paths sum the same float32
+values in the same order and scale them the same way, so every output of
+the local energy, of the one-pass local energy and VMC gradient and of the
+Metropolis moves is compared bit for bit.  The atoms with equal spin groups
+of at most five electrons (be4, ne10) take the fused path; the 18-electron
+atom (groups of nine) does not, and the option must not change it either.
+Oracle parity of the fused path is covered by the parity and gate tests,
+which run with the default."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_2011_07125_amd import ferminet as F  # noqa: E402
+from paper_2011_07125_amd import inputs as I  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _restore_default():
+    yield
+    F.set_option(F.FN_OPT_FUSED_MEANFIELD, 1)
+    F.release_workspaces()
+
+
+def _run(w, d, form, fused, walkers):
+    F.set_option(F.FN_OPT_FUSED_MEANFIELD, 1 if fused else 0)
+    cfg = w["cfg"]
+    pos = d["pos"][:walkers].clone()
+    args = (cfg, pos, d["nuc_pos"], d["nuc_charge"], d["params"])
+    res = {}
+    out = F.ferminet_local_energy(*args, precision=form, rescue=I.RESCUE[w["name"]][form])
+    res.update({"le_" + k: v for k, v in out.items()})
+    out, grad, stats = F.vmc_local_energy_gradient(*args, precision=form, rescue=I.RESCUE[w["name"]][form])
+    res.update({"leg_" + k: v for k, v in out.items()})
+    res["grad"] = grad
+    res["stats"] = stats
+    s, l = F.ferminet_logpsi(*args, precision=form)
+    acc = F.vmc_mcmc_step(*args, l, s, 3, 0.05, 17, 0, precision=form)
+    res.update({"mc_pos": pos, "mc_logpsi": l, "mc_sign": s, "mc_acc": acc})
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+@pytest.mark.parametrize("form", ["bf16", "fp32_fp64det"])
+@pytest.mark.parametrize("name,walkers", [("be4", 256), ("ne10", 4096), ("ar18", 64)])
+def test_fused_meanfield_same_bits(name, walkers, form):
+    say(f"case fused mean field {name} {form} W={walkers}")
+    w = I.make_workload(name)
+    w["name"] = name
+    d = F.to_device(w)
+    a = _run(w, d, form, True, walkers)
+    b = _run(w, d, form, False, walkers)
+    for k in a:
+        same = np.array_equal(a[k], b[k], equal_nan=True)
+        if not same:
+            diff = np.abs(a[k].astype(np.float64) - b[k].astype(np.float64))
+            say(f"   {k}: max |d| {np.nanmax(diff):.3e} at {np.unravel_index(np.nanargmax(diff), diff.shape)}")
+        assert same, f"{name}/{form}: {k} differs between the fused and the separate mean-field pass"
