@@ -40,16 +40,21 @@ LAYER_SRC = os.path.join(ROOT, "paper_2011_07125_amd", "csrc", "layer.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "layer_gemm_ne10_traffic.md")
 
 
-def layer_flops(cfg, W, T):
-    """Algorithmic FLOPs of the L layer GEMMs (jet rows x [h_i, g^up_i,
-    g^down_i] x d1, unpadded) and of the L mean-field GEMMs."""
+def layer_flops_each(cfg, W, T):
+    """Algorithmic FLOPs of each of the L layer GEMMs (jet rows x [h_i,
+    g^up_i, g^down_i] x d1, unpadded): [(layer, mean-field GEMM)]."""
     n, N, d1, d2, L = cfg["n_elec"], cfg["n_nuc"], cfg["width1"], cfg["width2"], cfg["n_layers"]
-    main = mf = 0
+    out = []
     for l in range(L):
         din, ein = (4 * N, 4) if l == 0 else (d1, d2)
-        main += 2 * W * n * T * (din + 2 * ein) * d1
-        mf += 2 * W * T * (2 * din) * d1
-    return main, mf
+        out.append((2 * W * n * T * (din + 2 * ein) * d1, 2 * W * T * (2 * din) * d1))
+    return out
+
+
+def layer_flops(cfg, W, T):
+    """Algorithmic FLOPs of the L layer GEMMs and of the L mean-field GEMMs."""
+    each = layer_flops_each(cfg, W, T)
+    return sum(m for m, _ in each), sum(f for _, f in each)
 
 
 def walker_flops(cfg):
@@ -78,19 +83,29 @@ def step_ceiling(cfg, mcmc_steps, grad):
     return PEAK["bf16"] * 1e12 / per_walker
 
 
-def layer_bytes(cfg, W, T):
-    """Algorithmic HBM bytes of the L one-electron layer GEMMs of the jet
+def layer_bytes_each(cfg, W, T, fused):
+    """Algorithmic HBM bytes of each one-electron layer GEMM of the jet
     pass: read the jet rows of [h_i, g^up_i, g^down_i] and the per-walker
     mean-field rows P, write the new jet rows (float32), read the weights
-    once (bfloat16 hi and lo planes).  The residual re-reads h_i, which is
+    once (bfloat16 hi and lo planes); a launch that also forms the spin
+    means of its output (fused, every layer but the last) writes the two
+    per-walker mean rows as well.  The residual re-reads h_i, which is
     already counted in the input."""
     n, N, d1, d2, L = cfg["n_elec"], cfg["n_nuc"], cfg["width1"], cfg["width2"], cfg["n_layers"]
-    total = 0
+    out = []
     for l in range(L):
         din, ein = (4 * N, 4) if l == 0 else (d1, d2)
         k = din + 2 * ein
-        total += 4 * W * n * T * (k + d1) + 4 * W * T * d1 + 4 * k * d1
-    return total
+        b = 4 * W * n * T * (k + d1) + 4 * W * T * d1 + 4 * k * d1
+        if fused and l + 1 < L:
+            b += 4 * W * 2 * T * d1
+        out.append(b)
+    return out
+
+
+def layer_bytes(cfg, W, T):
+    """Algorithmic HBM bytes of the L one-electron layer GEMMs (no fused means)."""
+    return sum(layer_bytes_each(cfg, W, T, False))
 
 
 def measured_traffic():
@@ -362,17 +377,24 @@ def main():
         ms_it = t0.elapsed_time(t1) / n_it
         res["vmc_iteration_bf16"] = {"ms_per_iteration": ms_it, "value": W / (ms_it * 1e-3),
                                      "unit": "walker-iterations/s", "mcmc_steps": 10}
-    main_fl, mf_fl = layer_flops(cfg, W, T)
-    # dominant kernel: the one-electron layer GEMM of the jet pass (L
-    # launches per local-energy call, layer 0 included), a dense contraction
-    # priced against the bf16 MFMA peak with its algorithmic FLOPs (jet rows
-    # x [h_i, g^up_i, g^down_i] x d1, unpadded; one multiply-add counted
-    # once although the split form issues three bf16 MFMAs for it).  Its HBM
-    # rate at the bytes of its float32 jets is kept as a secondary figure.
-    tot, cnt = st_bf.get("gemm_layer", (0.0, 0))
+    # dominant kernel: the one-electron layer GEMM of the jet pass, a dense
+    # contraction priced against the bf16 MFMA peak with its algorithmic
+    # FLOPs (jet rows x [h_i, g^up_i, g^down_i] x d1, unpadded; one
+    # multiply-add counted once although the split form issues three bf16
+    # MFMAs for it).  Where the spin groups allow it, the launches of every
+    # layer but the last also form the spin means of their output (stage
+    # gemm_layer_mf, one spin group per tile): those are the dominant
+    # launches and the figure is theirs; otherwise all L launches (stage
+    # gemm_layer).  Its HBM rate at the bytes of its float32 jets is kept as
+    # a secondary figure.
     L = cfg["n_layers"]
-    flops_per_launch = main_fl / L
-    bytes_per_launch = layer_bytes(cfg, W, T) / L
+    fl_each = [m for m, _ in layer_flops_each(cfg, W, T)]
+    fused = st_bf.get("gemm_layer_mf", (0.0, 0))[1] > 0
+    by_each = layer_bytes_each(cfg, W, T, fused)
+    sel = list(range(L - 1)) if fused else list(range(L))
+    tot, cnt = st_bf.get("gemm_layer_mf" if fused else "gemm_layer", (0.0, 0))
+    flops_per_launch = sum(fl_each[l] for l in sel) / len(sel)
+    bytes_per_launch = sum(by_each[l] for l in sel) / len(sel)
     jet_launch_ms = tot / cnt if cnt else None
     tflops = flops_per_launch / (jet_launch_ms * 1e-3) / 1e12 if jet_launch_ms else None
     gbs = bytes_per_launch / (jet_launch_ms * 1e-3) / 1e9 if jet_launch_ms else None
@@ -381,7 +403,9 @@ def main():
     ceiling = step_ceiling(cfg, mcmc_steps, grad)
     roof = {"bound": "mfma", "achieved": tflops, "peak": PEAK["bf16"], "unit": "TFLOP/s",
             "frac": (tflops / PEAK["bf16"]) if tflops else None, "traffic": traffic,
-            "kernel": "layer_gemm_kernel<MODE_BF16X3,128,128,4,2,jet> (one-electron layer, tanh-jet epilogue)",
+            "kernel": (f"layer_gemm_kernel<MODE_BF16X3,{32 * cfg['n_up']},128,{cfg['n_up']},2,jet_mf> (one-electron "
+                       f"layers 0..{L - 2}: tanh-jet epilogue and the spin means of the output)") if fused else
+                      "layer_gemm_kernel<MODE_BF16X3,128,128,4,2,jet> (one-electron layer, tanh-jet epilogue)",
             "flops_per_launch": flops_per_launch, "avg_launch_ms": jet_launch_ms, "launches_timed": cnt,
             "hbm_secondary": {"achieved": gbs, "peak": HBM_GBS, "unit": "GB/s",
                               "frac": (gbs / HBM_GBS) if gbs else None, "bytes_per_launch": bytes_per_launch},
@@ -406,7 +430,8 @@ def main():
                                f"({cfg['n_up']} up/{cfg['n_down']} down), {W} walkers, {cfg['n_layers']} layers "
                                f"{cfg['width1']}/{cfg['width2']}, {cfg['n_det']} dets, isotropic envelope",
                    "walkers": W, "step": f"{mcmc_steps} Metropolis move{'s' if mcmc_steps > 1 else ''} + local energy" + (" + VMC gradient" if grad else ""),
-                   "form": "bf16x3 layer GEMMs (fp32 accumulation), fp32 orbital GEMM, fp64 determinants, fp64 re-evaluation of the "
+                   "form": "bf16x3 layer GEMMs (fp32 accumulation), orbital GEMM on fp32 operands split into three bf16 parts (six "
+                           "bf16 MFMAs, fp32 accumulation), fp64 determinants, fp64 re-evaluation of the "
                            f"{args.rescue_bf16:.0%} walkers of largest rounding-error scale",
                    "rescue_fraction": args.rescue_bf16,
                    "parallelism": "single GPU"},

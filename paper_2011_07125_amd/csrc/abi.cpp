@@ -152,7 +152,7 @@ enum Mode { VALUE = 0, JET = 1 };
 enum Stage {
   ST_PACK, ST_FEATURES, ST_TWO_E, ST_MEANFIELD, ST_GEMM_MF, ST_GEMM_LAYER, ST_GEMM_ORB, ST_DET, ST_COMBINE,
   ST_PROPOSE, ST_ACCEPT, ST_ADJ_FWD, ST_ADJ_DET, ST_ADJ_ORB, ST_ADJ_LAYERS, ST_ADJ_TWO_E, ST_ADJ_REDUCE,
-  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_KFAC, ST_TRAIN, ST_COUNT
+  ST_GEMM_LAYER_VALUE, ST_RESCUE, ST_KFAC, ST_TRAIN, ST_GEMM_LAYER_MF, ST_COUNT
 };
 
 struct Bufs {
@@ -545,7 +545,7 @@ static const char* kStageNames[ST_COUNT] = {
     "pack_weights", "features",  "two_electron", "meanfield",    "gemm_meanfield", "gemm_layer",
     "gemm_orbital", "det",       "combine",      "mcmc_propose", "mcmc_accept",    "adj_forward",
     "adj_det",      "adj_orbital", "adj_layers", "adj_two_electron", "adj_reduce",     "gemm_layer_value",
-    "rescue_fp64",  "kfac_precondition", "train_step"};
+    "rescue_fp64",  "kfac_precondition", "train_step", "gemm_layer_mf"};
 static std::mutex g_time_mu;
 static std::atomic<bool> g_timing{false};
 struct StageRec {
@@ -713,7 +713,8 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
       hbar_ready = layer_mf_supported(h);
       if (!hbar_ready) h.mf_out = nullptr;
     }
-    FN_T(SG(m == JET ? ST_GEMM_LAYER : ST_GEMM_LAYER_VALUE), launch_jet_gemm(p.mode, EPI_TANHJET, h, s));
+    FN_T(SG(m == JET ? (hbar_ready ? ST_GEMM_LAYER_MF : ST_GEMM_LAYER) : ST_GEMM_LAYER_VALUE),
+         launch_jet_gemm(p.mode, EPI_TANHJET, h, s));
     Hin = Hout;
     Hout = Hout == b.Ha ? b.Hb : b.Ha;
   }
