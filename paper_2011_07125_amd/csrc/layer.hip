@@ -481,7 +481,10 @@ layer_gemm_kernel(
   // spin-group tiles: every electron of the tile exists (the host checks
   // it), and the output tile is staged in LDS over the exchange buffer once
   // every wave has read it
-  float* mfs = reinterpret_cast<float*>(smem);  // [BM][BN]
+  // rows padded by 4 floats: the four 4-row lane groups of a store hit
+  // different banks
+  constexpr int MF_LD = BN + 4;
+  float* mfs = reinterpret_cast<float*>(smem);  // [BM][MF_LD]
   if constexpr (KIND == KIND_JET_MF) __syncthreads();
   else if (!gval) return;
   // per 16-row tile: all residual loads first, then the stores.  Row t
@@ -509,7 +512,7 @@ layer_gemm_kernel(
         const float o = deriv ? fmaf(dy[j], acc[i][j][r], br) : br;  // selected: pad rows may hold anything
         stf(o, rO, voO + j * 64, so);
         if (first && a.val_out) a.val_out[(size_t)g * a.N + cw + c + j * 16] = o;
-        if constexpr (KIND == KIND_JET_MF) mfs[(wrow0 + i * 16 + kq * 4 + r) * BN + cl + j * 16] = o;
+        if constexpr (KIND == KIND_JET_MF) mfs[(wrow0 + i * 16 + kq * 4 + r) * MF_LD + cl + j * 16] = o;
       }
     }
   }
@@ -526,7 +529,7 @@ layer_gemm_kernel(
       float4 sm = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int e = 0; e < WM; ++e) {
-        const float4 v = *reinterpret_cast<const float4*>(mfs + (e * rows_per + t) * BN + c4);
+        const float4 v = *reinterpret_cast<const float4*>(mfs + (e * rows_per + t) * MF_LD + c4);
         sm.x += v.x;
         sm.y += v.y;
         sm.z += v.z;
@@ -541,7 +544,7 @@ template <int MODE, int BM, int BN, int WM, int WN, int KIND>
 static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   using C = LayerCfg<MODE, BM, BN, WM, WN>;
   // the spin-group tiles stage their output tile in LDS
-  constexpr int BYTES = KIND == KIND_JET_MF && BM * BN * 4 > C::BYTES ? BM * BN * 4 : C::BYTES;
+  constexpr int BYTES = KIND == KIND_JET_MF && BM * (BN + 4) * 4 > C::BYTES ? BM * (BN + 4) * 4 : C::BYTES;
   const int E = KIND == KIND_JET || KIND == KIND_JET_MF ? BM / a.rows_per : BM;
   const int n_mtiles = (a.n_groups + E - 1) / E;
   const int n_ntiles = (a.N + BN - 1) / BN;
