@@ -265,10 +265,56 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
       }
       __syncthreads();
       // phase 2: four columns of one (electron e, jet row t) per item, one
-      // 16-byte store (ldg is a multiple of 32).  (e, t, c4) and the
-      // electron's index ie within its walker advance with carries.
-      {
-        const int nc4 = ldg / 4;
+      // 16-byte store (ldg is a multiple of 32).
+      const int nc4 = ldg / 4;
+      if (ein % 4 == 0 && blockDim.x % nc4 == 0 && Tp % (blockDim.x / nc4) == 0) {
+        // every thread keeps one column quad c0 (in one spin half: ncol =
+        // 2 ein) and the jet rows t = tid / nc4 + k blockDim / nc4 of every
+        // electron of the block, so that everything but the electron is
+        // worked out once per row (the jet passes: the same items as below,
+        // in another order)
+        const int c0 = (tid % nc4) * 4, rstep = blockDim.x / nc4;
+        const int al = c0 >= ein ? 1 : 0;
+        const bool colv = c0 < ncol;
+        const S sc = al == 0 ? inv_up : inv_dn;
+        const int e_end = min(a.ipb, n_groups - gbase);
+        for (int t = tid / nc4; t < Tp; t += rstep) {
+          const bool live = t < T && colv;
+          const int jt = t >= 1 ? ((t - 1) * 43691) >> 17 : -1;  // (t - 1) / 3, exact for t < 2^16
+          const int cc = t - 1 - 3 * jt;
+          const bool row_shared = t == 0 || t == T - 1;
+          const int qq = t == 0 ? 0 : t == T - 1 ? 4 : 1 + cc;
+          // partner row of jt: only the quads of jt's spin half are nonzero
+          const bool own_half = (al == 0) == (jt < n_up);
+          const S* ssrc = Ss + (size_t)qq * ncol + c0;
+          const int jp = jt < 0 ? 0 : jt < n ? jt : n - 1;  // the address of a row that reads it
+          const S* psrc = Ps + ((size_t)jp * R2 + 4 + cc) * PS + (c0 - al * ein);
+          S* dst = G + ((int64_t)gbase * Tp + t) * ldg + c0;
+          int ie = i0;
+          for (int e = 0; e < e_end; ++e) {
+            S v[4] = {0, 0, 0, 0};
+            if (live) {
+              if (row_shared || jt == ie) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = ssrc[(size_t)e * nq * ncol + k];
+              } else if (own_half) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = psrc[(size_t)e * n * R2 * PS + k] * sc;
+              }
+            }
+            S* d = dst + (int64_t)e * Tp * ldg;
+            if constexpr (sizeof(S) == 4) {
+              *reinterpret_cast<float4*>(d) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+            } else {
+              reinterpret_cast<double2*>(d)[0] = double2{(double)v[0], (double)v[1]};
+              reinterpret_cast<double2*>(d)[1] = double2{(double)v[2], (double)v[3]};
+            }
+            ie = ie + 1 == n ? 0 : ie + 1;
+          }
+        }
+      } else {
+        // general case: (e, t, c4) and the electron's index ie within its
+        // walker advance with carries
         int c4 = tid % nc4, row = tid / nc4;
         const int dc4 = blockDim.x % nc4, drow = blockDim.x / nc4;
         int e = row / Tp, t = row - e * Tp;
