@@ -19,6 +19,31 @@ namespace fn {
 
 constexpr int TB = 32;
 
+// the value of v in lane l of the wavefront (l uniform)
+__device__ inline double readlane_f64(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l), hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One TB x TB tile product on the float64 matrix cores, for a 256-thread
+// workgroup: wave w forms the 16 x 16 output block (w / 2, w % 2) of
+//   C[r][c] = sum_k X(r, k) Y(k, c)
+// with 8 steps of v_mfma_f64_16x16x4 (k = 4 s + lane / 16).  The result of
+// element q of the lane is row 16 (w / 2) + lane / 16 + 4 q, column
+// 16 (w % 2) + lane % 16, handed to put(row, col, value).
+template <class FX, class FY, class FP>
+__device__ inline void tile_mm_f64(int tid, FX X, FY Y, FP put) {
+  const int lane = tid & 63, w = tid >> 6;
+  const int r0 = (w >> 1) * 16, c0 = (w & 1) * 16, lr = lane & 15, lk = lane >> 4;
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < TB / 4; ++s)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X(r0 + lr, 4 * s + lk), Y(4 * s + lk, c0 + lr), acc, 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) put(r0 + lk + 4 * q, c0 + lr, acc[q]);
+}
+
 // ------------------------------------------------------------- set-up
 // per dense layer b (blockIdx.x): damped copies of A and G, and M, in
 // float64; blockIdx.y takes PREP_ROWS rows of each.  Every workgroup forms
@@ -84,34 +109,65 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(SpdBatch bt, double* S, 
   const int tb = min(TB, n - t0);
   double* A = S + bt.off[mat];
   double* I = S + bt.offI[mat] + (size_t)kb * TB * TB;
-  __shared__ double D[TB][TB + 1], V[TB][TB + 1];
+  __shared__ double D[TB][TB + 1], V[TB][TB + 1], RD[TB];
   for (int e = tid; e < TB * TB; e += 256) {
     const int r = e / TB, c = e % TB;
     D[r][c] = (r < tb && c < tb) ? A[(size_t)(t0 + r) * n + t0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int j = 0; j < TB; ++j) {
-    if (tid == 0) D[j][j] = sqrt(D[j][j]);
-    __syncthreads();
-    for (int i = j + 1 + tid; i < TB; i += 256) D[i][j] /= D[j][j];
-    __syncthreads();
-    for (int e = tid; e < TB * TB; e += 256) {
-      const int i = e / TB, k = e % TB;
-      if (k > j && k <= i) D[i][k] -= D[i][j] * D[k][j];
-    }
-    __syncthreads();
-  }
-  // V = D^-1 (lower triangular): thread c solves D v = e_c
-  if (tid < TB) {
-    const int c = tid;
-    for (int r = 0; r < TB; ++r) {
-      double x = 0.0;
-      if (r >= c) {
-        x = r == c ? 1.0 : 0.0;
-        for (int k = c; k < r; ++k) x -= D[r][k] * V[k][c];
-        x /= D[r][r];
+  // the factorisation in one wavefront: lane i < TB holds row i in
+  // registers; column j's pivot and entries reach every lane by readlane
+  // (uniform lane indices), so no barrier is needed.  Lanes past TB work on
+  // zero rows and store nothing.
+  if (tid < 64) {
+    const int i = tid;
+    double a[TB];
+#pragma unroll
+    for (int k = 0; k < TB; ++k) a[k] = i < TB ? D[i][k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      const double d = sqrt(readlane_f64(a[j], j)), rd = 1.0 / d;
+      a[j] = i == j ? d : (i > j ? a[j] * rd : a[j]);
+#pragma unroll
+      for (int k = j + 1; k < TB; ++k) {
+        const double lkj = readlane_f64(a[j], k);
+        a[k] = i >= k ? a[k] - a[j] * lkj : a[k];
       }
-      V[r][c] = x;
+    }
+    if (i < TB) {
+#pragma unroll
+      for (int k = 0; k < TB; ++k) D[i][k] = a[k];
+      // the reciprocals of the diagonal, off the substitution's critical path
+#pragma unroll
+      for (int k = 0; k < TB; ++k)
+        if (k == i) RD[i] = 1.0 / a[k];
+    }
+  }
+  __syncthreads();
+  // V = D^-1 (lower triangular) by forward substitution, column c by the
+  // eight lanes 8 c .. 8 c + 7: row r of the column is
+  //   (delta_rc - sum_{c <= k < r} D[r][k] V[k][c]) / D[r][r],
+  // each lane summing k = c + g, c + g + 8, ... and keeping its own V[k][c]
+  {
+    const int c = tid >> 3, g = tid & 7;
+    double vk[TB / 8];
+#pragma unroll
+    for (int q = 0; q < TB / 8; ++q) vk[q] = 0.0;
+    for (int r = 0; r < TB; ++r) {
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < TB / 8; ++q) {
+        const int k = c + g + 8 * q;
+        if (k < r) part += D[r][k] * vk[q];
+      }
+      part += __shfl_xor(part, 1, 8);
+      part += __shfl_xor(part, 2, 8);
+      part += __shfl_xor(part, 4, 8);
+      const double x = r < c ? 0.0 : ((r == c ? 1.0 : 0.0) - part) * RD[r];
+#pragma unroll
+      for (int q = 0; q < TB / 8; ++q)
+        if (r == c + g + 8 * q) vk[q] = x;
+      if (g == 0) V[r][c] = x;
     }
   }
   __syncthreads();
@@ -137,20 +193,11 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(SpdBatch bt, double* S,
     P[r][c] = r < rb ? A[(size_t)(r0 + r) * n + t0 + c] : 0.0;  // kb < ib: the tile's columns are whole
   }
   __syncthreads();
-  double out[TB * TB / 256];
-#pragma unroll
-  for (int q = 0; q < TB * TB / 256; ++q) {
-    const int e = tid + q * 256, r = e / TB, c = e % TB;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < TB; ++k) acc += P[r][k] * V[c][k];
-    out[q] = acc;
-  }
-#pragma unroll
-  for (int q = 0; q < TB * TB / 256; ++q) {
-    const int e = tid + q * 256, r = e / TB, c = e % TB;
-    if (r < rb) A[(size_t)(r0 + r) * n + t0 + c] = out[q];
-  }
+  tile_mm_f64(
+      tid, [&](int r, int k) { return P[r][k]; }, [&](int k, int c) { return V[c][k]; },
+      [&](int r, int c, double v) {
+        if (r < rb) A[(size_t)(r0 + r) * n + t0 + c] = v;
+      });
 }
 
 // trailing tiles (ib, jb), kb < jb <= ib: A[ib][jb] -= L[ib][kb] L[jb][kb]^T;
@@ -176,14 +223,11 @@ __global__ __launch_bounds__(256) void chol_update_kernel(SpdBatch bt, double* S
     Pj[r][c] = r < cb ? A[(size_t)(c0 + r) * n + t0 + c] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int r = e / TB, c = e % TB;
-    if (r >= rb || c >= cb) continue;
-    double s = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < TB; ++k) s += Pi[r][k] * Pj[c][k];
-    A[(size_t)(r0 + r) * n + c0 + c] -= s;
-  }
+  tile_mm_f64(
+      tid, [&](int r, int k) { return Pi[r][k]; }, [&](int k, int c) { return Pj[c][k]; },
+      [&](int r, int c, double v) {
+        if (r < rb && c < cb) A[(size_t)(r0 + r) * n + c0 + c] -= v;
+      });
 }
 
 // ------------------------------------------------------------ triangular solves
@@ -215,15 +259,9 @@ __global__ __launch_bounds__(256) void trsm_step_kernel(SpdBatch bt, double* S, 
     Bk[r][c] = (r < tb && c < cb) ? src[(size_t)(t0 + r) * m + c0 + c] : 0.0;
   }
   __syncthreads();
-  constexpr int Q = TB * TB / 256;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = tid + q * 256, r = e / TB, c = e % TB;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < TB; ++k) acc += V[r][k] * Bk[k][c];
-    Zk[r][c] = acc;
-  }
+  tile_mm_f64(
+      tid, [&](int r, int k) { return V[r][k]; }, [&](int k, int c) { return Bk[k][c]; },
+      [&](int r, int c, double v) { Zk[r][c] = v; });
   __syncthreads();
   if (ib == kb) {
     for (int e = tid; e < TB * TB; e += 256) {
@@ -239,16 +277,11 @@ __global__ __launch_bounds__(256) void trsm_step_kernel(SpdBatch bt, double* S, 
     else V[r][c] = (r < rb && c < tb) ? L[(size_t)(t0 + c) * n + r0 + r] : 0.0;
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = tid + q * 256, r = e / TB, c = e % TB;
-    if (r < rb && c < cb) {
-      double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < TB; ++k) acc += V[r][k] * Zk[k][c];
-      src[(size_t)(r0 + r) * m + c0 + c] -= acc;
-    }
-  }
+  tile_mm_f64(
+      tid, [&](int r, int k) { return V[r][k]; }, [&](int k, int c) { return Zk[k][c]; },
+      [&](int r, int c, double v) {
+        if (r < rb && c < cb) src[(size_t)(r0 + r) * m + c0 + c] -= v;
+      });
 }
 
 // ------------------------------------------------------------ transposes
