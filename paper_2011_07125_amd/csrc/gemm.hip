@@ -641,6 +641,10 @@ static hipError_t pick(const JetGemmArgs& a, hipStream_t s) {
       if (bn == 96) return run<MODE, 96, 96, EPI>(a, s);
       return run<MODE, 96, 64, EPI>(a, s);
     }
+    // orbital products of 32-row jets: row tiles of three electrons (more
+    // workgroups per CU than four-electron tiles; the Ne-like orbital stage
+    // 0.58 -> 0.51 ms in the six-product form, 0.67 -> 0.65 ms in fp32)
+    if (EPI == EPI_ORBITAL && a.rows_per == 32 && bn == 96) return run<MODE, 96, 96, EPI>(a, s);
     if (bn == 128) return run<MODE, 128, 128, EPI>(a, s);
     if (bn == 96) return run<MODE, 128, 96, EPI>(a, s);
     return run<MODE, 128, 64, EPI>(a, s);
