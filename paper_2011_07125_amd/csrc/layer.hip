@@ -606,6 +606,13 @@ hipError_t launch_layer_plain(int mode, const JetGemmArgs& a, hipStream_t s) {
   }
   f.rows_per = 1;
   f.T = 1;
+  // 64-row tiles when 128-row tiles give the launch fewer than about 1024
+  // workgroups (the per-walker products of the value passes: 0.068 -> 0.058
+  // ms for the Ne-like mean-field products of one pass; the jet pass's keep
+  // 128 rows, 0.46 against 0.59 ms)
+  if ((int64_t)(f.n_groups + 127) / 128 * ((f.N + 127) / 128) < 1024)
+    return mode == MODE_BF16X3 ? run_layer<MODE_BF16X3, 64, 128, 4, 2, KIND_PLAIN>(f, s)
+                               : run_layer<MODE_F32, 64, 128, 4, 2, KIND_PLAIN>(f, s);
   return mode == MODE_BF16X3 ? run_layer<MODE_BF16X3, 128, 128, 4, 2, KIND_PLAIN>(f, s)
                              : run_layer<MODE_F32, 128, 128, 4, 2, KIND_PLAIN>(f, s);
 }
