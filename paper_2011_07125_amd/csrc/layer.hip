@@ -479,10 +479,9 @@ layer_gemm_kernel(
     if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + cw + c + j * 16] = u0;
   }
   // spin-group tiles: every electron of the tile exists (the host checks
-  // it), and the output tile is staged in LDS over the exchange buffer once
-  // every wave has read it
-  // rows padded by 4 floats: the four 4-row lane groups of a store hit
-  // different banks
+  // it); the output tile is staged in LDS, over the exchange buffer once
+  // every wave has read it, in rows padded by 4 floats so that the four
+  // 4-row lane groups of a store hit different banks
   constexpr int MF_LD = BN + 4;
   float* mfs = reinterpret_cast<float*>(smem);  // [BM][MF_LD]
   if constexpr (KIND == KIND_JET_MF) __syncthreads();
