@@ -221,22 +221,32 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
   // of range (zeros, no memory access).  With the same number of loads on
   // every path the compiler's wait counts keep the later stages in flight
   // instead of draining them at each LDS store.
+  set_tile(0);
+  // the first tile's bases (a single-tile workgroup's only ones)
+  auto a0_base = [&](long row0) { return (const float*)a.a0 + row0 * a.lda0; };
+  auto a1_base = [&](long row0) {
+    return a.ka1 > 0 ? (const float*)a.a1 + row0 * a.lda1 : (const float*)a.a0;
+  };
+  auto b_base = [&](const void* bt, int n0) { return uniform((const char*)bt + (size_t)n0 * a.ldb * ESZ); };
+  const float* const pA0f = a0_base(c_row0);
+  const float* const pA1f = a1_base(c_row0);
+  const __amdgpu_buffer_rsrc_t rBf = rsrc(b_base(a.bt, c_n0));
+  const __amdgpu_buffer_rsrc_t rBlf = rsrc(MODE == MODE_F32 ? a.bt : b_base(a.bt_lo, c_n0));
+  const int n0f = c_n0;
   auto gload = [&](Regs& R) {
     // single-tile workgroups: the steps past the last one are dead
     const bool live = LOOP ? c_live : c_lk < nkt;
-    const int kb = ktile(LOOP || live ? c_lk : 0, c_n0) * BK;
+    const int kb = ktile(LOOP || live ? c_lk : 0, LOOP ? c_n0 : n0f) * BK;
     const bool s0 = kb < a.ka0;
-    const float* pa = s0 ? (const float*)a.a0 + c_row0 * a.lda0
-                         : (a.ka1 > 0 ? (const float*)a.a1 + c_row0 * a.lda1 : (const float*)a.a0);
+    const float* pa = LOOP ? (s0 ? a0_base(c_row0) : a1_base(c_row0)) : (s0 ? pA0f : pA1f);
     const __amdgpu_buffer_rsrc_t rA = rsrc(uniform(pa));
     const int soA = (s0 ? kb : kb - a.ka0) * 4;
     const int dead = live ? 0 : kOutOfRange;  // or-ed into the lane offsets
 #pragma unroll
     for (int i = 0; i < C::NVA; ++i)
       R.ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA, (s0 ? voff0[i] : voff1[i]) | dead, soA, 0);
-    const __amdgpu_buffer_rsrc_t rB = rsrc(uniform((const char*)a.bt + (size_t)c_n0 * a.ldb * ESZ));
-    const __amdgpu_buffer_rsrc_t rBl =
-        rsrc(uniform(MODE == MODE_F32 ? (const char*)a.bt : (const char*)a.bt_lo + (size_t)c_n0 * a.ldb * ESZ));
+    const __amdgpu_buffer_rsrc_t rB = LOOP ? rsrc(b_base(a.bt, c_n0)) : rBf;
+    const __amdgpu_buffer_rsrc_t rBl = LOOP ? rsrc(MODE == MODE_F32 ? a.bt : b_base(a.bt_lo, c_n0)) : rBlf;
 #pragma unroll
     for (int i = 0; i < C::NVB; ++i) {
       R.rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rB, voffB[i] | dead, kb * ESZ, 0);
@@ -578,7 +588,6 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
     constexpr int NS = 2;
     static_assert(NS % 2 == 0, "a group of NS steps starts in LDS buffer 0");
     Regs R[NS];
-    set_tile(0);
     if (nkt > 0) {
       gload(R[0]);
       sstore(R[0], 0);
@@ -629,7 +638,6 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
     Regs R0;
     // value pass (short K loop, wide epilogue) and float32 operands (eight
     // MFMA k-steps per K step hide the loads): one register stage
-    set_tile(0);
     if (nkt > 0) {
       gload(R0);
       sstore(R0, 0);
