@@ -130,23 +130,18 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
   constexpr int EPI = LOOP ? 2 * C::STAGE : 0;
   extern __shared__ __attribute__((aligned(16))) char smem[];
 
-  // one tile per workgroup: workgroup t takes row tile m and column tile n,
-  // the column tiles of a row tile 8 workgroups apart (the same XCD); the
-  // last 8 row tiles may include padding (m >= n_mtiles).  Looping
-  // workgroups (K steps in pairs across tiles: an even count) take row tiles
-  // blockIdx.x, blockIdx.x + gridDim.x, ..., each with its column tiles in
-  // turn, so that the second read of the activations is served by L2.
-  const int nkt = (a.ka0 + a.ka1) / BK;
-  const bool loops = LOOP && nkt % 2 == 0;
+  // tile t (row tile m, column tile n): the column tiles of a row tile are
+  // 8 tiles apart, so that they run on the same XCD; the last 8 row tiles
+  // may include padding (m >= n_mtiles)
+  const int n_tiles = (n_mtiles + 7) / 8 * 8 * n_ntiles;
   auto tile_m = [&](int t) { return (t / (8 * n_ntiles)) * 8 + (t % 8); };
   auto tile_n = [&](int t) { return (t / 8) % n_ntiles; };
   const int t0 = blockIdx.x;
-  if (!loops && tile_m(t0) >= n_mtiles) return;
-  // the workgroup's tile sequence (a row tile past the last ends it)
-  auto seq_m = [&](int lt) {
-    return loops ? t0 + lt / n_ntiles * (int)gridDim.x : (lt == 0 ? tile_m(t0) : n_mtiles);
-  };
-  auto seq_n = [&](int lt) { return loops ? lt % n_ntiles : tile_n(t0); };
+  if (!LOOP && tile_m(t0) >= n_mtiles) return;
+  // K steps go in pairs across tiles (two register stages): with an odd
+  // count each workgroup takes one tile (the host launches one per tile)
+  const int nkt = (a.ka0 + a.ka1) / BK;
+  const int tstep = LOOP && nkt % 2 == 0 ? gridDim.x : n_tiles;  // n_tiles: no second tile
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave / WN, wn = wave % WN;
@@ -162,7 +157,7 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
   // A loader: 8 float4 per 32-wide tile row, at byte offsets from the
   // tile's first row, computed for the first tile.  The spin-group tiles
   // (whole groups of consecutive electrons, all present) share them.
-  const int g0 = LOOP ? 0 : seq_m(0) * E;
+  const int g0 = LOOP ? 0 : tile_m(t0) * E;
   const int q0 = g0 / a.n_sub, m0 = g0 - q0 * a.n_sub;
   int voff0[C::NVA], voff1[C::NVA];
 #pragma unroll
@@ -215,10 +210,11 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
   bool c_live = false;
   long c_row0 = 0;
   auto set_tile = [&](int lt) {
-    const int m = seq_m(lt);
-    c_live = m < n_mtiles;
-    c_n0 = seq_n(c_live ? lt : 0) * BN;
-    c_row0 = LOOP || lt == 0 ? tile_row0(c_live ? m : seq_m(0)) : c_row0;
+    const int t = t0 + lt * tstep;
+    c_live = t < n_tiles && tile_m(t) < n_mtiles;
+    const int tt = c_live ? t : t0;
+    c_n0 = tile_n(tt) * BN;
+    c_row0 = LOOP || lt == 0 ? tile_row0(tile_m(tt)) : c_row0;
   };
   // every call issues the same loads, whatever the step: the segment is
   // picked by selects, and a step of a tile that does not exist reads out
@@ -370,8 +366,8 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
   };
 
   // ---------------------------------------------------------------- epilogue
-  auto epilogue = [&](int m_t, int n_t) {
-    const int g0 = m_t * E, n0 = n_t * BN;
+  auto epilogue = [&](int t) {
+    const int m_t = tile_m(t), g0 = m_t * E, n0 = tile_n(t) * BN;
     // accumulator (i, j, r) of lane (kq, c) is tile row wm WROWS + 16 i + 4 kq + r,
     // tile column wn WCOLS + 16 j + c
     const int T = a.T;
@@ -629,16 +625,14 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
       }
     };
     if constexpr (LOOP) {
-      for (int lt = 0;; ++lt) {
-        const int m = seq_m(lt);
-        if (m >= n_mtiles) break;
+      for (int t = t0; t < n_tiles; t += tstep) {
         ksteps();
-        epilogue(m, seq_n(lt));
+        if (tile_m(t) < n_mtiles) epilogue(t);
         zero_acc();
       }
     } else {
       ksteps();
-      epilogue(seq_m(0), seq_n(0));
+      epilogue(t0);
     }
   } else {
     Regs R0;
@@ -655,7 +649,7 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
       if (kt + 1 < nkt) sstore(R0, (kt + 1) & 1);
       __syncthreads();
     }
-    epilogue(seq_m(0), seq_n(0));
+    epilogue(t0);
   }
 }
 
@@ -673,15 +667,16 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
   const int E = KIND == KIND_JET || KIND == KIND_JET_MF ? BM / a.rows_per : BM;
   const int n_mtiles = (a.n_groups + E - 1) / E;
   const int n_ntiles = (a.N + BN - 1) / BN;
-  int grid = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
+  const int n_tiles = ((n_mtiles + 7) / 8) * 8 * n_ntiles;
   auto kern = &layer_gemm_kernel<MODE, BM, BN, WM, WN, KIND>;
   // once per instantiation (a local static is initialised once, thread-safely)
   static const hipError_t attr =
       hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, BYTES);
   if (attr != hipSuccess) return hipErrorInvalidValue;
+  int grid = n_tiles;
   if (LOOP && (a.ka0 + a.ka1) / C::BK % 2 == 0) {
     // as many workgroups as are resident at once, in multiples of 8 (one
-    // per XCD), each looping over row tiles (the kernel's condition)
+    // per XCD), each looping over tiles (the kernel's condition)
     static const int per_cu = [&]() {
       int n = 0;
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, C::NT, BYTES) == hipSuccess && n > 0 ? n : 1;
@@ -690,7 +685,7 @@ static hipError_t run_layer(const JetGemmArgs& a, hipStream_t s) {
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return hipErrorInvalidValue;
     const int resident = std::max(8, n_cu * per_cu / 8 * 8);
-    grid = std::min(n_mtiles, resident);
+    grid = std::min(n_tiles, resident);
   }
   hipLaunchKernelGGL(kern, dim3(grid), dim3(C::NT), BYTES, s, a, n_mtiles, n_ntiles);
   return hipGetLastError();
