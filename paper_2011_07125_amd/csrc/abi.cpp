@@ -949,6 +949,9 @@ static fn_status atb_add(const AdjBufs& b, const float* X, int64_t ldx, int xcol
   a.N = N;
   a.part = b.part;
   a.sym = sym ? 1 : 0;
+  // the split form's sums over rows on split-bfloat16 products (per-walker
+  // products keep float32: a walker's few rows would pad a 32-row step)
+  a.bf16 = b.pw != nullptr && gld == 0 ? 1 : 0;
   if (gld > 0) {
     a.dst = dst;
     a.dst_ld = gld;

@@ -237,11 +237,17 @@ int64_t atb_part_floats(int K1max, int Nmax) {
 
 // VEC: ldx, xcol, ldy multiples of 4 and 16-byte aligned bases (one 16-byte
 // load per operand; the last vector of a row is read element by element
-// when K1 or N is not a multiple of 4)
-template <bool VEC>
+// when K1 or N is not a multiple of 4).
+// BF: split-bfloat16 products, 32 rows per step.  The rows are the
+// reduction index, so an MFMA operand wants eight consecutive rows of one
+// column per lane: each lane gathers them from the float32 tile in LDS
+// (rows of 66 floats: the four 8-row groups of a read hit distinct banks)
+// and splits them into hi and lo parts in registers.
+template <bool VEC, bool BF>
 __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_split) {
-  __shared__ float Xs[2][16][64 + 4];
-  __shared__ float Ys[2][16][64 + 4];
+  constexpr int BR = BF ? 32 : 16, LD = BF ? 64 + 2 : 64 + 4;
+  __shared__ float Xs[2][BR][LD];
+  __shared__ float Ys[2][BR][LD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int tk = blockIdx.x, tn = blockIdx.y;
@@ -261,11 +267,10 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
   floatx4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid / 16, lc = (tid % 16) * 4;  // loader: row 0..15, 4 columns
+  const int lr = tid / 16, lc = (tid % 16) * 4;  // loader: rows lr (+ 16 h), 4 columns
   const bool kin = k0 + lc < a.K1, nin = n0 + lc < a.N;
-  float xv[4], yv[4];
-  auto load = [&](int64_t r0) {
-    const int64_t r = r0 + lr;
+  float xv[BR / 16][4], yv[BR / 16][4];
+  auto load_row = [&](int64_t r, float* xv, float* yv) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) xv[q] = yv[q] = 0.0f;
     if (r >= r_end) return;
@@ -295,24 +300,56 @@ __global__ __launch_bounds__(256) void atb_kernel(AtbArgs a, int64_t rows_per_sp
       }
     }
   };
+  auto load = [&](int64_t r0) {
+#pragma unroll
+    for (int h = 0; h < BR / 16; ++h) load_row(r0 + lr + 16 * h, xv[h], yv[h]);
+  };
   if (r_begin < r_end) load(r_begin);
   int buf = 0;
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += 16, buf ^= 1) {
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += BR, buf ^= 1) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Xs[buf][lr][lc + q] = xv[q];
-      Ys[buf][lr][lc + q] = yv[q];
-    }
+    for (int h = 0; h < BR / 16; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Xs[buf][lr + 16 * h][lc + q] = xv[h][q];
+        Ys[buf][lr + 16 * h][lc + q] = yv[h][q];
+      }
     __syncthreads();
-    if (r0 + 16 < r_end) load(r0 + 16);
+    if (r0 + BR < r_end) load(r0 + BR);
+    if constexpr (BF) {
+      // lane (kq, c): rows 8 kq .. 8 kq + 7 of column c of each 16-column tile
+      const int r8 = (lane >> 4) * 8, c = lane & 15;
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+      auto frag = [&](const float (*T)[LD], int col, bf16x8* hi, bf16x8* lo) {
+        uint32_t h[4], l[4];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int rr = ks * 4 + (lane >> 4);
-      float af[2], bf[2];
-      for (int i = 0; i < 2; ++i) af[i] = Xs[buf][rr][wm * 32 + i * 16 + (lane & 15)];
-      for (int j = 0; j < 2; ++j) bf[j] = Ys[buf][rr][wn * 32 + j * 16 + (lane & 15)];
+        for (int p = 0; p < 4; ++p) split_bf16x2(T[r8 + 2 * p][col], T[r8 + 2 * p + 1][col], &h[p], &l[p]);
+        *hi = __builtin_bit_cast(bf16x8, uint4{h[0], h[1], h[2], h[3]});
+        *lo = __builtin_bit_cast(bf16x8, uint4{l[0], l[1], l[2], l[3]});
+      };
+#pragma unroll
+      for (int i = 0; i < 2; ++i) frag(Xs[buf], wm * 32 + i * 16 + c, &ah[i], &al[i]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) frag(Ys[buf], wn * 32 + j * 16 + c, &bh[j], &bl[j]);
+#pragma unroll
       for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int rr = ks * 4 + (lane >> 4);
+        float af[2], bf[2];
+        for (int i = 0; i < 2; ++i) af[i] = Xs[buf][rr][wm * 32 + i * 16 + (lane & 15)];
+        for (int j = 0; j < 2; ++j) bf[j] = Ys[buf][rr][wn * 32 + j * 16 + (lane & 15)];
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
     }
     // the other buffer is written next step, after this step's barrier
   }
@@ -347,13 +384,21 @@ hipError_t launch_atb(const AtbArgs& a, hipStream_t s) {
   if (a.R <= 0 || a.K1 <= 0 || a.N <= 0) return hipSuccess;
   if (a.dst && (a.seg <= 0 || a.R % a.seg != 0 || a.sym)) return hipErrorInvalidValue;
   const int sp = a.dst ? (int)std::min<int64_t>(a.R / a.seg, 32768) : atb_splits(a.R, a.K1, a.N);
-  const int64_t rps = a.dst ? a.seg : ((a.R + sp - 1) / sp + 15) / 16 * 16;
+  // the split form steps over 32 rows (per walker: its segment, padded with zeros)
+  const bool bf = a.bf16 != 0;
+  const int br = bf ? 32 : 16;
+  const int64_t rps = a.dst ? a.seg : ((a.R + sp - 1) / sp + br - 1) / br * br;
   const int tkn = (a.K1 + 63) / 64;
   dim3 grid(a.sym ? tkn * (tkn + 1) / 2 : tkn, a.sym ? 1 : (a.N + 63) / 64, sp);
   const bool vec = a.ldx % 4 == 0 && a.xcol % 4 == 0 && a.ldy % 4 == 0 && ((uintptr_t)a.X % 16) == 0 &&
                    ((uintptr_t)a.Y % 16) == 0;
-  if (vec) hipLaunchKernelGGL(atb_kernel<true>, grid, dim3(256), 0, s, a, rps);
-  else hipLaunchKernelGGL(atb_kernel<false>, grid, dim3(256), 0, s, a, rps);
+  if (bf) {
+    if (vec) hipLaunchKernelGGL((atb_kernel<true, true>), grid, dim3(256), 0, s, a, rps);
+    else hipLaunchKernelGGL((atb_kernel<false, true>), grid, dim3(256), 0, s, a, rps);
+  } else {
+    if (vec) hipLaunchKernelGGL((atb_kernel<true, false>), grid, dim3(256), 0, s, a, rps);
+    else hipLaunchKernelGGL((atb_kernel<false, false>), grid, dim3(256), 0, s, a, rps);
+  }
   return hipGetLastError();
 }
 

@@ -161,6 +161,9 @@ struct AtbArgs {
   float* dst = nullptr;
   int64_t dst_ld = 0;
   int seg = 0;
+  // split-bfloat16 products (the bf16 form): each operand x = hi + lo in
+  // bfloat16, x y ~ hi hi + hi lo + lo hi on v_mfma_f32_16x16x32_bf16
+  int bf16 = 0;
 };
 int atb_splits(int64_t R, int K1, int N);   // partials written by launch_atb
 int64_t atb_part_floats(int K1max, int Nmax);  // bound on splits * K1 * N over K1 <= K1max, N <= Nmax
