@@ -429,6 +429,46 @@ __global__ void rowsum_partial_kernel(const float* src, int64_t rows, int cols, 
   if (add) part[c] += v;
   else part[(int64_t)blockIdx.y * cols + c] = v;
 }
+// pass 1 for narrow rows (cols a multiple of 4, at most 256): a thread
+// sums one column quad over every rl-th row of its chunk with 16-byte loads
+// (rl = 256 / (cols / 4) row lanes per block), and the row lanes are then
+// added in order through LDS
+__global__ __launch_bounds__(256) void rowsum_narrow_kernel(const float* src, int64_t rows, int cols, int64_t lds,
+                                                             int64_t chunk, float* part, int add) {
+  __shared__ float4 sh[256];
+  const int nq = cols / 4, rl = 256 / nq;
+  const int tid = threadIdx.x, q = tid % nq, lane_r = tid / nq;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
+  const int64_t r1 = std::min<int64_t>(r0 + chunk, rows);
+  float4 s0 = {0.f, 0.f, 0.f, 0.f}, s1 = {0.f, 0.f, 0.f, 0.f};
+  if (lane_r < rl) {
+    int64_t r = r0 + lane_r;
+    for (; r + rl < r1; r += 2 * rl) {
+      const float4 u = *reinterpret_cast<const float4*>(src + r * lds + 4 * q);
+      const float4 v = *reinterpret_cast<const float4*>(src + (r + rl) * lds + 4 * q);
+      s0.x += u.x, s0.y += u.y, s0.z += u.z, s0.w += u.w;
+      s1.x += v.x, s1.y += v.y, s1.z += v.z, s1.w += v.w;
+    }
+    if (r < r1) {
+      const float4 u = *reinterpret_cast<const float4*>(src + r * lds + 4 * q);
+      s0.x += u.x, s0.y += u.y, s0.z += u.z, s0.w += u.w;
+    }
+  }
+  sh[tid] = float4{s0.x + s1.x, s0.y + s1.y, s0.z + s1.z, s0.w + s1.w};
+  __syncthreads();
+  if (lane_r != 0) return;
+  float4 t = sh[q];
+  for (int k = 1; k < rl; ++k) {
+    const float4 u = sh[k * nq + q];
+    t.x += u.x, t.y += u.y, t.z += u.z, t.w += u.w;
+  }
+  float* dst = add ? part + 4 * q : part + (int64_t)blockIdx.y * cols + 4 * q;
+  if (add) {
+    dst[0] += t.x, dst[1] += t.y, dst[2] += t.z, dst[3] += t.w;
+  } else {
+    dst[0] = t.x, dst[1] = t.y, dst[2] = t.z, dst[3] = t.w;
+  }
+}
 // pass 2: dst[c] += sum_y part[y][c]; 64 columns x 4 slices of y per block
 __global__ __launch_bounds__(256) void rowsum_final_kernel(const float* part, int ny, int cols, float* dst,
                                                             int sym_n) {
@@ -476,13 +516,20 @@ hipError_t launch_rowsum_add(const float* src, int64_t rows, int cols, int64_t l
   int ny = std::min(rowsum_chunks(rows, chunk), 128);
   const int64_t ch = (rows + ny - 1) / ny;
   ny = (int)((rows + ch - 1) / ch);
+  const bool narrow = sym_n == 0 && cols % 4 == 0 && cols <= 256 && lds % 4 == 0 && ((uintptr_t)src % 16) == 0;
   if (ny == 1) {  // one pass, into dst
-    hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, 1), dim3(256), 0, s, src, rows, cols, lds, ch,
-                       dst, sym_n, 1);
+    if (narrow)
+      hipLaunchKernelGGL(rowsum_narrow_kernel, dim3(1, 1), dim3(256), 0, s, src, rows, cols, lds, ch, dst, 1);
+    else
+      hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, 1), dim3(256), 0, s, src, rows, cols, lds,
+                         ch, dst, sym_n, 1);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, ch,
-                     tmp, sym_n, 0);
+  if (narrow)
+    hipLaunchKernelGGL(rowsum_narrow_kernel, dim3(1, ny), dim3(256), 0, s, src, rows, cols, lds, ch, tmp, 0);
+  else
+    hipLaunchKernelGGL(rowsum_partial_kernel, dim3((cols + 255) / 256, ny), dim3(256), 0, s, src, rows, cols, lds, ch,
+                       tmp, sym_n, 0);
   hipLaunchKernelGGL(rowsum_final_kernel, dim3((cols + 63) / 64), dim3(256), 0, s, tmp, ny, cols, dst, sym_n);
   return hipGetLastError();
 }
