@@ -6,10 +6,11 @@
 // float32 activations (about 50 for K = 320, N = 256), far below the ridge
 // of the bfloat16 matrix cores, so the kernel is organised around HBM
 // streaming rather than MFMA reuse:
-//  * a 512-thread workgroup owns BM rows (whole electrons, and a whole
-//    number of waves per electron) x BN = 128 columns; the column tiles of
-//    one row tile are issued back to back on the same XCD, so the repeated
-//    read of the activations is served by that XCD's L2;
+//  * a workgroup (512 threads for 128-row tiles) owns BM rows (whole
+//    electrons, and a whole number of waves per electron) x BN = 128
+//    columns; the column tiles of one row tile are issued back to back on
+//    the same XCD, so the repeated read of the activations is served by
+//    that XCD's L2;
 //  * for small atoms (equal spin groups of at most five electrons, 32 jet
 //    rows) a tile is instead one spin group of one walker, one wave row per
 //    electron, and the tile's mean of its output rows is written too: the
@@ -25,7 +26,8 @@
 //    loads run two K steps ahead in registers; every step issues the same
 //    loads (selects, out-of-range offsets past the end), so that the
 //    compiler's wait counts leave them in flight;
-//  * the epilogue does not stage the tile in LDS: per column, the jet rows of
+//  * the epilogue does not stage the tile in LDS (but for the copy the
+//    spin-group tiles sum into the means): per column, the jet rows of
 //    one electron sit in the accumulators of the wave's four lane groups (and
 //    of the electron's other waves when the jet is taller than a wave's
 //    rows).  The sum of squared tangents is reduced with cross-lane shuffles
