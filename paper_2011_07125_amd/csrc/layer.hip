@@ -502,25 +502,34 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
       s2[j] += __shfl_xor(s2[j], 16, 64);
       s2[j] += __shfl_xor(s2[j], 32, 64);
     }
-    // cross-wave exchange (stage buffers are free after the main loop's last barrier)
+    // cross-wave exchange (stage buffers are free after the main loop's last
+    // barrier), unless one wave holds the electron's whole jet: then its
+    // sums are complete and its value row is in lane group 0 (the same sums,
+    // so the same bits)
     float* red = reinterpret_cast<float*>(smem + EPI);  // [WM][BN] partial sums
     float* val = red + WM * BN;                   // [WM][BN] value rows
     const int cl = wn * C::WCOLS + c;
-    if (kq == 0) {
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        red[wm * BN + cl + j * 16] = s2[j];
-        if (tw0 == 0) val[wm * BN + cl + j * 16] = acc[0][j][0];
-      }
-    }
-    __syncthreads();
     const int wfirst = wm - tw0 / WROWS, wper = rows_per / WROWS;
+    const bool whole = wper == 1;
+    if (!whole) {
+      if (kq == 0) {
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          red[wm * BN + cl + j * 16] = s2[j];
+          if (tw0 == 0) val[wm * BN + cl + j * 16] = acc[0][j][0];
+        }
+      }
+      __syncthreads();
+    }
     float y[TN], dy[TN], lapc[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       float ss = 0.0f;
-      for (int w = wfirst; w < wfirst + wper; ++w) ss += red[w * BN + cl + j * 16];
-      const float u0 = val[wfirst * BN + cl + j * 16] + a.bias[cw + c + j * 16];
+      if (whole) ss += s2[j];
+      else
+        for (int w = wfirst; w < wfirst + wper; ++w) ss += red[w * BN + cl + j * 16];
+      const float vrow = whole ? __shfl(acc[0][j][0], c, 64) : val[wfirst * BN + cl + j * 16];
+      const float u0 = vrow + a.bias[cw + c + j * 16];
       tanh_sech2f(u0, &y[j], &dy[j]);
       lapc[j] = -2.0f * y[j] * dy[j] * ss;
       if (a.pre_out && tw0 == 0 && kq == 0 && gval) a.pre_out[(size_t)g * a.N + cw + c + j * 16] = u0;
@@ -531,7 +540,9 @@ layer_gemm_kernel(JetGemmArgs a, int n_mtiles, int n_ntiles) {
     // c ^ 16 ((R >> 2) & 3), so that the four 4-row lane groups of a store
     // hit different banks (and a 160-row tile takes 80 KiB, two per CU)
     float* mfs = reinterpret_cast<float*>(smem + EPI);  // [BM][BN], swizzled
-    if constexpr (KIND == KIND_JET_MF) __syncthreads();
+    if constexpr (KIND == KIND_JET_MF) {
+      if (!whole) __syncthreads();
+    }
     else if (!gval) return;
     // per 16-row tile: all residual loads first, then the stores.  Row t
     // becomes y (t = 0), sech^2 u0 times its tangent (0 < t < T - 1), the
