@@ -53,8 +53,12 @@ def _run(w, d, form, fused, walkers, rescue=None):
 
 
 @pytest.mark.parametrize("form", ["bf16", "fp32_fp64det"])
-@pytest.mark.parametrize("name,walkers", [("be4", 256), ("ne10", 4096), ("ar18", 64)])
+@pytest.mark.parametrize("name,walkers", [("be4", 256), ("ne10", 4096), ("ne10", 777), ("ar18", 64)])
 def test_fused_meanfield_same_bits(name, walkers, form):
+    """777 Ne-like walkers: 1554 spin-group row tiles (padded to 1560) of
+    two column tiles each, spread over the resident workgroups, so that
+    the looping workgroups take unequal numbers of tiles, padding tiles
+    among them."""
     say(f"case fused mean field {name} {form} W={walkers}")
     w = I.make_workload(name)
     w["name"] = name
