@@ -159,8 +159,9 @@ def det_terms(cfg, pos, nuc_pos, params, threads=None):
 
 
 def node_conditioning(cfg, pos, nuc_pos, params, threads=None):
-    """kappa_w = max_k |P_k| / |psi| >= 1 (infinite at an exact node): how
-    strongly the signed sum of Eq. (4) cancels at each walker."""
+    """kappa_w = max_k |P_k| / |psi| (at least 1/K, 1 for a single
+    determinant, infinite at an exact node): how strongly the signed sum of
+    Eq. (4) cancels at each walker."""
     sk, lk = det_terms(cfg, pos, nuc_pos, params, threads)
     m = lk.max(axis=1, keepdims=True)
     s = (sk * np.exp(lk - m)).sum(axis=1)

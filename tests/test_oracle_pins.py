@@ -543,6 +543,50 @@ def test_T7_signed_sum_over_determinants_and_omega():
     np.testing.assert_allclose(b["e_loc"], a["e_loc"], rtol=1e-10)
 
 
+def test_error_scale_terms_of_the_reevaluation_key():
+    """The terms of the float64 re-evaluation's error scale, pinned to the
+    signed sum of Eq. (4) and to the orientation of the orbital matrices:
+      * det_terms: (sign_k, log|P_k|) of each term equals the value of the
+        network restricted to determinant k (the slices of T7);
+      * orbital_matrices: det A^up_k det A^down_k = P_k, and A[i][j] =
+        phi_i(r_j): exchanging two up electrons exchanges two columns of
+        every up matrix (a transposed matrix would exchange rows and change
+        its 1-norm condition number);
+      * node_conditioning: kappa = max_k |P_k| / |psi| from those terms, at
+        least 1/K (|psi| <= sum_k |P_k|), 1 for a single determinant."""
+    w = small_workload(W=5)
+    cfg, p = w["cfg"], w["params"]
+    K = cfg["n_det"]
+    pos = w["pos"].astype(np.float64)
+    sk, lk = O.det_terms(cfg, pos, w["nuc_pos"], p)
+    up, dn = O.orbital_matrices(cfg, pos, w["nuc_pos"], p)
+    for k in range(K):
+        c1, q = _det_slice(cfg, p, [k])
+        r = O.evaluate(c1, pos, w["nuc_pos"], w["nuc_charge"], q, energy=False)
+        assert (sk[:, k] == r["sign"]).all()
+        np.testing.assert_allclose(lk[:, k], r["logpsi"], atol=1e-12)
+        pk = np.linalg.det(up[:, k]) * np.linalg.det(dn[:, k])
+        np.testing.assert_allclose(pk, sk[:, k] * np.exp(lk[:, k]), rtol=1e-10)
+    full = O.evaluate(cfg, pos, w["nuc_pos"], w["nuc_charge"], p, energy=False)
+    psi = full["sign"] * np.exp(full["logpsi"])
+    kappa = O.node_conditioning(cfg, pos, w["nuc_pos"], p)
+    np.testing.assert_allclose(kappa, np.exp(lk).max(axis=1) / np.abs(psi), rtol=1e-10)
+    assert (kappa >= 1.0 / K - 1e-12).all()
+    c1, q = _det_slice(cfg, p, [1])
+    np.testing.assert_allclose(O.node_conditioning(c1, pos, w["nuc_pos"], q), 1.0, rtol=1e-12)
+    # orientation: swap up electrons 0 and 2
+    pos2 = pos.copy()
+    pos2[:, [0, 2]] = pos2[:, [2, 0]]
+    up2, dn2 = O.orbital_matrices(cfg, pos2, w["nuc_pos"], p)
+    np.testing.assert_allclose(up2, up[..., [2, 1, 0]], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(dn2, dn, rtol=1e-12, atol=1e-14)
+    amp, kap, cmax = O.amplification(cfg, pos, w["nuc_pos"], p)
+    c1n = lambda m: np.abs(m).sum(axis=-2).max(axis=-1) * np.abs(np.linalg.inv(m)).sum(axis=-2).max(axis=-1)
+    want = np.maximum(np.maximum(1.0, c1n(up).max(axis=1)), c1n(dn).max(axis=1))
+    np.testing.assert_allclose(cmax, want, rtol=1e-10)
+    np.testing.assert_allclose(amp, kap * cmax, rtol=1e-15)
+
+
 # ------------------------------------------------ finite differences
 def test_T8_laplacian_and_gradient_vs_finite_differences():
     """d_c log|psi| and sum_c d^2_c log|psi| from the second-order jets equal
