@@ -1009,8 +1009,9 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
                           int64_t gld = 0) {
   const int64_t R = Wc * p.n;
   fn_status st;
+  // the cotangent of the current layer's output, updated in place into
+  // that of its input
   float* CHc = b.CH[0];
-  float* CHn = b.CH[1];
   std::vector<KfacBlk> kb;
   if (kout) kb = kfac_blocks(p, nullptr);
   auto kblk = [&](int kind, int layer) -> const KfacBlk* {
@@ -1054,12 +1055,15 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
                   wh ? wh + (int64_t)p.d1 * b.ldu : nullptr);
     if (st != FN_OK) return st;
   }
-  // one-electron layers, last to first
+  // one-electron layers, last to first.  The mean-field part of a layer's
+  // input cotangent (CMF, per walker) is added to CH by the next layer's
+  // cotangent pass, which reads CH anyway.
+  const float* cmf_pending = nullptr;
   for (int l = p.L - 1; l >= 0; --l) {
     const int din = p.din[l], ein = p.ein[l];
     const float* V = params + p.offV[l];
-    FN_T(ST_ADJ_LAYERS, launch_adj_cp(CHc, b.PRE[l + 1], R * p.d1, b.CP, s));
-    FN_T(ST_ADJ_LAYERS, launch_adj_walker_sum(b.CP, (int)Wc, p.n, p.d1, b.S, s));
+    FN_T(ST_ADJ_LAYERS,
+         launch_adj_cp_sum(CHc, b.PRE[l + 1], cmf_pending, (int)Wc, p.n, p.nu, p.d1, b.CP, b.S, s));
     const int ldh = l == 0 ? p.dinp[0] : p.d1;
     if (grad) {
       if (gld > 0)
@@ -1099,16 +1103,16 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
                   ST_ADJ_LAYERS, s, hi((int64_t)3 * din * p.d1), lo((int64_t)3 * din * p.d1));
     if (st != FN_OK) return st;
     if (l == 0) break;  // the input features carry no parameters
-    // cot h^l_i = cp_i A^T (+ cot h^{l+1}_i) + cot hbar^{a(i)} / n_a
-    const bool res = din == p.d1;
-    if (res) FN_T(ST_ADJ_LAYERS, launch_copy_f32(CHc, CHn, R * p.d1, s));
-    st = gemm_cwt(b.CP, p.d1, p.d1, R, V, p.d1, din, CHn, p.d1, res ? 1 : 0, 0, 0, 0, ST_ADJ_LAYERS, s, hi(0), lo(0));
+    // cot h^l_i = cp_i A^T + cot h^{l+1}_i + cot hbar^{a(i)} / n_a: the
+    // first two terms in place (for l > 0, h^l is the output of layer
+    // l - 1, so din = d1 and the residual is always there), the last one
+    // with the next cotangent pass
+    st = gemm_cwt(b.CP, p.d1, p.d1, R, V, p.d1, din, CHc, p.d1, 1, 0, 0, 0, ST_ADJ_LAYERS, s, hi(0), lo(0));
     if (st != FN_OK) return st;
     st = gemm_cwt(b.S, p.d1, p.d1, Wc, V + (int64_t)din * p.d1, p.d1, 2 * din, b.CMF, 2 * din, 0, 0, 0, 0,
                   ST_ADJ_LAYERS, s, hi((int64_t)din * p.d1), lo((int64_t)din * p.d1));
     if (st != FN_OK) return st;
-    FN_T(ST_ADJ_LAYERS, launch_adj_scatter_mf(b.CMF, (int)Wc, p.n, p.nu, din, din, CHn, p.d1, s));
-    std::swap(CHc, CHn);
+    cmf_pending = b.CMF;
   }
   // two-electron stream
   if (p.L >= 2) {

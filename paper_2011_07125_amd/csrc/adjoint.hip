@@ -551,59 +551,47 @@ hipError_t launch_sym_mirror(float* M, int n, hipStream_t s) {
 }
 
 // ----------------------------------------------------------- elementwise
-// CP[r][c] = CH[r][c] * sech^2(PRE[r][c])
-__global__ void adj_cp_kernel(const float* ch, const float* pre, int64_t total, float* cp) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-    cp[i] = ch[i] * sech2f(pre[i]);
-}
-
-hipError_t launch_adj_cp(const float* ch, const float* pre, int64_t total, float* cp, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(adj_cp_kernel, dim3(grid), dim3(256), 0, s, ch, pre, total, cp);
-  return hipGetLastError();
-}
-
-// S[w][c] = sum_{i < n} CP[(w n + i)][c]
-__global__ void adj_walker_sum_kernel(const float* cp, int W, int n, int cols, float* S) {
+// The cotangent pass of a one-electron layer, one thread per (walker,
+// column), the walker's electrons in order:
+//   CH[(w n + i)][c] += CMF[w][a(i) cols + c] / n_a   (when cmf is given:
+//       the mean-field part of the cotangent of h, from the layer above)
+//   CP[(w n + i)][c]  = CH[(w n + i)][c] sech^2(PRE[(w n + i)][c])
+//   S[w][c]           = sum_i CP[(w n + i)][c]   (fixed order)
+// Rows have cols entries (the layer's input and output widths agree
+// whenever cmf is given).
+__global__ void adj_cp_sum_kernel(float* ch, const float* pre, const float* cmf, int W, int n, int n_up, int cols,
+                                  float* cp, float* S) {
   const int64_t total = (int64_t)W * cols;
+  const float na_up = n_up > 0 ? (float)n_up : 1.0f, na_dn = n > n_up ? (float)(n - n_up) : 1.0f;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int c = (int)(idx % cols);
     const int64_t w = idx / cols;
+    const float m_up = cmf ? cmf[w * 2 * cols + c] : 0.0f, m_dn = cmf ? cmf[w * 2 * cols + cols + c] : 0.0f;
     float acc = 0.0f;
-    for (int i = 0; i < n; ++i) acc += cp[(w * n + i) * cols + c];
+    for (int i = 0; i < n; ++i) {
+      // products rounded before the sum, as stored (no multiply-add
+      // contraction)
+#pragma clang fp contract(off)
+      const int64_t e = (w * n + i) * cols + c;
+      float h = ch[e];
+      if (cmf) {
+        h += i < n_up ? m_up / na_up : m_dn / na_dn;
+        ch[e] = h;
+      }
+      const float v = h * sech2f(pre[e]);
+      cp[e] = v;
+      acc += v;
+    }
     S[idx] = acc;
   }
 }
 
-hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float* S, hipStream_t s) {
+hipError_t launch_adj_cp_sum(float* ch, const float* pre, const float* cmf, int W, int n, int n_up, int cols,
+                             float* cp, float* S, hipStream_t s) {
   const int64_t total = (int64_t)W * cols;
   if (total <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(adj_walker_sum_kernel, dim3(grid), dim3(256), 0, s, cp, W, n, cols, S);
-  return hipGetLastError();
-}
-
-// CH[(w n + j)][f] += CMF[w][a(j) ldm_half + f] / n_a  for f < din
-__global__ void adj_scatter_mf_kernel(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh) {
-  const int64_t total = (int64_t)W * n * din;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
-    const int f = (int)(idx % din);
-    const int64_t g = idx / din;
-    const int j = (int)(g % n);
-    const int64_t w = g / n;
-    const int al = j < n_up ? 0 : 1;
-    const int na = al == 0 ? n_up : n - n_up;
-    ch[g * ldh + f] += cmf[w * 2 * half + al * half + f] / (float)na;
-  }
-}
-
-hipError_t launch_adj_scatter_mf(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh,
-                                 hipStream_t s) {
-  const int64_t total = (int64_t)W * n * din;
-  if (total <= 0) return hipSuccess;
-  const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
-  hipLaunchKernelGGL(adj_scatter_mf_kernel, dim3(grid), dim3(256), 0, s, cmf, W, n, n_up, din, half, ch, ldh);
+  hipLaunchKernelGGL(adj_cp_sum_kernel, dim3(grid), dim3(256), 0, s, ch, pre, cmf, W, n, n_up, cols, cp, S);
   return hipGetLastError();
 }
 

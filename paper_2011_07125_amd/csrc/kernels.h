@@ -189,10 +189,12 @@ hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, 
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
                                const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
                                float* dsigma, hipStream_t s, int64_t walker_ld = 0);
-hipError_t launch_adj_cp(const float* ch, const float* pre, int64_t total, float* cp, hipStream_t s);
-hipError_t launch_adj_walker_sum(const float* cp, int W, int n, int cols, float* S, hipStream_t s);
-hipError_t launch_adj_scatter_mf(const float* cmf, int W, int n, int n_up, int din, int half, float* ch, int ldh,
-                                 hipStream_t s);
+// the cotangent pass of a one-electron layer (W walkers of n electrons,
+// rows of cols): CH += the mean-field cotangent CMF [W][2 cols] / n_a (when
+// cmf is not NULL), CP = CH sech^2(PRE), S[w] = sum over the walker's
+// electrons of CP
+hipError_t launch_adj_cp_sum(float* ch, const float* pre, const float* cmf, int W, int n, int n_up, int cols,
+                             float* cp, float* S, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 // dst[r * ldd + c] = src[r * lds + c] for r < rows, c < cols
 hipError_t launch_copy_rows(const float* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int cols,
