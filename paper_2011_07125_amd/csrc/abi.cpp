@@ -1066,10 +1066,11 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
          launch_adj_cp_sum(CHc, b.PRE[l + 1], cmf_pending, (int)Wc, p.n, p.nu, p.d1, b.CP, b.S, s));
     const int ldh = l == 0 ? p.dinp[0] : p.d1;
     if (grad) {
+      // bias: sum over the electrons of CP, from its per-walker sums S
       if (gld > 0)
-        FN_T(ST_ADJ_REDUCE, launch_rowsum_seg_add(b.CP, R, p.n, p.d1, p.d1, grad + p.offb[l], gld, s));
+        FN_T(ST_ADJ_REDUCE, launch_rowsum_seg_add(b.S, Wc, 1, p.d1, p.d1, grad + p.offb[l], gld, s));
       else
-        FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.CP, R, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
+        FN_T(ST_ADJ_REDUCE, launch_rowsum_add(b.S, Wc, p.d1, p.d1, b.tmp, grad + p.offb[l], kRowChunk, s));
       // dA = sum h_i^T cp_i
       st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s, false, gld, p.n);
       if (st != FN_OK) return st;
