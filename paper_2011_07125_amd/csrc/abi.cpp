@@ -338,8 +338,10 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, boo
   }
   b.S = (float*)cv.take((size_t)Wc * p.d1 * 4);
   b.CMF = (float*)cv.take((size_t)Wc * 2 * dmax * 4);
-  // X^T Y partials: splits(R) * K1 * N with K1 <= max(d1, dinp, 2 ein), N <= max(d1, K n_a)
-  int64_t k1max = std::max<int64_t>(p.d1, std::max(dmax, 2 * std::max(4, p.d2)));
+  // X^T Y partials: splits(R) * K1 * N with K1 <= max(d1, 2 dinp, 2 ein)
+  // (2 dinp: the mean-field weights of both spins in one product),
+  // N <= max(d1, K n_a)
+  int64_t k1max = std::max<int64_t>(p.d1, std::max(2 * dmax, 2 * std::max(4, p.d2)));
   int64_t nmax = std::max<int64_t>(p.d1, (int64_t)p.K * std::max(p.nu, p.nd));
   b.kcols = 0;
   b.ldf = 0;
@@ -1074,9 +1076,12 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
       // dA = sum h_i^T cp_i
       st = atb_add(b, b.H[l], ldh, 0, 0, 0, 0, b.CP, p.d1, R, din, p.d1, grad + p.offV[l], s, false, gld, p.n);
       if (st != FN_OK) return st;
-      // dB^a = sum_w hbar^a_w^T S_w
-      for (int a = 0; a < 2; ++a) {
-        st = atb_add(b, b.Hbar[l], 2 * p.dinp[l], a * p.dinp[l], 0, 0, 0, b.S, p.d1, Wc, din, p.d1,
+      // dB^a = sum_w hbar^a_w^T S_w; one product for both spins where
+      // their column blocks of Hbar are adjacent (no padding), as the two
+      // blocks of dB are in the parameters
+      const int nsp = p.dinp[l] == din ? 1 : 2;
+      for (int a = 0; a < nsp; ++a) {
+        st = atb_add(b, b.Hbar[l], 2 * p.dinp[l], a * p.dinp[l], 0, 0, 0, b.S, p.d1, Wc, din * (3 - nsp), p.d1,
                      grad + p.offV[l] + (int64_t)(din + a * din) * p.d1, s, false, gld, 1);
         if (st != FN_OK) return st;
       }
