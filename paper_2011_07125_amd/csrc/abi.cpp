@@ -235,6 +235,7 @@ struct AdjBufs {
   float* cot_u[2];
   float* cot_env[2];
   float* part;
+  int64_t part_n;  // floats of part
   float* tmp;
   float* part2;
   float* wo[2];     // orbital weights w_a, columns padded to ldu (float32)
@@ -357,6 +358,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, boo
   }
   const int64_t part_n = atb_part_floats((int)k1max, (int)nmax);
   b.part = (float*)cv.take((size_t)part_n * 4);
+  b.part_n = part_n;
   b.p2 = 0;
   for (int l = 0; l + 1 < p.L; ++l) b.p2 += (int64_t)p.ein[l] * p.d2 + p.d2;
   b.ldp2 = b.p2 + b.kcols;
@@ -1031,7 +1033,7 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
     if (grad) {
       FN_T(ST_ADJ_ORB, launch_adj_env_grad(b.cot_env[a], pos, nuc, params + p.offpi[a], params + p.offsg[a],
                                            p.env_full, (int)Wc, p.K, na, j0, p.n, p.N, grad + p.offpi[a],
-                                           grad + p.offsg[a], s, gld));
+                                           grad + p.offsg[a], s, gld, b.part, b.part_n));
       if (gld > 0)
         FN_T(ST_ADJ_REDUCE, launch_rowsum_seg_add(b.cot_u[a], Wc * na, na, p.K * na, b.ldu, grad + p.offg[a], gld, s));
       else

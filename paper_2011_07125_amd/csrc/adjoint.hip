@@ -79,19 +79,23 @@ __device__ inline float block_sum256(float v, float* sh) {
   return r;
 }
 
-// envelope parameters: one block per (orbital column (k,i), nucleus m),
-// d = r_j - R_m, e = exp(-s):
+// envelope parameters: one block per (orbital column (k,i), nucleus m)
+// and split of the rows (w, j) (blockIdx.y, rps rows each), d = r_j - R_m,
+// e = exp(-s):
 //   isotropic: s = |sigma| |d|
 //     dpi    += sum_{w,j} cot_env e
 //     dsigma += sum_{w,j} cot_env pi e (-sign(sigma) |d|)
 //   full:      s = |Sigma d| = |u|
 //     dpi          += sum_{w,j} cot_env e
 //     dSigma[a][b] += sum_{w,j} cot_env pi e (-u_a d_b / s)
+// With part, each split writes its sums (dpi first, then the NS dsigma
+// entries) to part[split][column m][1 + NS] for env_grad_final_kernel;
+// otherwise the one split adds them to dpi and dsigma.
 template <bool FULL>
 __global__ __launch_bounds__(256) void adj_env_grad_kernel(const float* cot_env, const float* pos, const float* nuc,
                                                            const float* pi, const float* sigma, int W, int K,
                                                            int na, int j0, int n, int N, float* dpi,
-                                                           float* dsigma) {
+                                                           float* dsigma, int64_t rps, float* part) {
   __shared__ float sh[4];
   constexpr int NS = FULL ? 9 : 1;
   const int col = blockIdx.x / N, m = blockIdx.x % N;
@@ -103,8 +107,8 @@ __global__ __launch_bounds__(256) void adj_env_grad_kernel(const float* cot_env,
   float api = 0.0f, asg[NS];
 #pragma unroll
   for (int q = 0; q < NS; ++q) asg[q] = 0.0f;
-  const int64_t rows = (int64_t)W * na;
-  for (int64_t r = threadIdx.x; r < rows; r += 256) {
+  const int64_t r_end = std::min<int64_t>((int64_t)W * na, (blockIdx.y + 1) * rps);
+  for (int64_t r = blockIdx.y * rps + threadIdx.x; r < r_end; r += 256) {
     const int j = (int)(r % na);
     const int64_t w = r / na;
     const float* x = pos + (w * n + j0 + j) * 3;
@@ -134,10 +138,29 @@ __global__ __launch_bounds__(256) void adj_env_grad_kernel(const float* cot_env,
 #pragma unroll
   for (int q = 0; q < NS; ++q) asg[q] = block_sum256(asg[q], sh);
   if (threadIdx.x == 0) {
-    dpi[col * N + m] += api;
+    if (part) {
+      float* o = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (1 + NS);
+      o[0] = api;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) dsigma[((size_t)col * N + m) * NS + q] += asg[q];
+      for (int q = 0; q < NS; ++q) o[1 + q] = asg[q];
+    } else {
+      dpi[col * N + m] += api;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) dsigma[((size_t)col * N + m) * NS + q] += asg[q];
+    }
   }
+}
+
+// the splits' sums of adj_env_grad_kernel added in split order: one thread
+// per (column m, entry q), q = 0 for dpi, 1 + b for dsigma entry b
+__global__ void env_grad_final_kernel(const float* part, int splits, int cols, int ns, float* dpi, float* dsigma) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cols * (1 + ns)) return;
+  const int cm = t / (1 + ns), q = t - cm * (1 + ns);
+  float v = 0.0f;
+  for (int sp = 0; sp < splits; ++sp) v += part[(size_t)sp * cols * (1 + ns) + t];
+  if (q == 0) dpi[cm] += v;
+  else dsigma[(size_t)cm * ns + q - 1] += v;
 }
 
 // per walker (one thread per walker, orbital column and nucleus, the sum
@@ -194,7 +217,7 @@ __global__ void adj_env_grad_walker_kernel(const float* cot_env, const float* po
 
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
                                const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
-                               float* dsigma, hipStream_t s, int64_t walker_ld) {
+                               float* dsigma, hipStream_t s, int64_t walker_ld, float* part, int64_t part_floats) {
   if (na <= 0 || W <= 0) return hipSuccess;
   if (walker_ld > 0) {
     const int64_t total = (int64_t)W * K * na * N;
@@ -207,12 +230,24 @@ hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const flo
                          W, K, na, j0, n, N, dpi, dsigma, walker_ld);
     return hipGetLastError();
   }
+  // rows split so that a thread takes at most about eight rows (the loop is
+  // bound by the latency of its loads), as many splits as part holds
+  const int cols = K * na * N, ns = full ? 9 : 1;
+  const int64_t rows = (int64_t)W * na;
+  int64_t splits = std::min<int64_t>((rows + 2047) / 2048, 64);
+  if (part) splits = std::min<int64_t>(splits, part_floats / ((int64_t)cols * (1 + ns)));
+  if (!part || splits < 2) splits = 1;
+  const int64_t rps = (rows + splits - 1) / splits;
+  float* pp = splits > 1 ? part : nullptr;
   if (full)
-    hipLaunchKernelGGL(adj_env_grad_kernel<true>, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W,
-                       K, na, j0, n, N, dpi, dsigma);
+    hipLaunchKernelGGL(adj_env_grad_kernel<true>, dim3(cols, (unsigned)splits), dim3(256), 0, s, cot_env, pos, nuc, pi,
+                       sigma, W, K, na, j0, n, N, dpi, dsigma, rps, pp);
   else
-    hipLaunchKernelGGL(adj_env_grad_kernel<false>, dim3(K * na * N), dim3(256), 0, s, cot_env, pos, nuc, pi, sigma, W,
-                       K, na, j0, n, N, dpi, dsigma);
+    hipLaunchKernelGGL(adj_env_grad_kernel<false>, dim3(cols, (unsigned)splits), dim3(256), 0, s, cot_env, pos, nuc,
+                       pi, sigma, W, K, na, j0, n, N, dpi, dsigma, rps, pp);
+  if (pp)
+    hipLaunchKernelGGL(env_grad_final_kernel, dim3((cols * (1 + ns) + 255) / 256), dim3(256), 0, s, pp, (int)splits,
+                       cols, ns, dpi, dsigma);
   return hipGetLastError();
 }
 

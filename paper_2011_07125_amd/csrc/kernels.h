@@ -185,10 +185,13 @@ hipError_t launch_adj_orbital_cot(bool fp64, const void* binv, const void* rho, 
                                   const float* env, int W, int K, int na, int ldu, float* cot_u, float* cot_env,
                                   hipStream_t s);
 // dpi, dsigma += the envelope-parameter gradient summed over the W walkers,
-// or (walker_ld > 0) per walker at dpi + w walker_ld, dsigma + w walker_ld
+// or (walker_ld > 0) per walker at dpi + w walker_ld, dsigma + w walker_ld.
+// part (part_floats floats, or NULL): scratch for the partial sums of the
+// walker rows' splits
 hipError_t launch_adj_env_grad(const float* cot_env, const float* pos, const float* nuc, const float* pi,
                                const float* sigma, bool full, int W, int K, int na, int j0, int n, int N, float* dpi,
-                               float* dsigma, hipStream_t s, int64_t walker_ld = 0);
+                               float* dsigma, hipStream_t s, int64_t walker_ld = 0, float* part = nullptr,
+                               int64_t part_floats = 0);
 // the cotangent pass of a one-electron layer (W walkers of n electrons,
 // rows of cols): CH += the mean-field cotangent CMF [W][2 cols] / n_a (when
 // cmf is not NULL), CP = CH sech^2(PRE), S[w] = sum over the walker's
