@@ -485,24 +485,36 @@ static hipError_t run_det_mid(int na, const PT* phi, int grid, int T, int n3, R*
   return hipGetLastError();
 }
 
-// Small matrices (n_a <= 6): one thread per matrix, everything in registers.
-// The orbital jets are stored matrix-index fastest, phi[(t n_a^2 + e) M + mat]
-// with M = W K, so that consecutive threads read consecutive addresses.
-// Gauss-Jordan elimination with partial pivoting on [B | I] gives B^-1,
-// the pivots give sign and log|det B|.
-template <class R, int NA, class PT>
-__global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M, int T, int n3, R* D, int dstride,
-                                                        R* ainv) {
-  const int64_t mat = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (mat >= M) return;
-  constexpr int NSQ = NA * NA;
-  R* out = D + mat * dstride;
+// Small matrices (n_a <= 6): P threads per matrix (consecutive lanes of one
+// wavefront), everything in registers.  The orbital jets are stored
+// matrix-index fastest, phi[(t n_a^2 + e) M + mat] with M = W K, so that
+// consecutive threads read consecutive addresses.  Each of the P threads
+// factors the matrix (the same instructions, so the same bits): Gauss-Jordan
+// elimination with partial pivoting on [B | I] gives B^-1, the pivots give
+// sign and log|det B|.  The tangent rows are dealt out over the P threads
+// (thread p takes t = p, p + P, ...); each writes its d_t, and the terms of
+// q = sum_t tr((B^-1 M_t)^2) go through LDS so that the first thread adds
+// them in t order, as one thread alone would.
+constexpr int DET_SMALL_MAX_TAN = 3 * MAXNA;  // tangent rows of the LDS terms (3n, n <= 32)
+
+template <class R, int NA, class PT, int P>
+__global__ __launch_bounds__(64) void det_small_kernel(const PT* phi, int64_t M, int T, int n3, R* D, int dstride,
+                                                       R* ainv) {
+  constexpr int NSQ = NA * NA, MPB = 64 / P;  // matrices per block (one wavefront)
+  __shared__ R qs[P > 1 ? MPB : 1][P > 1 ? DET_SMALL_MAX_TAN : 1];
+  const int lm = threadIdx.x / P, p = threadIdx.x % P;
+  const int64_t mat = (int64_t)blockIdx.x * MPB + lm;
+  const bool valid = mat < M;
+  if (P == 1 && !valid) return;
+  // lanes past the last matrix factor the last one and store nothing
+  const int64_t mr = valid ? mat : M - 1;
+  R* out = D + mr * dstride;
   R B[NA][NA], X[NA][NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j)
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      B[j][i] = (R)phi[(int64_t)(j * NA + i) * M + mat];
+      B[j][i] = (R)phi[(int64_t)(j * NA + i) * M + mr];
       X[j][i] = j == i ? (R)1 : (R)0;
     }
   R nb = 0;  // ||B||_inf
@@ -519,17 +531,17 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
   for (int c = 0; c < NA; ++c) {
     // pivot row p >= c with the largest |B[p][c]|; exchange rows c and p
     R best = fabs(B[c][c]);
-    int p = c;
+    int pr = c;
 #pragma unroll
     for (int r = c + 1; r < NA; ++r)
       if (fabs(B[r][c]) > best) {
         best = fabs(B[r][c]);
-        p = r;
+        pr = r;
       }
     if (best == (R)0) singular = true;
 #pragma unroll
     for (int r = c + 1; r < NA; ++r)
-      if (r == p) {
+      if (r == pr) {
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
           R t = B[c][k];
@@ -540,7 +552,7 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
           X[r][k] = t;
         }
       }
-    if (p != c) sg = -sg;
+    if (pr != c) sg = -sg;
     const R piv = singular ? (R)1 : B[c][c];
     if (piv < 0) sg = -sg;
     la += log(fabs(piv));
@@ -561,24 +573,28 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
         }
       }
   }
-  if (singular) {
-    for (int e = 0; e < dstride; ++e) out[e] = (R)0;
-    out[1] = -INFINITY;
-    if (T > 1) out[4 + n3] = INFINITY;
-    if (ainv)
-      for (int e = 0; e < NSQ; ++e) ainv[mat * NSQ + e] = (R)0;
-    return;
-  }
-  out[0] = sg;
-  out[1] = la;
-  if (ainv) {
+  const bool lead = valid && p == 0;
+  const bool store = valid && !singular;
+  if (lead) {
+    if (singular) {
+      for (int e = 0; e < dstride; ++e) out[e] = (R)0;
+      out[1] = -INFINITY;
+      if (T > 1) out[4 + n3] = INFINITY;
+      if (ainv)
+        for (int e = 0; e < NSQ; ++e) ainv[mat * NSQ + e] = (R)0;
+    } else {
+      out[0] = sg;
+      out[1] = la;
+      if (ainv) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < NA; ++b) ainv[mat * NSQ + a * NA + b] = X[a][b];
+          for (int b = 0; b < NA; ++b) ainv[mat * NSQ + a * NA + b] = X[a][b];
+      }
+    }
   }
-  if (T <= 1) return;
-  {
+  if (T <= 1) return;  // uniform over the launch
+  if (lead && !singular) {
     R ni = 0;  // ||B^-1||_inf
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
@@ -591,9 +607,9 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
   }
   // d_t = tr(B^-1 M_t), q = sum_t tr((B^-1 M_t)^2), lap = tr(B^-1 lap B)
   R q = 0;
-  for (int tt = 0; tt <= n3; ++tt) {
+  for (int tt = p; tt <= n3; tt += P) {
     const int row = tt < n3 ? 1 + tt : T - 1;
-    const PT* Pm = phi + (int64_t)row * NSQ * M + mat;
+    const PT* Pm = phi + (int64_t)row * NSQ * M + mr;
     R Mt[NA][NA];
 #pragma unroll
     for (int c = 0; c < NA; ++c)
@@ -613,36 +629,59 @@ __global__ __launch_bounds__(256) void det_small_kernel(const PT* phi, int64_t M
 #pragma unroll
     for (int a = 0; a < NA; ++a) d += Y[a][a];
     if (tt < n3) {
-      out[2 + tt] = d;
+      if (store) out[2 + tt] = d;
       R qq = 0;
 #pragma unroll
       for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < NA; ++b) qq += Y[a][b] * Y[b][a];
-      q += qq;
-    } else {
+      if constexpr (P > 1) qs[lm][tt] = qq;
+      else q += qq;
+    } else if (store) {
       out[3 + n3] = d;
     }
   }
-  out[2 + n3] = q;
+  if constexpr (P > 1) {
+    __syncthreads();
+    if (lead && !singular)
+      for (int tt = 0; tt < n3; ++tt) q += qs[lm][tt];
+  }
+  if (lead && !singular) out[2 + n3] = q;
 }
 
-template <class R, class PT>
-static hipError_t run_det_small(int na, const PT* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
-                                hipStream_t s) {
+template <class R, class PT, int P>
+static hipError_t run_det_small_p(int na, const PT* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
+                                  hipStream_t s) {
   // one wavefront per block, so that the few thousand matrices of a
   // float64 re-evaluation still spread over the compute units
-  const int grid = (int)((M + 63) / 64);
+  const int grid = (int)((M + 64 / P - 1) / (64 / P));
   switch (na) {
-    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
-    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6, PT>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 1: hipLaunchKernelGGL((det_small_kernel<R, 1, PT, P>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 2: hipLaunchKernelGGL((det_small_kernel<R, 2, PT, P>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 3: hipLaunchKernelGGL((det_small_kernel<R, 3, PT, P>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 4: hipLaunchKernelGGL((det_small_kernel<R, 4, PT, P>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 5: hipLaunchKernelGGL((det_small_kernel<R, 5, PT, P>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
+    case 6: hipLaunchKernelGGL((det_small_kernel<R, 6, PT, P>), dim3(grid), dim3(64), 0, s, phi, M, T, n3, D, dstride, ainv); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// threads per matrix: one for the value passes and for batches that give
+// every SIMD a wavefront (32768 matrices or more: the extra factorisations
+// and loads of more threads cost more than they save, 61 -> 81 us for the
+// 65536 matrices of a Ne-like spin at four per matrix); with tangents and
+// fewer matrices, up to eight, so that the few wavefronts of a small batch
+// (the float64 re-evaluation: 29 -> 12 us for 1968 matrices at eight) take
+// fewer serial steps
+template <class R, class PT>
+static hipError_t run_det_small(int na, const PT* phi, int64_t M, int T, int n3, R* D, int dstride, R* ainv,
+                                hipStream_t s) {
+  if (T <= 1 || n3 > DET_SMALL_MAX_TAN || M >= 32768)
+    return run_det_small_p<R, PT, 1>(na, phi, M, T, n3, D, dstride, ainv, s);
+  if (M >= 16384) return run_det_small_p<R, PT, 2>(na, phi, M, T, n3, D, dstride, ainv, s);
+  if (M >= 8192) return run_det_small_p<R, PT, 4>(na, phi, M, T, n3, D, dstride, ainv, s);
+  return run_det_small_p<R, PT, 8>(na, phi, M, T, n3, D, dstride, ainv, s);
 }
 
 bool det_uses_small(int na) { return na <= DET_SMALL_MAX; }
