@@ -605,16 +605,28 @@ __global__ __launch_bounds__(64) void det_small_kernel(const PT* phi, int64_t M,
     }
     out[4 + n3] = nb * ni;
   }
-  // d_t = tr(B^-1 M_t), q = sum_t tr((B^-1 M_t)^2), lap = tr(B^-1 lap B)
-  R q = 0;
-  for (int tt = p; tt <= n3; tt += P) {
+  // d_t = tr(B^-1 M_t), q = sum_t tr((B^-1 M_t)^2), lap = tr(B^-1 lap B).
+  // The next tangent matrix is loaded while this one is multiplied; every
+  // step issues the same loads (the last one reloads its own matrix), so
+  // that the wait before a step is only for the loads of the step before.
+  auto load_t = [&](int tt, PT (&dst)[NA][NA]) {
     const int row = tt < n3 ? 1 + tt : T - 1;
     const PT* Pm = phi + (int64_t)row * NSQ * M + mr;
+#pragma unroll
+    for (int c = 0; c < NA; ++c)
+#pragma unroll
+      for (int b = 0; b < NA; ++b) dst[c][b] = Pm[(int64_t)(c * NA + b) * M];
+  };
+  R q = 0;
+  PT nxt[NA][NA];
+  if (p <= n3) load_t(p, nxt);
+  for (int tt = p; tt <= n3; tt += P) {
     R Mt[NA][NA];
 #pragma unroll
     for (int c = 0; c < NA; ++c)
 #pragma unroll
-      for (int b = 0; b < NA; ++b) Mt[c][b] = (R)Pm[(int64_t)(c * NA + b) * M];
+      for (int b = 0; b < NA; ++b) Mt[c][b] = (R)nxt[c][b];
+    load_t(min(tt + P, n3), nxt);
     R Y[NA][NA];
     R d = 0;
 #pragma unroll
