@@ -71,11 +71,30 @@ __global__ __launch_bounds__(1024) void select_top_kernel(const float* key, int 
       if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1);
     }
     __syncthreads();
-    if (tid == 0) {
-      int above = 0, d = 255;
-      for (; d > 0 && above + hist[d] < need; --d) above += hist[d];
-      s_pick[0] = d;
-      s_pick[1] = need - above;
+    if (tid < 64) {
+      // the byte value d of the need-th largest key: the first bin from
+      // the top whose count reaches need together with the bins above it
+      // (bin 0 if none does).  Lane l holds bins 255 - 4 l - j, j < 4; a
+      // scan over the wavefront gives the count above each lane's bins.
+      int h[4], tot = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tot += h[j] = hist[255 - 4 * tid - j];
+      int inc = tot;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(inc, off, 64);
+        if (tid >= off) inc += t;
+      }
+      int above = inc - tot;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int d = 255 - 4 * tid - j;
+        if (above < need && (d == 0 || above + h[j] >= need)) {
+          s_pick[0] = d;
+          s_pick[1] = need - above;
+        }
+        above += h[j];
+      }
     }
     __syncthreads();
     prefix |= (uint32_t)s_pick[0] << shift;
