@@ -628,7 +628,8 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   const int T = b.T, Tp = b.Tp;
   const int64_t R = Wc * p.n;
   auto SG = [stage_all](int st) { return stage_all >= 0 ? stage_all : st; };
-  FN_T(SG(ST_FEATURES), launch_features(p.f64, pos, nuc, (int)Wc, p.n, p.N, T, Tp, b.H0, p.dinp[0], s));
+  // the input jets and, for the first layer, their spin means
+  FN_T(SG(ST_FEATURES), launch_features(p.f64, pos, nuc, (int)Wc, p.n, p.nu, p.N, T, Tp, b.H0, p.dinp[0], b.Hbar, s));
   if (cap)
     FN_T(SG(ST_FEATURES), launch_copy_rows((const float*)b.H0, (int64_t)Tp * p.dinp[0], cap->H[0], p.dinp[0], R,
                                            p.dinp[0], s));
@@ -657,7 +658,7 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
                                           p.gwp[l], s));
   const void* Hin = b.H0;
   void* Hout = b.Ha;
-  bool hbar_ready = false;  // the previous layer's kernel wrote the spin means of Hin
+  bool hbar_ready = true;  // the previous kernel wrote the spin means of Hin
   for (int l = 0; l < p.L; ++l) {
     if (!hbar_ready)
       FN_T(SG(ST_MEANFIELD), launch_meanfield(p.f64, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
@@ -807,7 +808,7 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
                                const float* params, const void* pk, const AdjBufs& b, hipStream_t s) {
   Bufs fb;
   fb.pk = const_cast<void*>(pk);
-  FN_T(ST_ADJ_FWD, launch_features(false, pos, nuc, (int)Wc, p.n, p.N, 1, 1, b.H[0], p.dinp[0], s));
+  FN_T(ST_ADJ_FWD, launch_features(false, pos, nuc, (int)Wc, p.n, p.nu, p.N, 1, 1, b.H[0], p.dinp[0], b.Hbar[0], s));
   TwoElecArgs te;
   memset(&te, 0, sizeof(te));
   te.pos = pos;
@@ -830,7 +831,8 @@ static fn_status forward_store(const Plan& p, int64_t Wc, const float* pos, cons
   const int mode = p.bf16 ? MODE_BF16X3 : MODE_F32;
   for (int l = 0; l < p.L; ++l) {
     const int ldh = l == 0 ? p.dinp[0] : p.d1;
-    FN_T(ST_ADJ_FWD, launch_meanfield(false, b.H[l], ldh, (int)Wc, p.n, p.nu, 1, p.dinp[l], b.Hbar[l], s));
+    if (l > 0)  // the features kernel wrote the first layer's
+      FN_T(ST_ADJ_FWD, launch_meanfield(false, b.H[l], ldh, (int)Wc, p.n, p.nu, 1, p.dinp[l], b.Hbar[l], s));
     JetGemmArgs g;
     memset(&g, 0, sizeof(g));
     g.a0 = b.Hbar[l];

@@ -70,65 +70,104 @@ hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t
 //   h_i = concat_I (r_i - R_I, |r_i - R_I|)
 // d/dr_i of (r_i - R_I)_c = e_c; of |r_i - R_I| = (r_i - R_I)/|r_i - R_I|;
 // Laplacian of |r_i - R_I| = 2 / |r_i - R_I|.  S: float or double
-// (arithmetic and storage).
+// (arithmetic and storage).  Also the spin means the first layer's mean
+// field reads, Hbar[(w Tp + t)][a ldh + f] = mean_{j of spin a} H0[...]:
+// the sums take j in order from zero and are scaled as the separate
+// mean-field pass scales them (by 1/n_a in float32, divided by n_a in
+// float64), so they are the means of the stored values.
 //
-// Item k of electron g is jet row t = k / nv and nucleus I = k % nv (nv =
-// ldh / 4): its four features, stored as one vector.  A block handles
-// several electrons when one electron has fewer items than threads (the
-// value pass has one row), and steps over the electrons of the batch.
+// Item k of walker w is jet row t = k / nv and nucleus I = k % nv (nv =
+// ldh / 4): its four features for every electron of the walker in turn,
+// stored as one vector each.  A block handles several walkers when one
+// walker has fewer items than threads (the value pass has one row).
 template <class S>
-__global__ __launch_bounds__(256) void features_kernel(const float* pos, const float* nuc, int W, int n, int N, int T,
-                                                       int Tp, S* H0, int ldh) {
-  const int nv = ldh / 4, items = Tp * nv, groups = W * n;
-  const int epb = items >= (int)blockDim.x ? 1 : (int)blockDim.x / items;  // electrons per block step
-  for (int g0 = blockIdx.x * epb; g0 < groups; g0 += gridDim.x * epb) {
-    for (int q = threadIdx.x; q < epb * items; q += blockDim.x) {
+__global__ __launch_bounds__(256) void features_kernel(const float* pos, const float* nuc, int W, int n, int n_up,
+                                                       int N, int T, int Tp, S* H0, int ldh, S* Hbar) {
+  const int nv = ldh / 4, items = Tp * nv;
+  const int wpb = items >= (int)blockDim.x ? 1 : (int)blockDim.x / items;  // walkers per block step
+  for (int w0 = blockIdx.x * wpb; w0 < W; w0 += gridDim.x * wpb) {
+    for (int q = threadIdx.x; q < wpb * items; q += blockDim.x) {
       const int e = q / items, k = q - e * items;
-      const int g = g0 + e;
-      if (g >= groups) break;  // e grows with q
+      const int w = w0 + e;
+      if (w >= W) break;  // e grows with q
       const int t = k / nv, I = k - t * nv;
-      S v[4] = {0, 0, 0, 0};
-      if (I < N && t < T) {
-        const float* r = pos + (int64_t)g * 3;
-        const S d0 = (S)r[0] - (S)nuc[3 * I], d1 = (S)r[1] - (S)nuc[3 * I + 1], d2 = (S)r[2] - (S)nuc[3 * I + 2];
-        const S dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        const S dc[3] = {d0, d1, d2};
-        if (t == 0) {
-          v[0] = d0;
-          v[1] = d1;
-          v[2] = d2;
-          v[3] = dist;
-        } else if (t == T - 1) {
-          v[3] = (S)2 / dist;
-        } else {
-          const int jt = (t - 1) / 3, c = (t - 1) - 3 * jt;
-          if (jt == g % n) {
-            v[c] = (S)1;
-            v[3] = dc[c] / dist;
+      S su[4] = {0, 0, 0, 0}, sd[4] = {0, 0, 0, 0};
+      for (int j = 0; j < n; ++j) {
+        const int64_t g = (int64_t)w * n + j;
+        S v[4] = {0, 0, 0, 0};
+        if (I < N && t < T) {
+          const float* r = pos + g * 3;
+          const S d0 = (S)r[0] - (S)nuc[3 * I], d1 = (S)r[1] - (S)nuc[3 * I + 1], d2 = (S)r[2] - (S)nuc[3 * I + 2];
+          const S dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+          const S dc[3] = {d0, d1, d2};
+          if (t == 0) {
+            v[0] = d0;
+            v[1] = d1;
+            v[2] = d2;
+            v[3] = dist;
+          } else if (t == T - 1) {
+            v[3] = (S)2 / dist;
+          } else {
+            const int jt = (t - 1) / 3, c = (t - 1) - 3 * jt;
+            if (jt == j) {
+              v[c] = (S)1;
+              v[3] = dc[c] / dist;
+            }
           }
         }
+        S* dst = H0 + (g * Tp + t) * ldh + 4 * I;
+        if constexpr (sizeof(S) == 4) {
+          *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+        } else {
+          reinterpret_cast<double2*>(dst)[0] = double2{(double)v[0], (double)v[1]};
+          reinterpret_cast<double2*>(dst)[1] = double2{(double)v[2], (double)v[3]};
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (j < n_up) su[c] += v[c];
+          else sd[c] += v[c];
+        }
       }
-      S* dst = H0 + ((int64_t)g * Tp + t) * ldh + 4 * I;
+      S mu[4], md[4];
+      const int nd = n - n_up;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if constexpr (sizeof(S) == 4) {
+          mu[c] = su[c] * (n_up > 0 ? 1.0f / (float)n_up : 0.0f);
+          md[c] = sd[c] * (nd > 0 ? 1.0f / (float)nd : 0.0f);
+        } else {
+          mu[c] = n_up > 0 ? su[c] / (S)n_up : (S)0;
+          md[c] = nd > 0 ? sd[c] / (S)nd : (S)0;
+        }
+      }
+      S* hb = Hbar + ((int64_t)w * Tp + t) * 2 * ldh + 4 * I;
       if constexpr (sizeof(S) == 4) {
-        *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+        *reinterpret_cast<float4*>(hb) = float4{mu[0], mu[1], mu[2], mu[3]};
+        *reinterpret_cast<float4*>(hb + ldh) = float4{md[0], md[1], md[2], md[3]};
       } else {
-        reinterpret_cast<double2*>(dst)[0] = double2{(double)v[0], (double)v[1]};
-        reinterpret_cast<double2*>(dst)[1] = double2{(double)v[2], (double)v[3]};
+        reinterpret_cast<double2*>(hb)[0] = double2{mu[0], mu[1]};
+        reinterpret_cast<double2*>(hb)[1] = double2{mu[2], mu[3]};
+        reinterpret_cast<double2*>(hb + ldh)[0] = double2{md[0], md[1]};
+        reinterpret_cast<double2*>(hb + ldh)[1] = double2{md[2], md[3]};
       }
     }
   }
 }
 
-hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
-                           void* H0, int ldh, hipStream_t s) {
-  const int64_t groups = (int64_t)W * n;
-  if (groups <= 0) return hipSuccess;
+hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int n_up, int N, int T, int Tp,
+                           void* H0, int ldh, void* Hbar, hipStream_t s) {
+  if ((int64_t)W * n <= 0) return hipSuccess;
   // rows of 16-byte-aligned vectors (buffers are 256-byte aligned)
-  if (groups >= (1LL << 31) || ldh % 4 != 0 || ldh < 4 * N) return hipErrorInvalidValue;
-  const int items = Tp * (ldh / 4), epb = items >= 256 ? 1 : 256 / items;
-  const int grid = (int)std::min<int64_t>((groups + epb - 1) / epb, 16384);
-  if (f64) hipLaunchKernelGGL(features_kernel<double>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (double*)H0, ldh);
-  else hipLaunchKernelGGL(features_kernel<float>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, N, T, Tp, (float*)H0, ldh);
+  if ((int64_t)W * n >= (1LL << 31) || ldh % 4 != 0 || ldh < 4 * N || n_up < 0 || n_up > n)
+    return hipErrorInvalidValue;
+  const int items = Tp * (ldh / 4), wpb = items >= 256 ? 1 : 256 / items;
+  const int grid = (int)std::min<int64_t>((W + wpb - 1) / wpb, 16384);
+  if (f64)
+    hipLaunchKernelGGL(features_kernel<double>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, n_up, N, T, Tp,
+                       (double*)H0, ldh, (double*)Hbar);
+  else
+    hipLaunchKernelGGL(features_kernel<float>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, n_up, N, T, Tp,
+                       (float*)H0, ldh, (float*)Hbar);
   return hipGetLastError();
 }
 

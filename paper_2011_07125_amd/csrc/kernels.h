@@ -78,9 +78,11 @@ hipError_t launch_layer_plain(int mode, const JetGemmArgs& a, hipStream_t s);
 // bfloat16 hi planes at dst and lo planes at dst + plane (elements)
 hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t plane, const int64_t* plan,
                                int n_items, hipStream_t s);
-// f64: float64 arithmetic and storage (otherwise float32)
-hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int N, int T, int Tp,
-                           void* H0, int ldh, hipStream_t s);
+// f64: float64 arithmetic and storage (otherwise float32).  The input
+// jets H0 [W n][Tp][ldh] and their spin means Hbar [W Tp][2 ldh] (the first
+// n_up electrons of a walker are spin up)
+hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int n_up, int N, int T,
+                           int Tp, void* H0, int ldh, void* Hbar, hipStream_t s);
 struct TwoElecArgs {
   const float* pos;   // [W][n][3]
   const float* params;
