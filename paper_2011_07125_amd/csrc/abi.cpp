@@ -629,10 +629,9 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
   const int64_t R = Wc * p.n;
   auto SG = [stage_all](int st) { return stage_all >= 0 ? stage_all : st; };
   // the input jets and, for the first layer, their spin means
-  FN_T(SG(ST_FEATURES), launch_features(p.f64, pos, nuc, (int)Wc, p.n, p.nu, p.N, T, Tp, b.H0, p.dinp[0], b.Hbar, s));
-  if (cap)
-    FN_T(SG(ST_FEATURES), launch_copy_rows((const float*)b.H0, (int64_t)Tp * p.dinp[0], cap->H[0], p.dinp[0], R,
-                                           p.dinp[0], s));
+  // (and their value rows for the reverse pass, when it reads this pass)
+  FN_T(SG(ST_FEATURES), launch_features(p.f64, pos, nuc, (int)Wc, p.n, p.nu, p.N, T, Tp, b.H0, p.dinp[0], b.Hbar, s,
+                                        cap ? cap->H[0] : nullptr, cap ? cap->Hbar[0] : nullptr));
   TwoElecArgs te;
   memset(&te, 0, sizeof(te));
   te.pos = pos;
@@ -650,19 +649,16 @@ static fn_status forward(const Plan& p, Mode m, int64_t Wc, const float* pos, co
     te.G[l] = b.G[l];
     te.ldg[l] = p.gwp[l];
     te.h2_out[l] = cap ? cap->h2[l] : nullptr;
+    te.g_val_out[l] = cap ? cap->G[l] : nullptr;
   }
   FN_T(SG(ST_TWO_E), launch_two_electron(p.f64, te, s));
-  if (cap)
-    for (int l = 0; l < p.L; ++l)
-      FN_T(SG(ST_TWO_E), launch_copy_rows((const float*)b.G[l], (int64_t)Tp * p.gwp[l], cap->G[l], p.gwp[l], R,
-                                          p.gwp[l], s));
   const void* Hin = b.H0;
   void* Hout = b.Ha;
   bool hbar_ready = true;  // the previous kernel wrote the spin means of Hin
   for (int l = 0; l < p.L; ++l) {
     if (!hbar_ready)
       FN_T(SG(ST_MEANFIELD), launch_meanfield(p.f64, Hin, p.dinp[l], (int)Wc, p.n, p.nu, Tp, p.dinp[l], b.Hbar, s));
-    if (cap)
+    if (cap && l > 0)  // the features kernel wrote the first layer's
       FN_T(SG(ST_MEANFIELD), launch_copy_rows((const float*)b.Hbar, (int64_t)Tp * 2 * p.dinp[l], cap->Hbar[l],
                                               2 * p.dinp[l], Wc, 2 * p.dinp[l], s));
     JetGemmArgs g;

@@ -82,7 +82,8 @@ hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t
 // walker has fewer items than threads (the value pass has one row).
 template <class S>
 __global__ __launch_bounds__(256) void features_kernel(const float* pos, const float* nuc, int W, int n, int n_up,
-                                                       int N, int T, int Tp, S* H0, int ldh, S* Hbar) {
+                                                       int N, int T, int Tp, S* H0, int ldh, S* Hbar,
+                                                       float* h0_val, float* hbar_val) {
   const int nv = ldh / 4, items = Tp * nv;
   const int wpb = items >= (int)blockDim.x ? 1 : (int)blockDim.x / items;  // walkers per block step
   for (int w0 = blockIdx.x * wpb; w0 < W; w0 += gridDim.x * wpb) {
@@ -116,6 +117,8 @@ __global__ __launch_bounds__(256) void features_kernel(const float* pos, const f
           }
         }
         S* dst = H0 + (g * Tp + t) * ldh + 4 * I;
+        if (h0_val && t == 0)
+          *reinterpret_cast<float4*>(h0_val + g * ldh + 4 * I) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
         if constexpr (sizeof(S) == 4) {
           *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
         } else {
@@ -141,6 +144,11 @@ __global__ __launch_bounds__(256) void features_kernel(const float* pos, const f
         }
       }
       S* hb = Hbar + ((int64_t)w * Tp + t) * 2 * ldh + 4 * I;
+      if (hbar_val && t == 0) {
+        float* o = hbar_val + (int64_t)w * 2 * ldh + 4 * I;
+        *reinterpret_cast<float4*>(o) = float4{(float)mu[0], (float)mu[1], (float)mu[2], (float)mu[3]};
+        *reinterpret_cast<float4*>(o + ldh) = float4{(float)md[0], (float)md[1], (float)md[2], (float)md[3]};
+      }
       if constexpr (sizeof(S) == 4) {
         *reinterpret_cast<float4*>(hb) = float4{mu[0], mu[1], mu[2], mu[3]};
         *reinterpret_cast<float4*>(hb + ldh) = float4{md[0], md[1], md[2], md[3]};
@@ -155,7 +163,7 @@ __global__ __launch_bounds__(256) void features_kernel(const float* pos, const f
 }
 
 hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int n_up, int N, int T, int Tp,
-                           void* H0, int ldh, void* Hbar, hipStream_t s) {
+                           void* H0, int ldh, void* Hbar, hipStream_t s, float* h0_val, float* hbar_val) {
   if ((int64_t)W * n <= 0) return hipSuccess;
   // rows of 16-byte-aligned vectors (buffers are 256-byte aligned)
   if ((int64_t)W * n >= (1LL << 31) || ldh % 4 != 0 || ldh < 4 * N || n_up < 0 || n_up > n)
@@ -164,10 +172,10 @@ hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, 
   const int grid = (int)std::min<int64_t>((W + wpb - 1) / wpb, 16384);
   if (f64)
     hipLaunchKernelGGL(features_kernel<double>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, n_up, N, T, Tp,
-                       (double*)H0, ldh, (double*)Hbar);
+                       (double*)H0, ldh, (double*)Hbar, h0_val, hbar_val);
   else
     hipLaunchKernelGGL(features_kernel<float>, dim3(grid), dim3(256), 0, s, pos, nuc, W, n, n_up, N, T, Tp,
-                       (float*)H0, ldh, (float*)Hbar);
+                       (float*)H0, ldh, (float*)Hbar, h0_val, hbar_val);
   return hipGetLastError();
 }
 
@@ -180,6 +188,7 @@ struct TwoElecDev {
   void* G[8];
   int ldg[8];
   float* h2_out[8];
+  float* g_val_out[8];
 };
 
 // slot s of the block: electron ii = s / (n R2), partner j = (s / R2) % n,
@@ -266,6 +275,7 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
     {
       S* G = reinterpret_cast<S*>(a.G[l]);
       const int ldg = a.ldg[l];
+      float* const gv = a.g_val_out[l];  // row 0 of the jets, compactly (optional)
       const int T = a.T, Tp = a.Tp;
       const int nq = two_e_shared_rows(R2), ncol = 2 * ein;
       const S inv_up = n_up > 0 ? (S)1 / (S)n_up : (S)0, inv_dn = n_dn > 0 ? (S)1 / (S)n_dn : (S)0;
@@ -342,6 +352,9 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
               }
             }
             S* d = dst + (int64_t)e * Tp * ldg;
+            if (gv && t == 0)
+              *reinterpret_cast<float4*>(gv + (int64_t)(gbase + e) * ldg + c0) =
+                  float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
             if constexpr (sizeof(S) == 4) {
               *reinterpret_cast<float4*>(d) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
             } else {
@@ -394,6 +407,9 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
               }
             }
             S* dst = G + ((int64_t)(gbase + e) * Tp + t) * ldg + c0;
+            if (gv && t == 0)
+              *reinterpret_cast<float4*>(gv + (int64_t)(gbase + e) * ldg + c0) =
+                  float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
             if constexpr (sizeof(S) == 4) {
               *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
             } else {
@@ -648,6 +664,7 @@ hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s) {
     d.G[l] = l < a.L ? a.G[l] : nullptr;
     d.ldg[l] = l < a.L ? a.ldg[l] : 0;
     d.h2_out[l] = l < a.L ? a.h2_out[l] : nullptr;
+    d.g_val_out[l] = l < a.L ? a.g_val_out[l] : nullptr;
   }
   d.W = a.W; d.n = a.n; d.n_up = a.n_up; d.L = a.L; d.d2 = a.d2; d.T = a.T; d.Tp = a.Tp;
   d.R2 = a.T > 1 ? 8 : 1;

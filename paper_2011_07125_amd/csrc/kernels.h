@@ -81,8 +81,11 @@ hipError_t launch_pack_weights(int mode, const float* params, void* dst, int64_t
 // f64: float64 arithmetic and storage (otherwise float32).  The input
 // jets H0 [W n][Tp][ldh] and their spin means Hbar [W Tp][2 ldh] (the first
 // n_up electrons of a walker are spin up)
+// h0_val, hbar_val (optional, float32): row 0 (the values) of H0 and of
+// Hbar, [W n][ldh] and [W][2 ldh]
 hipError_t launch_features(bool f64, const float* pos, const float* nuc, int W, int n, int n_up, int N, int T,
-                           int Tp, void* H0, int ldh, void* Hbar, hipStream_t s);
+                           int Tp, void* H0, int ldh, void* Hbar, hipStream_t s, float* h0_val = nullptr,
+                           float* hbar_val = nullptr);
 struct TwoElecArgs {
   const float* pos;   // [W][n][3]
   const float* params;
@@ -92,6 +95,7 @@ struct TwoElecArgs {
   void* G[8];         // G^l [(w n + i) Tp + t][ldg_l] (float32, or float64 with f64)
   int ldg[8];
   float* h2_out[8];   // optional, float32: the values h^l_ij [w][i][j][ein_l] (both modes)
+  float* g_val_out[8];  // optional, float32: row 0 (the values) of G^l, [w n + i][ldg_l]
 };
 hipError_t launch_two_electron(bool f64, const TwoElecArgs& a, hipStream_t s);
 // electrons per workgroup of the two-electron stream (0: does not fit in LDS)
