@@ -517,6 +517,66 @@ __global__ __launch_bounds__(256) void two_electron_kernel(TwoElecDev a) {
         }
       }
       ein = d2;
+    } else if constexpr (sizeof(S) == 8 && D2 >= 16) {
+      // float64: the same product on v_mfma_f64_16x16x4f64, whose item r of
+      // lane (kq, c) is row kq + 4 r: jet row q = kq + 4 (r & 1) of pair
+      // r >> 1 (the value row of pair p is item 2 p of lane group 0)
+      const int lane = tid & 63, wave = tid >> 6, lr = lane & 15, lk = lane >> 4;
+      const int n_rt = two_e_rows(slots) / 16;
+      const bool res = ein == d2;
+      const S* cb = Ws + D2 * D2;
+      for (int tm = wave; tm < n_rt; tm += 4) {
+        doublex4 acc[D2 / 16];
+#pragma unroll
+        for (int tn = 0; tn < D2 / 16; ++tn) acc[tn] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < ein; ks += 4) {
+          const double av = Ps[(size_t)(tm * 16 + lr) * PS + ks + lk];
+#pragma unroll
+          for (int tn = 0; tn < D2 / 16; ++tn)
+            acc[tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Ws[(ks + lk) * D2 + tn * 16 + lr], acc[tn], 0, 0, 0);
+        }
+#pragma unroll
+        for (int tn = 0; tn < D2 / 16; ++tn) {
+          const int col = tn * 16 + lr;
+          double o4[4];
+          if (R2 == 8) {
+#pragma unroll
+            for (int pp = 0; pp < 2; ++pp) {
+              const double u0 = __shfl(acc[tn][2 * pp], lr, 64) + cb[col];
+              double sq = 0.0;
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int q = lk + 4 * h;
+                if (q >= 1 && q <= 6) sq += acc[tn][2 * pp + h] * acc[tn][2 * pp + h];
+              }
+              sq += __shfl_xor(sq, 16, 64);
+              sq += __shfl_xor(sq, 32, 64);
+              double y, dy;
+              tanh_sech2(u0, &y, &dy);
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int q = lk + 4 * h, r = 2 * pp + h;
+                o4[r] = q == 0 ? y : q <= 6 ? dy * acc[tn][r] : dy * acc[tn][r] - 2.0 * y * dy * sq;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              double y, dy;
+              tanh_sech2(acc[tn][r] + cb[col], &y, &dy);
+              o4[r] = y;
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const size_t e = (size_t)(tm * 16 + lk + 4 * r) * PS + col;
+            double v = o4[r];
+            if (res) v += Ps[e];
+            Ps[e] = col < d2 ? v : 0.0;
+          }
+        }
+      }
+      ein = d2;
     } else {
       S u[D2];
 #pragma unroll
