@@ -795,14 +795,51 @@ __global__ void meanfield4_kernel(const float* H, int ldh, int W, int n, int n_u
   }
 }
 
+// float64 version: one thread per 2 consecutive features of one (walker,
+// jet row), both spins, 16-byte loads (din_p and ldh even), the sums in j
+// order divided by n_a as meanfield_kernel does
+__global__ void meanfield2_kernel(const double* H, int ldh, int W, int n, int n_up, int Tp, int din_p, double* Hbar) {
+  const int q2 = din_p / 2;
+  const int64_t total = (int64_t)W * Tp * q2;
+  const int64_t js = (int64_t)Tp * ldh;  // electron stride
+  const int nd = n - n_up;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(idx % q2) * 2;
+    const int64_t row = idx / q2;  // w Tp + t
+    const int t = (int)(row % Tp);
+    const int64_t w = row / Tp;
+    const double* src = H + (w * n * Tp + t) * (int64_t)ldh + f;
+    double2 su = {0.0, 0.0}, sd = {0.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+      const double2 v = *reinterpret_cast<const double2*>(src + j * js);
+      if (j < n_up) {
+        su.x += v.x;
+        su.y += v.y;
+      } else {
+        sd.x += v.x;
+        sd.y += v.y;
+      }
+    }
+    double* o = Hbar + row * 2 * din_p + f;
+    *reinterpret_cast<double2*>(o) = n_up > 0 ? double2{su.x / (double)n_up, su.y / (double)n_up} : double2{0.0, 0.0};
+    *reinterpret_cast<double2*>(o + din_p) = nd > 0 ? double2{sd.x / (double)nd, sd.y / (double)nd} : double2{0.0, 0.0};
+  }
+}
+
 hipError_t launch_meanfield(bool f64, const void* H, int ldh, int W, int n, int n_up, int Tp, int din_p, void* Hbar,
                             hipStream_t s) {
   int64_t total = (int64_t)W * Tp * 2 * din_p;
   int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
   if (grid <= 0) return hipSuccess;
   if (f64) {
-    hipLaunchKernelGGL(meanfield_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)H, ldh, W, n, n_up, Tp,
-                       din_p, (double*)Hbar);
+    if (din_p % 2 == 0 && ldh % 2 == 0) {
+      const int64_t t2 = (int64_t)W * Tp * (din_p / 2);
+      hipLaunchKernelGGL(meanfield2_kernel, dim3((unsigned)std::min<int64_t>((t2 + 255) / 256, 65536)), dim3(256), 0, s,
+                         (const double*)H, ldh, W, n, n_up, Tp, din_p, (double*)Hbar);
+    } else {
+      hipLaunchKernelGGL(meanfield_kernel<double>, dim3(grid), dim3(256), 0, s, (const double*)H, ldh, W, n, n_up, Tp,
+                         din_p, (double*)Hbar);
+    }
     return hipGetLastError();
   }
   if (din_p % 4 == 0 && ldh % 4 == 0) {
