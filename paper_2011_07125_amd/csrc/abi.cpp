@@ -227,7 +227,7 @@ struct AdjBufs {
   void* rho;
   float* sign;
   float* logpsi;
-  float* CH[2];
+  float* CH;  // cotangents of a layer's output, then of its input (in place)
   float* CP;
   float* S;
   float* CMF;
@@ -329,8 +329,7 @@ static void carve_adjoint(const Plan& p, int64_t Wc, Carver& cv, AdjBufs& b, boo
   b.rho = cv.take((size_t)Wc * p.K * rb);
   b.sign = (float*)cv.take((size_t)Wc * 4);
   b.logpsi = (float*)cv.take((size_t)Wc * 4);
-  b.CH[0] = (float*)cv.take((size_t)R * p.d1 * 4);
-  b.CH[1] = (float*)cv.take((size_t)R * p.d1 * 4);
+  b.CH = (float*)cv.take((size_t)R * p.d1 * 4);
   b.CP = (float*)cv.take((size_t)R * p.d1 * 4);
   if (p.bf16) {
     b.pw_lo = (p.P + 7) / 8 * 8;  // 16-byte aligned lo plane
@@ -1013,7 +1012,7 @@ static fn_status backward(const Plan& p, int64_t Wc, const float* pos, const flo
   fn_status st;
   // the cotangent of the current layer's output, updated in place into
   // that of its input
-  float* CHc = b.CH[0];
+  float* CHc = b.CH;
   std::vector<KfacBlk> kb;
   if (kout) kb = kfac_blocks(p, nullptr);
   auto kblk = [&](int kind, int layer) -> const KfacBlk* {
